@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark: marginal-gain rays/s and replan p50/p99 latency, batched vs plain, one MI355X.
+
+One step = one replanning request: every node of the workload's tree(s) is
+evaluated (absolute and depth-buffer marginal gain, yaw window, depth buffer)
+and the gains and yaw windows are copied back to host memory. Inputs (map and
+trees) are resident on the GPU before the timed region starts.
+
+Modes
+  plain    paper-style (Sec. IV-C): one launch pair per depth level, stream
+           synchronised and gains/yaws copied to the host after every level.
+  batched  the whole request in one call (mg_eval_marginal_batch), one copy
+           of the results at the end.
+`value` is the batched mode's rays/s; the plain mode is reported beside it.
+
+Prints ONE JSON line (rank 0, N = 1). Extra fields: latency percentiles,
+the roofline of the dominant kernel and the oracle's CPU rate on a bounded
+sample (the oracle is used only in that leg).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="step", choices=["tiny", "step", "batch64", "large"])
+    ap.add_argument("--trees", type=int, default=None, help="keep only the first trees of a multi-tree workload")
+    ap.add_argument("--modes", default="plain,batched")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6)
+    return ap.parse_args()
+
+
+def work_counts(name):
+    """Per-workload oracle work counts (visits V, unknown visits U, ancestor tests T)."""
+    p = os.path.join(ROOT, "tests", "golden", "work_counts.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        return json.load(f).get(name)
+
+
+def cpu_baseline(w, target_rays):
+    """The oracle as it stands, one thread, on ancestor-closed chains of leaves of tree 0."""
+    from oracle import mgref
+    t = w.trees[0]
+    dep = t.depth()
+    order = np.argsort(-dep, kind="stable")
+    leaves = []
+    mask = np.zeros(t.n, np.uint8)
+    for nd in order:
+        leaves.append(int(nd))
+        mask = mgref.ancestor_closure(t.parent, leaves)
+        if mask.sum() * w.sensor.rays >= target_rays:
+            break
+    t0 = time.perf_counter()
+    mgref.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=1)
+    dt = time.perf_counter() - t0
+    rays = int(mask.sum()) * w.sensor.rays
+    return {"value": rays / dt, "unit": "rays/s", "cores": 1, "kind": "oracle",
+            "sample": f"{int(mask.sum())} nodes ({len(leaves)} deepest leaves of tree 0 and their ancestors), "
+                      f"{rays} rays, {dt:.1f} s on one thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        sys.exit(2)
+    import torch
+    from paper_2609_40297_amd import mg, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    mg.lib()
+    log(f"[bench] generating workload {args.workload}")
+    w = W.make(args.workload, n_trees=args.trees)
+    sen = w.sensor
+    n_total = sum(t.n for t in w.trees)
+    rays_per_step = n_total * sen.rays
+    log(f"[bench] {len(w.trees)} trees, {n_total} nodes, {rays_per_step} rays per step")
+
+    stream = torch.cuda.current_stream()
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    trees = [mg.Tree(M, t.pos_m, t.parent, sen) for t in w.trees]
+    dev = torch.device("cuda", 0)
+    g_all = torch.empty(n_total, dtype=torch.int32, device=dev)
+    y_all = torch.empty(n_total, dtype=torch.int32, device=dev)
+    host_g = torch.empty(n_total, dtype=torch.int32).pin_memory()
+    host_y = torch.empty(n_total, dtype=torch.int32).pin_memory()
+    per_tree_host = [(np.zeros(t.n, np.uint32), np.zeros(t.n, np.int32)) for t in trees]
+    handles = [t.handle for t in trees]
+
+    def step_plain():
+        for T, (hg, hy) in zip(trees, per_tree_host):
+            mg.mg_eval_marginal_levelsync(T.handle, hg, hy, None, None, None)
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    kernel_ms = []
+
+    def step_batched():
+        ev0.record(stream)
+        mg.mg_eval_marginal_batch(handles, g_all, y_all, None)
+        ev1.record(stream)
+        host_g.copy_(g_all, non_blocking=True)
+        host_y.copy_(y_all, non_blocking=True)
+        stream.synchronize()
+        kernel_ms.append(ev0.elapsed_time(ev1))
+
+    results = {}
+    for mode in args.modes.split(","):
+        fn = {"plain": step_plain, "batched": step_batched}[mode]
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        kernel_ms.clear()
+        lat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            fn()
+            lat.append((time.perf_counter() - s0) * 1e3)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        results[mode] = dict(rays_per_s=rays_per_step * args.steps / total, ms_per_step=total * 1e3 / args.steps,
+                             p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                             kernel_ms=float(np.mean(kernel_ms)) if kernel_ms else None)
+        log(f"[bench] {mode}: {results[mode]}")
+
+    # parity of the two modes on this workload (identical results required)
+    if "plain" in results and "batched" in results:
+        off = 0
+        for (hg, hy), t in zip(per_tree_host, trees):
+            assert np.array_equal(hg, host_g.numpy()[off:off + t.n].view(np.uint32)), "plain and batched differ"
+            assert np.array_equal(hy, host_y.numpy()[off:off + t.n]), "plain and batched differ"
+            off += t.n
+
+    main_mode = "batched" if "batched" in results else "plain"
+    R = results[main_mode]
+    roof = None
+    wc = work_counts(args.workload if args.trees is None else f"{args.workload}:{args.trees}")
+    if wc is not None and R.get("kernel_ms"):
+        alg_bytes = wc["visits"] * 1 + wc["anc_tests"] * 4 + wc["rays"] * 4
+        achieved = alg_bytes / (R["kernel_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "mg_eval_marginal_batch (trace + window kernels)",
+                "algorithmic_bytes_per_step": alg_bytes}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle, one thread, bounded sample)")
+        cpu = cpu_baseline(w, args.cpu_sample_rays)
+        log(f"[bench] cpu: {cpu}")
+
+    line = {
+        "metric": "marginal-gain rays/s + replan p50/p99 ms, batched vs plain, 1xMI355X",
+        "value": R["rays_per_s"],
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": R["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {W.WORKLOADS[args.workload]}", "trees": len(w.trees),
+                   "nodes": n_total, "rays_per_step": rays_per_step, "mode": main_mode},
+        "p50_ms": R["p50_ms"],
+        "p99_ms": R["p99_ms"],
+        "modes": results,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    for T in trees:
+        T.close()
+    M.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,147 @@
+/*
+ * mg.h — C ABI of the MI355X (gfx950) path-dependent marginal information
+ * gain library (paper: "GPU-Accelerated Path-Dependent Marginal Information
+ * Gain for Autonomous Exploration").
+ *
+ * The library evaluates, for every node of an RRT of candidate viewpoints,
+ * the number of unknown voxels its sensor rays meet (absolute gain, eq. 1)
+ * and the number left after dropping those its ancestors' depth buffers
+ * already see (path-dependent marginal gain, eq. 2, approximated with depth
+ * buffers as in Sec. IV-A/IV-B), together with the best yaw window. Nodes are
+ * evaluated after all their ancestors (Sec. IV-C); each node's first-hit depth
+ * buffer stays on the device for its descendants (Sec. IV-A).
+ *
+ * Conventions
+ *   - Every call returns MG_OK (0) or a negative MG_E_* code; the message of
+ *     the last failure on the calling thread is returned by mg_last_error().
+ *     No C++ exception crosses this interface.
+ *   - Host-side validation happens before any device work: a call that
+ *     returns MG_E_INVALID has enqueued nothing.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream). Evaluation
+ *     calls are asynchronous on that stream; their outputs are valid once the
+ *     caller has synchronised it. A device fault surfaces as MG_E_DEVICE.
+ *   - Handles are opaque and owned by the library until destroyed. One handle
+ *     must not be used from two streams at the same time; different handles
+ *     may be used concurrently from different threads.
+ *   - Units: positions in metres; depths in voxel units (multiply by the voxel
+ *     size for metres); gains are integer counts of ray-voxel incidences
+ *     (multiply by voxel_m^3 for the volume of eq. 1 and 2).
+ */
+#ifndef MG_H
+#define MG_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MG_OK = 0,
+    MG_E_INVALID = -1,      /* bad argument or input; nothing was enqueued      */
+    MG_E_NOMEM = -2,        /* device or host allocation failed                 */
+    MG_E_DEVICE = -3,       /* a HIP call or a kernel failed                    */
+    MG_E_BUSY = -4,         /* the handle is still referenced                   */
+    MG_E_UNSUPPORTED = -5   /* valid input outside the sizes this build handles */
+};
+
+typedef struct mg_map_s* mg_map;
+typedef struct mg_tree_s* mg_tree;
+
+/* Candidate-ray sensor (Sec. III-B yaw set, Sec. IV-A depth buffers).
+ * n_az columns cover 360 degrees, column c's centre at
+ * az_offset_deg + (c + 1/2) * 360 / n_az; n_el rows cover fov_v_deg,
+ * row j's centre at -fov_v_deg/2 + (j + 1/2) * fov_v_deg / n_el. The yaw set
+ * is yaw_bins azimuth bins; a yaw window of w = yaw_bins * fov_h_deg / 360
+ * bins holds w_buf = n_az * w / yaw_bins columns and defines a depth buffer of
+ * n_el x w_buf pixels. Requires w and w_buf integral, 2*w < yaw_bins,
+ * yaw_bins <= 256, n_az*n_el <= 2^22, 0 < fov_v_deg < 180 and range_m > 0;
+ * otherwise MG_E_INVALID. */
+typedef struct {
+    int32_t n_az;
+    int32_t n_el;
+    float fov_h_deg;
+    float fov_v_deg;
+    float range_m;
+    int32_t yaw_bins;
+    float az_offset_deg;
+} mg_sensor;
+
+/* Occupancy map (Sec. III-A: voxels of edge voxel_m labelled free, occupied
+ * or unknown; Sec. IV: converted to a contiguous grid and moved to the GPU).
+ *   states: HOST array [nz][ny][nx], x fastest, values 0 unknown, 1 free,
+ *           2 occupied (any other value: MG_E_INVALID). The library copies it
+ *           into its device layout before returning; the caller may free it
+ *           on return.
+ *   origin_m: world position of the grid's minimum corner.
+ * Sizes: 1 <= nx, ny, nz <= 8192 and nx*ny*nz < 2^32. */
+int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
+                  const float origin_m[3], void* hip_stream, mg_map* out);
+
+/* Frees the map. MG_E_BUSY while trees created on it still exist. */
+int mg_map_destroy(mg_map map);
+
+/* Candidate tree (Sec. III-A: nodes with positions; Sec. IV-D: the whole tree
+ * is built first, then evaluated).
+ *   pos_m: HOST array [n][3] in metres; parent: HOST array [n] with
+ *   parent[0] = -1 and 0 <= parent[i] < i. Depth <= 64, every node inside the
+ *   map, n >= 1; otherwise MG_E_INVALID. Both arrays are copied. Device
+ *   buffers for all later evaluations (depth buffers, bins, ancestor lists)
+ *   are allocated here, so evaluation calls allocate nothing. */
+int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* parent, int32_t n,
+                   const mg_sensor* sensor, void* hip_stream, mg_tree* out);
+
+int mg_tree_destroy(mg_tree tree);
+
+/* Number of nodes and depth-buffer size (n_el * w_buf) of a tree; -1 on a NULL handle. */
+int32_t mg_tree_nodes(mg_tree tree);
+int32_t mg_tree_buffer_pixels(mg_tree tree);
+
+/* Device bytes held by the tree (node data, depth buffers, bins): what an
+ * admission controller must reserve for it. */
+int64_t mg_tree_footprint_bytes(mg_tree tree);
+
+/* Path-dependent marginal gain of every node (eq. 2 with depth buffers,
+ * Sec. IV-B), nodes in depth order (Sec. IV-C), one launch pair per depth
+ * level (trace + window selection).
+ *   gain    DEVICE uint32[n]: marginal gain at the chosen window (incidences).
+ *   yaw_bin DEVICE int32[n]: chosen window k (bins k..k+w-1); the yaw angle
+ *           of the window centre is az_offset + k*360/B + fov_h/2.
+ *   depth   DEVICE float[n][n_el][w_buf] or NULL: each node's depth buffer at
+ *           its chosen window (first-hit parameter t in voxel units).
+ * All three are caller-owned device memory. */
+int mg_eval_marginal(mg_tree tree, void* hip_stream, uint32_t* gain, int32_t* yaw_bin, float* depth);
+
+/* Paper-style evaluation (Sec. IV-C: results return to the CPU after every
+ * level): as mg_eval_marginal, but after each level the stream is
+ * synchronised and that level's gains and yaw bins are copied into the HOST
+ * arrays host_gain / host_yaw_bin ([n], required). Blocks until done. */
+int mg_eval_marginal_levelsync(mg_tree tree, void* hip_stream, uint32_t* gain, int32_t* yaw_bin,
+                               float* depth, uint32_t* host_gain, int32_t* host_yaw_bin);
+
+/* Many trees at once (on one or several maps, same sensor geometry: equal
+ * n_az, n_el, yaw_bins and fov): one persistent launch in which each node
+ * starts as soon as its parent has finished. Outputs are concatenated in tree
+ * order (tree t's nodes start at the sum of the node counts of trees < t).
+ * Results equal per-tree mg_eval_marginal calls. The launch is recorded once
+ * per distinct tree list and replayed as a HIP graph. */
+int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
+                           int32_t* yaw_bin, float* depth);
+
+/* Absolute gain of every node (eq. 1 maximised over the yaw windows), no
+ * conditioning and no level order: one flat launch over all nodes.
+ *   gain DEVICE uint32[n], yaw_bin DEVICE int32[n]. */
+int mg_eval_absolute(mg_tree tree, void* hip_stream, uint32_t* gain, int32_t* yaw_bin);
+
+/* Host-only diagnostics: the sensor tables the library builds (no device
+ * work). dir and inv [n_az*n_el][3] (ray r = c*n_el + j), bv [n_az][2]
+ * (column left-boundary unit vectors), ts [n_el+1] (tan(e)|tan(e)| at row
+ * boundaries), bins [n_az], c0 [yaw_bins]. Any pointer may be NULL. */
+int mg_sensor_tables(const mg_sensor* sensor, float* dir, float* inv, float* bv, float* ts,
+                     int32_t* bins, int32_t* c0);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,569 @@
+// Host side of the C ABI declared in include/mg.h: validation, device
+// layouts, sensor tables and launch sequencing.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mg.h"
+#include "mg_batch.h"
+#include "mg_internal.h"
+
+using namespace mgk;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string t_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "%s: %s (%s:%d)", #expr, \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                      \
+    } while (0)
+
+extern "C" const char* mg_last_error(void) { return t_err.c_str(); }
+
+// ---------------------------------------------------------------- sensor tables
+
+namespace {
+
+struct SensorKey {
+    int32_t n_az, n_el, bins;
+    float fov_h, fov_v, range, az_off;
+    int device;
+    bool operator<(const SensorKey& o) const {
+        return std::tie(n_az, n_el, bins, fov_h, fov_v, range, az_off, device) <
+               std::tie(o.n_az, o.n_el, o.bins, o.fov_h, o.fov_v, o.range, o.az_off, o.device);
+    }
+};
+
+struct HostTables {
+    int32_t W = 0, H = 0, B = 0, w = 0, WB = 0;
+    std::vector<float> dir, inv, bv, ts;   // dir/inv [R*3], bv [W*2], ts [H+1]
+    std::vector<int32_t> bins, c0;
+};
+
+double snap_small(double x) { return std::fabs(x) < 1e-9 ? 0.0 : x; }
+
+// Validates a sensor and derives the window geometry. Column c's centre is at
+// az_offset + (c + 1/2) 360/W degrees, its bin the one holding that centre,
+// bin(c) = floor((2c+1) B / (2W)); window k holds the w_buf columns whose
+// centres fall in bins k..k+w-1, the first being ceil((2kW - B)/(2B)) mod W.
+int check_sensor(const mg_sensor* s, int32_t* w_out, int32_t* wb_out) {
+    if (!s) return fail(MG_E_INVALID, "sensor is NULL");
+    if (s->n_az < 1 || s->n_el < 1 || s->yaw_bins < 1)
+        return fail(MG_E_INVALID, "sensor sizes must be positive");
+    if (!(s->fov_h_deg > 0.0f) || !(s->fov_v_deg > 0.0f) || !(s->fov_v_deg < 180.0f) || !(s->range_m > 0.0f) ||
+        !std::isfinite(s->az_offset_deg))
+        return fail(MG_E_INVALID, "sensor angles/range out of range");
+    double wd = (double)s->yaw_bins * (double)s->fov_h_deg / 360.0;
+    long w = std::lround(wd);
+    if (w < 1 || std::fabs(wd - (double)w) > 1e-6)
+        return fail(MG_E_INVALID, "yaw_bins * fov_h / 360 must be an integer >= 1");
+    if (2 * w >= s->yaw_bins) return fail(MG_E_INVALID, "a yaw window must span less than 180 degrees");
+    if (((long)s->n_az * w) % s->yaw_bins != 0)
+        return fail(MG_E_INVALID, "n_az * window_bins must be a multiple of yaw_bins");
+    if (s->yaw_bins > kMaxBins || s->n_az > kMaxAz || s->n_el > kMaxEl || (long)s->n_az * s->n_el > (1L << 22))
+        return fail(MG_E_UNSUPPORTED, "sensor larger than this build supports");
+    *w_out = (int32_t)w;
+    *wb_out = (int32_t)((long)s->n_az * w / s->yaw_bins);
+    return MG_OK;
+}
+
+// The trigonometry of the sensor, evaluated once in double precision and
+// rounded to float (components below 1e-9 in magnitude become +0).
+void build_tables(const mg_sensor* s, int32_t w, int32_t wb, HostTables* T) {
+    const int W = s->n_az, H = s->n_el, B = s->yaw_bins;
+    T->W = W; T->H = H; T->B = B; T->w = w; T->WB = wb;
+    T->dir.assign((size_t)W * H * 3, 0.f);
+    T->inv.assign((size_t)W * H * 3, 0.f);
+    T->bv.assign((size_t)W * 2, 0.f);
+    T->ts.assign((size_t)H + 1, 0.f);
+    T->bins.assign(W, 0);
+    T->c0.assign(B, 0);
+    const double rad = M_PI / 180.0;
+    const double step_az = 360.0 / (double)W;
+    const double step_el = (double)s->fov_v_deg / (double)H;
+    for (int c = 0; c < W; ++c) {
+        const double az = ((double)s->az_offset_deg + ((double)c + 0.5) * step_az) * rad;
+        for (int j = 0; j < H; ++j) {
+            const double el = (-(double)s->fov_v_deg / 2.0 + ((double)j + 0.5) * step_el) * rad;
+            const double v[3] = {std::cos(el) * std::cos(az), std::cos(el) * std::sin(az), std::sin(el)};
+            const size_t r = (size_t)c * H + j;
+            for (int a = 0; a < 3; ++a) {
+                const float f = (float)snap_small(v[a]);
+                T->dir[3 * r + a] = f;
+                T->inv[3 * r + a] = f != 0.0f ? 1.0f / f : 0.0f;
+            }
+        }
+        const double beta = ((double)s->az_offset_deg + (double)c * step_az) * rad;
+        T->bv[2 * c] = (float)snap_small(std::cos(beta));
+        T->bv[2 * c + 1] = (float)snap_small(std::sin(beta));
+        T->bins[c] = (int32_t)(((long)(2 * c + 1) * B) / (2L * W));
+    }
+    for (int j = 0; j <= H; ++j) {
+        const double e = (-(double)s->fov_v_deg / 2.0 + (double)j * step_el) * rad;
+        const double t = snap_small(std::tan(e));
+        T->ts[j] = (float)(t * std::fabs(t));
+    }
+    for (int k = 0; k < B; ++k) {
+        const long num = 2L * k * W - B, den = 2L * B;
+        const long first = num >= 0 ? (num + den - 1) / den : 0;
+        T->c0[k] = (int32_t)(first % W);
+    }
+}
+
+// Device copy of one sensor's tables, shared by all trees with that sensor on
+// that device (reference counted).
+struct SensorRes {
+    SensorKey key;
+    int refs = 0;
+    HostTables host;
+    float4 *d4 = nullptr, *iv4 = nullptr;
+    int32_t *bins = nullptr, *c0 = nullptr;
+    float2* bv = nullptr;
+    float* ts = nullptr;
+    size_t bytes = 0;
+};
+
+std::mutex g_sensor_mu;
+std::map<SensorKey, SensorRes*> g_sensors;
+
+void free_sensor(SensorRes* r) {
+    (void)hipFree(r->d4); (void)hipFree(r->iv4); (void)hipFree(r->bins); (void)hipFree(r->c0); (void)hipFree(r->bv); (void)hipFree(r->ts);
+    delete r;
+}
+
+int acquire_sensor(const mg_sensor* s, hipStream_t stream, SensorRes** out) {
+    int32_t w, wb;
+    int rc = check_sensor(s, &w, &wb);
+    if (rc != MG_OK) return rc;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    SensorKey key{s->n_az, s->n_el, s->yaw_bins, s->fov_h_deg, s->fov_v_deg, s->range_m, s->az_offset_deg, dev};
+    std::lock_guard<std::mutex> lk(g_sensor_mu);
+    auto it = g_sensors.find(key);
+    if (it != g_sensors.end()) {
+        it->second->refs++;
+        *out = it->second;
+        return MG_OK;
+    }
+    std::unique_ptr<SensorRes> r(new (std::nothrow) SensorRes());
+    if (!r) return fail(MG_E_NOMEM, "host allocation failed");
+    r->key = key;
+    build_tables(s, w, wb, &r->host);
+    const HostTables& T = r->host;
+    const size_t R = (size_t)T.W * T.H;
+    std::vector<float4> d4(R), iv4(R);
+    for (size_t i = 0; i < R; ++i) {
+        d4[i] = make_float4(T.dir[3 * i], T.dir[3 * i + 1], T.dir[3 * i + 2], 0.f);
+        iv4[i] = make_float4(T.inv[3 * i], T.inv[3 * i + 1], T.inv[3 * i + 2], 0.f);
+    }
+    auto cleanup = [&]() { SensorRes* p = r.release(); free_sensor(p); };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc(&r->d4, R * sizeof(float4));
+    if (e == hipSuccess) e = hipMalloc(&r->iv4, R * sizeof(float4));
+    if (e == hipSuccess) e = hipMalloc(&r->bins, T.W * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&r->c0, T.B * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&r->bv, T.W * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc(&r->ts, (T.H + 1) * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d4, d4.data(), R * sizeof(float4), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->iv4, iv4.data(), R * sizeof(float4), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->bins, T.bins.data(), T.W * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->c0, T.c0.data(), T.B * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->bv, T.bv.data(), T.W * sizeof(float2), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->ts, T.ts.data(), (T.H + 1) * sizeof(float), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "sensor upload: %s", hipGetErrorString(e));
+    }
+    r->bytes = R * 2 * sizeof(float4) + T.W * (sizeof(int32_t) + sizeof(float2)) + T.B * sizeof(int32_t) +
+               (T.H + 1) * sizeof(float);
+    r->refs = 1;
+    SensorRes* p = r.release();
+    g_sensors[key] = p;
+    *out = p;
+    return MG_OK;
+}
+
+void release_sensor(SensorRes* r) {
+    std::lock_guard<std::mutex> lk(g_sensor_mu);
+    if (--r->refs == 0) {
+        g_sensors.erase(r->key);
+        free_sensor(r);
+    }
+}
+
+SensorDev sensor_dev(const SensorRes* r, float rv) {
+    const HostTables& T = r->host;
+    SensorDev sd;
+    sd.d4 = r->d4; sd.iv4 = r->iv4; sd.bin_of_col = r->bins; sd.bv = r->bv; sd.ts = r->ts; sd.c0_of_win = r->c0;
+    sd.W = T.W; sd.H = T.H; sd.B = T.B; sd.w = T.w; sd.WB = T.WB;
+    sd.R = T.W * T.H;
+    sd.T = (sd.R + kThreads - 1) / kThreads;
+    sd.rv = rv;
+    sd.rv2 = rv * rv;
+    sd.inv_daz = (float)((double)T.W / (2.0 * M_PI));
+    sd.el0 = (float)(-(double)r->key.fov_v / 2.0 * M_PI / 180.0);
+    sd.inv_del = (float)((double)T.H / ((double)r->key.fov_v * M_PI / 180.0));
+    return sd;
+}
+
+}  // namespace
+
+extern "C" int mg_sensor_tables(const mg_sensor* sensor, float* dir, float* inv, float* bv, float* ts, int32_t* bins,
+                                int32_t* c0) {
+    int32_t w, wb;
+    int rc = check_sensor(sensor, &w, &wb);
+    if (rc != MG_OK) return rc;
+    HostTables T;
+    build_tables(sensor, w, wb, &T);
+    if (dir) std::memcpy(dir, T.dir.data(), T.dir.size() * sizeof(float));
+    if (inv) std::memcpy(inv, T.inv.data(), T.inv.size() * sizeof(float));
+    if (bv) std::memcpy(bv, T.bv.data(), T.bv.size() * sizeof(float));
+    if (ts) std::memcpy(ts, T.ts.data(), T.ts.size() * sizeof(float));
+    if (bins) std::memcpy(bins, T.bins.data(), T.bins.size() * sizeof(int32_t));
+    if (c0) std::memcpy(c0, T.c0.data(), T.c0.size() * sizeof(int32_t));
+    return MG_OK;
+}
+
+// ---------------------------------------------------------------- maps
+
+struct mg_map_s {
+    MapDev dev{};
+    uint8_t* bricks = nullptr;
+    float voxel_m = 0.f;
+    float origin[3] = {0, 0, 0};
+    int device = 0;
+    size_t bytes = 0;
+    std::atomic<int> trees{0};
+};
+
+extern "C" int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
+                             const float origin_m[3], void* hip_stream, mg_map* out) {
+    if (!out) return fail(MG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!states || !origin_m) return fail(MG_E_INVALID, "states/origin is NULL");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 8192 || ny > 8192 || nz > 8192)
+        return fail(MG_E_INVALID, "grid dims must be in [1, 8192]");
+    if (!(voxel_m > 0.0f) || !std::isfinite(voxel_m)) return fail(MG_E_INVALID, "voxel_m must be positive");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(origin_m[a])) return fail(MG_E_INVALID, "origin must be finite");
+    const size_t nvox = (size_t)nx * ny * nz;
+    if (nvox >= (1ull << 32)) return fail(MG_E_INVALID, "grid has 2^32 voxels or more");
+    const int32_t nbx = (nx + 7) / 8, nby = (ny + 7) / 8, nbz = (nz + 7) / 8;
+    const size_t padded = (size_t)nbx * nby * nbz * 512u;
+    if (padded >= (1ull << 32)) return fail(MG_E_UNSUPPORTED, "bricked grid exceeds 2^32 bytes");
+    for (size_t i = 0; i < nvox; ++i)
+        if (states[i] > 2) return fail(MG_E_INVALID, "voxel %zu has state %u (expected 0, 1 or 2)", i, states[i]);
+
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::unique_ptr<mg_map_s> m(new (std::nothrow) mg_map_s());
+    if (!m) return fail(MG_E_NOMEM, "host allocation failed");
+    HIP_TRY(hipGetDevice(&m->device));
+    uint8_t* dense = nullptr;
+    HIP_TRY(hipMalloc(&dense, nvox));
+    hipError_t e = hipMalloc(&m->bricks, padded);
+    if (e == hipSuccess) e = hipMemcpyAsync(dense, states, nvox, hipMemcpyHostToDevice, s);
+    m->dev.bricks = m->bricks;
+    m->dev.nx = nx; m->dev.ny = ny; m->dev.nz = nz;
+    m->dev.nbx = nbx; m->dev.nby = nby; m->dev.nbz = nbz;
+    if (e == hipSuccess) e = launch_brick(dense, m->bricks, m->dev, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dense);
+    if (e != hipSuccess) {
+        (void)hipFree(m->bricks);
+        return fail(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "map upload: %s", hipGetErrorString(e));
+    }
+    m->voxel_m = voxel_m;
+    for (int a = 0; a < 3; ++a) m->origin[a] = origin_m[a];
+    m->bytes = padded;
+    *out = m.release();
+    return MG_OK;
+}
+
+extern "C" int mg_map_destroy(mg_map map) {
+    if (!map) return fail(MG_E_INVALID, "map is NULL");
+    if (map->trees.load() != 0) return fail(MG_E_BUSY, "%d trees still use this map", map->trees.load());
+    (void)hipFree(map->bricks);
+    delete map;
+    return MG_OK;
+}
+
+// ---------------------------------------------------------------- trees
+
+struct mg_tree_s {
+    mg_map map = nullptr;
+    SensorRes* sensor = nullptr;
+    mg_sensor params{};
+    int32_t n = 0;
+    int32_t levels = 0;
+    std::vector<int32_t> level_ptr;       // host copy [levels+1]
+    std::vector<int32_t> level_nodes_h;   // host copy [n]
+    std::vector<int32_t> parent_h;
+    std::vector<int32_t> depth_h;
+    // device
+    void* block = nullptr;                // one allocation for all node data
+    TreeDev dev{};
+    SensorDev sd{};
+    size_t bytes = 0;
+    int device = 0;
+    uint32_t* scratch_gain = nullptr;     // used when the caller asks only for host results
+    int32_t* scratch_yaw = nullptr;
+};
+
+namespace {
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+}
+
+extern "C" int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* parent, int32_t n,
+                              const mg_sensor* sensor, void* hip_stream, mg_tree* out) {
+    if (!out) return fail(MG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!map || !pos_m || !parent) return fail(MG_E_INVALID, "map/pos/parent is NULL");
+    if (n < 1) return fail(MG_E_INVALID, "a tree needs at least one node");
+    if (n > (1 << 24)) return fail(MG_E_UNSUPPORTED, "more than 2^24 nodes");
+    int32_t w, wb;
+    int rc = check_sensor(sensor, &w, &wb);
+    if (rc != MG_OK) return rc;
+    if (parent[0] != -1) return fail(MG_E_INVALID, "parent[0] must be -1");
+    std::vector<int32_t> depth(n, 0);
+    for (int32_t i = 1; i < n; ++i) {
+        if (parent[i] < 0 || parent[i] >= i) return fail(MG_E_INVALID, "parent[%d] = %d must be in [0, %d)", i, parent[i], i);
+        depth[i] = depth[parent[i]] + 1;
+        if (depth[i] > kMaxAnc) return fail(MG_E_INVALID, "node %d is deeper than %d", i, kMaxAnc);
+    }
+    // positions in voxel units: (p - origin) then / voxel size, in float
+    std::vector<float4> q4(n);
+    const int32_t dims[3] = {map->dev.nx, map->dev.ny, map->dev.nz};
+    for (int32_t i = 0; i < n; ++i) {
+        float qv[3];
+        for (int a = 0; a < 3; ++a) {
+            const float v = (pos_m[3 * i + a] - map->origin[a]) / map->voxel_m;
+            if (!(v >= 0.0f) || !(v < (float)dims[a]) || (int32_t)std::floor(v) >= dims[a])
+                return fail(MG_E_INVALID, "node %d lies outside the map", i);
+            qv[a] = v;
+        }
+        q4[i] = make_float4(qv[0], qv[1], qv[2], 0.f);
+    }
+    // levels (CSR by depth, ids ascending within a level), ancestors, children
+    int32_t maxd = 0;
+    for (int32_t i = 0; i < n; ++i) maxd = depth[i] > maxd ? depth[i] : maxd;
+    std::vector<int32_t> level_ptr(maxd + 2, 0), level_nodes(n);
+    for (int32_t i = 0; i < n; ++i) level_ptr[depth[i] + 1]++;
+    for (int32_t d = 0; d <= maxd; ++d) level_ptr[d + 1] += level_ptr[d];
+    {
+        std::vector<int32_t> fill(level_ptr.begin(), level_ptr.end() - 1);
+        for (int32_t i = 0; i < n; ++i) level_nodes[fill[depth[i]]++] = i;
+    }
+    std::vector<int32_t> anc_ptr(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) anc_ptr[i + 1] = anc_ptr[i] + depth[i];
+    std::vector<int32_t> anc_ids((size_t)anc_ptr[n] + 1);
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t k = anc_ptr[i];
+        for (int32_t a = parent[i]; a >= 0; a = parent[a]) anc_ids[k++] = a;
+    }
+    std::vector<int32_t> child_ptr(n + 1, 0), child_ids((size_t)n);
+    for (int32_t i = 1; i < n; ++i) child_ptr[parent[i] + 1]++;
+    for (int32_t i = 0; i < n; ++i) child_ptr[i + 1] += child_ptr[i];
+    {
+        std::vector<int32_t> fill(child_ptr.begin(), child_ptr.end() - 1);
+        for (int32_t i = 1; i < n; ++i) child_ids[fill[parent[i]]++] = i;
+    }
+
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::unique_ptr<mg_tree_s> t(new (std::nothrow) mg_tree_s());
+    if (!t) return fail(MG_E_NOMEM, "host allocation failed");
+    rc = acquire_sensor(sensor, s, &t->sensor);
+    if (rc != MG_OK) return rc;
+    const SensorRes* sr = t->sensor;
+    const size_t R = (size_t)sr->host.W * sr->host.H;
+    const int32_t B = sr->host.B;
+    // one device block: q4 | anc_ptr | anc_ids | level_nodes | child_ptr | child_ids | c0 | gain | yaw | bins | dpan
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t o_q4 = take(sizeof(float4) * n);
+    const size_t o_ap = take(sizeof(int32_t) * (n + 1));
+    const size_t o_ai = take(sizeof(int32_t) * anc_ids.size());
+    const size_t o_ln = take(sizeof(int32_t) * n);
+    const size_t o_cp = take(sizeof(int32_t) * (n + 1));
+    const size_t o_ci = take(sizeof(int32_t) * n);
+    const size_t o_c0 = take(sizeof(int32_t) * n);
+    const size_t o_g = take(sizeof(uint32_t) * n);
+    const size_t o_y = take(sizeof(int32_t) * n);
+    const size_t o_bins = take(sizeof(uint32_t) * 2 * B * (size_t)n);
+    const size_t o_dpan = take(sizeof(float) * R * (size_t)n);
+    const size_t total = off;
+    hipError_t e = hipMalloc(&t->block, total);
+    if (e != hipSuccess) {
+        release_sensor(t->sensor);
+        return fail(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "tree allocation (%zu bytes): %s", total,
+                    hipGetErrorString(e));
+    }
+    char* base = (char*)t->block;
+    auto up = [&](size_t o, const void* src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    std::vector<int32_t> zeros_c0(n, 0);
+    if (e == hipSuccess) e = up(o_q4, q4.data(), sizeof(float4) * n);
+    if (e == hipSuccess) e = up(o_ap, anc_ptr.data(), sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = up(o_ai, anc_ids.data(), sizeof(int32_t) * anc_ids.size());
+    if (e == hipSuccess) e = up(o_ln, level_nodes.data(), sizeof(int32_t) * n);
+    if (e == hipSuccess) e = up(o_cp, child_ptr.data(), sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = up(o_ci, child_ids.data(), sizeof(int32_t) * n);
+    if (e == hipSuccess) e = up(o_c0, zeros_c0.data(), sizeof(int32_t) * n);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(t->block);
+        release_sensor(t->sensor);
+        return fail(MG_E_DEVICE, "tree upload: %s", hipGetErrorString(e));
+    }
+    t->dev.q4 = (const float4*)(base + o_q4);
+    t->dev.anc_ptr = (const int32_t*)(base + o_ap);
+    t->dev.anc_ids = (const int32_t*)(base + o_ai);
+    t->dev.level_nodes = (const int32_t*)(base + o_ln);
+    t->dev.child_ptr = (const int32_t*)(base + o_cp);
+    t->dev.child_ids = (const int32_t*)(base + o_ci);
+    t->dev.c0 = (int32_t*)(base + o_c0);
+    t->dev.bins = (uint32_t*)(base + o_bins);
+    t->dev.dpan = (float*)(base + o_dpan);
+    t->dev.n = n;
+    t->scratch_gain = (uint32_t*)(base + o_g);
+    t->scratch_yaw = (int32_t*)(base + o_y);
+    const float rv = sensor->range_m / map->voxel_m;
+    t->sd = sensor_dev(sr, rv);
+    t->map = map;
+    t->params = *sensor;
+    t->n = n;
+    t->levels = maxd + 1;
+    t->level_ptr = level_ptr;
+    t->level_nodes_h = level_nodes;
+    t->parent_h.assign(parent, parent + n);
+    t->depth_h = depth;
+    t->bytes = total;
+    HIP_TRY(hipGetDevice(&t->device));
+    map->trees++;
+    *out = t.release();
+    return MG_OK;
+}
+
+extern "C" int mg_tree_destroy(mg_tree t) {
+    if (!t) return fail(MG_E_INVALID, "tree is NULL");
+    mgb::forget_tree(t);
+    (void)hipFree(t->block);
+    release_sensor(t->sensor);
+    t->map->trees--;
+    delete t;
+    return MG_OK;
+}
+
+extern "C" int32_t mg_tree_nodes(mg_tree t) { return t ? t->n : -1; }
+extern "C" int32_t mg_tree_buffer_pixels(mg_tree t) { return t ? t->sd.H * t->sd.WB : -1; }
+extern "C" int64_t mg_tree_footprint_bytes(mg_tree t) { return t ? (int64_t)t->bytes : -1; }
+
+// ---------------------------------------------------------------- evaluation
+
+namespace {
+
+int check_device(mg_tree t) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != t->device) return fail(MG_E_INVALID, "tree lives on device %d, current device is %d", t->device, dev);
+    return MG_OK;
+}
+
+// Depth-ordered evaluation: for each level, trace all its nodes' rays, then
+// select their windows; level d+1 reads the buffers and windows of levels <= d.
+int eval_levels(mg_tree t, hipStream_t s, uint32_t* gain, int32_t* yaw, float* depth, uint32_t* host_gain,
+                int32_t* host_yaw) {
+    HIP_TRY(launch_zero_u32(t->dev.bins, (size_t)2 * t->sd.B * t->n, s));
+    for (int32_t d = 0; d < t->levels; ++d) {
+        const int32_t b = t->level_ptr[d], cnt = t->level_ptr[d + 1] - b;
+        const int32_t* nodes = t->dev.level_nodes + b;
+        HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, nodes, cnt, true, s));
+        HIP_TRY(launch_finish(t->sd, t->dev, nodes, cnt, true, gain, yaw, s));
+        if (host_gain) {
+            // results of this level back to the host before the next level (Sec. IV-C)
+            HIP_TRY(hipMemcpyAsync(host_gain, gain, sizeof(uint32_t) * t->n, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(host_yaw, yaw, sizeof(int32_t) * t->n, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+    }
+    if (depth) HIP_TRY(launch_depth_out(t->sd, t->dev, depth, s));
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" int mg_eval_marginal(mg_tree t, void* hip_stream, uint32_t* gain, int32_t* yaw_bin, float* depth) {
+    if (!t || !gain || !yaw_bin) return fail(MG_E_INVALID, "tree/gain/yaw_bin is NULL");
+    int rc = check_device(t);
+    if (rc != MG_OK) return rc;
+    return eval_levels(t, (hipStream_t)hip_stream, gain, yaw_bin, depth, nullptr, nullptr);
+}
+
+extern "C" int mg_eval_marginal_levelsync(mg_tree t, void* hip_stream, uint32_t* gain, int32_t* yaw_bin,
+                                          float* depth, uint32_t* host_gain, int32_t* host_yaw_bin) {
+    if (!t || !host_gain || !host_yaw_bin) return fail(MG_E_INVALID, "tree/host outputs are NULL");
+    int rc = check_device(t);
+    if (rc != MG_OK) return rc;
+    if (!gain) gain = t->scratch_gain;
+    if (!yaw_bin) yaw_bin = t->scratch_yaw;
+    hipStream_t s = (hipStream_t)hip_stream;
+    rc = eval_levels(t, s, gain, yaw_bin, depth, host_gain, host_yaw_bin);
+    if (rc != MG_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+extern "C" int mg_eval_absolute(mg_tree t, void* hip_stream, uint32_t* gain, int32_t* yaw_bin) {
+    if (!t || !gain || !yaw_bin) return fail(MG_E_INVALID, "tree/gain/yaw_bin is NULL");
+    int rc = check_device(t);
+    if (rc != MG_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(launch_zero_u32(t->dev.bins, (size_t)2 * t->sd.B * t->n, s));
+    HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, t->dev.level_nodes, t->n, false, s));
+    HIP_TRY(launch_finish(t->sd, t->dev, t->dev.level_nodes, t->n, false, gain, yaw_bin, s));
+    return MG_OK;
+}
+
+// ---------------------------------------------------------------- batch (see mg_batch.hip)
+
+namespace mgb {
+int tree_view(mg_tree t, TreeView* v) {
+    v->map = &t->map->dev;
+    v->sd = &t->sd;
+    v->td = &t->dev;
+    v->params = t->params;
+    v->n = t->n;
+    v->levels = t->levels;
+    v->device = t->device;
+    return MG_OK;
+}
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace mgb

@@ -1,0 +1,67 @@
+// Internal device-side descriptors shared by the kernels and the host API.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mgk {
+
+constexpr int kThreads = 256;      // rays per workgroup (4 wave64)
+constexpr int kMaxAnc = 64;        // deepest supported ancestor chain
+constexpr int kMaxBins = 256;      // yaw bins
+constexpr int kMaxAz = 4096;       // panorama columns (LDS holds their boundaries)
+constexpr int kMaxEl = 2048;
+
+enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2 };
+
+// Occupancy grid in 8x8x8-voxel bricks (512 B each, x fastest inside a
+// brick, bricks x fastest): a ray stays inside one brick for several steps,
+// so its gathers hit few cache lines.
+struct MapDev {
+    const uint8_t* bricks;
+    int32_t nx, ny, nz;     // true extent in voxels
+    int32_t nbx, nby, nbz;  // bricks per axis
+};
+
+// Panorama ray tables and yaw-window geometry (built on the host, see mg_api).
+struct SensorDev {
+    const float4* d4;          // [R] unit direction (w unused)
+    const float4* iv4;         // [R] 1/d per component, 0 where d == 0
+    const int32_t* bin_of_col; // [W]
+    const float2* bv;          // [W] left boundary unit vector of each column
+    const float* ts;           // [H+1] tan(e)|tan(e)| at the row boundaries
+    const int32_t* c0_of_win;  // [B] first column of window k
+    int32_t W, H, B, w, WB, R, T;   // R = W*H rays, T = workgroups per node
+    float rv;                  // range in voxel units
+    float rv2;                 // rv*rv (no depth can exceed it)
+    float inv_daz;             // columns per radian (estimates only)
+    float el0;                 // lowest elevation, radians (estimates only)
+    float inv_del;             // rows per radian (estimates only)
+};
+
+// One tree's device state. Depth buffers are kept as full panoramas: the
+// first-hit parameter of every ray of node n lives at dpan[n*R + r] and the
+// node's buffer is the window slice starting at column c0[n].
+struct TreeDev {
+    const float4* q4;          // [n] position in voxel units
+    const int32_t* anc_ptr;    // [n+1] CSR into anc_ids
+    const int32_t* anc_ids;    // ancestors, nearest first
+    const int32_t* level_nodes;// [n] nodes sorted by depth
+    const int32_t* child_ptr;  // [n+1]
+    const int32_t* child_ids;
+    uint32_t* bins;            // [n][2][B]: absolute, then marginal
+    float* dpan;               // [n][R]
+    int32_t* c0;               // [n]
+    int32_t n;
+};
+
+// Launchers (mg_kernels.hip).
+hipError_t launch_brick(const uint8_t* dense, uint8_t* bricks, const MapDev& m, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
+hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
+                        int32_t n_nodes, bool marginal, hipStream_t s);
+hipError_t launch_finish(const SensorDev& sd, const TreeDev& td, const int32_t* nodes, int32_t n_nodes,
+                         bool marginal, uint32_t* gain, int32_t* yaw, hipStream_t s);
+hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth, hipStream_t s);
+
+}  // namespace mgk

@@ -1,0 +1,359 @@
+// gfx950 kernels of the marginal-gain path.
+//
+// Exactness: every decision (which voxels a ray visits, whether an ancestor
+// sees a voxel, which window wins) is taken in IEEE binary32 with the
+// operation order of the definitions below and without contraction into
+// fused multiply-adds. Approximate arithmetic (rcp, sqrt, a polynomial atan)
+// appears only in *estimates* of a pixel index that are then corrected by the
+// exact boundary tests, so it never changes a result.
+#pragma clang fp contract(off)
+
+#include "mg_internal.h"
+
+namespace mgk {
+
+// ---------------------------------------------------------------- map layout
+
+__device__ __forceinline__ uint32_t brick_offset(int32_t x, int32_t y, int32_t z, int32_t nbx, int32_t nby) {
+    uint32_t b = (uint32_t)(x >> 3) + (uint32_t)nbx * ((uint32_t)(y >> 3) + (uint32_t)nby * (uint32_t)(z >> 3));
+    return (b << 9) | ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
+}
+
+// Dense [nz][ny][nx] -> bricks; padding voxels (beyond the true extent) are
+// never read by a traversal and are set to "occupied".
+__global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__ bricks, MapDev m) {
+    const uint32_t total = (uint32_t)m.nbx * m.nby * m.nbz * 512u;
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < total; o += gridDim.x * blockDim.x) {
+        uint32_t b = o >> 9, in = o & 511u;
+        int32_t bx = (int32_t)(b % (uint32_t)m.nbx);
+        int32_t by = (int32_t)((b / (uint32_t)m.nbx) % (uint32_t)m.nby);
+        int32_t bz = (int32_t)(b / ((uint32_t)m.nbx * (uint32_t)m.nby));
+        int32_t x = bx * 8 + (int32_t)(in & 7u), y = by * 8 + (int32_t)((in >> 3) & 7u),
+                z = bz * 8 + (int32_t)(in >> 6);
+        uint8_t v = kOccupied;
+        if (x < m.nx && y < m.ny && z < m.nz)
+            v = dense[(size_t)x + (size_t)m.nx * ((size_t)y + (size_t)m.ny * (size_t)z)];
+        bricks[o] = v;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- estimates
+
+// atan on [-1, 1]: the 9th-degree odd polynomial of Abramowitz & Stegun
+// 4.4.47 (|error| <= 1e-5 rad). Used only to guess a pixel index.
+__device__ __forceinline__ float atan_unit(float x) {
+    float x2 = x * x;
+    float p = fmaf(x2, 0.0208351f, -0.0851330f);
+    p = fmaf(x2, p, 0.1801410f);
+    p = fmaf(x2, p, -0.3302995f);
+    p = fmaf(x2, p, 0.9998660f);
+    return p * x;
+}
+
+// Approximate atan2(y, x) for y >= 0, in [0, pi].
+__device__ __forceinline__ float atan2_upper(float y, float x) {
+    float ax = fabsf(x);
+    float a;
+    if (y <= ax) a = atan_unit(y * __builtin_amdgcn_rcpf(ax));
+    else a = 1.57079633f - atan_unit(ax * __builtin_amdgcn_rcpf(y));
+    return x < 0.f ? 3.14159265f - a : a;
+}
+
+// Approximate atan(y / x) for x > 0, in (-pi/2, pi/2).
+__device__ __forceinline__ float atan_ratio(float y, float x) {
+    float ay = fabsf(y);
+    float a;
+    if (ay <= x) a = atan_unit(ay * __builtin_amdgcn_rcpf(x));
+    else a = 1.57079633f - atan_unit(x * __builtin_amdgcn_rcpf(ay));
+    return y < 0.f ? -a : a;
+}
+
+// ---------------------------------------------------------------- ancestor test
+
+struct AncLDS {
+    float qx, qy, qz;
+    int32_t c0;
+    float b0x, b0y;       // left boundary of the window
+    float b1x, b1y;       // right boundary (left boundary of column c0 + w_buf)
+    const float* dpan;    // the ancestor's panorama of first hits
+};
+
+// Does ancestor A see the voxel (ix,iy,iz)? The voxel centre must fall in a
+// pixel cell of A's window (azimuth between two column boundaries, elevation
+// between two row boundaries; cells half-open) and its squared range from A
+// must be <= the squared depth stored for that pixel. Row and column are the
+// numbers of inner boundaries the centre lies at-or-beyond; they are guessed
+// from approximate angles and then settled by the exact boundary tests, which
+// are monotone along the boundaries, so the result is the exact count.
+__device__ __forceinline__ bool ancestor_sees(const AncLDS& A, int32_t ix, int32_t iy, int32_t iz,
+                                              const SensorDev& S, const float2* __restrict__ s_bv,
+                                              const float* __restrict__ s_ts) {
+    const float rx = ((float)ix + 0.5f) - A.qx;
+    const float ry = ((float)iy + 0.5f) - A.qy;
+    const float rz = ((float)iz + 0.5f) - A.qz;
+    const float rho2 = rx * rx + ry * ry;
+    const float range2 = rho2 + rz * rz;
+    if (!(range2 <= S.rv2)) return false;            // beyond every stored depth
+    const float sz = rz * fabsf(rz);
+    if (!(sz >= rho2 * s_ts[0])) return false;        // below the band
+    if (!(sz < rho2 * s_ts[S.H])) return false;       // above the band
+    const float w0 = A.b0x * ry - A.b0y * rx;
+    if (!(w0 >= 0.f)) return false;                   // right of the window
+    if (!(A.b1x * ry - A.b1y * rx < 0.f)) return false;  // left of the window
+
+    // column: guess from the angle past the window's left boundary, then settle
+    const float u0 = A.b0x * rx + A.b0y * ry;
+    int32_t col = (int32_t)fminf(fmaxf(atan2_upper(w0, u0) * S.inv_daz, 0.f), (float)(S.WB - 1));
+    for (;;) {
+        if (col + 1 >= S.WB) break;
+        int32_t c = A.c0 + col + 1;
+        c = c >= S.W ? c - S.W : c;
+        const float2 b = s_bv[c];
+        if (!(b.x * ry - b.y * rx >= 0.f)) break;
+        ++col;
+    }
+    for (;;) {
+        if (col == 0) break;
+        int32_t c = A.c0 + col;
+        c = c >= S.W ? c - S.W : c;
+        const float2 b = s_bv[c];
+        if (b.x * ry - b.y * rx >= 0.f) break;
+        --col;
+    }
+    // row: guess from the elevation angle, then settle
+    const float rho = __builtin_amdgcn_sqrtf(rho2);
+    int32_t row = (int32_t)fminf(fmaxf((atan_ratio(rz, rho) - S.el0) * S.inv_del, 0.f), (float)(S.H - 1));
+    for (;;) {
+        if (row + 1 >= S.H) break;
+        if (!(sz >= rho2 * s_ts[row + 1])) break;
+        ++row;
+    }
+    for (;;) {
+        if (row == 0) break;
+        if (sz >= rho2 * s_ts[row]) break;
+        --row;
+    }
+    int32_t c = A.c0 + col;
+    c = c >= S.W ? c - S.W : c;
+    const float D = A.dpan[c * S.H + row];
+    return range2 <= D * D;
+}
+
+// ---------------------------------------------------------------- ray traversal
+
+// One workgroup = kThreads consecutive rays of one node. Each lane walks its
+// ray with the Amanatides-Woo 3D DDA (face-crossing parameters recomputed as
+// (boundary - q) * (1/d); ties step x, then y, then z; a voxel is visited while
+// its entry parameter is below the range and it is inside the grid). Unknown
+// voxels count into the ray column's absolute bin and, unless an ancestor
+// sees them (nearest ancestor first), into its marginal bin. An occupied voxel
+// ends the ray; its entry parameter (or the range) is the ray's first hit.
+template <bool kMarginal>
+__global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
+                                                    const int32_t* __restrict__ nodes) {
+    extern __shared__ char smem[];
+    float2* s_bv = reinterpret_cast<float2*>(smem);
+    float* s_ts = reinterpret_cast<float*>(s_bv + S.W);
+    uint32_t* s_bins = reinterpret_cast<uint32_t*>(s_ts + S.H + 1);   // [2B]
+    AncLDS* s_anc = reinterpret_cast<AncLDS*>(
+        smem + ((reinterpret_cast<char*>(s_bins + 2 * S.B) - smem + 15) & ~static_cast<ptrdiff_t>(15)));
+
+    const int32_t tid = threadIdx.x;
+    const int32_t node = nodes[blockIdx.x / S.T];
+    const int32_t tile = blockIdx.x % S.T;
+    int32_t na = 0;
+    if (kMarginal) {
+        const int32_t a0 = Tr.anc_ptr[node];
+        na = Tr.anc_ptr[node + 1] - a0;
+        for (int32_t k = tid; k < na; k += kThreads) {
+            const int32_t a = Tr.anc_ids[a0 + k];
+            const float4 qa = Tr.q4[a];
+            const int32_t c0 = Tr.c0[a];
+            int32_t c1 = c0 + S.WB;
+            c1 = c1 >= S.W ? c1 - S.W : c1;
+            const float2 b0 = S.bv[c0], b1 = S.bv[c1];
+            AncLDS A;
+            A.qx = qa.x; A.qy = qa.y; A.qz = qa.z; A.c0 = c0;
+            A.b0x = b0.x; A.b0y = b0.y; A.b1x = b1.x; A.b1y = b1.y;
+            A.dpan = Tr.dpan + (size_t)a * S.R;
+            s_anc[k] = A;
+        }
+    }
+    for (int32_t i = tid; i < S.W; i += kThreads) s_bv[i] = S.bv[i];
+    for (int32_t i = tid; i <= S.H; i += kThreads) s_ts[i] = S.ts[i];
+    for (int32_t i = tid; i < 2 * S.B; i += kThreads) s_bins[i] = 0u;
+    __syncthreads();
+
+    const int32_t r = tile * kThreads + tid;
+    if (r < S.R) {
+        const int32_t col = r / S.H;
+        const int32_t bin = S.bin_of_col[col];
+        const float4 q = Tr.q4[node];
+        const float4 d = S.d4[r];
+        const float4 iv = S.iv4[r];
+        int32_t ix = (int32_t)floorf(q.x), iy = (int32_t)floorf(q.y), iz = (int32_t)floorf(q.z);
+        const int32_t sx = d.x > 0.f ? 1 : (d.x < 0.f ? -1 : 0);
+        const int32_t sy = d.y > 0.f ? 1 : (d.y < 0.f ? -1 : 0);
+        const int32_t sz = d.z > 0.f ? 1 : (d.z < 0.f ? -1 : 0);
+        int32_t bx = d.x > 0.f ? ix + 1 : ix;
+        int32_t by = d.y > 0.f ? iy + 1 : iy;
+        int32_t bz = d.z > 0.f ? iz + 1 : iz;
+        float tx = sx ? ((float)bx - q.x) * iv.x : __builtin_inff();
+        float ty = sy ? ((float)by - q.y) * iv.y : __builtin_inff();
+        float tz = sz ? ((float)bz - q.z) * iv.z : __builtin_inff();
+        float t = 0.f, h = S.rv;
+        uint32_t n_abs = 0, n_marg = 0;
+        for (;;) {
+            if ((uint32_t)ix >= (uint32_t)M.nx || (uint32_t)iy >= (uint32_t)M.ny || (uint32_t)iz >= (uint32_t)M.nz)
+                break;
+            if (!(t < S.rv)) break;
+            const uint8_t st = M.bricks[brick_offset(ix, iy, iz, M.nbx, M.nby)];
+            if (st == kOccupied) { h = t; break; }
+            if (st == kUnknown) {
+                ++n_abs;
+                if (kMarginal) {
+                    bool seen = false;
+                    for (int32_t k = 0; k < na && !seen; ++k) seen = ancestor_sees(s_anc[k], ix, iy, iz, S, s_bv, s_ts);
+                    n_marg += seen ? 0u : 1u;
+                }
+            }
+            if (tx <= ty && tx <= tz) {
+                t = tx; ix += sx; bx += sx; tx = ((float)bx - q.x) * iv.x;
+            } else if (ty <= tz) {
+                t = ty; iy += sy; by += sy; ty = ((float)by - q.y) * iv.y;
+            } else {
+                t = tz; iz += sz; bz += sz; tz = ((float)bz - q.z) * iv.z;
+            }
+        }
+        if (kMarginal) Tr.dpan[(size_t)node * S.R + r] = h;
+        if (n_abs) atomicAdd(&s_bins[bin], n_abs);
+        if (kMarginal && n_marg) atomicAdd(&s_bins[S.B + bin], n_marg);
+    }
+    __syncthreads();
+    uint32_t* gb = Tr.bins + (size_t)node * 2 * S.B;
+    for (int32_t i = tid; i < 2 * S.B; i += kThreads) {
+        const uint32_t v = s_bins[i];
+        if (v) atomicAdd(&gb[i], v);
+    }
+}
+
+// ---------------------------------------------------------------- window selection
+
+// One workgroup per node: window sums from a prefix sum over the bins taken
+// circularly (P[i+1] = P[i] + bins[i mod B], S(k) = P[k+w] - P[k]), then the
+// largest sum with the smallest k. Writes gain and window; in marginal mode
+// also the node's window start column for its descendants.
+__global__ __launch_bounds__(kThreads) void k_finish(SensorDev S, TreeDev Tr, const int32_t* __restrict__ nodes,
+                                                     int marginal, uint32_t* __restrict__ gain,
+                                                     int32_t* __restrict__ yaw) {
+    __shared__ uint32_t s_p[2 * kMaxBins + 1];
+    __shared__ unsigned long long s_best[kThreads / 64];
+    const int32_t tid = threadIdx.x;
+    const int32_t node = nodes[blockIdx.x];
+    const uint32_t* bins = Tr.bins + (size_t)node * 2 * S.B + (marginal ? S.B : 0);
+    const int32_t L = S.B + S.w;   // extended length <= 2*kMaxBins
+    for (int32_t i = tid; i < L; i += kThreads) s_p[i + 1] = bins[i % S.B];
+    if (tid == 0) s_p[0] = 0u;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of s_p[1..L]
+    for (int32_t off = 1; off < L; off <<= 1) {
+        uint32_t v0 = 0, v1 = 0;
+        const int32_t i0 = tid + 1, i1 = tid + 1 + kThreads;
+        if (i0 <= L && i0 - off >= 1) v0 = s_p[i0 - off];
+        if (i1 <= L && i1 - off >= 1) v1 = s_p[i1 - off];
+        __syncthreads();
+        if (i0 <= L) s_p[i0] += v0;
+        if (i1 <= L) s_p[i1] += v1;
+        __syncthreads();
+    }
+    unsigned long long key = 0ull;
+    for (int32_t k = tid; k < S.B; k += kThreads) {
+        const uint32_t sum = s_p[k + S.w] - s_p[k];
+        const unsigned long long kk = ((unsigned long long)sum << 32) | (uint32_t)(S.B - 1 - k);
+        key = kk > key ? kk : key;
+    }
+    for (int32_t off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        key = o > key ? o : key;
+    }
+    if ((tid & 63) == 0) s_best[tid >> 6] = key;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long best = s_best[0];
+        for (int32_t i = 1; i < kThreads / 64; ++i) best = s_best[i] > best ? s_best[i] : best;
+        const int32_t k = S.B - 1 - (int32_t)(uint32_t)(best & 0xffffffffull);
+        gain[node] = (uint32_t)(best >> 32);
+        yaw[node] = k;
+        if (marginal) Tr.c0[node] = S.c0_of_win[k];
+    }
+}
+
+// depth[n][j][i] = first hit of ray ((c0[n] + i) mod W, j)
+__global__ void k_depth_out(SensorDev S, TreeDev Tr, float* __restrict__ depth) {
+    const size_t per = (size_t)S.H * S.WB;
+    const size_t total = per * (size_t)Tr.n;
+    for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < total; o += (size_t)gridDim.x * blockDim.x) {
+        const int32_t node = (int32_t)(o / per);
+        const int32_t rem = (int32_t)(o - (size_t)node * per);
+        const int32_t j = rem / S.WB, i = rem - j * S.WB;
+        int32_t c = Tr.c0[node] + i;
+        c = c >= S.W ? c - S.W : c;
+        depth[o] = Tr.dpan[(size_t)node * S.R + (size_t)c * S.H + j];
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int grid_for(size_t n, int threads) {
+    size_t g = (n + threads - 1) / threads;
+    return (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
+}
+
+hipError_t launch_brick(const uint8_t* dense, uint8_t* bricks, const MapDev& m, hipStream_t s) {
+    size_t total = (size_t)m.nbx * m.nby * m.nbz * 512u;
+    hipLaunchKernelGGL(k_brick, dim3(grid_for(total, 256)), dim3(256), 0, s, dense, bricks, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+static size_t trace_lds_bytes(const SensorDev& sd) {
+    return sizeof(float2) * sd.W + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B +
+           sizeof(AncLDS) * kMaxAnc + 16;
+}
+
+hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
+                        int32_t n_nodes, bool marginal, hipStream_t s) {
+    if (n_nodes <= 0) return hipSuccess;
+    dim3 grid((unsigned)n_nodes * (unsigned)sd.T);
+    size_t lds = trace_lds_bytes(sd);
+    if (marginal)
+        hipLaunchKernelGGL(k_trace<true>, grid, dim3(kThreads), lds, s, m, sd, td, nodes);
+    else
+        hipLaunchKernelGGL(k_trace<false>, grid, dim3(kThreads), lds, s, m, sd, td, nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const SensorDev& sd, const TreeDev& td, const int32_t* nodes, int32_t n_nodes,
+                         bool marginal, uint32_t* gain, int32_t* yaw, hipStream_t s) {
+    if (n_nodes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finish, dim3(n_nodes), dim3(kThreads), 0, s, sd, td, nodes, marginal ? 1 : 0, gain, yaw);
+    return hipGetLastError();
+}
+
+hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth, hipStream_t s) {
+    size_t total = (size_t)sd.H * sd.WB * td.n;
+    hipLaunchKernelGGL(k_depth_out, dim3(grid_for(total, 256)), dim3(256), 0, s, sd, td, depth);
+    return hipGetLastError();
+}
+
+}  // namespace mgk

@@ -1,0 +1,250 @@
+"""Python binding of the C ABI in ``include/mg.h`` (argument marshalling only).
+
+Every step of the gain evaluation runs in the HIP library ``libmg.so``; this
+module converts numpy arrays and torch tensors to pointers and raises on error
+codes. Importing it loads the library and fails loudly when it is missing:
+there is no fallback implementation.
+
+Device outputs are torch tensors on the current device; the HIP stream passed
+to the library is ``torch.cuda.current_stream()`` unless one is given.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmg.so")
+
+MG_OK, MG_E_INVALID, MG_E_NOMEM, MG_E_DEVICE, MG_E_BUSY, MG_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+_NAMES = {-1: "MG_E_INVALID", -2: "MG_E_NOMEM", -3: "MG_E_DEVICE", -4: "MG_E_BUSY", -5: "MG_E_UNSUPPORTED"}
+
+# Every entry point declared in include/mg.h.
+EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_tree_nodes",
+           "mg_tree_buffer_pixels", "mg_tree_footprint_bytes", "mg_eval_marginal", "mg_eval_marginal_levelsync",
+           "mg_eval_marginal_batch", "mg_eval_absolute", "mg_sensor_tables", "mg_last_error")
+
+
+class MGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class mg_sensor(C.Structure):
+    _fields_ = [("n_az", C.c_int32), ("n_el", C.c_int32), ("fov_h_deg", C.c_float), ("fov_v_deg", C.c_float),
+                ("range_m", C.c_float), ("yaw_bins", C.c_int32), ("az_offset_deg", C.c_float)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        L.mg_map_create.argtypes = [P, I32, I32, I32, C.c_float, P, P, C.POINTER(P)]
+        L.mg_map_destroy.argtypes = [P]
+        L.mg_tree_upload.argtypes = [P, P, P, I32, C.POINTER(mg_sensor), P, C.POINTER(P)]
+        L.mg_tree_destroy.argtypes = [P]
+        L.mg_tree_nodes.argtypes = [P]
+        L.mg_tree_nodes.restype = I32
+        L.mg_tree_buffer_pixels.argtypes = [P]
+        L.mg_tree_buffer_pixels.restype = I32
+        L.mg_tree_footprint_bytes.argtypes = [P]
+        L.mg_tree_footprint_bytes.restype = I64
+        L.mg_eval_marginal.argtypes = [P, P, P, P, P]
+        L.mg_eval_marginal_levelsync.argtypes = [P, P, P, P, P, P, P]
+        L.mg_eval_marginal_batch.argtypes = [P, I32, P, P, P, P]
+        L.mg_eval_absolute.argtypes = [P, P, P, P]
+        L.mg_sensor_tables.argtypes = [C.POINTER(mg_sensor), P, P, P, P, P, P]
+        L.mg_last_error.argtypes = []
+        L.mg_last_error.restype = C.c_char_p
+        for name in ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_eval_marginal",
+                     "mg_eval_marginal_levelsync", "mg_eval_marginal_batch", "mg_eval_absolute",
+                     "mg_sensor_tables"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != MG_OK:
+        raise MGError(rc, lib().mg_last_error().decode())
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_sensor(s) -> mg_sensor:
+    return mg_sensor(int(s.n_az), int(s.n_el), float(s.fov_h_deg), float(s.fov_v_deg), float(s.range_m),
+                     int(s.yaw_bins), float(getattr(s, "az_offset_deg", 0.0)))
+
+
+# ----------------------------------------------------------------- raw entry points (same names)
+
+def mg_map_create(states: np.ndarray, voxel_m: float, origin_m, stream=None) -> int:
+    st = np.ascontiguousarray(states, dtype=np.uint8)
+    nz, ny, nx = st.shape
+    org = np.ascontiguousarray(origin_m, dtype=np.float32)
+    out = C.c_void_p()
+    _check(lib().mg_map_create(_np_ptr(st), nx, ny, nz, float(voxel_m), _np_ptr(org), _stream(stream),
+                               C.byref(out)))
+    return out.value
+
+
+def mg_map_destroy(handle: int):
+    _check(lib().mg_map_destroy(C.c_void_p(handle)))
+
+
+def mg_tree_upload(map_handle: int, pos_m: np.ndarray, parent: np.ndarray, sensor, stream=None) -> int:
+    pos = np.ascontiguousarray(pos_m, dtype=np.float32)
+    par = np.ascontiguousarray(parent, dtype=np.int32)
+    sp = make_sensor(sensor)
+    out = C.c_void_p()
+    _check(lib().mg_tree_upload(C.c_void_p(map_handle), _np_ptr(pos), _np_ptr(par), int(par.shape[0]),
+                                C.byref(sp), _stream(stream), C.byref(out)))
+    return out.value
+
+
+def mg_tree_destroy(handle: int):
+    _check(lib().mg_tree_destroy(C.c_void_p(handle)))
+
+
+def mg_tree_footprint_bytes(handle: int) -> int:
+    return int(lib().mg_tree_footprint_bytes(C.c_void_p(handle)))
+
+
+def mg_eval_marginal(tree: int, gain, yaw_bin, depth=None, stream=None):
+    _check(lib().mg_eval_marginal(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin),
+                                  _dev_ptr(depth)))
+
+
+def mg_eval_marginal_levelsync(tree: int, host_gain: np.ndarray, host_yaw: np.ndarray, gain=None, yaw_bin=None,
+                               depth=None, stream=None):
+    assert host_gain.dtype == np.uint32 and host_yaw.dtype == np.int32
+    assert host_gain.flags.c_contiguous and host_yaw.flags.c_contiguous
+    _check(lib().mg_eval_marginal_levelsync(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin),
+                                            _dev_ptr(depth), _np_ptr(host_gain), _np_ptr(host_yaw)))
+
+
+def mg_eval_marginal_batch(trees: Sequence[int], gain, yaw_bin, depth=None, stream=None):
+    arr = (C.c_void_p * len(trees))(*trees)
+    _check(lib().mg_eval_marginal_batch(C.cast(arr, C.c_void_p), len(trees), _stream(stream), _dev_ptr(gain),
+                                        _dev_ptr(yaw_bin), _dev_ptr(depth)))
+
+
+def mg_eval_absolute(tree: int, gain, yaw_bin, stream=None):
+    _check(lib().mg_eval_absolute(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin)))
+
+
+def mg_sensor_tables(sensor):
+    sp = make_sensor(sensor)
+    W, H, B = sp.n_az, sp.n_el, sp.yaw_bins
+    out = dict(dir=np.zeros((W * H, 3), np.float32), inv=np.zeros((W * H, 3), np.float32),
+               bv=np.zeros((W, 2), np.float32), ts=np.zeros(H + 1, np.float32), bins=np.zeros(W, np.int32),
+               c0=np.zeros(B, np.int32))
+    _check(lib().mg_sensor_tables(C.byref(sp), _np_ptr(out["dir"]), _np_ptr(out["inv"]), _np_ptr(out["bv"]),
+                                  _np_ptr(out["ts"]), _np_ptr(out["bins"]), _np_ptr(out["c0"])))
+    return out
+
+
+# ----------------------------------------------------------------- owning wrappers
+
+class Map:
+    """Device-resident occupancy grid (wraps mg_map_create / mg_map_destroy)."""
+
+    def __init__(self, states: np.ndarray, voxel_m: float, origin_m=(0.0, 0.0, 0.0), stream=None):
+        self.handle = mg_map_create(states, voxel_m, origin_m, stream)
+        self.shape = tuple(np.asarray(states).shape)
+
+    def close(self):
+        if self.handle:
+            mg_map_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    """Device-resident candidate tree (wraps mg_tree_upload / mg_tree_destroy)."""
+
+    def __init__(self, m: Map, pos_m: np.ndarray, parent: np.ndarray, sensor, stream=None):
+        self.map = m
+        self.sensor = sensor
+        self.handle = mg_tree_upload(m.handle, pos_m, parent, sensor, stream)
+        self.n = int(np.asarray(parent).shape[0])
+        self.pixels = int(lib().mg_tree_buffer_pixels(C.c_void_p(self.handle)))
+
+    @property
+    def footprint_bytes(self) -> int:
+        return mg_tree_footprint_bytes(self.handle)
+
+    def outputs(self, depth=False, device=None):
+        import torch
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        g = torch.empty(self.n, dtype=torch.int32, device=dev)      # uint32 bits
+        y = torch.empty(self.n, dtype=torch.int32, device=dev)
+        d = torch.empty((self.n, self.pixels), dtype=torch.float32, device=dev) if depth else None
+        return g, y, d
+
+    def eval_marginal(self, depth=False, stream=None):
+        g, y, d = self.outputs(depth)
+        mg_eval_marginal(self.handle, g, y, d, stream)
+        return g, y, d
+
+    def eval_absolute(self, stream=None):
+        g, y, _ = self.outputs(False)
+        mg_eval_absolute(self.handle, g, y, stream)
+        return g, y
+
+    def close(self):
+        if self.handle:
+            mg_tree_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_batch(trees: Sequence[Tree], depth=False, stream=None):
+    import torch
+    n = sum(t.n for t in trees)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    g = torch.empty(n, dtype=torch.int32, device=dev)
+    y = torch.empty(n, dtype=torch.int32, device=dev)
+    d = torch.empty((n, trees[0].pixels), dtype=torch.float32, device=dev) if depth else None
+    mg_eval_marginal_batch([t.handle for t in trees], g, y, d, stream)
+    return g, y, d
+
+
+def as_u32(t) -> np.ndarray:
+    """Host copy of an int32 tensor holding uint32 gains."""
+    return t.cpu().numpy().view(np.uint32)

@@ -1,0 +1,43 @@
+"""Writes work_counts.json: per-workload work of the method, counted by the oracle.
+
+visits V (voxels visited by the DDA), unk_visits U (unknown ones), anc_tests T
+(ancestor tests, parent first, stopping at the first that observes), rays R.
+These are the numerators of the roofline figures (algorithmic bytes per ray:
+V/R grid gathers of 1 byte, T/R depth reads of 4 bytes, one 4-byte first-hit
+write). Calls only the oracle and the workload generator.
+
+Usage: python tests/golden/make_work_counts.py [workload ...]
+"""
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import mgref  # noqa: E402
+from paper_2609_40297_amd import workloads as W  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "work_counts.json")
+
+
+def count(name, n_trees=None):
+    w = W.make(name, n_trees=n_trees)
+    tot = dict(visits=0, unk_visits=0, anc_tests=0, rays=0, nodes=0)
+    for t in w.trees:
+        o = mgref.eval_tree(w.map, t, w.sensor, n_threads=os.cpu_count() or 1)
+        for k in ("visits", "unk_visits", "anc_tests"):
+            tot[k] += int(o["counters"][k])
+        tot["rays"] += t.n * w.sensor.rays
+        tot["nodes"] += t.n
+    return tot
+
+
+if __name__ == "__main__":
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for arg in sys.argv[1:] or ["tiny", "step"]:
+        name, _, nt = arg.partition(":")
+        data[arg] = count(name, int(nt) if nt else None)
+        print(arg, data[arg], flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
