@@ -404,6 +404,10 @@ extern "C" int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* par
     const SensorRes* sr = t->sensor;
     const size_t R = (size_t)sr->host.W * sr->host.H;
     const int32_t B = sr->host.B;
+    if (R * (size_t)n >= (1ull << 32)) {
+        release_sensor(t->sensor);
+        return fail(MG_E_UNSUPPORTED, "nodes x rays = %zu exceeds 2^32 per tree", R * (size_t)n);
+    }
     // one device block: q4 | anc_ptr | anc_ids | level_nodes | child_ptr | child_ids | c0 | gain | yaw | bins | dpan
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };

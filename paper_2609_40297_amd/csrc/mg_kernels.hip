@@ -14,11 +14,6 @@ namespace mgk {
 
 // ---------------------------------------------------------------- map layout
 
-__device__ __forceinline__ uint32_t brick_offset(int32_t x, int32_t y, int32_t z, int32_t nbx, int32_t nby) {
-    uint32_t b = (uint32_t)(x >> 3) + (uint32_t)nbx * ((uint32_t)(y >> 3) + (uint32_t)nby * (uint32_t)(z >> 3));
-    return (b << 9) | ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
-}
-
 // Dense [nz][ny][nx] -> bricks; padding voxels (beyond the true extent) are
 // never read by a traversal and are set to "occupied".
 __global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__ bricks, MapDev m) {
@@ -80,22 +75,23 @@ struct AncLDS {
     int32_t c0;
     float b0x, b0y;       // left boundary of the window
     float b1x, b1y;       // right boundary (left boundary of column c0 + w_buf)
-    const float* dpan;    // the ancestor's panorama of first hits
+    uint32_t dpan_off;    // element offset of the ancestor's panorama of first hits
+    uint32_t pad[3];
 };
 
-// Does ancestor A see the voxel (ix,iy,iz)? The voxel centre must fall in a
+// Does ancestor A see the voxel centre (cx, cy, cz)? The centre must fall in a
 // pixel cell of A's window (azimuth between two column boundaries, elevation
 // between two row boundaries; cells half-open) and its squared range from A
 // must be <= the squared depth stored for that pixel. Row and column are the
 // numbers of inner boundaries the centre lies at-or-beyond; they are guessed
 // from approximate angles and then settled by the exact boundary tests, which
 // are monotone along the boundaries, so the result is the exact count.
-__device__ __forceinline__ bool ancestor_sees(const AncLDS& A, int32_t ix, int32_t iy, int32_t iz,
-                                              const SensorDev& S, const float2* __restrict__ s_bv,
-                                              const float* __restrict__ s_ts) {
-    const float rx = ((float)ix + 0.5f) - A.qx;
-    const float ry = ((float)iy + 0.5f) - A.qy;
-    const float rz = ((float)iz + 0.5f) - A.qz;
+__device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float cy, float cz, const SensorDev& S,
+                                              const float2* __restrict__ s_bv, const float* __restrict__ s_ts,
+                                              const float* __restrict__ dpan) {
+    const float rx = cx - A.qx;
+    const float ry = cy - A.qy;
+    const float rz = cz - A.qz;
     const float rho2 = rx * rx + ry * ry;
     const float range2 = rho2 + rz * rz;
     if (!(range2 <= S.rv2)) return false;            // beyond every stored depth
@@ -140,19 +136,84 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, int32_t ix, int32
     }
     int32_t c = A.c0 + col;
     c = c >= S.W ? c - S.W : c;
-    const float D = A.dpan[c * S.H + row];
+    const float D = dpan[A.dpan_off + (uint32_t)(c * S.H + row)];
     return range2 <= D * D;
 }
 
 // ---------------------------------------------------------------- ray traversal
 
-// One workgroup = kThreads consecutive rays of one node. Each lane walks its
-// ray with the Amanatides-Woo 3D DDA (face-crossing parameters recomputed as
-// (boundary - q) * (1/d); ties step x, then y, then z; a voxel is visited while
-// its entry parameter is below the range and it is inside the grid). Unknown
-// voxels count into the ray column's absolute bin and, unless an ancestor
-// sees them (nearest ancestor first), into its marginal bin. An occupied voxel
-// ends the ray; its entry parameter (or the range) is the ray's first hit.
+constexpr int kQCap = 512;   // queued unknown voxels per wave
+
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t brick_addr(int32_t x, int32_t y, int32_t z, const MapDev& M) {
+    const uint32_t bi = (uint32_t)(x >> 3) +
+                        __umul24((uint32_t)M.nbx, (uint32_t)(y >> 3) + __umul24((uint32_t)M.nby, (uint32_t)(z >> 3)));
+    return (bi << 9) | ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
+}
+
+// Counts the queued voxels per bin (a queue entry carries its ray's bin).
+__device__ __forceinline__ void count_by_bin(const uint2* __restrict__ q, int32_t n, uint32_t* __restrict__ bins,
+                                             int32_t lane) {
+    for (int32_t base = 0; base < n; base += 64) {
+        const int32_t i = base + lane;
+        bool pending = i < n;
+        const uint32_t bin = pending ? (q[i].y >> 16) : 0u;
+        uint64_t left = __ballot(pending);
+        while (left) {
+            const int32_t leader = __builtin_ctzll(left);
+            const uint32_t b = __shfl(bin, leader, 64);
+            const uint64_t same = __ballot(pending && bin == b);
+            if (lane == leader) atomicAdd(&bins[b], (uint32_t)__popcll(same));
+            pending = pending && bin != b;
+            left &= ~same;
+        }
+    }
+}
+
+// Tests the n queued voxels against the ancestors, nearest first. Each pass
+// tests every voxel still unobserved against one ancestor and compacts the
+// survivors in place (a lane writes its survivor only after the whole chunk
+// has been read, and survivors never overtake the read position). What is left
+// after the last ancestor is new to the path and counts into the marginal bins.
+__device__ __forceinline__ void drain_queue(uint2* __restrict__ q, int32_t n, const AncLDS* __restrict__ s_anc,
+                                            int32_t na, const SensorDev& S, const float2* __restrict__ s_bv,
+                                            const float* __restrict__ s_ts, const float* __restrict__ dpan,
+                                            uint32_t* __restrict__ marg_bins, int32_t lane) {
+    for (int32_t k = 0; k < na && n > 0; ++k) {
+        const AncLDS A = s_anc[k];
+        int32_t m = 0;
+        for (int32_t base = 0; base < n; base += 64) {
+            const int32_t i = base + lane;
+            const bool act = i < n;
+            const uint2 e = act ? q[i] : make_uint2(0u, 0u);
+            bool keep = false;
+            if (act) {
+                const float cx = (float)(int32_t)(e.x & 0xffffu) + 0.5f;
+                const float cy = (float)(int32_t)(e.x >> 16) + 0.5f;
+                const float cz = (float)(int32_t)(e.y & 0xffffu) + 0.5f;
+                keep = !ancestor_sees(A, cx, cy, cz, S, s_bv, s_ts, dpan);
+            }
+            const uint64_t bal = __ballot(keep);
+            if (keep) q[m + (int32_t)lane_prefix(bal)] = e;
+            m += __popcll(bal);
+        }
+        n = m;
+    }
+    count_by_bin(q, n, marg_bins, lane);
+}
+
+// One workgroup = kThreads consecutive rays of one node; each wave owns a
+// queue in LDS. A lane walks its ray with the Amanatides-Woo 3D DDA
+// (face-crossing parameters recomputed as (boundary - q) * (1/d); ties step x,
+// then y, then z; a voxel is visited while its entry parameter is below the
+// range and it is inside the grid). The grid byte of the next voxel is loaded
+// one step ahead. An occupied voxel ends the ray and its entry parameter (or
+// the range) is the ray's first hit; unknown voxels count into the absolute
+// bin of the ray's column and, in marginal mode, are queued; whenever the
+// queue could overflow it is drained against the ancestors.
 template <bool kMarginal>
 __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
                                                     const int32_t* __restrict__ nodes) {
@@ -160,10 +221,12 @@ __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeD
     float2* s_bv = reinterpret_cast<float2*>(smem);
     float* s_ts = reinterpret_cast<float*>(s_bv + S.W);
     uint32_t* s_bins = reinterpret_cast<uint32_t*>(s_ts + S.H + 1);   // [2B]
-    AncLDS* s_anc = reinterpret_cast<AncLDS*>(
-        smem + ((reinterpret_cast<char*>(s_bins + 2 * S.B) - smem + 15) & ~static_cast<ptrdiff_t>(15)));
+    char* tail = smem + ((reinterpret_cast<char*>(s_bins + 2 * S.B) - smem + 15) & ~static_cast<ptrdiff_t>(15));
+    AncLDS* s_anc = reinterpret_cast<AncLDS*>(tail);
+    uint2* s_queue = reinterpret_cast<uint2*>(tail + sizeof(AncLDS) * kMaxAnc);
 
     const int32_t tid = threadIdx.x;
+    const int32_t lane = tid & 63;
     const int32_t node = nodes[blockIdx.x / S.T];
     const int32_t tile = blockIdx.x % S.T;
     int32_t na = 0;
@@ -180,7 +243,8 @@ __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeD
             AncLDS A;
             A.qx = qa.x; A.qy = qa.y; A.qz = qa.z; A.c0 = c0;
             A.b0x = b0.x; A.b0y = b0.y; A.b1x = b1.x; A.b1y = b1.y;
-            A.dpan = Tr.dpan + (size_t)a * S.R;
+            A.dpan_off = (uint32_t)a * (uint32_t)S.R;
+            A.pad[0] = A.pad[1] = A.pad[2] = 0u;
             s_anc[k] = A;
         }
     }
@@ -189,51 +253,71 @@ __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeD
     for (int32_t i = tid; i < 2 * S.B; i += kThreads) s_bins[i] = 0u;
     __syncthreads();
 
+    uint2* q = s_queue + (tid >> 6) * kQCap;
     const int32_t r = tile * kThreads + tid;
-    if (r < S.R) {
-        const int32_t col = r / S.H;
-        const int32_t bin = S.bin_of_col[col];
-        const float4 q = Tr.q4[node];
-        const float4 d = S.d4[r];
-        const float4 iv = S.iv4[r];
-        int32_t ix = (int32_t)floorf(q.x), iy = (int32_t)floorf(q.y), iz = (int32_t)floorf(q.z);
-        const int32_t sx = d.x > 0.f ? 1 : (d.x < 0.f ? -1 : 0);
-        const int32_t sy = d.y > 0.f ? 1 : (d.y < 0.f ? -1 : 0);
-        const int32_t sz = d.z > 0.f ? 1 : (d.z < 0.f ? -1 : 0);
-        int32_t bx = d.x > 0.f ? ix + 1 : ix;
-        int32_t by = d.y > 0.f ? iy + 1 : iy;
-        int32_t bz = d.z > 0.f ? iz + 1 : iz;
-        float tx = sx ? ((float)bx - q.x) * iv.x : __builtin_inff();
-        float ty = sy ? ((float)by - q.y) * iv.y : __builtin_inff();
-        float tz = sz ? ((float)bz - q.z) * iv.z : __builtin_inff();
-        float t = 0.f, h = S.rv;
-        uint32_t n_abs = 0, n_marg = 0;
-        for (;;) {
-            if ((uint32_t)ix >= (uint32_t)M.nx || (uint32_t)iy >= (uint32_t)M.ny || (uint32_t)iz >= (uint32_t)M.nz)
-                break;
-            if (!(t < S.rv)) break;
-            const uint8_t st = M.bricks[brick_offset(ix, iy, iz, M.nbx, M.nby)];
-            if (st == kOccupied) { h = t; break; }
-            if (st == kUnknown) {
-                ++n_abs;
-                if (kMarginal) {
-                    bool seen = false;
-                    for (int32_t k = 0; k < na && !seen; ++k) seen = ancestor_sees(s_anc[k], ix, iy, iz, S, s_bv, s_ts);
-                    n_marg += seen ? 0u : 1u;
+    const bool has_ray = r < S.R;
+    const int32_t rr = has_ray ? r : 0;
+    const int32_t bin = S.bin_of_col[rr / S.H];
+    const float4 p = Tr.q4[node];
+    const float4 d = S.d4[rr];
+    const float4 iv = S.iv4[rr];
+    int32_t ix = (int32_t)floorf(p.x), iy = (int32_t)floorf(p.y), iz = (int32_t)floorf(p.z);
+    const int32_t sx = d.x > 0.f ? 1 : (d.x < 0.f ? -1 : 0);
+    const int32_t sy = d.y > 0.f ? 1 : (d.y < 0.f ? -1 : 0);
+    const int32_t sz = d.z > 0.f ? 1 : (d.z < 0.f ? -1 : 0);
+    int32_t bx = d.x > 0.f ? ix + 1 : ix;
+    int32_t by = d.y > 0.f ? iy + 1 : iy;
+    int32_t bz = d.z > 0.f ? iz + 1 : iz;
+    float tx = sx ? ((float)bx - p.x) * iv.x : __builtin_inff();
+    float ty = sy ? ((float)by - p.y) * iv.y : __builtin_inff();
+    float tz = sz ? ((float)bz - p.z) * iv.z : __builtin_inff();
+    float t = 0.f, h = S.rv;
+    uint32_t n_abs = 0;
+    // the node lies inside the grid and t = 0 < rv, so its own voxel is visited
+    bool alive = has_ray;
+    uint32_t st = alive ? (uint32_t)M.bricks[brick_addr(ix, iy, iz, M)] : 0u;
+    int32_t qn = 0;
+    while (__ballot(alive)) {
+        while (__ballot(alive) && (!kMarginal || qn + 64 <= kQCap)) {
+            const int32_t cx = ix, cy = iy, cz = iz;
+            const float tc = t;
+            // step to the next voxel and start loading it before using this one
+            bool next_ok = false;
+            uint32_t st_next = 0u;
+            if (alive) {
+                if (tx <= ty && tx <= tz) {
+                    t = tx; ix += sx; bx += sx; tx = ((float)bx - p.x) * iv.x;
+                    next_ok = (uint32_t)ix < (uint32_t)M.nx;
+                } else if (ty <= tz) {
+                    t = ty; iy += sy; by += sy; ty = ((float)by - p.y) * iv.y;
+                    next_ok = (uint32_t)iy < (uint32_t)M.ny;
+                } else {
+                    t = tz; iz += sz; bz += sz; tz = ((float)bz - p.z) * iv.z;
+                    next_ok = (uint32_t)iz < (uint32_t)M.nz;
                 }
+                next_ok = next_ok && (t < S.rv);
+                if (next_ok) st_next = (uint32_t)M.bricks[brick_addr(ix, iy, iz, M)];
             }
-            if (tx <= ty && tx <= tz) {
-                t = tx; ix += sx; bx += sx; tx = ((float)bx - q.x) * iv.x;
-            } else if (ty <= tz) {
-                t = ty; iy += sy; by += sy; ty = ((float)by - q.y) * iv.y;
-            } else {
-                t = tz; iz += sz; bz += sz; tz = ((float)bz - q.z) * iv.z;
+            const bool unk = alive && st == kUnknown;
+            if (alive && st == kOccupied) { h = tc; next_ok = false; }
+            n_abs += unk ? 1u : 0u;
+            if (kMarginal) {
+                const uint64_t bal = __ballot(unk);
+                if (unk)
+                    q[qn + (int32_t)lane_prefix(bal)] =
+                        make_uint2((uint32_t)cx | ((uint32_t)cy << 16), (uint32_t)cz | ((uint32_t)bin << 16));
+                qn += __popcll(bal);
             }
+            alive = alive && next_ok;
+            st = st_next;
         }
-        if (kMarginal) Tr.dpan[(size_t)node * S.R + r] = h;
-        if (n_abs) atomicAdd(&s_bins[bin], n_abs);
-        if (kMarginal && n_marg) atomicAdd(&s_bins[S.B + bin], n_marg);
+        if (kMarginal) {
+            drain_queue(q, qn, s_anc, na, S, s_bv, s_ts, Tr.dpan, s_bins + S.B, lane);
+            qn = 0;
+        }
     }
+    if (kMarginal && has_ray) Tr.dpan[(size_t)node * S.R + r] = h;
+    if (n_abs) atomicAdd(&s_bins[bin], n_abs);
     __syncthreads();
     uint32_t* gb = Tr.bins + (size_t)node * 2 * S.B;
     for (int32_t i = tid; i < 2 * S.B; i += kThreads) {
@@ -327,8 +411,8 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
 }
 
 static size_t trace_lds_bytes(const SensorDev& sd) {
-    return sizeof(float2) * sd.W + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B +
-           sizeof(AncLDS) * kMaxAnc + 16;
+    return sizeof(float2) * sd.W + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B + 16 +
+           sizeof(AncLDS) * kMaxAnc + sizeof(uint2) * kQCap * (kThreads / 64);
 }
 
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
