@@ -118,11 +118,14 @@ int mg_eval_marginal_levelsync(mg_tree tree, void* hip_stream, uint32_t* gain, i
                                float* depth, uint32_t* host_gain, int32_t* host_yaw_bin);
 
 /* Many trees at once (on one or several maps, same sensor geometry: equal
- * n_az, n_el, yaw_bins and fov): one persistent launch in which each node
- * starts as soon as its parent has finished. Outputs are concatenated in tree
- * order (tree t's nodes start at the sum of the node counts of trees < t).
- * Results equal per-tree mg_eval_marginal calls. The launch is recorded once
- * per distinct tree list and replayed as a HIP graph. */
+ * n_az, n_el, yaw_bins, fov and azimuth offset): all trees advance one depth
+ * level at a time (Sec. IV-C), each level being one trace launch over every
+ * node of that depth in every tree plus one window-selection launch, so small
+ * levels of one tree share the GPU with those of the others. Outputs are
+ * concatenated in tree order (tree t's nodes start at the sum of the node
+ * counts of trees < t). Results equal per-tree mg_eval_marginal calls. The
+ * launch plan (tree descriptors, per-level work lists) is built on the first
+ * call with a given tree list and reused. */
 int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
                            int32_t* yaw_bin, float* depth);
 

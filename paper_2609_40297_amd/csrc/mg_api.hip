@@ -563,6 +563,8 @@ int tree_view(mg_tree t, TreeView* v) {
     v->map = &t->map->dev;
     v->sd = &t->sd;
     v->td = &t->dev;
+    v->level_ptr = &t->level_ptr;
+    v->level_nodes = &t->level_nodes_h;
     v->params = t->params;
     v->n = t->n;
     v->levels = t->levels;

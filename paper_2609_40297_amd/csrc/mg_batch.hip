@@ -1,27 +1,168 @@
-// Multi-tree evaluation.
+// Multi-tree evaluation: all trees advance one depth level at a time; each
+// level is one trace launch over every (tree, node) of that depth followed by
+// one window-selection launch. Launch plans are cached per tree list.
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "mg_batch.h"
 
+using namespace mgk;
+
+namespace {
+
+struct Plan {
+    std::vector<mg_tree> trees;
+    void* block = nullptr;                 // BatchTree[n_trees] | items[total]
+    const BatchTree* dtrees = nullptr;
+    const unsigned long long* ditems = nullptr;
+    std::vector<int32_t> level_ptr;        // items of global level d: [level_ptr[d], level_ptr[d+1])
+    SensorDev sd{};
+    uint32_t total = 0, max_nodes = 0;
+    int device = 0;
+    ~Plan() {
+        if (block) (void)hipFree(block);
+    }
+};
+
+std::mutex g_mu;
+std::map<std::vector<mg_tree>, std::unique_ptr<Plan>> g_plans;
+constexpr size_t kMaxPlans = 64;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int hip_fail(hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return mgb::set_error(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, m.c_str());
+}
+
+bool same_geometry(const mg_sensor& a, const mg_sensor& b) {
+    return a.n_az == b.n_az && a.n_el == b.n_el && a.yaw_bins == b.yaw_bins && a.fov_h_deg == b.fov_h_deg &&
+           a.fov_v_deg == b.fov_v_deg && a.az_offset_deg == b.az_offset_deg;
+}
+
+int build_plan(const std::vector<mg_tree>& trees, hipStream_t stream, std::unique_ptr<Plan>* out) {
+    std::unique_ptr<Plan> P(new Plan());
+    P->trees = trees;
+    const int32_t nt = (int32_t)trees.size();
+    std::vector<BatchTree> bt(nt);
+    mgb::TreeView v0;
+    mgb::tree_view(trees[0], &v0);
+    int32_t levels = 0;
+    std::vector<mgb::TreeView> views(nt);
+    for (int32_t i = 0; i < nt; ++i) {
+        mgb::TreeView& v = views[i];
+        mgb::tree_view(trees[i], &v);
+        if (!same_geometry(v.params, v0.params))
+            return mgb::set_error(MG_E_INVALID, "trees in a batch must share the sensor geometry");
+        if (v.device != v0.device) return mgb::set_error(MG_E_INVALID, "trees in a batch must share a device");
+        bt[i].map = *v.map;
+        bt[i].td = *v.td;
+        bt[i].rv = v.sd->rv;
+        bt[i].rv2 = v.sd->rv2;
+        bt[i].node_base = P->total;
+        bt[i].pad = 0;
+        if ((uint64_t)P->total + (uint64_t)v.n >= (1ull << 31))
+            return mgb::set_error(MG_E_UNSUPPORTED, "batch has 2^31 nodes or more");
+        P->total += (uint32_t)v.n;
+        P->max_nodes = std::max(P->max_nodes, (uint32_t)v.n);
+        levels = std::max(levels, v.levels);
+    }
+    P->sd = *v0.sd;
+    P->device = v0.device;
+    // items grouped by global depth level, trees in order within a level
+    P->level_ptr.assign(levels + 1, 0);
+    std::vector<unsigned long long> items;
+    items.reserve(P->total);
+    for (int32_t d = 0; d < levels; ++d) {
+        for (int32_t i = 0; i < nt; ++i) {
+            const std::vector<int32_t>& lp = *views[i].level_ptr;
+            const std::vector<int32_t>& ln = *views[i].level_nodes;
+            if (d + 1 >= (int32_t)lp.size()) continue;
+            for (int32_t k = lp[d]; k < lp[d + 1]; ++k)
+                items.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)ln[k]);
+        }
+        P->level_ptr[d + 1] = (int32_t)items.size();
+        if ((uint64_t)(P->level_ptr[d + 1] - P->level_ptr[d]) * (uint64_t)P->sd.T >= (1ull << 31))
+            return mgb::set_error(MG_E_UNSUPPORTED, "a depth level of the batch has 2^31 workgroups or more");
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t o_trees = take(sizeof(BatchTree) * nt);
+    const size_t o_items = take(sizeof(unsigned long long) * items.size());
+    hipError_t e = hipMalloc(&P->block, off);
+    if (e != hipSuccess) return hip_fail(e, "batch plan allocation");
+    char* base = (char*)P->block;
+    e = hipMemcpyAsync(base + o_trees, bt.data(), sizeof(BatchTree) * nt, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + o_items, items.data(), sizeof(unsigned long long) * items.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "batch plan upload");
+    P->dtrees = (const BatchTree*)(base + o_trees);
+    P->ditems = (const unsigned long long*)(base + o_items);
+    *out = std::move(P);
+    return MG_OK;
+}
+
+int run_plan(const Plan& P, hipStream_t s, uint32_t* gain, int32_t* yaw, float* depth) {
+    hipError_t e = launch_batch_zero(P.dtrees, (int32_t)P.trees.size(), P.max_nodes, P.sd, s);
+    if (e != hipSuccess) return hip_fail(e, "batch zero");
+    for (size_t d = 0; d + 1 < P.level_ptr.size(); ++d) {
+        const int32_t b = P.level_ptr[d], n = P.level_ptr[d + 1] - b;
+        e = launch_batch_level(P.dtrees, P.ditems + b, n, P.sd, gain, yaw, depth, s);
+        if (e != hipSuccess) return hip_fail(e, "batch level");
+    }
+    return MG_OK;
+}
+
+}  // namespace
+
 namespace mgb {
-void forget_tree(mg_tree) {}
+void forget_tree(mg_tree t) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    bool any = false;
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::find(it->first.begin(), it->first.end(), t) != it->first.end()) {
+            if (!any) (void)hipDeviceSynchronize();      // launches of the plan may still be queued
+            any = true;
+            it = g_plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
 }  // namespace mgb
 
 extern "C" int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
                                       int32_t* yaw_bin, float* depth) {
     if (!trees || n_trees < 1 || !gain || !yaw_bin) return mgb::set_error(MG_E_INVALID, "bad batch arguments");
-    size_t off = 0, doff = 0;
-    for (int32_t i = 0; i < n_trees; ++i) {
-        mgb::TreeView v;
+    for (int32_t i = 0; i < n_trees; ++i)
         if (!trees[i]) return mgb::set_error(MG_E_INVALID, "NULL tree in batch");
-        mgb::tree_view(trees[i], &v);
-        int rc = mg_eval_marginal(trees[i], hip_stream, gain + off, yaw_bin + off, depth ? depth + doff : nullptr);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::vector<mg_tree> key(trees, trees + n_trees);
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) {
+        if (g_plans.size() >= kMaxPlans) {
+            (void)hipDeviceSynchronize();
+            g_plans.clear();
+        }
+        std::unique_ptr<Plan> P;
+        int rc = build_plan(key, s, &P);
         if (rc != MG_OK) return rc;
-        off += v.n;
-        doff += (size_t)v.n * v.sd->H * v.sd->WB;
+        it = g_plans.emplace(key, std::move(P)).first;
     }
-    return MG_OK;
+    const Plan& P = *it->second;
+    if (P.device != dev) return mgb::set_error(MG_E_INVALID, "batch trees live on another device");
+    return run_plan(P, s, gain, yaw_bin, depth);
 }

@@ -55,6 +55,17 @@ struct TreeDev {
     int32_t n;
 };
 
+// One tree of a multi-tree batch: its map and node data, its range in voxel
+// units (maps may differ in voxel size) and the index of its node 0 in the
+// batch outputs.
+struct BatchTree {
+    MapDev map;
+    TreeDev td;
+    float rv, rv2;
+    uint32_t node_base;
+    uint32_t pad;
+};
+
 // Launchers (mg_kernels.hip).
 hipError_t launch_brick(const uint8_t* dense, uint8_t* bricks, const MapDev& m, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
@@ -63,5 +74,10 @@ hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td,
 hipError_t launch_finish(const SensorDev& sd, const TreeDev& td, const int32_t* nodes, int32_t n_nodes,
                          bool marginal, uint32_t* gain, int32_t* yaw, hipStream_t s);
 hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth, hipStream_t s);
+size_t trace_lds_bytes(const SensorDev& sd);
+hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const SensorDev& sd,
+                             hipStream_t s);
+hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
+                              const SensorDev& sd, uint32_t* gain, int32_t* yaw, float* depth, hipStream_t s);
 
 }  // namespace mgk

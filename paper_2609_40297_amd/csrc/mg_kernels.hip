@@ -205,30 +205,48 @@ __device__ __forceinline__ void drain_queue(uint2* __restrict__ q, int32_t n, co
     count_by_bin(q, n, marg_bins, lane);
 }
 
-// One workgroup = kThreads consecutive rays of one node; each wave owns a
-// queue in LDS. A lane walks its ray with the Amanatides-Woo 3D DDA
-// (face-crossing parameters recomputed as (boundary - q) * (1/d); ties step x,
-// then y, then z; a voxel is visited while its entry parameter is below the
-// range and it is inside the grid). The grid byte of the next voxel is loaded
-// one step ahead. An occupied voxel ends the ray and its entry parameter (or
-// the range) is the ray's first hit; unknown voxels count into the absolute
-// bin of the ray's column and, in marginal mode, are queued; whenever the
-// queue could overflow it is drained against the ancestors.
-template <bool kMarginal>
-__global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
-                                                    const int32_t* __restrict__ nodes) {
-    extern __shared__ char smem[];
-    float2* s_bv = reinterpret_cast<float2*>(smem);
-    float* s_ts = reinterpret_cast<float*>(s_bv + S.W);
-    uint32_t* s_bins = reinterpret_cast<uint32_t*>(s_ts + S.H + 1);   // [2B]
-    char* tail = smem + ((reinterpret_cast<char*>(s_bins + 2 * S.B) - smem + 15) & ~static_cast<ptrdiff_t>(15));
-    AncLDS* s_anc = reinterpret_cast<AncLDS*>(tail);
-    uint2* s_queue = reinterpret_cast<uint2*>(tail + sizeof(AncLDS) * kMaxAnc);
+// LDS carve-up shared by the trace kernels: boundary table | row table | bins
+// [2B] | ancestors | per-wave queues.
+struct TraceLDS {
+    float2* bv;
+    float* ts;
+    uint32_t* bins;
+    AncLDS* anc;
+    uint2* queue;
+};
 
+__device__ __forceinline__ TraceLDS carve_lds(char* smem, const SensorDev& S) {
+    TraceLDS L;
+    L.bv = reinterpret_cast<float2*>(smem);
+    L.ts = reinterpret_cast<float*>(L.bv + S.W);
+    L.bins = reinterpret_cast<uint32_t*>(L.ts + S.H + 1);
+    char* tail = smem + ((reinterpret_cast<char*>(L.bins + 2 * S.B) - smem + 15) & ~static_cast<ptrdiff_t>(15));
+    L.anc = reinterpret_cast<AncLDS*>(tail);
+    L.queue = reinterpret_cast<uint2*>(tail + sizeof(AncLDS) * kMaxAnc);
+    return L;
+}
+
+__device__ __forceinline__ void load_tables(const TraceLDS& L, const SensorDev& S) {
+    for (int32_t i = threadIdx.x; i < S.W; i += kThreads) L.bv[i] = S.bv[i];
+    for (int32_t i = threadIdx.x; i <= S.H; i += kThreads) L.ts[i] = S.ts[i];
+}
+
+// One workgroup = kThreads consecutive rays (tile `tile`) of one node; each
+// wave owns a queue in LDS. A lane walks its ray with the Amanatides-Woo 3D
+// DDA (face-crossing parameters recomputed as (boundary - q) * (1/d); ties
+// step x, then y, then z; a voxel is visited while its entry parameter is
+// below the range and it is inside the grid). The grid byte of the next voxel
+// is loaded one step ahead. An occupied voxel ends the ray and its entry
+// parameter (or the range) is the ray's first hit; unknown voxels count into
+// the absolute bin of the ray's column and, in marginal mode, are queued;
+// whenever the queue could overflow it is drained against the ancestors.
+// Requires the tables in LDS; ends with the tile's bins added to the node's
+// global bins.
+template <bool kMarginal>
+__device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
+                                           int32_t tile, const TraceLDS& L) {
     const int32_t tid = threadIdx.x;
     const int32_t lane = tid & 63;
-    const int32_t node = nodes[blockIdx.x / S.T];
-    const int32_t tile = blockIdx.x % S.T;
     int32_t na = 0;
     if (kMarginal) {
         const int32_t a0 = Tr.anc_ptr[node];
@@ -239,21 +257,19 @@ __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeD
             const int32_t c0 = Tr.c0[a];
             int32_t c1 = c0 + S.WB;
             c1 = c1 >= S.W ? c1 - S.W : c1;
-            const float2 b0 = S.bv[c0], b1 = S.bv[c1];
+            const float2 b0 = L.bv[c0], b1 = L.bv[c1];
             AncLDS A;
             A.qx = qa.x; A.qy = qa.y; A.qz = qa.z; A.c0 = c0;
             A.b0x = b0.x; A.b0y = b0.y; A.b1x = b1.x; A.b1y = b1.y;
             A.dpan_off = (uint32_t)a * (uint32_t)S.R;
             A.pad[0] = A.pad[1] = A.pad[2] = 0u;
-            s_anc[k] = A;
+            L.anc[k] = A;
         }
     }
-    for (int32_t i = tid; i < S.W; i += kThreads) s_bv[i] = S.bv[i];
-    for (int32_t i = tid; i <= S.H; i += kThreads) s_ts[i] = S.ts[i];
-    for (int32_t i = tid; i < 2 * S.B; i += kThreads) s_bins[i] = 0u;
+    for (int32_t i = tid; i < 2 * S.B; i += kThreads) L.bins[i] = 0u;
     __syncthreads();
 
-    uint2* q = s_queue + (tid >> 6) * kQCap;
+    uint2* q = L.queue + (tid >> 6) * kQCap;
     const int32_t r = tile * kThreads + tid;
     const bool has_ray = r < S.R;
     const int32_t rr = has_ray ? r : 0;
@@ -312,36 +328,42 @@ __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeD
             st = st_next;
         }
         if (kMarginal) {
-            drain_queue(q, qn, s_anc, na, S, s_bv, s_ts, Tr.dpan, s_bins + S.B, lane);
+            drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, Tr.dpan, L.bins + S.B, lane);
             qn = 0;
         }
     }
     if (kMarginal && has_ray) Tr.dpan[(size_t)node * S.R + r] = h;
-    if (n_abs) atomicAdd(&s_bins[bin], n_abs);
+    if (n_abs) atomicAdd(&L.bins[bin], n_abs);
     __syncthreads();
     uint32_t* gb = Tr.bins + (size_t)node * 2 * S.B;
     for (int32_t i = tid; i < 2 * S.B; i += kThreads) {
-        const uint32_t v = s_bins[i];
+        const uint32_t v = L.bins[i];
         if (v) atomicAdd(&gb[i], v);
     }
 }
 
+template <bool kMarginal>
+__global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
+                                                    const int32_t* __restrict__ nodes) {
+    extern __shared__ char smem[];
+    const TraceLDS L = carve_lds(smem, S);
+    load_tables(L, S);
+    trace_tile<kMarginal>(M, S, Tr, nodes[blockIdx.x / S.T], blockIdx.x % S.T, L);
+}
+
 // ---------------------------------------------------------------- window selection
 
-// One workgroup per node: window sums from a prefix sum over the bins taken
-// circularly (P[i+1] = P[i] + bins[i mod B], S(k) = P[k+w] - P[k]), then the
-// largest sum with the smallest k. Writes gain and window; in marginal mode
-// also the node's window start column for its descendants.
-__global__ __launch_bounds__(kThreads) void k_finish(SensorDev S, TreeDev Tr, const int32_t* __restrict__ nodes,
-                                                     int marginal, uint32_t* __restrict__ gain,
-                                                     int32_t* __restrict__ yaw) {
-    __shared__ uint32_t s_p[2 * kMaxBins + 1];
-    __shared__ unsigned long long s_best[kThreads / 64];
+// Window sums from a prefix sum over the bins taken circularly
+// (P[i+1] = P[i] + bins[i mod B], S(k) = P[k+w] - P[k]), then the largest sum
+// with the smallest k. Whole workgroup; returns (sum << 32) | (B - 1 - k) to
+// every thread. Bins are read with atomic loads (they were accumulated with
+// device-scope atomics, possibly by other workgroups).
+__device__ __forceinline__ unsigned long long select_window(const uint32_t* bins, const SensorDev& S,
+                                                            uint32_t* s_p, unsigned long long* s_best) {
     const int32_t tid = threadIdx.x;
-    const int32_t node = nodes[blockIdx.x];
-    const uint32_t* bins = Tr.bins + (size_t)node * 2 * S.B + (marginal ? S.B : 0);
     const int32_t L = S.B + S.w;   // extended length <= 2*kMaxBins
-    for (int32_t i = tid; i < L; i += kThreads) s_p[i + 1] = bins[i % S.B];
+    for (int32_t i = tid; i < L; i += kThreads)
+        s_p[i + 1] = __hip_atomic_load(&bins[i % S.B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tid == 0) s_p[0] = 0u;
     __syncthreads();
     // inclusive Hillis-Steele scan of s_p[1..L]
@@ -367,13 +389,85 @@ __global__ __launch_bounds__(kThreads) void k_finish(SensorDev S, TreeDev Tr, co
     }
     if ((tid & 63) == 0) s_best[tid >> 6] = key;
     __syncthreads();
-    if (tid == 0) {
-        unsigned long long best = s_best[0];
-        for (int32_t i = 1; i < kThreads / 64; ++i) best = s_best[i] > best ? s_best[i] : best;
+    unsigned long long best = s_best[0];
+    for (int32_t i = 1; i < kThreads / 64; ++i) best = s_best[i] > best ? s_best[i] : best;
+    __syncthreads();
+    return best;
+}
+
+// One workgroup per node of a level: gain and window; in marginal mode also
+// the node's window start column for its descendants.
+__global__ __launch_bounds__(kThreads) void k_finish(SensorDev S, TreeDev Tr, const int32_t* __restrict__ nodes,
+                                                     int marginal, uint32_t* __restrict__ gain,
+                                                     int32_t* __restrict__ yaw) {
+    __shared__ uint32_t s_p[2 * kMaxBins + 1];
+    __shared__ unsigned long long s_best[kThreads / 64];
+    const int32_t node = nodes[blockIdx.x];
+    const unsigned long long best =
+        select_window(Tr.bins + (size_t)node * 2 * S.B + (marginal ? S.B : 0), S, s_p, s_best);
+    if (threadIdx.x == 0) {
         const int32_t k = S.B - 1 - (int32_t)(uint32_t)(best & 0xffffffffull);
         gain[node] = (uint32_t)(best >> 32);
         yaw[node] = k;
         if (marginal) Tr.c0[node] = S.c0_of_win[k];
+    }
+}
+
+// ---------------------------------------------------------------- multi-tree, level by level
+
+// Clears the bins of every tree in a batch. Grid: (blocks, n_trees).
+__global__ void k_batch_zero(const BatchTree* __restrict__ trees, int32_t B2) {
+    const BatchTree& T = trees[blockIdx.y];
+    const size_t nb = (size_t)T.td.n * (size_t)B2;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nb; i += (size_t)gridDim.x * blockDim.x)
+        T.td.bins[i] = 0u;
+}
+
+// One depth level of all trees at once: work item = (tree, node) from
+// `items` (tree << 32 | node), T workgroups per item.
+__global__ __launch_bounds__(kThreads) void k_trace_multi(const BatchTree* __restrict__ trees,
+                                                          const unsigned long long* __restrict__ items, SensorDev S) {
+    extern __shared__ char smem[];
+    const TraceLDS L = carve_lds(smem, S);
+    load_tables(L, S);
+    const unsigned long long it = items[blockIdx.x / S.T];
+    const BatchTree& BT = trees[(uint32_t)(it >> 32)];
+    SensorDev St = S;
+    St.rv = BT.rv;
+    St.rv2 = BT.rv2;
+    trace_tile<true>(BT.map, St, BT.td, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
+}
+
+// Window selection for one depth level of all trees; writes the outputs at
+// the batch numbering (node_base + node) and the node's depth buffer.
+__global__ __launch_bounds__(kThreads) void k_finish_multi(const BatchTree* __restrict__ trees,
+                                                           const unsigned long long* __restrict__ items, SensorDev S,
+                                                           uint32_t* __restrict__ gain, int32_t* __restrict__ yaw,
+                                                           float* __restrict__ depth) {
+    __shared__ uint32_t s_p[2 * kMaxBins + 1];
+    __shared__ unsigned long long s_best[kThreads / 64];
+    const unsigned long long it = items[blockIdx.x];
+    const BatchTree& BT = trees[(uint32_t)(it >> 32)];
+    const int32_t node = (int32_t)(uint32_t)it;
+    const unsigned long long best = select_window(BT.td.bins + (size_t)node * 2 * S.B + S.B, S, s_p, s_best);
+    const int32_t k = S.B - 1 - (int32_t)(uint32_t)(best & 0xffffffffull);
+    const int32_t c0 = S.c0_of_win[k];
+    const uint32_t g = BT.node_base + (uint32_t)node;
+    if (threadIdx.x == 0) {
+        gain[g] = (uint32_t)(best >> 32);
+        yaw[g] = k;
+        BT.td.c0[node] = c0;
+    }
+    if (depth) {
+        const int32_t per = S.H * S.WB;
+        const float* src = BT.td.dpan + (size_t)node * S.R;
+        float* dst = depth + (size_t)g * per;
+        for (int32_t o = threadIdx.x; o < per; o += kThreads) {
+            const int32_t j = o / S.WB, ii = o - j * S.WB;
+            int32_t c = c0 + ii;
+            c = c >= S.W ? c - S.W : c;
+            dst[o] = src[c * S.H + j];
+        }
     }
 }
 
@@ -410,7 +504,7 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-static size_t trace_lds_bytes(const SensorDev& sd) {
+size_t trace_lds_bytes(const SensorDev& sd) {
     return sizeof(float2) * sd.W + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B + 16 +
            sizeof(AncLDS) * kMaxAnc + sizeof(uint2) * kQCap * (kThreads / 64);
 }
@@ -437,6 +531,29 @@ hipError_t launch_finish(const SensorDev& sd, const TreeDev& td, const int32_t* 
 hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth, hipStream_t s) {
     size_t total = (size_t)sd.H * sd.WB * td.n;
     hipLaunchKernelGGL(k_depth_out, dim3(grid_for(total, 256)), dim3(256), 0, s, sd, td, depth);
+    return hipGetLastError();
+}
+
+}  // namespace mgk
+
+namespace mgk {
+
+hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const SensorDev& sd,
+                             hipStream_t s) {
+    const uint32_t blocks = (uint32_t)grid_for((size_t)max_nodes * 2 * sd.B, 256);
+    hipLaunchKernelGGL(k_batch_zero, dim3(blocks, (unsigned)n_trees), dim3(256), 0, s, trees, 2 * sd.B);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
+                              const SensorDev& sd, uint32_t* gain, int32_t* yaw, float* depth, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_trace_multi, dim3((unsigned)n_items * (unsigned)sd.T), dim3(kThreads), trace_lds_bytes(sd), s,
+                       trees, items, sd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finish_multi, dim3((unsigned)n_items), dim3(kThreads), 0, s, trees, items, sd, gain, yaw,
+                       depth);
     return hipGetLastError();
 }
 
