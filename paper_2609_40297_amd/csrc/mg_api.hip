@@ -65,6 +65,9 @@ struct HostTables {
     int32_t W = 0, H = 0, B = 0, w = 0, WB = 0;
     std::vector<float> dir, inv, bv, ts;   // dir/inv [R*3], bv [W*2], ts [H+1]
     std::vector<int32_t> bins, c0;
+    // pixel-guess tables (see SensorDev)
+    std::vector<uint16_t> lut_col, lut_row;
+    float lut_col_scale = 0.f, lut_row_lo = 0.f, lut_row_scale = 0.f;
 };
 
 double snap_small(double x) { return std::fabs(x) < 1e-9 ? 0.0 : x; }
@@ -135,6 +138,62 @@ void build_tables(const mg_sensor* s, int32_t w, int32_t wb, HostTables* T) {
         const long first = num >= 0 ? (num + den - 1) / den : 0;
         T->c0[k] = (int32_t)(first % W);
     }
+    // Column guess: pseudo-angle p of a direction theta degrees past the window's
+    // left boundary, p = t/(1+t) with t = tan(theta) below 90 degrees and
+    // 2 - p(180 - theta) above; monotone in theta and cheap on the device.
+    auto pseudo = [](double th) {
+        if (th >= 90.0) {
+            const double t = std::tan((180.0 - th) * M_PI / 180.0);
+            return 2.0 - t / (1.0 + t);
+        }
+        const double t = std::tan(th * M_PI / 180.0);
+        return t / (1.0 + t);
+    };
+    auto unpseudo = [](double p) {
+        if (p <= 1.0) return std::atan2(p, 1.0 - p) * 180.0 / M_PI;
+        const double q = 2.0 - p;
+        return 180.0 - std::atan2(q, 1.0 - q) * 180.0 / M_PI;
+    };
+    const double fov_h = (double)wb * step_az;
+    const double p_end = pseudo(fov_h);
+    // the smallest table (from 4 entries per column, doubling up to 4096) in
+    // which no bucket spans more than one column boundary
+    int ncol = std::max(1, std::min(4096, 4 * wb));
+    for (;;) {
+        T->lut_col.assign(ncol, 0);
+        bool fine = true;
+        long prev = 0;
+        for (int i = 0; i <= ncol; ++i) {
+            const double th = unpseudo((double)i * p_end / (double)ncol);
+            const long c = std::min<long>(std::max<long>((long)std::floor(th / step_az), 0), wb - 1);
+            if (i < ncol) T->lut_col[i] = (uint16_t)c;
+            if (i > 0 && c - prev > 1) fine = false;
+            prev = c;
+        }
+        if (fine || ncol >= 4096) break;
+        ncol = std::min(4096, ncol * 2);
+    }
+    T->lut_col_scale = (float)((double)ncol / p_end);
+    // Row guess: elevation tangent, uniform table between the band's limits.
+    const double half = (double)s->fov_v_deg / 2.0;
+    const double t_lo = std::tan(-half * M_PI / 180.0), t_hi = std::tan(half * M_PI / 180.0);
+    int nrow = std::max(1, std::min(4096, 4 * H));
+    for (;;) {
+        T->lut_row.assign(nrow, 0);
+        bool fine = true;
+        long prev = 0;
+        for (int i = 0; i <= nrow; ++i) {
+            const double el = std::atan(t_lo + (double)i * (t_hi - t_lo) / (double)nrow) * 180.0 / M_PI;
+            const long r = std::min<long>(std::max<long>((long)std::floor((el + half) / step_el), 0), H - 1);
+            if (i < nrow) T->lut_row[i] = (uint16_t)r;
+            if (i > 0 && r - prev > 1) fine = false;
+            prev = r;
+        }
+        if (fine || nrow >= 4096) break;
+        nrow = std::min(4096, nrow * 2);
+    }
+    T->lut_row_lo = (float)t_lo;
+    T->lut_row_scale = (float)((double)nrow / (t_hi - t_lo));
 }
 
 // Device copy of one sensor's tables, shared by all trees with that sensor on
@@ -147,6 +206,7 @@ struct SensorRes {
     int32_t *bins = nullptr, *c0 = nullptr;
     float2* bv = nullptr;
     float* ts = nullptr;
+    uint16_t* luts = nullptr;   // lut_col then lut_row
     size_t bytes = 0;
 };
 
@@ -155,6 +215,7 @@ std::map<SensorKey, SensorRes*> g_sensors;
 
 void free_sensor(SensorRes* r) {
     (void)hipFree(r->d4); (void)hipFree(r->iv4); (void)hipFree(r->bins); (void)hipFree(r->c0); (void)hipFree(r->bv); (void)hipFree(r->ts);
+    (void)hipFree(r->luts);
     delete r;
 }
 
@@ -191,6 +252,11 @@ int acquire_sensor(const mg_sensor* s, hipStream_t stream, SensorRes** out) {
     if (e == hipSuccess) e = hipMalloc(&r->c0, T.B * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&r->bv, T.W * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc(&r->ts, (T.H + 1) * sizeof(float));
+    const size_t nlut = T.lut_col.size() + T.lut_row.size();
+    std::vector<uint16_t> luts(T.lut_col);
+    luts.insert(luts.end(), T.lut_row.begin(), T.lut_row.end());
+    if (e == hipSuccess) e = hipMalloc(&r->luts, nlut * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMemcpyAsync(r->luts, luts.data(), nlut * sizeof(uint16_t), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(r->d4, d4.data(), R * sizeof(float4), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(r->iv4, iv4.data(), R * sizeof(float4), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(r->bins, T.bins.data(), T.W * sizeof(int32_t), hipMemcpyHostToDevice, stream);
@@ -228,9 +294,13 @@ SensorDev sensor_dev(const SensorRes* r, float rv) {
     sd.T = (sd.R + kThreads - 1) / kThreads;
     sd.rv = rv;
     sd.rv2 = rv * rv;
-    sd.inv_daz = (float)((double)T.W / (2.0 * M_PI));
-    sd.el0 = (float)(-(double)r->key.fov_v / 2.0 * M_PI / 180.0);
-    sd.inv_del = (float)((double)T.H / ((double)r->key.fov_v * M_PI / 180.0));
+    sd.lut_col = r->luts;
+    sd.lut_row = r->luts + T.lut_col.size();
+    sd.n_lut_col = (int32_t)T.lut_col.size();
+    sd.n_lut_row = (int32_t)T.lut_row.size();
+    sd.lut_col_scale = T.lut_col_scale;
+    sd.lut_row_lo = T.lut_row_lo;
+    sd.lut_row_scale = T.lut_row_scale;
     return sd;
 }
 

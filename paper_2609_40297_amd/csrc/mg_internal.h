@@ -34,9 +34,15 @@ struct SensorDev {
     int32_t W, H, B, w, WB, R, T;   // R = W*H rays, T = workgroups per node
     float rv;                  // range in voxel units
     float rv2;                 // rv*rv (no depth can exceed it)
-    float inv_daz;             // columns per radian (estimates only)
-    float el0;                 // lowest elevation, radians (estimates only)
-    float inv_del;             // rows per radian (estimates only)
+    // Guess tables for the pixel lookup (a guess only picks where the exact
+    // boundary comparisons start): column from a pseudo-angle past the
+    // window's left boundary, row from the elevation tangent.
+    const uint16_t* lut_col;   // [n_lut_col]
+    const uint16_t* lut_row;   // [n_lut_row]
+    int32_t n_lut_col, n_lut_row;
+    float lut_col_scale;       // pseudo-angle -> lut_col index
+    float lut_row_lo;          // tangent at the bottom of the band
+    float lut_row_scale;       // tangent -> lut_row index
 };
 
 // One tree's device state. Depth buffers are kept as full panoramas: the

@@ -37,37 +37,6 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, size_t n) {
         p[i] = 0u;
 }
 
-// ---------------------------------------------------------------- estimates
-
-// atan on [-1, 1]: the 9th-degree odd polynomial of Abramowitz & Stegun
-// 4.4.47 (|error| <= 1e-5 rad). Used only to guess a pixel index.
-__device__ __forceinline__ float atan_unit(float x) {
-    float x2 = x * x;
-    float p = fmaf(x2, 0.0208351f, -0.0851330f);
-    p = fmaf(x2, p, 0.1801410f);
-    p = fmaf(x2, p, -0.3302995f);
-    p = fmaf(x2, p, 0.9998660f);
-    return p * x;
-}
-
-// Approximate atan2(y, x) for y >= 0, in [0, pi].
-__device__ __forceinline__ float atan2_upper(float y, float x) {
-    float ax = fabsf(x);
-    float a;
-    if (y <= ax) a = atan_unit(y * __builtin_amdgcn_rcpf(ax));
-    else a = 1.57079633f - atan_unit(ax * __builtin_amdgcn_rcpf(y));
-    return x < 0.f ? 3.14159265f - a : a;
-}
-
-// Approximate atan(y / x) for x > 0, in (-pi/2, pi/2).
-__device__ __forceinline__ float atan_ratio(float y, float x) {
-    float ay = fabsf(y);
-    float a;
-    if (ay <= x) a = atan_unit(ay * __builtin_amdgcn_rcpf(x));
-    else a = 1.57079633f - atan_unit(x * __builtin_amdgcn_rcpf(ay));
-    return y < 0.f ? -a : a;
-}
-
 // ---------------------------------------------------------------- ancestor test
 
 struct AncLDS {
@@ -79,64 +48,85 @@ struct AncLDS {
     uint32_t pad[3];
 };
 
+__device__ __forceinline__ int32_t wrap(int32_t c, int32_t W) { return c >= W ? c - W : c; }
+
+// r lies at or to the left (counter-clockwise side) of boundary direction b.
+__device__ __forceinline__ bool left_of(float2 b, float rx, float ry) { return b.x * ry - b.y * rx >= 0.f; }
+
 // Does ancestor A see the voxel centre (cx, cy, cz)? The centre must fall in a
 // pixel cell of A's window (azimuth between two column boundaries, elevation
 // between two row boundaries; cells half-open) and its squared range from A
 // must be <= the squared depth stored for that pixel. Row and column are the
-// numbers of inner boundaries the centre lies at-or-beyond; they are guessed
-// from approximate angles and then settled by the exact boundary tests, which
-// are monotone along the boundaries, so the result is the exact count.
+// numbers of inner boundaries the centre lies at-or-beyond; a table lookup
+// guesses them and the exact boundary comparisons settle them. Those
+// comparisons are monotone along the boundaries, so the settled index is the
+// exact count whatever the guess. The cheap rejections (range, band, wedge)
+// form one mask so that a wave branches once.
 __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float cy, float cz, const SensorDev& S,
                                               const float2* __restrict__ s_bv, const float* __restrict__ s_ts,
+                                              float ts0, float tsH, const uint16_t* __restrict__ s_lut_col,
+                                              const uint16_t* __restrict__ s_lut_row,
                                               const float* __restrict__ dpan) {
     const float rx = cx - A.qx;
     const float ry = cy - A.qy;
     const float rz = cz - A.qz;
     const float rho2 = rx * rx + ry * ry;
     const float range2 = rho2 + rz * rz;
-    if (!(range2 <= S.rv2)) return false;            // beyond every stored depth
     const float sz = rz * fabsf(rz);
-    if (!(sz >= rho2 * s_ts[0])) return false;        // below the band
-    if (!(sz < rho2 * s_ts[S.H])) return false;       // above the band
     const float w0 = A.b0x * ry - A.b0y * rx;
-    if (!(w0 >= 0.f)) return false;                   // right of the window
-    if (!(A.b1x * ry - A.b1y * rx < 0.f)) return false;  // left of the window
+    const float w1 = A.b1x * ry - A.b1y * rx;
+    const bool inside = (range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH) & (w0 >= 0.f) & (w1 < 0.f);
+    if (!inside) return false;
 
-    // column: guess from the angle past the window's left boundary, then settle
+    // Column: pseudo-angle past the left boundary (monotone in the angle) picks a
+    // table bucket holding at most one column boundary; one comparison with that
+    // boundary decides between the bucket's two columns and a second one checks
+    // the other side. Lanes whose check fails (rounding at a bucket edge) settle
+    // with the boundary-by-boundary walk.
     const float u0 = A.b0x * rx + A.b0y * ry;
-    int32_t col = (int32_t)fminf(fmaxf(atan2_upper(w0, u0) * S.inv_daz, 0.f), (float)(S.WB - 1));
-    for (;;) {
-        if (col + 1 >= S.WB) break;
-        int32_t c = A.c0 + col + 1;
-        c = c >= S.W ? c - S.W : c;
-        const float2 b = s_bv[c];
-        if (!(b.x * ry - b.y * rx >= 0.f)) break;
-        ++col;
+    float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
+    pa = u0 < 0.f ? 2.f - pa : pa;
+    const int32_t gc = s_lut_col[(int32_t)fminf(fmaxf(pa * S.lut_col_scale, 0.f), (float)(S.n_lut_col - 1))];
+    const bool c_up = (gc + 1 < S.WB) && left_of(s_bv[wrap(A.c0 + gc + 1, S.W)], rx, ry);
+    int32_t col = gc + (c_up ? 1 : 0);
+    const int32_t cv = c_up ? col + 1 : col;          // the boundary that is still unchecked
+    const bool cv_ok = c_up ? (cv >= S.WB || !left_of(s_bv[wrap(A.c0 + min(cv, S.WB - 1), S.W)], rx, ry))
+                            : (cv == 0 || left_of(s_bv[wrap(A.c0 + cv, S.W)], rx, ry));
+    if (__ballot(!cv_ok)) {
+        if (!cv_ok) {
+            for (;;) {
+                if (col + 1 >= S.WB || !left_of(s_bv[wrap(A.c0 + col + 1, S.W)], rx, ry)) break;
+                ++col;
+            }
+            for (;;) {
+                if (col == 0 || left_of(s_bv[wrap(A.c0 + col, S.W)], rx, ry)) break;
+                --col;
+            }
+        }
     }
-    for (;;) {
-        if (col == 0) break;
-        int32_t c = A.c0 + col;
-        c = c >= S.W ? c - S.W : c;
-        const float2 b = s_bv[c];
-        if (b.x * ry - b.y * rx >= 0.f) break;
-        --col;
+    // Row: elevation tangent picks a bucket holding at most one row boundary;
+    // same two comparisons, same fallback.
+    const float tg = rz * __builtin_amdgcn_rsqf(rho2);
+    const int32_t gr = s_lut_row[(int32_t)fminf(fmaxf((tg - S.lut_row_lo) * S.lut_row_scale, 0.f),
+                                                (float)(S.n_lut_row - 1))];
+    const bool r_up = (gr + 1 < S.H) && (sz >= rho2 * s_ts[gr + 1]);
+    int32_t row = gr + (r_up ? 1 : 0);
+    const int32_t rv_ = r_up ? row + 1 : row;
+    const bool rv_ok = r_up ? (rv_ >= S.H || !(sz >= rho2 * s_ts[min(rv_, S.H)]))
+                            : (rv_ == 0 || sz >= rho2 * s_ts[rv_]);
+    if (__ballot(!rv_ok)) {
+        if (!rv_ok) {
+            for (;;) {
+                if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
+                ++row;
+            }
+            for (;;) {
+                if (row == 0 || sz >= rho2 * s_ts[row]) break;
+                --row;
+            }
+        }
     }
-    // row: guess from the elevation angle, then settle
-    const float rho = __builtin_amdgcn_sqrtf(rho2);
-    int32_t row = (int32_t)fminf(fmaxf((atan_ratio(rz, rho) - S.el0) * S.inv_del, 0.f), (float)(S.H - 1));
-    for (;;) {
-        if (row + 1 >= S.H) break;
-        if (!(sz >= rho2 * s_ts[row + 1])) break;
-        ++row;
-    }
-    for (;;) {
-        if (row == 0) break;
-        if (sz >= rho2 * s_ts[row]) break;
-        --row;
-    }
-    int32_t c = A.c0 + col;
-    c = c >= S.W ? c - S.W : c;
-    const float D = dpan[A.dpan_off + (uint32_t)(c * S.H + row)];
+    const float D = dpan[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
     return range2 <= D * D;
 }
 
@@ -149,8 +139,9 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
 }
 
 __device__ __forceinline__ uint32_t brick_addr(int32_t x, int32_t y, int32_t z, const MapDev& M) {
-    const uint32_t bi = (uint32_t)(x >> 3) +
-                        __umul24((uint32_t)M.nbx, (uint32_t)(y >> 3) + __umul24((uint32_t)M.nby, (uint32_t)(z >> 3)));
+    // brick counts and indices are < 2^24: masking lets the compiler use 24-bit multiply-adds
+    const uint32_t bzy = ((uint32_t)M.nby & 0xffffffu) * (((uint32_t)z >> 3) & 0xffffffu) + ((uint32_t)y >> 3);
+    const uint32_t bi = ((uint32_t)M.nbx & 0xffffffu) * (bzy & 0xffffffu) + ((uint32_t)x >> 3);
     return (bi << 9) | ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
 }
 
@@ -180,8 +171,10 @@ __device__ __forceinline__ void count_by_bin(const uint2* __restrict__ q, int32_
 // after the last ancestor is new to the path and counts into the marginal bins.
 __device__ __forceinline__ void drain_queue(uint2* __restrict__ q, int32_t n, const AncLDS* __restrict__ s_anc,
                                             int32_t na, const SensorDev& S, const float2* __restrict__ s_bv,
-                                            const float* __restrict__ s_ts, const float* __restrict__ dpan,
+                                            const float* __restrict__ s_ts, const uint16_t* __restrict__ s_lut_col,
+                                            const uint16_t* __restrict__ s_lut_row, const float* __restrict__ dpan,
                                             uint32_t* __restrict__ marg_bins, int32_t lane) {
+    const float ts0 = s_ts[0], tsH = s_ts[S.H];
     for (int32_t k = 0; k < na && n > 0; ++k) {
         const AncLDS A = s_anc[k];
         int32_t m = 0;
@@ -194,7 +187,7 @@ __device__ __forceinline__ void drain_queue(uint2* __restrict__ q, int32_t n, co
                 const float cx = (float)(int32_t)(e.x & 0xffffu) + 0.5f;
                 const float cy = (float)(int32_t)(e.x >> 16) + 0.5f;
                 const float cz = (float)(int32_t)(e.y & 0xffffu) + 0.5f;
-                keep = !ancestor_sees(A, cx, cy, cz, S, s_bv, s_ts, dpan);
+                keep = !ancestor_sees(A, cx, cy, cz, S, s_bv, s_ts, ts0, tsH, s_lut_col, s_lut_row, dpan);
             }
             const uint64_t bal = __ballot(keep);
             if (keep) q[m + (int32_t)lane_prefix(bal)] = e;
@@ -213,6 +206,8 @@ struct TraceLDS {
     uint32_t* bins;
     AncLDS* anc;
     uint2* queue;
+    uint16_t* lut_col;
+    uint16_t* lut_row;
 };
 
 __device__ __forceinline__ TraceLDS carve_lds(char* smem, const SensorDev& S) {
@@ -223,12 +218,16 @@ __device__ __forceinline__ TraceLDS carve_lds(char* smem, const SensorDev& S) {
     char* tail = smem + ((reinterpret_cast<char*>(L.bins + 2 * S.B) - smem + 15) & ~static_cast<ptrdiff_t>(15));
     L.anc = reinterpret_cast<AncLDS*>(tail);
     L.queue = reinterpret_cast<uint2*>(tail + sizeof(AncLDS) * kMaxAnc);
+    L.lut_col = reinterpret_cast<uint16_t*>(L.queue + kQCap * (kThreads / 64));
+    L.lut_row = L.lut_col + S.n_lut_col;
     return L;
 }
 
 __device__ __forceinline__ void load_tables(const TraceLDS& L, const SensorDev& S) {
     for (int32_t i = threadIdx.x; i < S.W; i += kThreads) L.bv[i] = S.bv[i];
     for (int32_t i = threadIdx.x; i <= S.H; i += kThreads) L.ts[i] = S.ts[i];
+    for (int32_t i = threadIdx.x; i < S.n_lut_col; i += kThreads) L.lut_col[i] = S.lut_col[i];
+    for (int32_t i = threadIdx.x; i < S.n_lut_row; i += kThreads) L.lut_row[i] = S.lut_row[i];
 }
 
 // One workgroup = kThreads consecutive rays (tile `tile`) of one node; each
@@ -277,58 +276,56 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     const float4 p = Tr.q4[node];
     const float4 d = S.d4[rr];
     const float4 iv = S.iv4[rr];
-    int32_t ix = (int32_t)floorf(p.x), iy = (int32_t)floorf(p.y), iz = (int32_t)floorf(p.z);
     const int32_t sx = d.x > 0.f ? 1 : (d.x < 0.f ? -1 : 0);
     const int32_t sy = d.y > 0.f ? 1 : (d.y < 0.f ? -1 : 0);
     const int32_t sz = d.z > 0.f ? 1 : (d.z < 0.f ? -1 : 0);
-    int32_t bx = d.x > 0.f ? ix + 1 : ix;
-    int32_t by = d.y > 0.f ? iy + 1 : iy;
-    int32_t bz = d.z > 0.f ? iz + 1 : iz;
-    float tx = sx ? ((float)bx - p.x) * iv.x : __builtin_inff();
-    float ty = sy ? ((float)by - p.y) * iv.y : __builtin_inff();
-    float tz = sz ? ((float)bz - p.z) * iv.z : __builtin_inff();
+    // the face crossed when stepping is voxel + 1 for a positive direction
+    const int32_t ox = d.x > 0.f ? 1 : 0, oy = d.y > 0.f ? 1 : 0, oz = d.z > 0.f ? 1 : 0;
+    int32_t ix = (int32_t)floorf(p.x), iy = (int32_t)floorf(p.y), iz = (int32_t)floorf(p.z);
+    float tx = sx ? ((float)(ix + ox) - p.x) * iv.x : __builtin_inff();
+    float ty = sy ? ((float)(iy + oy) - p.y) * iv.y : __builtin_inff();
+    float tz = sz ? ((float)(iz + oz) - p.z) * iv.z : __builtin_inff();
     float t = 0.f, h = S.rv;
     uint32_t n_abs = 0;
+    const uint32_t ebin = (uint32_t)bin << 16;
     // the node lies inside the grid and t = 0 < rv, so its own voxel is visited
     bool alive = has_ray;
-    uint32_t st = alive ? (uint32_t)M.bricks[brick_addr(ix, iy, iz, M)] : 0u;
+    uint32_t st = M.bricks[alive ? brick_addr(ix, iy, iz, M) : 0u];
     int32_t qn = 0;
     while (__ballot(alive)) {
+        // Straight-line step: the next voxel is found and its byte requested
+        // before the current voxel is used; a finished lane keeps loading a
+        // harmless in-bounds byte instead of branching.
         while (__ballot(alive) && (!kMarginal || qn + 64 <= kQCap)) {
-            const int32_t cx = ix, cy = iy, cz = iz;
-            const float tc = t;
-            // step to the next voxel and start loading it before using this one
-            bool next_ok = false;
-            uint32_t st_next = 0u;
-            if (alive) {
-                if (tx <= ty && tx <= tz) {
-                    t = tx; ix += sx; bx += sx; tx = ((float)bx - p.x) * iv.x;
-                    next_ok = (uint32_t)ix < (uint32_t)M.nx;
-                } else if (ty <= tz) {
-                    t = ty; iy += sy; by += sy; ty = ((float)by - p.y) * iv.y;
-                    next_ok = (uint32_t)iy < (uint32_t)M.ny;
-                } else {
-                    t = tz; iz += sz; bz += sz; tz = ((float)bz - p.z) * iv.z;
-                    next_ok = (uint32_t)iz < (uint32_t)M.nz;
-                }
-                next_ok = next_ok && (t < S.rv);
-                if (next_ok) st_next = (uint32_t)M.bricks[brick_addr(ix, iy, iz, M)];
-            }
-            const bool unk = alive && st == kUnknown;
-            if (alive && st == kOccupied) { h = tc; next_ok = false; }
+            const bool mx = (tx <= ty) & (tx <= tz);
+            const bool my = !mx & (ty <= tz);
+            const bool mz = !mx & !my;
+            const float tn = mx ? tx : (my ? ty : tz);
+            const int32_t jx = ix + (mx ? sx : 0);
+            const int32_t jy = iy + (my ? sy : 0);
+            const int32_t jz = iz + (mz ? sz : 0);
+            const bool next_ok = alive & ((uint32_t)jx < (uint32_t)M.nx) & ((uint32_t)jy < (uint32_t)M.ny) &
+                                 ((uint32_t)jz < (uint32_t)M.nz) & (tn < S.rv);
+            const uint32_t st_next = M.bricks[next_ok ? brick_addr(jx, jy, jz, M) : 0u];
+            const bool unk = alive & (st == kUnknown);
+            const bool occ = alive & (st == kOccupied);
+            h = occ ? t : h;
             n_abs += unk ? 1u : 0u;
             if (kMarginal) {
                 const uint64_t bal = __ballot(unk);
-                if (unk)
-                    q[qn + (int32_t)lane_prefix(bal)] =
-                        make_uint2((uint32_t)cx | ((uint32_t)cy << 16), (uint32_t)cz | ((uint32_t)bin << 16));
+                if (unk) q[qn + (int32_t)lane_prefix(bal)] = make_uint2((uint32_t)ix | ((uint32_t)iy << 16), (uint32_t)iz | ebin);
                 qn += __popcll(bal);
             }
-            alive = alive && next_ok;
+            tx = mx ? ((float)(jx + ox) - p.x) * iv.x : tx;
+            ty = my ? ((float)(jy + oy) - p.y) * iv.y : ty;
+            tz = mz ? ((float)(jz + oz) - p.z) * iv.z : tz;
+            ix = jx; iy = jy; iz = jz;
+            t = tn;
+            alive = next_ok & !occ;
             st = st_next;
         }
         if (kMarginal) {
-            drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, Tr.dpan, L.bins + S.B, lane);
+            drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, L.lut_col, L.lut_row, Tr.dpan, L.bins + S.B, lane);
             qn = 0;
         }
     }
@@ -506,7 +503,8 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
 
 size_t trace_lds_bytes(const SensorDev& sd) {
     return sizeof(float2) * sd.W + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B + 16 +
-           sizeof(AncLDS) * kMaxAnc + sizeof(uint2) * kQCap * (kThreads / 64);
+           sizeof(AncLDS) * kMaxAnc + sizeof(uint2) * kQCap * (kThreads / 64) +
+           sizeof(uint16_t) * (sd.n_lut_col + sd.n_lut_row);
 }
 
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
