@@ -134,6 +134,52 @@ int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stre
  *   gain DEVICE uint32[n], yaw_bin DEVICE int32[n]. */
 int mg_eval_absolute(mg_tree tree, void* hip_stream, uint32_t* gain, int32_t* yaw_bin);
 
+/* ---------------------------------------------------------------- serving
+ * Replanning requests from many robots (maps stay resident; each request is a
+ * whole tree, Sec. IV-D), evaluated by a worker thread with continuous
+ * batching: every step advances all in-flight requests by one depth level
+ * (Sec. IV-C inside each request) in one trace launch plus one window launch,
+ * so requests at different depths and on different maps share the GPU.
+ * Requests are admitted between steps, first come first served, when fewer
+ * than max_inflight are in flight and their tree fits in the server's device
+ * arena (admission by device-memory footprint, mg_tree_footprint_bytes).
+ * Results equal mg_eval_marginal on the same tree, alone or in any mix. */
+typedef struct mg_server_s* mg_server;
+
+typedef struct {
+    mg_sensor sensor;          /* geometry and range of every request          */
+    int32_t max_inflight;      /* requests advanced together, at most (>= 1)   */
+    int64_t arena_bytes;       /* device memory for in-flight trees (>= 1)     */
+} mg_server_config;
+
+/* Allocates the arena (the only device allocation of the server) and starts
+ * the worker thread on the current device. */
+int mg_server_create(const mg_server_config* cfg, mg_server* out);
+
+/* Queues a request: the marginal gain of the tree (pos_m [n][3] metres,
+ * parent [n], HOST arrays, copied and validated here as in mg_tree_upload) on
+ * `map`. Results go to the HOST arrays gain [n] and yaw_bin [n], which must
+ * stay valid until the request is reported done. MG_E_INVALID for a bad tree,
+ * MG_E_NOMEM when the tree can never fit in the arena. *ticket identifies the
+ * request. Thread-safe. */
+int mg_server_submit(mg_server server, mg_map map, const float* pos_m, const int32_t* parent, int32_t n,
+                     uint32_t* gain, int32_t* yaw_bin, int64_t* ticket);
+
+/* Non-blocking: *status = 0 while pending, 1 when done, or the request's
+ * negative error code. Once reported done (or failed) the ticket is retired;
+ * latency_us (may be NULL) receives submit-to-result time in microseconds. */
+int mg_server_poll(mg_server server, int64_t ticket, int32_t* status, double* latency_us);
+
+/* Blocks until the request is done; returns its status and retires the ticket. */
+int mg_server_wait(mg_server server, int64_t ticket, double* latency_us);
+
+/* Counters: steps run, requests completed, rays evaluated, requests in flight and queued. */
+int mg_server_stats(mg_server server, int64_t* steps, int64_t* completed, double* rays, int32_t* in_flight,
+                    int32_t* queued);
+
+/* Finishes every queued and in-flight request, stops the worker, frees the arena. */
+int mg_server_destroy(mg_server server);
+
 /* Host-only diagnostics: the sensor tables the library builds (no device
  * work). dir and inv [n_az*n_el][3] (ray r = c*n_el + j), bv [n_az][2]
  * (column left-boundary unit vectors), ts [n_el+1] (tan(e)|tan(e)| at row

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -399,22 +400,39 @@ struct mg_tree_s {
     std::vector<int32_t> depth_h;
     // device
     void* block = nullptr;                // one allocation for all node data
+    bool owns_block = true;               // false when placed in a server's arena
     TreeDev dev{};
     SensorDev sd{};
     size_t bytes = 0;
     int device = 0;
-    uint32_t* scratch_gain = nullptr;     // used when the caller asks only for host results
+    uint32_t* scratch_gain = nullptr;     // device outputs used when the caller gives none
     int32_t* scratch_yaw = nullptr;
 };
 
-namespace {
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-}
+namespace mgb {
 
-extern "C" int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* parent, int32_t n,
-                              const mg_sensor* sensor, void* hip_stream, mg_tree* out) {
-    if (!out) return fail(MG_E_INVALID, "out is NULL");
-    *out = nullptr;
+// Host side of a tree upload: validation and every array the device needs.
+struct HostTree {
+    int32_t n = 0, maxd = 0;
+    std::vector<float4> q4;
+    std::vector<int32_t> depth, level_ptr, level_nodes, anc_ptr, anc_ids, child_ptr, child_ids, parent;
+    // device block layout
+    size_t o_q4 = 0, o_ap = 0, o_ai = 0, o_ln = 0, o_cp = 0, o_ci = 0, o_c0 = 0, o_g = 0, o_y = 0, o_bins = 0,
+           o_dpan = 0, total = 0;
+};
+
+}  // namespace mgb
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Validates the tree against the map and sensor (parent[0] = -1, 0 <= parent[i] < i,
+// depth <= 64, every node inside the map, q = (p - origin) / voxel in float),
+// builds levels (ids ascending within a level), nearest-first ancestor lists
+// and child lists, and lays out the device block.
+int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t n, const mg_sensor* sensor,
+                 mgb::HostTree* H) {
     if (!map || !pos_m || !parent) return fail(MG_E_INVALID, "map/pos/parent is NULL");
     if (n < 1) return fail(MG_E_INVALID, "a tree needs at least one node");
     if (n > (1 << 24)) return fail(MG_E_UNSUPPORTED, "more than 2^24 nodes");
@@ -422,14 +440,15 @@ extern "C" int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* par
     int rc = check_sensor(sensor, &w, &wb);
     if (rc != MG_OK) return rc;
     if (parent[0] != -1) return fail(MG_E_INVALID, "parent[0] must be -1");
-    std::vector<int32_t> depth(n, 0);
+    H->n = n;
+    H->parent.assign(parent, parent + n);
+    H->depth.assign(n, 0);
     for (int32_t i = 1; i < n; ++i) {
         if (parent[i] < 0 || parent[i] >= i) return fail(MG_E_INVALID, "parent[%d] = %d must be in [0, %d)", i, parent[i], i);
-        depth[i] = depth[parent[i]] + 1;
-        if (depth[i] > kMaxAnc) return fail(MG_E_INVALID, "node %d is deeper than %d", i, kMaxAnc);
+        H->depth[i] = H->depth[parent[i]] + 1;
+        if (H->depth[i] > kMaxAnc) return fail(MG_E_INVALID, "node %d is deeper than %d", i, kMaxAnc);
     }
-    // positions in voxel units: (p - origin) then / voxel size, in float
-    std::vector<float4> q4(n);
+    H->q4.resize(n);
     const int32_t dims[3] = {map->dev.nx, map->dev.ny, map->dev.nz};
     for (int32_t i = 0; i < n; ++i) {
         float qv[3];
@@ -439,117 +458,145 @@ extern "C" int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* par
                 return fail(MG_E_INVALID, "node %d lies outside the map", i);
             qv[a] = v;
         }
-        q4[i] = make_float4(qv[0], qv[1], qv[2], 0.f);
+        H->q4[i] = make_float4(qv[0], qv[1], qv[2], 0.f);
     }
-    // levels (CSR by depth, ids ascending within a level), ancestors, children
-    int32_t maxd = 0;
-    for (int32_t i = 0; i < n; ++i) maxd = depth[i] > maxd ? depth[i] : maxd;
-    std::vector<int32_t> level_ptr(maxd + 2, 0), level_nodes(n);
-    for (int32_t i = 0; i < n; ++i) level_ptr[depth[i] + 1]++;
-    for (int32_t d = 0; d <= maxd; ++d) level_ptr[d + 1] += level_ptr[d];
+    H->maxd = 0;
+    for (int32_t i = 0; i < n; ++i) H->maxd = std::max(H->maxd, H->depth[i]);
+    H->level_ptr.assign(H->maxd + 2, 0);
+    H->level_nodes.assign(n, 0);
+    for (int32_t i = 0; i < n; ++i) H->level_ptr[H->depth[i] + 1]++;
+    for (int32_t d = 0; d <= H->maxd; ++d) H->level_ptr[d + 1] += H->level_ptr[d];
     {
-        std::vector<int32_t> fill(level_ptr.begin(), level_ptr.end() - 1);
-        for (int32_t i = 0; i < n; ++i) level_nodes[fill[depth[i]]++] = i;
+        std::vector<int32_t> fill(H->level_ptr.begin(), H->level_ptr.end() - 1);
+        for (int32_t i = 0; i < n; ++i) H->level_nodes[fill[H->depth[i]]++] = i;
     }
-    std::vector<int32_t> anc_ptr(n + 1, 0);
-    for (int32_t i = 0; i < n; ++i) anc_ptr[i + 1] = anc_ptr[i] + depth[i];
-    std::vector<int32_t> anc_ids((size_t)anc_ptr[n] + 1);
+    H->anc_ptr.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) H->anc_ptr[i + 1] = H->anc_ptr[i] + H->depth[i];
+    H->anc_ids.assign((size_t)H->anc_ptr[n] + 1, 0);
     for (int32_t i = 0; i < n; ++i) {
-        int32_t k = anc_ptr[i];
-        for (int32_t a = parent[i]; a >= 0; a = parent[a]) anc_ids[k++] = a;
+        int32_t k = H->anc_ptr[i];
+        for (int32_t a = parent[i]; a >= 0; a = parent[a]) H->anc_ids[k++] = a;
     }
-    std::vector<int32_t> child_ptr(n + 1, 0), child_ids((size_t)n);
-    for (int32_t i = 1; i < n; ++i) child_ptr[parent[i] + 1]++;
-    for (int32_t i = 0; i < n; ++i) child_ptr[i + 1] += child_ptr[i];
+    H->child_ptr.assign(n + 1, 0);
+    H->child_ids.assign((size_t)n, 0);
+    for (int32_t i = 1; i < n; ++i) H->child_ptr[parent[i] + 1]++;
+    for (int32_t i = 0; i < n; ++i) H->child_ptr[i + 1] += H->child_ptr[i];
     {
-        std::vector<int32_t> fill(child_ptr.begin(), child_ptr.end() - 1);
-        for (int32_t i = 1; i < n; ++i) child_ids[fill[parent[i]]++] = i;
+        std::vector<int32_t> fill(H->child_ptr.begin(), H->child_ptr.end() - 1);
+        for (int32_t i = 1; i < n; ++i) H->child_ids[fill[parent[i]]++] = i;
     }
-
-    hipStream_t s = (hipStream_t)hip_stream;
-    std::unique_ptr<mg_tree_s> t(new (std::nothrow) mg_tree_s());
-    if (!t) return fail(MG_E_NOMEM, "host allocation failed");
-    rc = acquire_sensor(sensor, s, &t->sensor);
-    if (rc != MG_OK) return rc;
-    const SensorRes* sr = t->sensor;
-    const size_t R = (size_t)sr->host.W * sr->host.H;
-    const int32_t B = sr->host.B;
-    if (R * (size_t)n >= (1ull << 32)) {
-        release_sensor(t->sensor);
-        return fail(MG_E_UNSUPPORTED, "nodes x rays = %zu exceeds 2^32 per tree", R * (size_t)n);
-    }
+    const size_t R = (size_t)sensor->n_az * sensor->n_el;
+    if (R * (size_t)n >= (1ull << 32)) return fail(MG_E_UNSUPPORTED, "nodes x rays = %zu exceeds 2^32 per tree", R * (size_t)n);
     // one device block: q4 | anc_ptr | anc_ids | level_nodes | child_ptr | child_ids | c0 | gain | yaw | bins | dpan
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-    const size_t o_q4 = take(sizeof(float4) * n);
-    const size_t o_ap = take(sizeof(int32_t) * (n + 1));
-    const size_t o_ai = take(sizeof(int32_t) * anc_ids.size());
-    const size_t o_ln = take(sizeof(int32_t) * n);
-    const size_t o_cp = take(sizeof(int32_t) * (n + 1));
-    const size_t o_ci = take(sizeof(int32_t) * n);
-    const size_t o_c0 = take(sizeof(int32_t) * n);
-    const size_t o_g = take(sizeof(uint32_t) * n);
-    const size_t o_y = take(sizeof(int32_t) * n);
-    const size_t o_bins = take(sizeof(uint32_t) * 2 * B * (size_t)n);
-    const size_t o_dpan = take(sizeof(float) * R * (size_t)n);
-    const size_t total = off;
-    hipError_t e = hipMalloc(&t->block, total);
-    if (e != hipSuccess) {
-        release_sensor(t->sensor);
-        return fail(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "tree allocation (%zu bytes): %s", total,
-                    hipGetErrorString(e));
-    }
-    char* base = (char*)t->block;
+    H->o_q4 = take(sizeof(float4) * n);
+    H->o_ap = take(sizeof(int32_t) * (n + 1));
+    H->o_ai = take(sizeof(int32_t) * H->anc_ids.size());
+    H->o_ln = take(sizeof(int32_t) * n);
+    H->o_cp = take(sizeof(int32_t) * (n + 1));
+    H->o_ci = take(sizeof(int32_t) * n);
+    H->o_c0 = take(sizeof(int32_t) * n);
+    H->o_g = take(sizeof(uint32_t) * n);
+    H->o_y = take(sizeof(int32_t) * n);
+    H->o_bins = take(sizeof(uint32_t) * 2 * sensor->yaw_bins * (size_t)n);
+    H->o_dpan = take(sizeof(float) * R * (size_t)n);
+    H->total = off;
+    return MG_OK;
+}
+
+// Copies the host arrays into `block` (at least H.total bytes) on `s` and waits
+// for the copies, then builds the handle. The handle frees the block on
+// destruction only when it owns it.
+int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, hipStream_t s, void* block,
+                  bool owns, mg_tree* out) {
+    std::unique_ptr<mg_tree_s> t(new (std::nothrow) mg_tree_s());
+    if (!t) return fail(MG_E_NOMEM, "host allocation failed");
+    int rc = acquire_sensor(sensor, s, &t->sensor);
+    if (rc != MG_OK) return rc;
+    const int32_t n = H.n;
+    char* base = (char*)block;
     auto up = [&](size_t o, const void* src, size_t bytes) {
         return bytes ? hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     };
     std::vector<int32_t> zeros_c0(n, 0);
-    if (e == hipSuccess) e = up(o_q4, q4.data(), sizeof(float4) * n);
-    if (e == hipSuccess) e = up(o_ap, anc_ptr.data(), sizeof(int32_t) * (n + 1));
-    if (e == hipSuccess) e = up(o_ai, anc_ids.data(), sizeof(int32_t) * anc_ids.size());
-    if (e == hipSuccess) e = up(o_ln, level_nodes.data(), sizeof(int32_t) * n);
-    if (e == hipSuccess) e = up(o_cp, child_ptr.data(), sizeof(int32_t) * (n + 1));
-    if (e == hipSuccess) e = up(o_ci, child_ids.data(), sizeof(int32_t) * n);
-    if (e == hipSuccess) e = up(o_c0, zeros_c0.data(), sizeof(int32_t) * n);
+    hipError_t e = up(H.o_q4, H.q4.data(), sizeof(float4) * n);
+    if (e == hipSuccess) e = up(H.o_ap, H.anc_ptr.data(), sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = up(H.o_ai, H.anc_ids.data(), sizeof(int32_t) * H.anc_ids.size());
+    if (e == hipSuccess) e = up(H.o_ln, H.level_nodes.data(), sizeof(int32_t) * n);
+    if (e == hipSuccess) e = up(H.o_cp, H.child_ptr.data(), sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = up(H.o_ci, H.child_ids.data(), sizeof(int32_t) * n);
+    if (e == hipSuccess) e = up(H.o_c0, zeros_c0.data(), sizeof(int32_t) * n);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        (void)hipFree(t->block);
         release_sensor(t->sensor);
         return fail(MG_E_DEVICE, "tree upload: %s", hipGetErrorString(e));
     }
-    t->dev.q4 = (const float4*)(base + o_q4);
-    t->dev.anc_ptr = (const int32_t*)(base + o_ap);
-    t->dev.anc_ids = (const int32_t*)(base + o_ai);
-    t->dev.level_nodes = (const int32_t*)(base + o_ln);
-    t->dev.child_ptr = (const int32_t*)(base + o_cp);
-    t->dev.child_ids = (const int32_t*)(base + o_ci);
-    t->dev.c0 = (int32_t*)(base + o_c0);
-    t->dev.bins = (uint32_t*)(base + o_bins);
-    t->dev.dpan = (float*)(base + o_dpan);
+    t->dev.q4 = (const float4*)(base + H.o_q4);
+    t->dev.anc_ptr = (const int32_t*)(base + H.o_ap);
+    t->dev.anc_ids = (const int32_t*)(base + H.o_ai);
+    t->dev.level_nodes = (const int32_t*)(base + H.o_ln);
+    t->dev.child_ptr = (const int32_t*)(base + H.o_cp);
+    t->dev.child_ids = (const int32_t*)(base + H.o_ci);
+    t->dev.c0 = (int32_t*)(base + H.o_c0);
+    t->dev.bins = (uint32_t*)(base + H.o_bins);
+    t->dev.dpan = (float*)(base + H.o_dpan);
     t->dev.n = n;
-    t->scratch_gain = (uint32_t*)(base + o_g);
-    t->scratch_yaw = (int32_t*)(base + o_y);
-    const float rv = sensor->range_m / map->voxel_m;
-    t->sd = sensor_dev(sr, rv);
+    t->scratch_gain = (uint32_t*)(base + H.o_g);
+    t->scratch_yaw = (int32_t*)(base + H.o_y);
+    t->sd = sensor_dev(t->sensor, sensor->range_m / map->voxel_m);
     t->map = map;
     t->params = *sensor;
     t->n = n;
-    t->levels = maxd + 1;
-    t->level_ptr = level_ptr;
-    t->level_nodes_h = level_nodes;
-    t->parent_h.assign(parent, parent + n);
-    t->depth_h = depth;
-    t->bytes = total;
-    HIP_TRY(hipGetDevice(&t->device));
+    t->levels = H.maxd + 1;
+    t->level_ptr = H.level_ptr;
+    t->level_nodes_h = H.level_nodes;
+    t->parent_h = H.parent;
+    t->depth_h = H.depth;
+    t->block = block;
+    t->owns_block = owns;
+    t->bytes = H.total;
+    (void)hipGetDevice(&t->device);
     map->trees++;
     *out = t.release();
     return MG_OK;
 }
 
+}  // namespace
+
+namespace mgb {
+int prepare(mg_map map, const float* pos_m, const int32_t* parent, int32_t n, const mg_sensor* sensor, HostTree* H) {
+    return prepare_tree(map, pos_m, parent, n, sensor, H);
+}
+size_t block_bytes(const HostTree& H) { return H.total; }
+int upload_into(mg_map map, const HostTree& H, const mg_sensor* sensor, hipStream_t s, void* block, mg_tree* out) {
+    return finish_upload(map, H, sensor, s, block, false, out);
+}
+void free_host_tree(HostTree* H) { delete H; }
+HostTree* new_host_tree() { return new (std::nothrow) HostTree(); }
+}  // namespace mgb
+
+extern "C" int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* parent, int32_t n,
+                              const mg_sensor* sensor, void* hip_stream, mg_tree* out) {
+    if (!out) return fail(MG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    mgb::HostTree H;
+    int rc = prepare_tree(map, pos_m, parent, n, sensor, &H);
+    if (rc != MG_OK) return rc;
+    void* block = nullptr;
+    hipError_t e = hipMalloc(&block, H.total);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "tree allocation (%zu bytes): %s", H.total,
+                    hipGetErrorString(e));
+    rc = finish_upload(map, H, sensor, (hipStream_t)hip_stream, block, true, out);
+    if (rc != MG_OK) (void)hipFree(block);
+    return rc;
+}
+
 extern "C" int mg_tree_destroy(mg_tree t) {
     if (!t) return fail(MG_E_INVALID, "tree is NULL");
     mgb::forget_tree(t);
-    (void)hipFree(t->block);
+    if (t->owns_block) (void)hipFree(t->block);
     release_sensor(t->sensor);
     t->map->trees--;
     delete t;
@@ -635,6 +682,8 @@ int tree_view(mg_tree t, TreeView* v) {
     v->td = &t->dev;
     v->level_ptr = &t->level_ptr;
     v->level_nodes = &t->level_nodes_h;
+    v->scratch_gain = t->scratch_gain;
+    v->scratch_yaw = t->scratch_yaw;
     v->params = t->params;
     v->n = t->n;
     v->levels = t->levels;

@@ -13,12 +13,22 @@ struct TreeView {
     const mgk::TreeDev* td;
     const std::vector<int32_t>* level_ptr;     // host copy, [levels + 1]
     const std::vector<int32_t>* level_nodes;   // host copy, [n]
+    uint32_t* scratch_gain;                    // device outputs inside the tree's block
+    int32_t* scratch_yaw;
     mg_sensor params;
     int32_t n, levels, device;
 };
 
 int tree_view(mg_tree t, TreeView* v);     // mg_api.hip
 int set_error(int code, const char* msg);  // mg_api.hip
+
+// Tree uploads into memory the caller provides (mg_api.hip), for the server's arena.
+struct HostTree;
+HostTree* new_host_tree();
+void free_host_tree(HostTree* H);
+int prepare(mg_map map, const float* pos_m, const int32_t* parent, int32_t n, const mg_sensor* sensor, HostTree* H);
+size_t block_bytes(const HostTree& H);
+int upload_into(mg_map map, const HostTree& H, const mg_sensor* sensor, hipStream_t s, void* block, mg_tree* out);
 void forget_tree(mg_tree t);               // mg_batch.hip: drop cached launch plans that use t
 
 }  // namespace mgb

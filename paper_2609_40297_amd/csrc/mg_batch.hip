@@ -19,6 +19,9 @@ namespace {
 
 struct Plan {
     std::vector<mg_tree> trees;
+    uint32_t* gain = nullptr;             // output buffers the descriptors point into
+    int32_t* yaw = nullptr;
+    float* depth = nullptr;
     void* block = nullptr;                 // BatchTree[n_trees] | items[total]
     const BatchTree* dtrees = nullptr;
     const unsigned long long* ditems = nullptr;
@@ -47,7 +50,8 @@ bool same_geometry(const mg_sensor& a, const mg_sensor& b) {
            a.fov_v_deg == b.fov_v_deg && a.az_offset_deg == b.az_offset_deg;
 }
 
-int build_plan(const std::vector<mg_tree>& trees, hipStream_t stream, std::unique_ptr<Plan>* out) {
+int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, float* depth, hipStream_t stream,
+               std::unique_ptr<Plan>* out) {
     std::unique_ptr<Plan> P(new Plan());
     P->trees = trees;
     const int32_t nt = (int32_t)trees.size();
@@ -66,8 +70,9 @@ int build_plan(const std::vector<mg_tree>& trees, hipStream_t stream, std::uniqu
         bt[i].td = *v.td;
         bt[i].rv = v.sd->rv;
         bt[i].rv2 = v.sd->rv2;
-        bt[i].node_base = P->total;
-        bt[i].pad = 0;
+        bt[i].gain = gain + P->total;
+        bt[i].yaw = yaw + P->total;
+        bt[i].depth = depth ? depth + (size_t)P->total * v.sd->H * v.sd->WB : nullptr;
         if ((uint64_t)P->total + (uint64_t)v.n >= (1ull << 31))
             return mgb::set_error(MG_E_UNSUPPORTED, "batch has 2^31 nodes or more");
         P->total += (uint32_t)v.n;
@@ -106,17 +111,20 @@ int build_plan(const std::vector<mg_tree>& trees, hipStream_t stream, std::uniqu
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "batch plan upload");
     P->dtrees = (const BatchTree*)(base + o_trees);
+    P->gain = gain;
+    P->yaw = yaw;
+    P->depth = depth;
     P->ditems = (const unsigned long long*)(base + o_items);
     *out = std::move(P);
     return MG_OK;
 }
 
-int run_plan(const Plan& P, hipStream_t s, uint32_t* gain, int32_t* yaw, float* depth) {
+int run_plan(const Plan& P, hipStream_t s) {
     hipError_t e = launch_batch_zero(P.dtrees, (int32_t)P.trees.size(), P.max_nodes, P.sd, s);
     if (e != hipSuccess) return hip_fail(e, "batch zero");
     for (size_t d = 0; d + 1 < P.level_ptr.size(); ++d) {
         const int32_t b = P.level_ptr[d], n = P.level_ptr[d + 1] - b;
-        e = launch_batch_level(P.dtrees, P.ditems + b, n, P.sd, gain, yaw, depth, s);
+        e = launch_batch_level(P.dtrees, P.ditems + b, n, P.sd, s);
         if (e != hipSuccess) return hip_fail(e, "batch level");
     }
     return MG_OK;
@@ -152,17 +160,22 @@ extern "C" int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, voi
     hipStream_t s = (hipStream_t)hip_stream;
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.find(key);
+    if (it != g_plans.end() && (it->second->gain != gain || it->second->yaw != yaw_bin || it->second->depth != depth)) {
+        (void)hipStreamSynchronize(s);          // the old descriptors may still be read
+        g_plans.erase(it);
+        it = g_plans.end();
+    }
     if (it == g_plans.end()) {
         if (g_plans.size() >= kMaxPlans) {
             (void)hipDeviceSynchronize();
             g_plans.clear();
         }
         std::unique_ptr<Plan> P;
-        int rc = build_plan(key, s, &P);
+        int rc = build_plan(key, gain, yaw_bin, depth, s, &P);
         if (rc != MG_OK) return rc;
         it = g_plans.emplace(key, std::move(P)).first;
     }
     const Plan& P = *it->second;
     if (P.device != dev) return mgb::set_error(MG_E_INVALID, "batch trees live on another device");
-    return run_plan(P, s, gain, yaw_bin, depth);
+    return run_plan(P, s);
 }

@@ -61,15 +61,15 @@ struct TreeDev {
     int32_t n;
 };
 
-// One tree of a multi-tree batch: its map and node data, its range in voxel
-// units (maps may differ in voxel size) and the index of its node 0 in the
-// batch outputs.
+// One tree of a multi-tree launch: its map and node data, its range in voxel
+// units (maps may differ in voxel size) and where its outputs go.
 struct BatchTree {
     MapDev map;
     TreeDev td;
     float rv, rv2;
-    uint32_t node_base;
-    uint32_t pad;
+    uint32_t* gain;            // [n]
+    int32_t* yaw;              // [n]
+    float* depth;              // [n][H][WB] or NULL
 };
 
 // Launchers (mg_kernels.hip).
@@ -84,6 +84,6 @@ size_t trace_lds_bytes(const SensorDev& sd);
 hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const SensorDev& sd,
                              hipStream_t s);
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                              const SensorDev& sd, uint32_t* gain, int32_t* yaw, float* depth, hipStream_t s);
+                              const SensorDev& sd, hipStream_t s);
 
 }  // namespace mgk

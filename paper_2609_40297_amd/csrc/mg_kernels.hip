@@ -435,12 +435,10 @@ __global__ __launch_bounds__(kThreads) void k_trace_multi(const BatchTree* __res
     trace_tile<true>(BT.map, St, BT.td, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
 }
 
-// Window selection for one depth level of all trees; writes the outputs at
-// the batch numbering (node_base + node) and the node's depth buffer.
+// Window selection for one depth level of all trees; writes each tree's
+// outputs and, when asked, the node's depth buffer.
 __global__ __launch_bounds__(kThreads) void k_finish_multi(const BatchTree* __restrict__ trees,
-                                                           const unsigned long long* __restrict__ items, SensorDev S,
-                                                           uint32_t* __restrict__ gain, int32_t* __restrict__ yaw,
-                                                           float* __restrict__ depth) {
+                                                           const unsigned long long* __restrict__ items, SensorDev S) {
     __shared__ uint32_t s_p[2 * kMaxBins + 1];
     __shared__ unsigned long long s_best[kThreads / 64];
     const unsigned long long it = items[blockIdx.x];
@@ -449,16 +447,15 @@ __global__ __launch_bounds__(kThreads) void k_finish_multi(const BatchTree* __re
     const unsigned long long best = select_window(BT.td.bins + (size_t)node * 2 * S.B + S.B, S, s_p, s_best);
     const int32_t k = S.B - 1 - (int32_t)(uint32_t)(best & 0xffffffffull);
     const int32_t c0 = S.c0_of_win[k];
-    const uint32_t g = BT.node_base + (uint32_t)node;
     if (threadIdx.x == 0) {
-        gain[g] = (uint32_t)(best >> 32);
-        yaw[g] = k;
+        BT.gain[node] = (uint32_t)(best >> 32);
+        BT.yaw[node] = k;
         BT.td.c0[node] = c0;
     }
-    if (depth) {
+    if (BT.depth) {
         const int32_t per = S.H * S.WB;
         const float* src = BT.td.dpan + (size_t)node * S.R;
-        float* dst = depth + (size_t)g * per;
+        float* dst = BT.depth + (size_t)node * per;
         for (int32_t o = threadIdx.x; o < per; o += kThreads) {
             const int32_t j = o / S.WB, ii = o - j * S.WB;
             int32_t c = c0 + ii;
@@ -544,14 +541,13 @@ hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t m
 }
 
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                              const SensorDev& sd, uint32_t* gain, int32_t* yaw, float* depth, hipStream_t s) {
+                              const SensorDev& sd, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_trace_multi, dim3((unsigned)n_items * (unsigned)sd.T), dim3(kThreads), trace_lds_bytes(sd), s,
                        trees, items, sd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_finish_multi, dim3((unsigned)n_items), dim3(kThreads), 0, s, trees, items, sd, gain, yaw,
-                       depth);
+    hipLaunchKernelGGL(k_finish_multi, dim3((unsigned)n_items), dim3(kThreads), 0, s, trees, items, sd);
     return hipGetLastError();
 }
 

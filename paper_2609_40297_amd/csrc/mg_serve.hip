@@ -1,0 +1,434 @@
+// Serving loop: replanning requests from many robots, continuously batched.
+//
+// A worker thread runs steps. A step advances every in-flight request by one
+// depth level (Sec. IV-C's order inside each request) with one trace launch and
+// one window launch over the union of their current-level nodes, so requests
+// at different depths, on different maps, share the GPU. Requests are admitted
+// between steps, first come first served, when a slot is free and their tree
+// fits in the server's device arena (admission by device-memory footprint);
+// a finished request's results are copied to the caller's host arrays and its
+// arena block is released. Nothing on the request path allocates device memory.
+#pragma clang fp contract(off)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mg_batch.h"
+
+using namespace mgk;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+// First-fit allocator over [0, size) with 256-byte granules and coalescing.
+class Arena {
+  public:
+    void reset(size_t size) {
+        free_.clear();
+        free_[0] = size;
+        size_ = size;
+    }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = (bytes + 255) / 256 * 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) / 256 * 256;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t size() const { return size_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0;
+};
+
+struct Request {
+    int64_t ticket = 0;
+    mg_map map = nullptr;
+    mgb::HostTree* host = nullptr;
+    int32_t n = 0;
+    uint32_t* out_gain = nullptr;    // caller's host arrays
+    int32_t* out_yaw = nullptr;
+    Clock::time_point t_submit, t_done;
+    size_t bytes = 0, arena_off = 0;
+    mg_tree tree = nullptr;
+    const std::vector<int32_t>* level_ptr = nullptr;
+    const std::vector<int32_t>* level_nodes = nullptr;
+    int32_t level = 0, levels = 0;
+    int rc = MG_OK;
+    int state = 0;                   // 0 queued, 1 in flight, 2 done (rc tells success)
+    ~Request() {
+        if (host) mgb::free_host_tree(host);
+    }
+};
+
+int hip_fail(hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return mgb::set_error(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, m.c_str());
+}
+
+}  // namespace
+
+struct mg_server_s {
+    mg_server_config cfg{};
+    int device = 0;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::vector<Request*> inflight;
+    std::unordered_map<int64_t, std::unique_ptr<Request>> all;
+    int64_t next_ticket = 1;
+    bool stop = false;
+    int fatal = MG_OK;
+    std::string fatal_msg;
+    hipStream_t compute = nullptr, upload = nullptr;
+    void* arena_mem = nullptr;
+    Arena arena;
+    // per-step launch descriptors: device arrays and pinned host staging
+    BatchTree* d_trees = nullptr;
+    unsigned long long* d_items = nullptr;
+    BatchTree* h_trees = nullptr;
+    unsigned long long* h_items = nullptr;
+    size_t cap_trees = 0, cap_items = 0;
+    uint32_t* h_stage = nullptr;        // pinned: gain then yaw of finished requests
+    size_t cap_stage = 0;
+    // statistics
+    int64_t steps = 0, completed = 0;
+    double rays_done = 0.0;
+
+    int grow(size_t trees, size_t items, size_t stage_words);
+    void run();
+    int step();
+};
+
+int mg_server_s::grow(size_t trees, size_t items, size_t stage_words) {
+    hipError_t e = hipSuccess;
+    if (trees > cap_trees) {
+        const size_t c = std::max(trees, cap_trees * 2);
+        (void)hipFree(d_trees);
+        (void)hipHostFree(h_trees);
+        d_trees = nullptr;
+        h_trees = nullptr;
+        e = hipMalloc(&d_trees, sizeof(BatchTree) * c);
+        if (e == hipSuccess) e = hipHostMalloc(&h_trees, sizeof(BatchTree) * c, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "server descriptors");
+        cap_trees = c;
+    }
+    if (items > cap_items) {
+        const size_t c = std::max(items, cap_items * 2);
+        (void)hipFree(d_items);
+        (void)hipHostFree(h_items);
+        d_items = nullptr;
+        h_items = nullptr;
+        e = hipMalloc(&d_items, sizeof(unsigned long long) * c);
+        if (e == hipSuccess) e = hipHostMalloc(&h_items, sizeof(unsigned long long) * c, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "server work lists");
+        cap_items = c;
+    }
+    if (stage_words > cap_stage) {
+        const size_t c = std::max(stage_words, cap_stage * 2);
+        (void)hipHostFree(h_stage);
+        h_stage = nullptr;
+        e = hipHostMalloc(&h_stage, sizeof(uint32_t) * c, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "server staging");
+        cap_stage = c;
+    }
+    return MG_OK;
+}
+
+// One step: admit, launch one level of every in-flight request, retire finished ones.
+int mg_server_s::step() {
+    // admission (FIFO; the head waits until a slot and enough arena are free)
+    for (;;) {
+        Request* r = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (queue.empty() || (int32_t)inflight.size() >= cfg.max_inflight) break;
+            r = queue.front();
+            size_t off = 0;
+            if (!arena.alloc(r->bytes, &off)) break;
+            r->arena_off = off;
+            queue.pop_front();
+        }
+        int rc = mgb::upload_into(r->map, *r->host, &cfg.sensor, upload, (char*)arena_mem + r->arena_off, &r->tree);
+        std::lock_guard<std::mutex> lk(mu);
+        if (rc != MG_OK) {
+            arena.release(r->arena_off, r->bytes);
+            r->rc = rc;
+            r->state = 2;
+            r->t_done = Clock::now();
+            cv_done.notify_all();
+            continue;
+        }
+        mgb::TreeView v;
+        mgb::tree_view(r->tree, &v);
+        r->level_ptr = v.level_ptr;
+        r->level_nodes = v.level_nodes;
+        r->level = 0;
+        r->levels = v.levels;
+        r->state = 1;
+        hipError_t e = launch_zero_u32(v.td->bins, (size_t)2 * v.sd->B * v.n, compute);
+        if (e != hipSuccess) return hip_fail(e, "server bins");
+        inflight.push_back(r);
+    }
+    std::vector<Request*> active;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        active = inflight;
+    }
+    if (active.empty()) return MG_OK;
+
+    // descriptors and the work list of this step
+    size_t n_items = 0, stage = 0;
+    for (Request* r : active) {
+        n_items += (size_t)((*r->level_ptr)[r->level + 1] - (*r->level_ptr)[r->level]);
+        if (r->level + 1 == r->levels) stage += 2 * (size_t)r->n;
+    }
+    int rc = grow(active.size(), n_items, stage);
+    if (rc != MG_OK) return rc;
+    SensorDev sd{};
+    size_t k = 0;
+    for (size_t i = 0; i < active.size(); ++i) {
+        Request* r = active[i];
+        mgb::TreeView v;
+        mgb::tree_view(r->tree, &v);
+        if (i == 0) sd = *v.sd;
+        BatchTree& bt = h_trees[i];
+        bt.map = *v.map;
+        bt.td = *v.td;
+        bt.rv = v.sd->rv;
+        bt.rv2 = v.sd->rv2;
+        bt.gain = v.scratch_gain;
+        bt.yaw = v.scratch_yaw;
+        bt.depth = nullptr;
+        for (int32_t j = (*r->level_ptr)[r->level]; j < (*r->level_ptr)[r->level + 1]; ++j)
+            h_items[k++] = ((unsigned long long)i << 32) | (uint32_t)(*r->level_nodes)[j];
+    }
+    hipError_t e = hipMemcpyAsync(d_trees, h_trees, sizeof(BatchTree) * active.size(), hipMemcpyHostToDevice, compute);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_items, h_items, sizeof(unsigned long long) * n_items, hipMemcpyHostToDevice, compute);
+    if (e == hipSuccess) e = launch_batch_level(d_trees, d_items, (int32_t)n_items, sd, compute);
+    size_t so = 0;
+    std::vector<std::pair<Request*, size_t>> finishing;
+    for (Request* r : active) {
+        if (r->level + 1 != r->levels || e != hipSuccess) continue;
+        mgb::TreeView v;
+        mgb::tree_view(r->tree, &v);
+        e = hipMemcpyAsync(h_stage + so, v.scratch_gain, sizeof(uint32_t) * r->n, hipMemcpyDeviceToHost, compute);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_stage + so + r->n, v.scratch_yaw, sizeof(int32_t) * r->n, hipMemcpyDeviceToHost,
+                               compute);
+        finishing.emplace_back(r, so);
+        so += 2 * (size_t)r->n;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(compute);
+    if (e != hipSuccess) return hip_fail(e, "server step");
+    ++steps;
+    for (auto& f : finishing) {
+        Request* r = f.first;
+        std::memcpy(r->out_gain, h_stage + f.second, sizeof(uint32_t) * r->n);
+        std::memcpy(r->out_yaw, h_stage + f.second + r->n, sizeof(int32_t) * r->n);
+        mg_tree_destroy(r->tree);
+        r->tree = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    for (Request* r : active) r->level++;
+    for (auto& f : finishing) {
+        Request* r = f.first;
+        arena.release(r->arena_off, r->bytes);
+        r->rc = MG_OK;
+        r->state = 2;
+        r->t_done = Clock::now();
+        rays_done += (double)r->n * cfg.sensor.n_az * cfg.sensor.n_el;
+        ++completed;
+        inflight.erase(std::find(inflight.begin(), inflight.end(), r));
+    }
+    if (!finishing.empty()) cv_done.notify_all();
+    return MG_OK;
+}
+
+void mg_server_s::run() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stop || !queue.empty() || !inflight.empty(); });
+            if (stop && queue.empty() && inflight.empty()) return;
+        }
+        const int rc = step();
+        if (rc != MG_OK) {
+            // a device error ends the server: every pending request fails with it
+            std::lock_guard<std::mutex> lk(mu);
+            fatal = rc;
+            fatal_msg = mg_last_error();
+            for (Request* r : inflight) { r->rc = rc; r->state = 2; r->t_done = Clock::now(); }
+            for (Request* r : queue) { r->rc = rc; r->state = 2; r->t_done = Clock::now(); }
+            inflight.clear();
+            queue.clear();
+            cv_done.notify_all();
+            return;
+        }
+    }
+}
+
+extern "C" int mg_server_create(const mg_server_config* cfg, mg_server* out) {
+    if (!out) return mgb::set_error(MG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!cfg || cfg->max_inflight < 1 || cfg->arena_bytes < 1)
+        return mgb::set_error(MG_E_INVALID, "server needs max_inflight >= 1 and arena_bytes >= 1");
+    float tab[1];
+    (void)tab;
+    int rc = mg_sensor_tables(&cfg->sensor, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (rc != MG_OK) return rc;
+    std::unique_ptr<mg_server_s> S(new (std::nothrow) mg_server_s());
+    if (!S) return mgb::set_error(MG_E_NOMEM, "host allocation failed");
+    S->cfg = *cfg;
+    hipError_t e = hipGetDevice(&S->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->compute, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&S->arena_mem, (size_t)cfg->arena_bytes);
+    if (e != hipSuccess) {
+        if (S->compute) (void)hipStreamDestroy(S->compute);
+        if (S->upload) (void)hipStreamDestroy(S->upload);
+        return hip_fail(e, "server setup");
+    }
+    S->arena.reset((size_t)cfg->arena_bytes);
+    mg_server_s* raw = S.get();
+    S->worker = std::thread([raw] { raw->run(); });
+    *out = S.release();
+    return MG_OK;
+}
+
+extern "C" int mg_server_submit(mg_server s, mg_map map, const float* pos_m, const int32_t* parent, int32_t n,
+                                uint32_t* gain, int32_t* yaw_bin, int64_t* ticket) {
+    if (!s || !ticket || !gain || !yaw_bin) return mgb::set_error(MG_E_INVALID, "server/ticket/outputs is NULL");
+    std::unique_ptr<Request> r(new (std::nothrow) Request());
+    if (!r) return mgb::set_error(MG_E_NOMEM, "host allocation failed");
+    r->host = mgb::new_host_tree();
+    if (!r->host) return mgb::set_error(MG_E_NOMEM, "host allocation failed");
+    const int rc = mgb::prepare(map, pos_m, parent, n, &s->cfg.sensor, r->host);
+    if (rc != MG_OK) return rc;
+    r->bytes = mgb::block_bytes(*r->host);
+    if (r->bytes > s->arena.size())
+        return mgb::set_error(MG_E_NOMEM, "the tree needs more device memory than the server's whole arena");
+    r->map = map;
+    r->n = n;
+    r->out_gain = gain;
+    r->out_yaw = yaw_bin;
+    r->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->fatal != MG_OK) return mgb::set_error(s->fatal, s->fatal_msg.c_str());
+    if (s->stop) return mgb::set_error(MG_E_BUSY, "server is shutting down");
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->queue.push_back(r.get());
+    s->all.emplace(r->ticket, std::move(r));
+    s->cv_work.notify_one();
+    return MG_OK;
+}
+
+static int finish_ticket(mg_server s, std::unique_lock<std::mutex>& lk, int64_t ticket, int32_t* status,
+                         double* latency_us) {
+    auto it = s->all.find(ticket);
+    Request* r = it->second.get();
+    if (latency_us) latency_us[0] = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+    const int rc = r->rc;
+    if (status) *status = rc == MG_OK ? 1 : rc;
+    s->all.erase(it);
+    (void)lk;
+    return rc;
+}
+
+extern "C" int mg_server_poll(mg_server s, int64_t ticket, int32_t* status, double* latency_us) {
+    if (!s || !status) return mgb::set_error(MG_E_INVALID, "server/status is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return mgb::set_error(MG_E_INVALID, "unknown ticket");
+    if (it->second->state != 2) {
+        *status = 0;
+        return MG_OK;
+    }
+    finish_ticket(s, lk, ticket, status, latency_us);
+    return MG_OK;
+}
+
+extern "C" int mg_server_wait(mg_server s, int64_t ticket, double* latency_us) {
+    if (!s) return mgb::set_error(MG_E_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return mgb::set_error(MG_E_INVALID, "unknown ticket");
+    Request* r = it->second.get();
+    s->cv_done.wait(lk, [&] { return r->state == 2; });
+    const int rc = finish_ticket(s, lk, ticket, nullptr, latency_us);
+    if (rc != MG_OK) return mgb::set_error(rc, "request failed");
+    return MG_OK;
+}
+
+extern "C" int mg_server_stats(mg_server s, int64_t* steps, int64_t* completed, double* rays, int32_t* in_flight,
+                               int32_t* queued) {
+    if (!s) return mgb::set_error(MG_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (steps) *steps = s->steps;
+    if (completed) *completed = s->completed;
+    if (rays) *rays = s->rays_done;
+    if (in_flight) *in_flight = (int32_t)s->inflight.size();
+    if (queued) *queued = (int32_t)s->queue.size();
+    return s->fatal;
+}
+
+extern "C" int mg_server_destroy(mg_server s) {
+    if (!s) return mgb::set_error(MG_E_INVALID, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (auto& kv : s->all)
+        if (kv.second->tree) mg_tree_destroy(kv.second->tree);
+    (void)hipStreamSynchronize(s->compute);
+    (void)hipFree(s->d_trees);
+    (void)hipFree(s->d_items);
+    (void)hipHostFree(s->h_trees);
+    (void)hipHostFree(s->h_items);
+    (void)hipHostFree(s->h_stage);
+    (void)hipFree(s->arena_mem);
+    (void)hipStreamDestroy(s->compute);
+    (void)hipStreamDestroy(s->upload);
+    delete s;
+    return MG_OK;
+}

@@ -25,7 +25,9 @@ _NAMES = {-1: "MG_E_INVALID", -2: "MG_E_NOMEM", -3: "MG_E_DEVICE", -4: "MG_E_BUS
 # Every entry point declared in include/mg.h.
 EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_tree_nodes",
            "mg_tree_buffer_pixels", "mg_tree_footprint_bytes", "mg_eval_marginal", "mg_eval_marginal_levelsync",
-           "mg_eval_marginal_batch", "mg_eval_absolute", "mg_sensor_tables", "mg_last_error")
+           "mg_eval_marginal_batch", "mg_eval_absolute", "mg_sensor_tables", "mg_last_error",
+           "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait", "mg_server_stats",
+           "mg_server_destroy")
 
 
 class MGError(RuntimeError):
@@ -37,6 +39,10 @@ class MGError(RuntimeError):
 class mg_sensor(C.Structure):
     _fields_ = [("n_az", C.c_int32), ("n_el", C.c_int32), ("fov_h_deg", C.c_float), ("fov_v_deg", C.c_float),
                 ("range_m", C.c_float), ("yaw_bins", C.c_int32), ("az_offset_deg", C.c_float)]
+
+
+class mg_server_config(C.Structure):
+    _fields_ = [("sensor", mg_sensor), ("max_inflight", C.c_int32), ("arena_bytes", C.c_int64)]
 
 
 _lib = None
@@ -64,11 +70,19 @@ def lib() -> C.CDLL:
         L.mg_eval_marginal_batch.argtypes = [P, I32, P, P, P, P]
         L.mg_eval_absolute.argtypes = [P, P, P, P]
         L.mg_sensor_tables.argtypes = [C.POINTER(mg_sensor), P, P, P, P, P, P]
+        L.mg_server_create.argtypes = [C.POINTER(mg_server_config), C.POINTER(P)]
+        L.mg_server_submit.argtypes = [P, P, P, P, I32, P, P, C.POINTER(I64)]
+        L.mg_server_poll.argtypes = [P, I64, C.POINTER(I32), C.POINTER(C.c_double)]
+        L.mg_server_wait.argtypes = [P, I64, C.POINTER(C.c_double)]
+        L.mg_server_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(I32),
+                                      C.POINTER(I32)]
+        L.mg_server_destroy.argtypes = [P]
         L.mg_last_error.argtypes = []
         L.mg_last_error.restype = C.c_char_p
         for name in ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_eval_marginal",
                      "mg_eval_marginal_levelsync", "mg_eval_marginal_batch", "mg_eval_absolute",
-                     "mg_sensor_tables"):
+                     "mg_sensor_tables", "mg_server_create", "mg_server_submit", "mg_server_poll",
+                     "mg_server_wait", "mg_server_stats", "mg_server_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -248,3 +262,63 @@ def eval_batch(trees: Sequence[Tree], depth=False, stream=None):
 def as_u32(t) -> np.ndarray:
     """Host copy of an int32 tensor holding uint32 gains."""
     return t.cpu().numpy().view(np.uint32)
+
+
+class Server:
+    """Continuous-batching request server (wraps the mg_server_* calls)."""
+
+    def __init__(self, sensor, max_inflight=16, arena_bytes=8 << 30):
+        cfg = mg_server_config(make_sensor(sensor), int(max_inflight), int(arena_bytes))
+        out = C.c_void_p()
+        _check(lib().mg_server_create(C.byref(cfg), C.byref(out)))
+        self.handle = out.value
+        self._keep = {}
+
+    def submit(self, m: Map, pos_m, parent) -> int:
+        pos = np.ascontiguousarray(pos_m, dtype=np.float32)
+        par = np.ascontiguousarray(parent, dtype=np.int32)
+        n = int(par.shape[0])
+        g = np.zeros(n, np.uint32)
+        y = np.zeros(n, np.int32)
+        t = C.c_int64()
+        _check(lib().mg_server_submit(C.c_void_p(self.handle), C.c_void_p(m.handle), _np_ptr(pos), _np_ptr(par), n,
+                                      _np_ptr(g), _np_ptr(y), C.byref(t)))
+        self._keep[t.value] = (g, y)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (gain, yaw, latency_us)."""
+        st = C.c_int32()
+        lat = C.c_double()
+        _check(lib().mg_server_poll(C.c_void_p(self.handle), C.c_int64(ticket), C.byref(st), C.byref(lat)))
+        if st.value == 0:
+            return None
+        g, y = self._keep.pop(ticket)
+        if st.value < 0:
+            raise MGError(st.value, "request failed")
+        return g, y, lat.value
+
+    def wait(self, ticket: int):
+        lat = C.c_double()
+        rc = lib().mg_server_wait(C.c_void_p(self.handle), C.c_int64(ticket), C.byref(lat))
+        g, y = self._keep.pop(ticket)
+        _check(rc)
+        return g, y, lat.value
+
+    def stats(self):
+        steps, done, q, f = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()
+        rays = C.c_double()
+        _check(lib().mg_server_stats(C.c_void_p(self.handle), C.byref(steps), C.byref(done), C.byref(rays),
+                                     C.byref(f), C.byref(q)))
+        return dict(steps=steps.value, completed=done.value, rays=rays.value, in_flight=f.value, queued=q.value)
+
+    def close(self):
+        if self.handle:
+            _check(lib().mg_server_destroy(C.c_void_p(self.handle)))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

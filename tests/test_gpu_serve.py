@@ -1,0 +1,116 @@
+"""GPU tests of the serving loop (mg_server_*): continuous batching must not
+change any result. Each request's gains and yaw windows are compared with a
+plain mg_eval_marginal of the same tree, alone and in a mix, under a small
+arena (admission waits for memory), with one request in flight at a time, and
+with invalid requests rejected without disturbing the others."""
+import numpy as np
+import pytest
+
+from paper_2609_40297_amd import workloads as W
+from tests.gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_40297_amd import mg as mgmod
+    mgmod.lib()
+    return mgmod
+
+
+@pytest.fixture(scope="module")
+def scene(mg):
+    """Two maps with different voxel sizes and six trees, one sensor geometry."""
+    import torch
+    w = W.make("batch64", n_trees=4)
+    m2, t2, _ = W.random_micro(41, dims=(40, 36, 20), n_nodes=30, max_depth=5, range_vox=1.0)
+    sen = w.sensor
+    M1 = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    M2 = mg.Map(m2.states, 0.2, (0.0, 0.0, 0.0))
+    reqs = [(M1, t.pos_m, t.parent) for t in w.trees]
+    reqs.append((M2, (t2.pos_m * np.float32(0.2)).astype(np.float32), t2.parent))
+    reqs.append((M1, w.trees[0].pos_m[:1].copy(), np.array([-1], np.int32)))
+    ref = []
+    for M, pos, par in reqs:
+        T = mg.Tree(M, pos, par, sen)
+        g, y, _ = T.eval_marginal()
+        torch.cuda.synchronize()
+        ref.append((mg.as_u32(g), y.cpu().numpy()))
+        T.close()
+    log(f"[serve] {len(reqs)} requests, nodes {[len(p) for _, _, p in reqs]}")
+    return sen, reqs, ref, (M1, M2)
+
+
+def _check(res, ref):
+    for i, ((g, y), (rg, ry)) in enumerate(zip(res, ref)):
+        assert np.array_equal(g, rg), f"gain of request {i}"
+        assert np.array_equal(y, ry), f"yaw of request {i}"
+
+
+def test_alone_and_mixed_are_identical(mg, scene):
+    sen, reqs, ref, _ = scene
+    S = mg.Server(sen, max_inflight=8, arena_bytes=4 << 30)
+    alone = []
+    for M, pos, par in reqs:
+        t = S.submit(M, pos, par)
+        g, y, lat = S.wait(t)
+        alone.append((g, y))
+    _check(alone, ref)
+    tickets = [S.submit(M, pos, par) for M, pos, par in reqs]
+    mixed = [S.wait(t)[:2] for t in tickets]
+    _check(mixed, ref)
+    st = S.stats()
+    assert st["completed"] == 2 * len(reqs) and st["in_flight"] == 0 and st["queued"] == 0
+    S.close()
+
+
+def test_small_arena_and_single_slot(mg, scene):
+    sen, reqs, ref, _ = scene
+    # room for roughly the largest tree only: admission must wait for memory
+    import math
+    biggest = max(len(p) for _, _, p in reqs)
+    per_node = sen.n_az * sen.n_el * 4 + 2 * sen.yaw_bins * 4 + 64
+    S = mg.Server(sen, max_inflight=8, arena_bytes=int(biggest * per_node * 1.3) + (1 << 20))
+    tickets = [S.submit(M, pos, par) for M, pos, par in reqs]
+    _check([S.wait(t)[:2] for t in tickets], ref)
+    S.close()
+    S1 = mg.Server(sen, max_inflight=1, arena_bytes=2 << 30)
+    tickets = [S1.submit(M, pos, par) for M, pos, par in reqs]
+    got = []
+    for t in tickets:
+        while True:
+            r = S1.poll(t)
+            if r is not None:
+                got.append(r[:2])
+                break
+    _check(got, ref)
+    S1.close()
+
+
+def test_bad_requests_do_not_disturb_others(mg, scene):
+    sen, reqs, ref, (M1, _) = scene
+    S = mg.Server(sen, max_inflight=4, arena_bytes=1 << 30)
+    tickets = []
+    for i, (M, pos, par) in enumerate(reqs):
+        tickets.append(S.submit(M, pos, par))
+        if i == 1:
+            bad = par.copy()
+            bad[-1] = len(bad) + 3                  # parent after the child
+            with pytest.raises(mg.MGError) as e:
+                S.submit(M, pos, bad)
+            assert e.value.code == mg.MG_E_INVALID
+            outside = pos.copy()
+            outside[0, 0] = -5.0
+            with pytest.raises(mg.MGError):
+                S.submit(M, outside, par)
+    tiny = mg.Server(sen, max_inflight=2, arena_bytes=4096)
+    with pytest.raises(mg.MGError) as e:
+        tiny.submit(M1, reqs[0][1], reqs[0][2])
+    assert e.value.code == mg.MG_E_NOMEM
+    tiny.close()
+    _check([S.wait(t)[:2] for t in tickets], ref)
+    S.close()
