@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="step", choices=["tiny", "step", "batch64", "large"])
+    ap.add_argument("--workload", default="step", choices=["tiny", "step", "batch64", "large", "serve16"])
+    ap.add_argument("--requests", type=int, default=64, help="serve16: number of replanning requests")
     ap.add_argument("--trees", type=int, default=None, help="keep only the first trees of a multi-tree workload")
     ap.add_argument("--modes", default="plain,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -81,12 +82,120 @@ def cpu_baseline(w, target_rays):
                       f"{rays} rays, {dt:.1f} s on one thread"}
 
 
+def serve_bench(args):
+    """16 robots, Poisson replanning requests at 20 Hz (seeded), replayed in real time.
+
+    plain-FIFO: one request at a time in arrival order, paper-style per-level
+    synchronisation; served: the continuous-batching server (16 slots). Latency
+    is arrival to results in host memory. Saturated throughput: all requests
+    submitted at once.
+    """
+    import torch
+    from paper_2609_40297_amd import mg, workloads as W
+
+    torch.cuda.set_device(0)
+    mg.lib()
+    reqs = W.serve_requests(args.requests)
+    robots = sorted({r for _, r, _, _, _ in reqs})
+    log(f"[bench] serve16: generating {len(robots)} robot maps and {len(reqs)} request trees")
+    maps, trajs = {}, {}
+    for r in robots:
+        maps[r], trajs[r] = W.make_robot(r)
+    sen = W.Sensor(**W.SENSOR_STEP)
+    trees = [W.make_rrt(seed, maps[r], trajs[r][-1], n, d) for _, r, seed, n, d in reqs]
+    arrivals = np.array([a for a, _, _, _, _ in reqs]) - reqs[0][0]
+    rays = [t.n * sen.rays for t in trees]
+    dev_maps = {r: mg.Map(maps[r].states, maps[r].voxel_m, maps[r].origin_m) for r in robots}
+    robot_of = [r for _, r, _, _, _ in reqs]
+    log(f"[bench] {sum(t.n for t in trees)} nodes, {sum(rays)} rays")
+
+    # plain FIFO, real-time arrivals
+    def plain_one(i):
+        T = mg.Tree(dev_maps[robot_of[i]], trees[i].pos_m, trees[i].parent, sen)
+        hg = np.zeros(T.n, np.uint32)
+        hy = np.zeros(T.n, np.int32)
+        mg.mg_eval_marginal_levelsync(T.handle, hg, hy, None, None, None)
+        T.close()
+        return hg, hy
+
+    for i in range(min(2, len(trees))):
+        plain_one(i)
+    torch.cuda.synchronize()
+    lat_plain, res_plain = [], []
+    t0 = time.perf_counter()
+    for i in range(len(trees)):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        res_plain.append(plain_one(i))
+        lat_plain.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
+    # served, real-time arrivals
+    S = mg.Server(sen, max_inflight=16, arena_bytes=16 << 30)
+    for i in range(min(2, len(trees))):
+        S.wait(S.submit(dev_maps[robot_of[i]], trees[i].pos_m, trees[i].parent))
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(len(trees)):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        tickets.append(S.submit(dev_maps[robot_of[i]], trees[i].pos_m, trees[i].parent))
+    served = [S.wait(t) for t in tickets]
+    lat_served = [x[2] / 1e3 for x in served]
+    for (g, y, _), (pg, py) in zip(served, res_plain):
+        assert np.array_equal(g, pg) and np.array_equal(y, py), "served and plain results differ"
+    # saturated throughput: everything submitted at once
+    t0 = time.perf_counter()
+    tickets = [S.submit(dev_maps[robot_of[i]], trees[i].pos_m, trees[i].parent) for i in range(len(trees))]
+    for t in tickets:
+        S.wait(t)
+    sat_served = time.perf_counter() - t0
+    S.close()
+    t0 = time.perf_counter()
+    for i in range(len(trees)):
+        plain_one(i)
+    sat_plain = time.perf_counter() - t0
+    total_rays = float(sum(rays))
+    res = {
+        "plain": {"p50_ms": float(np.percentile(lat_plain, 50)), "p99_ms": float(np.percentile(lat_plain, 99)),
+                  "saturated_rays_per_s": total_rays / sat_plain},
+        "served": {"p50_ms": float(np.percentile(lat_served, 50)), "p99_ms": float(np.percentile(lat_served, 99)),
+                   "saturated_rays_per_s": total_rays / sat_served},
+    }
+    log(f"[bench] serve16: {res}")
+    line = {
+        "metric": "marginal-gain rays/s + replan p50/p99 ms, batched vs plain, 1xMI355X",
+        "value": res["served"]["saturated_rays_per_s"],
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": len(trees),
+        "warmup": 2,
+        "ms_per_step": sat_served * 1e3 / len(trees),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serve16: {W.WORKLOADS['serve16']}", "requests": len(trees),
+                   "nodes": int(sum(t.n for t in trees)), "rays": int(total_rays), "mode": "served",
+                   "offered_rate_hz": 20.0},
+        "p50_ms": res["served"]["p50_ms"],
+        "p99_ms": res["served"]["p99_ms"],
+        "modes": res,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    for m in dev_maps.values():
+        m.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         log("bench.py: only --gpus 1 is supported (single-GPU build)")
         sys.exit(2)
+    if args.workload == "serve16":
+        return serve_bench(args)
     import torch
     from paper_2609_40297_amd import mg, workloads as W
 
