@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--modes", default="plain,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this size (calibrates HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -58,6 +60,43 @@ def work_counts(name):
         return None
     with open(p) as f:
         return json.load(f).get(name)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_multi_step_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_40297_amd", "csrc", "mg_kernels.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per trace launch from the committed counter summary, or None.
+
+    The summary records the SHA-256 of the kernel source it was taken with;
+    when the source has changed since, the figure no longer applies."""
+    if workload != "step" or not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    import hashlib
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for ln in f:
+            if ln.startswith("- ") and ":" in ln:
+                k, v = ln[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    with open(KERNEL_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha or "hbm_bytes_per_launch" not in vals:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
+def copy_probe(mib):
+    """A plain copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 3}), flush=True)
 
 
 def cpu_baseline(w, target_rays):
@@ -194,6 +233,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         log("bench.py: only --gpus 1 is supported (single-GPU build)")
         sys.exit(2)
+    if args.copy_probe_mib:
+        return copy_probe(args.copy_probe_mib)
     if args.workload == "serve16":
         return serve_bench(args)
     import torch
@@ -238,6 +279,7 @@ def main():
         kernel_ms.append(ev0.elapsed_time(ev1))
 
     results = {}
+    trace = None
     for mode in args.modes.split(","):
         fn = {"plain": step_plain, "batched": step_batched}[mode]
         for _ in range(args.warmup):
@@ -245,6 +287,9 @@ def main():
         torch.cuda.synchronize()
         kernel_ms.clear()
         lat = []
+        if mode == "batched":     # trace-kernel launches timed by events their own dispatches record
+            mg.mg_timing_read()
+            mg.mg_timing_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -253,6 +298,10 @@ def main():
             lat.append((time.perf_counter() - s0) * 1e3)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
+        if mode == "batched":
+            t_ms, t_n, t_wg = mg.mg_timing_read()
+            mg.mg_timing_enable(False)
+            trace = dict(total_ms=t_ms, launches=t_n, workgroups=t_wg)
         results[mode] = dict(rays_per_s=rays_per_step * args.steps / total, ms_per_step=total * 1e3 / args.steps,
                              p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                              kernel_ms=float(np.mean(kernel_ms)) if kernel_ms else None)
@@ -270,13 +319,19 @@ def main():
     R = results[main_mode]
     roof = None
     wc = work_counts(args.workload if args.trees is None else f"{args.workload}:{args.trees}")
-    if wc is not None and R.get("kernel_ms"):
-        alg_bytes = wc["visits"] * 1 + wc["anc_tests"] * 4 + wc["rays"] * 4
-        achieved = alg_bytes / (R["kernel_ms"] * 1e-3) / 1e9
+    if wc is not None and trace and trace["launches"]:
+        # algorithmic bytes of the trace kernel: 1 B per voxel visit (grid gather), 4 B per ancestor
+        # depth read, 4 B per ray (first-hit write), 2 x B x 4 B of bin counts per node
+        alg_step = wc["visits"] * 1 + wc["anc_tests"] * 4 + wc["rays"] * 4 + n_total * 2 * sen.yaw_bins * 4
+        launches_per_step = trace["launches"] / args.steps
+        avg_ms = trace["total_ms"] / trace["launches"]
+        alg_launch = alg_step / launches_per_step
+        achieved = alg_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "mg_eval_marginal_batch (trace + window kernels)",
-                "algorithmic_bytes_per_step": alg_bytes}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                "kernel": "k_trace_multi", "avg_launch_ms": avg_ms, "launches_per_step": launches_per_step,
+                "algorithmic_bytes_per_launch": alg_launch,
+                "kernel_share_of_step": trace["total_ms"] / args.steps / R["ms_per_step"]}
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, one thread, bounded sample)")

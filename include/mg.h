@@ -180,6 +180,21 @@ int mg_server_stats(mg_server server, int64_t* steps, int64_t* completed, double
 /* Finishes every queued and in-flight request, stops the worker, frees the arena. */
 int mg_server_destroy(mg_server server);
 
+/* ---------------------------------------------------------------- timing
+ * Measurement of the dominant kernel (the trace kernel of
+ * mg_eval_marginal_batch). While enabled (on != 0), every trace launch that
+ * mg_eval_marginal_batch makes on the current device carries a pair of HIP
+ * events recorded by the kernel dispatch itself, so the interval is the
+ * kernel's own execution. Enabling binds the timer to the current device;
+ * MG_E_BUSY if unread launches of another device remain. Process-wide. */
+int mg_timing_enable(int32_t on);
+
+/* Waits for the timed launches since the last read, returns the sum of their
+ * durations (ms), their number and the workgroups they ran (any pointer may be
+ * NULL), and resets the sums. At most 65536 launches may be timed between two
+ * reads (MG_E_BUSY from the launch call beyond that). */
+int mg_timing_read(double* total_ms, int64_t* launches, int64_t* workgroups);
+
 /* Host-only diagnostics: the sensor tables the library builds (no device
  * work). dir and inv [n_az*n_el][3] (ray r = c*n_el + j), bv [n_az][2]
  * (column left-boundary unit vectors), ts [n_el+1] (tan(e)|tan(e)| at row

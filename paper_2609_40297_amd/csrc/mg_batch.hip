@@ -119,13 +119,59 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
     return MG_OK;
 }
 
+// Optional per-launch timing of the trace kernel: each timed launch carries a
+// start/stop event pair that its own dispatch records.
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    int device = -1;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    int64_t units = 0;                     // workgroups (node tiles) launched while timed
+};
+Timing g_timing;
+constexpr size_t kMaxTimedLaunches = 1u << 16;
+
+// Next event pair for a timed launch on `device`, or {null, null} when timing is off.
+int next_events(int device, hipEvent_t* t0, hipEvent_t* t1) {
+    *t0 = *t1 = nullptr;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (!g_timing.on) return MG_OK;
+    if (g_timing.device != device)
+        return mgb::set_error(MG_E_INVALID, "kernel timing was enabled on another device");
+    if (g_timing.used == kMaxTimedLaunches)
+        return mgb::set_error(MG_E_BUSY, "too many timed launches since the last mg_timing_read");
+    if (g_timing.used == g_timing.ev.size()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            if (a) (void)hipEventDestroy(a);
+            return hip_fail(e, "timing event");
+        }
+        g_timing.ev.emplace_back(a, b);
+    }
+    *t0 = g_timing.ev[g_timing.used].first;
+    *t1 = g_timing.ev[g_timing.used].second;
+    ++g_timing.used;
+    return MG_OK;
+}
+
 int run_plan(const Plan& P, hipStream_t s) {
     hipError_t e = launch_batch_zero(P.dtrees, (int32_t)P.trees.size(), P.max_nodes, P.sd, s);
     if (e != hipSuccess) return hip_fail(e, "batch zero");
     for (size_t d = 0; d + 1 < P.level_ptr.size(); ++d) {
         const int32_t b = P.level_ptr[d], n = P.level_ptr[d + 1] - b;
-        e = launch_batch_level(P.dtrees, P.ditems + b, n, P.sd, s);
+        if (n <= 0) continue;
+        hipEvent_t t0, t1;
+        int rc = next_events(P.device, &t0, &t1);
+        if (rc != MG_OK) return rc;
+        e = launch_batch_level(P.dtrees, P.ditems + b, n, P.sd, s, t0, t1);
         if (e != hipSuccess) return hip_fail(e, "batch level");
+        if (t0) {
+            std::lock_guard<std::mutex> lk(g_timing.mu);
+            g_timing.units += (int64_t)n * P.sd.T;
+        }
     }
     return MG_OK;
 }
@@ -178,4 +224,44 @@ extern "C" int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, voi
     const Plan& P = *it->second;
     if (P.device != dev) return mgb::set_error(MG_E_INVALID, "batch trees live on another device");
     return run_plan(P, s);
+}
+
+extern "C" int mg_timing_enable(int32_t on) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (on && g_timing.device != dev) {
+        if (g_timing.used != 0) return mgb::set_error(MG_E_BUSY, "timed launches on another device are unread");
+        for (auto& p : g_timing.ev) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+        g_timing.ev.clear();
+        g_timing.device = dev;
+    }
+    g_timing.on = on != 0;
+    return MG_OK;
+}
+
+extern "C" int mg_timing_read(double* total_ms, int64_t* launches, int64_t* workgroups) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    double sum = 0.0;
+    for (size_t i = 0; i < g_timing.used; ++i) {
+        hipError_t e = hipEventSynchronize(g_timing.ev[i].second);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_timing.ev[i].first, g_timing.ev[i].second);
+        if (e != hipSuccess) {
+            g_timing.used = 0;
+            g_timing.units = 0;
+            return hip_fail(e, "timing readout");
+        }
+        sum += ms;
+    }
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = (int64_t)g_timing.used;
+    if (workgroups) *workgroups = g_timing.units;
+    g_timing.used = 0;
+    g_timing.units = 0;
+    return MG_OK;
 }

@@ -83,7 +83,8 @@ hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth
 size_t trace_lds_bytes(const SensorDev& sd);
 hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const SensorDev& sd,
                              hipStream_t s);
+// t0/t1 (may be null): events the trace kernel's dispatch itself records at its start and end.
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                              const SensorDev& sd, hipStream_t s);
+                              const SensorDev& sd, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 }  // namespace mgk

@@ -8,6 +8,8 @@
 // exact boundary tests, so it never changes a result.
 #pragma clang fp contract(off)
 
+#include <hip/hip_ext.h>
+
 #include "mg_internal.h"
 
 namespace mgk {
@@ -541,10 +543,14 @@ hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t m
 }
 
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                              const SensorDev& sd, hipStream_t s) {
+                              const SensorDev& sd, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_trace_multi, dim3((unsigned)n_items * (unsigned)sd.T), dim3(kThreads), trace_lds_bytes(sd), s,
-                       trees, items, sd);
+    const dim3 grid((unsigned)n_items * (unsigned)sd.T);
+    if (t0 && t1)
+        hipExtLaunchKernelGGL(k_trace_multi, grid, dim3(kThreads), (uint32_t)trace_lds_bytes(sd), s, t0, t1, 0u,
+                              trees, items, sd);
+    else
+        hipLaunchKernelGGL(k_trace_multi, grid, dim3(kThreads), trace_lds_bytes(sd), s, trees, items, sd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finish_multi, dim3((unsigned)n_items), dim3(kThreads), 0, s, trees, items, sd);

@@ -27,7 +27,7 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_tree_buffer_pixels", "mg_tree_footprint_bytes", "mg_eval_marginal", "mg_eval_marginal_levelsync",
            "mg_eval_marginal_batch", "mg_eval_absolute", "mg_sensor_tables", "mg_last_error",
            "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait", "mg_server_stats",
-           "mg_server_destroy")
+           "mg_server_destroy", "mg_timing_enable", "mg_timing_read")
 
 
 class MGError(RuntimeError):
@@ -77,12 +77,15 @@ def lib() -> C.CDLL:
         L.mg_server_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(I32),
                                       C.POINTER(I32)]
         L.mg_server_destroy.argtypes = [P]
+        L.mg_timing_enable.argtypes = [I32]
+        L.mg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(I64), C.POINTER(I64)]
         L.mg_last_error.argtypes = []
         L.mg_last_error.restype = C.c_char_p
         for name in ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_eval_marginal",
                      "mg_eval_marginal_levelsync", "mg_eval_marginal_batch", "mg_eval_absolute",
                      "mg_sensor_tables", "mg_server_create", "mg_server_submit", "mg_server_poll",
-                     "mg_server_wait", "mg_server_stats", "mg_server_destroy"):
+                     "mg_server_wait", "mg_server_stats", "mg_server_destroy", "mg_timing_enable",
+                     "mg_timing_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -170,6 +173,17 @@ def mg_eval_marginal_batch(trees: Sequence[int], gain, yaw_bin, depth=None, stre
 
 def mg_eval_absolute(tree: int, gain, yaw_bin, stream=None):
     _check(lib().mg_eval_absolute(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin)))
+
+
+def mg_timing_enable(on: bool):
+    _check(lib().mg_timing_enable(1 if on else 0))
+
+
+def mg_timing_read():
+    """(summed trace-kernel ms, timed launches, workgroups) since the last read."""
+    ms, n, wg = C.c_double(), C.c_int64(), C.c_int64()
+    _check(lib().mg_timing_read(C.byref(ms), C.byref(n), C.byref(wg)))
+    return ms.value, n.value, wg.value
 
 
 def mg_sensor_tables(sensor):

@@ -114,3 +114,31 @@ def test_batch_rejects_mixed_geometry(mg):
     a.close()
     b.close()
     M.close()
+
+
+def test_kernel_timing_counts_trace_launches_and_keeps_results(mg):
+    """Timed launches (events carried by the dispatch) give the same results and one interval per level."""
+    import torch
+    w = W.make("tiny")
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    T = mg.Tree(M, w.trees[0].pos_m, w.trees[0].parent, w.sensor)
+    ref = _per_tree(mg, [T])
+    levels = int(w.trees[0].depth().max()) + 1
+    mg.mg_timing_read()
+    mg.mg_timing_enable(True)
+    try:
+        for _ in range(2):
+            _check_batch(mg, [T], ref)
+        ms, n, wg = mg.mg_timing_read()
+    finally:
+        mg.mg_timing_enable(False)
+    sen = w.sensor
+    tiles = -(-sen.n_az * sen.n_el // 256)
+    assert n == 2 * levels
+    assert wg == 2 * T.n * tiles
+    assert ms > 0.0
+    assert mg.mg_timing_read() == (0.0, 0, 0)
+    _check_batch(mg, [T], ref)                       # timing off again: no intervals recorded
+    assert mg.mg_timing_read()[1] == 0
+    T.close()
+    M.close()
