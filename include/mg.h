@@ -72,7 +72,10 @@ typedef struct {
  *           into its device layout before returning; the caller may free it
  *           on return.
  *   origin_m: world position of the grid's minimum corner.
- * Sizes: 1 <= nx, ny, nz <= 8192 and nx*ny*nz < 2^32. */
+ * Sizes: 1 <= nx, ny, nz <= 8192 and nx*ny*nz < 2^32. The device copy is
+ * padded per axis to a power of two of 8-voxel bricks holding at least n + 1
+ * voxels (at most 8x the grid, e.g. 256 MiB for 512 x 512 x 128);
+ * MG_E_UNSUPPORTED when that exceeds 2^32 - 256 bytes. */
 int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
                   const float origin_m[3], void* hip_stream, mg_map* out);
 

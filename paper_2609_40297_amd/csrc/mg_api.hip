@@ -347,9 +347,16 @@ extern "C" int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int3
         if (!std::isfinite(origin_m[a])) return fail(MG_E_INVALID, "origin must be finite");
     const size_t nvox = (size_t)nx * ny * nz;
     if (nvox >= (1ull << 32)) return fail(MG_E_INVALID, "grid has 2^32 voxels or more");
-    const int32_t nbx = (nx + 7) / 8, nby = (ny + 7) / 8, nbz = (nz + 7) / 8;
+    // power-of-two brick counts holding at least n + 1 voxels per axis
+    auto bricks_for = [](int32_t n) {
+        int32_t nb = 1;
+        while (nb * 8 < n + 1) nb *= 2;
+        return nb;
+    };
+    const int32_t nbx = bricks_for(nx), nby = bricks_for(ny), nbz = bricks_for(nz);
     const size_t padded = (size_t)nbx * nby * nbz * 512u;
-    if (padded >= (1ull << 32)) return fail(MG_E_UNSUPPORTED, "bricked grid exceeds 2^32 bytes");
+    if (padded > (1ull << 32) - 256)
+        return fail(MG_E_UNSUPPORTED, "bricked grid (%d x %d x %d bricks) exceeds 2^32 - 256 bytes", nbx, nby, nbz);
     for (size_t i = 0; i < nvox; ++i)
         if (states[i] > 2) return fail(MG_E_INVALID, "voxel %zu has state %u (expected 0, 1 or 2)", i, states[i]);
 
@@ -364,6 +371,13 @@ extern "C" int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int3
     m->dev.bricks = m->bricks;
     m->dev.nx = nx; m->dev.ny = ny; m->dev.nz = nz;
     m->dev.nbx = nbx; m->dev.nby = nby; m->dev.nbz = nbz;
+    auto log2i = [](int32_t v) { uint32_t l = 0; while ((1 << l) < v) ++l; return l; };
+    m->dev.xm = (uint32_t)(8 * nbx - 1) & ~7u;
+    m->dev.ym = (uint32_t)(8 * nby - 1) & ~7u;
+    m->dev.zm = (uint32_t)(8 * nbz - 1) & ~7u;
+    m->dev.shy = 6u + log2i(nbx);
+    m->dev.shz = 6u + log2i(nbx) + log2i(nby);
+    m->dev.outside = voxel_addr(8 * nbx - 1, 0, 0, m->dev);
     if (e == hipSuccess) e = launch_brick(dense, m->bricks, m->dev, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dense);

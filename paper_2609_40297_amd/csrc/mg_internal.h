@@ -12,16 +12,33 @@ constexpr int kMaxBins = 256;      // yaw bins
 constexpr int kMaxAz = 4096;       // panorama columns (LDS holds their boundaries)
 constexpr int kMaxEl = 2048;
 
-enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2 };
+// kOutside marks the padding around the grid: a traversal that reaches it
+// has left the grid.
+enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3 };
 
 // Occupancy grid in 8x8x8-voxel bricks (512 B each, x fastest inside a
 // brick, bricks x fastest): a ray stays inside one brick for several steps,
-// so its gathers hit few cache lines.
+// so its gathers hit few cache lines. Brick counts are powers of two with at
+// least one padding voxel past the grid on every axis, so a voxel's byte
+// address is a bit-field merge of its coordinates; coordinate -1 wraps to the
+// last padding voxel of its axis, which holds kOutside like all padding.
 struct MapDev {
     const uint8_t* bricks;
     int32_t nx, ny, nz;     // true extent in voxels
-    int32_t nbx, nby, nbz;  // bricks per axis
+    int32_t nbx, nby, nbz;  // bricks per axis (powers of two, 8 * nb > n)
+    uint32_t xm, ym, zm;    // brick-index bits of a coordinate: (8 * nb - 1) & ~7
+    uint32_t shy, shz;      // left shifts placing (y & ym) and (z & zm) in the address
+    uint32_t outside;       // address of a padding byte (kOutside)
 };
+
+// Byte address of voxel (x, y, z) in the bricked grid, for -1 <= x <= nx
+// (likewise y, z): bits 0-8 are the position inside the brick, then the brick
+// index x-fastest.
+__host__ __device__ inline uint32_t voxel_addr(int32_t x, int32_t y, int32_t z, const MapDev& M) {
+    const uint32_t ux = (uint32_t)x, uy = (uint32_t)y, uz = (uint32_t)z;
+    return (ux & 7u) | ((uy & 7u) << 3) | ((uz & 7u) << 6) | ((ux & M.xm) << 6) | ((uy & M.ym) << M.shy) |
+           ((uz & M.zm) << M.shz);
+}
 
 // Panorama ray tables and yaw-window geometry (built on the host, see mg_api).
 struct SensorDev {

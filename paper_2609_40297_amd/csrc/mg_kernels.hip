@@ -3,9 +3,9 @@
 // Exactness: every decision (which voxels a ray visits, whether an ancestor
 // sees a voxel, which window wins) is taken in IEEE binary32 with the
 // operation order of the definitions below and without contraction into
-// fused multiply-adds. Approximate arithmetic (rcp, sqrt, a polynomial atan)
-// appears only in *estimates* of a pixel index that are then corrected by the
-// exact boundary tests, so it never changes a result.
+// fused multiply-adds. Approximate arithmetic (hardware reciprocal and
+// reciprocal square root) appears only in *estimates* of a pixel index that
+// are then corrected by the exact boundary tests, so it never changes a result.
 #pragma clang fp contract(off)
 
 #include <hip/hip_ext.h>
@@ -14,10 +14,20 @@
 
 namespace mgk {
 
+// Global-memory views of pointers that reach a kernel through a descriptor in
+// memory: the compiler then issues global (not flat) loads for them.
+typedef const __attribute__((address_space(1))) uint8_t* gbytes_t;
+typedef const __attribute__((address_space(1))) float* gfloats_t;
+__device__ __forceinline__ gbytes_t as_global(const uint8_t* p) { return (gbytes_t)p; }
+__device__ __forceinline__ gfloats_t as_global(const float* p) { return (gfloats_t)p; }
+
+// Wave ballot of a boolean (no widening of the predicate to an integer).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 // ---------------------------------------------------------------- map layout
 
 // Dense [nz][ny][nx] -> bricks; padding voxels (beyond the true extent) are
-// never read by a traversal and are set to "occupied".
+// set to kOutside, which ends a traversal that reaches them.
 __global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__ bricks, MapDev m) {
     const uint32_t total = (uint32_t)m.nbx * m.nby * m.nbz * 512u;
     for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < total; o += gridDim.x * blockDim.x) {
@@ -27,7 +37,7 @@ __global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__
         int32_t bz = (int32_t)(b / ((uint32_t)m.nbx * (uint32_t)m.nby));
         int32_t x = bx * 8 + (int32_t)(in & 7u), y = by * 8 + (int32_t)((in >> 3) & 7u),
                 z = bz * 8 + (int32_t)(in >> 6);
-        uint8_t v = kOccupied;
+        uint8_t v = kOutside;
         if (x < m.nx && y < m.ny && z < m.nz)
             v = dense[(size_t)x + (size_t)m.nx * ((size_t)y + (size_t)m.ny * (size_t)z)];
         bricks[o] = v;
@@ -94,7 +104,7 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     const int32_t cv = c_up ? col + 1 : col;          // the boundary that is still unchecked
     const bool cv_ok = c_up ? (cv >= S.WB || !left_of(s_bv[wrap(A.c0 + min(cv, S.WB - 1), S.W)], rx, ry))
                             : (cv == 0 || left_of(s_bv[wrap(A.c0 + cv, S.W)], rx, ry));
-    if (__ballot(!cv_ok)) {
+    if (ballot(!cv_ok)) {
         if (!cv_ok) {
             for (;;) {
                 if (col + 1 >= S.WB || !left_of(s_bv[wrap(A.c0 + col + 1, S.W)], rx, ry)) break;
@@ -116,7 +126,7 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     const int32_t rv_ = r_up ? row + 1 : row;
     const bool rv_ok = r_up ? (rv_ >= S.H || !(sz >= rho2 * s_ts[min(rv_, S.H)]))
                             : (rv_ == 0 || sz >= rho2 * s_ts[rv_]);
-    if (__ballot(!rv_ok)) {
+    if (ballot(!rv_ok)) {
         if (!rv_ok) {
             for (;;) {
                 if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
@@ -128,7 +138,7 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
             }
         }
     }
-    const float D = dpan[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
+    const float D = as_global(dpan)[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
     return range2 <= D * D;
 }
 
@@ -136,30 +146,37 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
 
 constexpr int kQCap = 512;   // queued unknown voxels per wave
 
+
 __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ uint32_t brick_addr(int32_t x, int32_t y, int32_t z, const MapDev& M) {
-    // brick counts and indices are < 2^24: masking lets the compiler use 24-bit multiply-adds
-    const uint32_t bzy = ((uint32_t)M.nby & 0xffffffu) * (((uint32_t)z >> 3) & 0xffffffu) + ((uint32_t)y >> 3);
-    const uint32_t bi = ((uint32_t)M.nbx & 0xffffffu) * (bzy & 0xffffffu) + ((uint32_t)x >> 3);
-    return (bi << 9) | ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
-}
+// Queue entry: .x = x | y << 16, .y = z | bin << 16 | (m - 1) << 24, where m
+// (1..64) is the number of ray incidences the entry stands for: neighbouring
+// lanes that reach the same unknown voxel in the same step, with the same bin,
+// share one entry (the ancestor test depends on the voxel alone).
+__device__ __forceinline__ uint32_t entry_bin(uint32_t ey) { return (ey >> 16) & 0xffu; }
 
-// Counts the queued voxels per bin (a queue entry carries its ray's bin).
+// Adds the incidences of the queued entries to their bins: per distinct bin,
+// the sum of the entries' multiplicities is assembled from ballots bit by bit.
 __device__ __forceinline__ void count_by_bin(const uint2* __restrict__ q, int32_t n, uint32_t* __restrict__ bins,
                                              int32_t lane) {
     for (int32_t base = 0; base < n; base += 64) {
         const int32_t i = base + lane;
         bool pending = i < n;
-        const uint32_t bin = pending ? (q[i].y >> 16) : 0u;
-        uint64_t left = __ballot(pending);
+        const uint32_t ey = pending ? q[i].y : 0u;
+        const uint32_t bin = entry_bin(ey);
+        const uint32_t extra = ey >> 24;      // multiplicity - 1, 6 bits
+        uint64_t left = ballot(pending);
         while (left) {
             const int32_t leader = __builtin_ctzll(left);
             const uint32_t b = __shfl(bin, leader, 64);
-            const uint64_t same = __ballot(pending && bin == b);
-            if (lane == leader) atomicAdd(&bins[b], (uint32_t)__popcll(same));
+            const bool mine = pending && bin == b;
+            const uint64_t same = ballot(mine);
+            uint32_t sum = (uint32_t)__popcll(same);
+#pragma unroll
+            for (int32_t k = 0; k < 6; ++k) sum += (uint32_t)__popcll(ballot(mine && ((extra >> k) & 1u))) << k;
+            if (lane == leader) atomicAdd(&bins[b], sum);
             pending = pending && bin != b;
             left &= ~same;
         }
@@ -191,7 +208,7 @@ __device__ __forceinline__ void drain_queue(uint2* __restrict__ q, int32_t n, co
                 const float cz = (float)(int32_t)(e.y & 0xffffu) + 0.5f;
                 keep = !ancestor_sees(A, cx, cy, cz, S, s_bv, s_ts, ts0, tsH, s_lut_col, s_lut_row, dpan);
             }
-            const uint64_t bal = __ballot(keep);
+            const uint64_t bal = ballot(keep);
             if (keep) q[m + (int32_t)lane_prefix(bal)] = e;
             m += __popcll(bal);
         }
@@ -275,57 +292,92 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     const bool has_ray = r < S.R;
     const int32_t rr = has_ray ? r : 0;
     const int32_t bin = S.bin_of_col[rr / S.H];
+    // lanes whose previous lane has the same bin (DPP wave shift right by one;
+    // lane 0 receives -1)
+    const bool bin_as_prev = __builtin_amdgcn_update_dpp(-1, bin, 0x138, 0xf, 0xf, false) == bin;
+    const uint64_t bin_as_prev_mask = ballot(bin_as_prev);
     const float4 p = Tr.q4[node];
     const float4 d = S.d4[rr];
     const float4 iv = S.iv4[rr];
     const int32_t sx = d.x > 0.f ? 1 : (d.x < 0.f ? -1 : 0);
     const int32_t sy = d.y > 0.f ? 1 : (d.y < 0.f ? -1 : 0);
     const int32_t sz = d.z > 0.f ? 1 : (d.z < 0.f ? -1 : 0);
-    // the face crossed when stepping is voxel + 1 for a positive direction
-    const int32_t ox = d.x > 0.f ? 1 : 0, oy = d.y > 0.f ? 1 : 0, oz = d.z > 0.f ? 1 : 0;
     int32_t ix = (int32_t)floorf(p.x), iy = (int32_t)floorf(p.y), iz = (int32_t)floorf(p.z);
-    float tx = sx ? ((float)(ix + ox) - p.x) * iv.x : __builtin_inff();
-    float ty = sy ? ((float)(iy + oy) - p.y) * iv.y : __builtin_inff();
-    float tz = sz ? ((float)(iz + oz) - p.z) * iv.z : __builtin_inff();
+    // Face-crossing parameters (b - q) / d with b the next voxel boundary,
+    // kept as floats (integers, exact): b moves by the step sign. An axis the
+    // ray does not move along has b = +inf and a factor 1, so its parameter
+    // stays +inf.
+    const float inf = __builtin_inff();
+    float bx = sx ? (float)(ix + (sx > 0 ? 1 : 0)) : inf;
+    float by = sy ? (float)(iy + (sy > 0 ? 1 : 0)) : inf;
+    float bz = sz ? (float)(iz + (sz > 0 ? 1 : 0)) : inf;
+    const float fx = sx ? iv.x : 1.f, fy = sy ? iv.y : 1.f, fz = sz ? iv.z : 1.f;
+    const float dbx = (float)sx, dby = (float)sy, dbz = (float)sz;
+    float tx = (bx - p.x) * fx;
+    float ty = (by - p.y) * fy;
+    float tz = (bz - p.z) * fz;
     float t = 0.f, h = S.rv;
     uint32_t n_abs = 0;
     const uint32_t ebin = (uint32_t)bin << 16;
-    // the node lies inside the grid and t = 0 < rv, so its own voxel is visited
-    bool alive = has_ray;
-    uint32_t st = M.bricks[alive ? brick_addr(ix, iy, iz, M) : 0u];
+    const gbytes_t grid = as_global(M.bricks);
+    // the node lies inside the grid and t = 0 < rv, so its own voxel is
+    // visited; a lane without a ray reads a padding byte and is done at once
+    uint32_t addr = has_ray ? voxel_addr(ix, iy, iz, M) : M.outside;   // address of the current voxel
+    uint32_t st = grid[addr];
     int32_t qn = 0;
-    while (__ballot(alive)) {
-        // Straight-line step: the next voxel is found and its byte requested
-        // before the current voxel is used; a finished lane keeps loading a
-        // harmless in-bounds byte instead of branching.
-        while (__ballot(alive) && (!kMarginal || qn + 64 <= kQCap)) {
+    uint64_t alive = ballot(has_ray);
+    while (alive) {
+        // Straight-line step without divergent branches: the current voxel's
+        // byte is used first, then the next voxel is found and its byte
+        // requested, so the load stays in flight until the next step uses it.
+        // A lane that has finished (or left the grid) reads a padding byte,
+        // which is neither unknown nor occupied. Every lane writes a queue
+        // slot (lanes without an entry write past the new end, into slots the
+        // next step overwrites).
+        do {
+            const bool unk = st == kUnknown;
+            const bool occ = st == kOccupied;
+            h = occ ? t : h;
+            n_abs += unk ? 1u : 0u;
+            if (kMarginal) {
+                // a lane whose unknown voxel and bin equal the previous lane's
+                // joins that lane's entry; the first lane of each run appends
+                // one entry carrying the run's length. Keys of other lanes are
+                // distinct values above every address.
+                const uint32_t key = unk ? addr : (0xffffffc0u | (uint32_t)lane);
+                const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int32_t)0xffffffbfu, (int32_t)key, 0x138,
+                                                                              0xf, 0xf, false);
+                const uint64_t dups = ballot(prev == key) & bin_as_prev_mask;
+                const uint64_t heads = ballot(unk) & ~dups;
+                const bool head = unk & !((prev == key) & bin_as_prev);
+                const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> lane) >> 1));
+                const int32_t below = (int32_t)lane_prefix(heads);
+                const int32_t npop = __popcll(heads);
+                const int32_t m = -(int32_t)head;     // all ones for a lane that appends
+                q[qn + ((below & m) | ((npop + lane - below) & ~m))] =
+                    make_uint2((uint32_t)ix | ((uint32_t)iy << 16), (uint32_t)iz | ebin | (extra << 24));
+                qn = __builtin_amdgcn_readfirstlane(qn + npop);
+            }
             const bool mx = (tx <= ty) & (tx <= tz);
             const bool my = !mx & (ty <= tz);
             const bool mz = !mx & !my;
             const float tn = mx ? tx : (my ? ty : tz);
-            const int32_t jx = ix + (mx ? sx : 0);
-            const int32_t jy = iy + (my ? sy : 0);
-            const int32_t jz = iz + (mz ? sz : 0);
-            const bool next_ok = alive & ((uint32_t)jx < (uint32_t)M.nx) & ((uint32_t)jy < (uint32_t)M.ny) &
-                                 ((uint32_t)jz < (uint32_t)M.nz) & (tn < S.rv);
-            const uint32_t st_next = M.bricks[next_ok ? brick_addr(jx, jy, jz, M) : 0u];
-            const bool unk = alive & (st == kUnknown);
-            const bool occ = alive & (st == kOccupied);
-            h = occ ? t : h;
-            n_abs += unk ? 1u : 0u;
-            if (kMarginal) {
-                const uint64_t bal = __ballot(unk);
-                if (unk) q[qn + (int32_t)lane_prefix(bal)] = make_uint2((uint32_t)ix | ((uint32_t)iy << 16), (uint32_t)iz | ebin);
-                qn += __popcll(bal);
-            }
-            tx = mx ? ((float)(jx + ox) - p.x) * iv.x : tx;
-            ty = my ? ((float)(jy + oy) - p.y) * iv.y : ty;
-            tz = mz ? ((float)(jz + oz) - p.z) * iv.z : tz;
-            ix = jx; iy = jy; iz = jz;
+            ix += mx ? sx : 0;
+            iy += my ? sy : 0;
+            iz += mz ? sz : 0;
+            const bool stepping = st < kOccupied;      // alive and not stopped here
+            const bool next_ok = stepping & (tn < S.rv);
+            addr = next_ok ? voxel_addr(ix, iy, iz, M) : M.outside;
+            st = grid[addr];
+            bx += mx ? dbx : 0.f;
+            by += my ? dby : 0.f;
+            bz += mz ? dbz : 0.f;
+            tx = (bx - p.x) * fx;
+            ty = (by - p.y) * fy;
+            tz = (bz - p.z) * fz;
             t = tn;
-            alive = next_ok & !occ;
-            st = st_next;
-        }
+            alive = ballot(next_ok);
+        } while (alive && (!kMarginal || qn + 64 <= kQCap));
         if (kMarginal) {
             drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, L.lut_col, L.lut_row, Tr.dpan, L.bins + S.B, lane);
             qn = 0;
@@ -434,7 +486,9 @@ __global__ __launch_bounds__(kThreads) void k_trace_multi(const BatchTree* __res
     SensorDev St = S;
     St.rv = BT.rv;
     St.rv2 = BT.rv2;
-    trace_tile<true>(BT.map, St, BT.td, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
+    const MapDev M = BT.map;     // copies: loaded once, not re-read through the descriptor
+    const TreeDev Tr = BT.td;
+    trace_tile<true>(M, St, Tr, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
 }
 
 // Window selection for one depth level of all trees; writes each tree's
