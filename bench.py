@@ -315,6 +315,8 @@ def main():
             assert np.array_equal(hy, host_y.numpy()[off:off + t.n]), "plain and batched differ"
             off += t.n
 
+    shape_idx, graphed = mg.mg_batch_plan_info(handles) if "batched" in results else (0, False)
+    shape = mg.mg_trace_shapes()[shape_idx]
     main_mode = "batched" if "batched" in results else "plain"
     R = results[main_mode]
     roof = None
@@ -352,7 +354,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W.WORKLOADS[args.workload]}", "trees": len(w.trees),
-                   "nodes": n_total, "rays_per_step": rays_per_step, "mode": main_mode},
+                   "nodes": n_total, "rays_per_step": rays_per_step, "mode": main_mode,
+                   "launch_shape": {"rays_per_workgroup": shape[0], "queue_per_wave": shape[1],
+                                    "chosen_by": "autotune", "graph": graphed}},
         "p50_ms": R["p50_ms"],
         "p99_ms": R["p99_ms"],
         "modes": results,

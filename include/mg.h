@@ -132,6 +132,29 @@ int mg_eval_marginal_levelsync(mg_tree tree, void* hip_stream, uint32_t* gain, i
 int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
                            int32_t* yaw_bin, float* depth);
 
+/* Launch configuration of mg_eval_marginal_batch for plans built after this
+ * call (cached plans are dropped, after the device has finished their work).
+ *   shape: -1 (default) = autotune: the first call with a tree list whose
+ *          workload shape (sensor, range, map dims, tree count, depth, node
+ *          count to a power of two) has not been seen times every compiled
+ *          launch shape of the trace kernel on that call's own trees, twice
+ *          each, keeps the fastest for that workload shape, and blocks until
+ *          done; 0 .. count-1 = that shape (mg_trace_shapes).
+ *   graph: 1 = the plan's launches are recorded once into a HIP graph and
+ *          each call replays it (on a library stream joined to hip_stream by
+ *          events before and after); 0 (default) = launched one by one.
+ * Results do not depend on either setting. MG_E_INVALID for other values. */
+int mg_batch_config(int32_t shape, int32_t graph);
+
+/* The compiled launch shapes of the trace kernel: *count, and for the first
+ * `capacity` shapes the rays per workgroup and the per-wave queue capacity
+ * (queued unknown voxels). Host only. */
+int mg_trace_shapes(int32_t* count, int32_t* threads, int32_t* queue, int32_t capacity);
+
+/* Launch shape index and whether a graph is replayed (1) for the cached plan
+ * of this tree list. MG_E_INVALID when the list has no plan yet. */
+int mg_batch_plan_info(const mg_tree* trees, int32_t n_trees, int32_t* shape, int32_t* graphed);
+
 /* Absolute gain of every node (eq. 1 maximised over the yaw windows), no
  * conditioning and no level order: one flat launch over all nodes.
  *   gain DEVICE uint32[n], yaw_bin DEVICE int32[n]. */
@@ -188,7 +211,8 @@ int mg_server_destroy(mg_server server);
  * mg_eval_marginal_batch). While enabled (on != 0), every trace launch that
  * mg_eval_marginal_batch makes on the current device carries a pair of HIP
  * events recorded by the kernel dispatch itself, so the interval is the
- * kernel's own execution. Enabling binds the timer to the current device;
+ * kernel's own execution (while enabled, batch plans are launched one by one
+ * instead of replaying their graph). Enabling binds the timer to the current device;
  * MG_E_BUSY if unread launches of another device remain. Process-wide. */
 int mg_timing_enable(int32_t on);
 

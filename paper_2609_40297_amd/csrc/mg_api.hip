@@ -640,7 +640,7 @@ int eval_levels(mg_tree t, hipStream_t s, uint32_t* gain, int32_t* yaw, float* d
     for (int32_t d = 0; d < t->levels; ++d) {
         const int32_t b = t->level_ptr[d], cnt = t->level_ptr[d + 1] - b;
         const int32_t* nodes = t->dev.level_nodes + b;
-        HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, nodes, cnt, true, s));
+        HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, nodes, cnt, true, d, s));
         HIP_TRY(launch_finish(t->sd, t->dev, nodes, cnt, true, gain, yaw, s));
         if (host_gain) {
             // results of this level back to the host before the next level (Sec. IV-C)
@@ -682,7 +682,7 @@ extern "C" int mg_eval_absolute(mg_tree t, void* hip_stream, uint32_t* gain, int
     if (rc != MG_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_TRY(launch_zero_u32(t->dev.bins, (size_t)2 * t->sd.B * t->n, s));
-    HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, t->dev.level_nodes, t->n, false, s));
+    HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, t->dev.level_nodes, t->n, false, 0, s));
     HIP_TRY(launch_finish(t->sd, t->dev, t->dev.level_nodes, t->n, false, gain, yaw_bin, s));
     return MG_OK;
 }

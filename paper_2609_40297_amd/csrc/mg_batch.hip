@@ -1,10 +1,15 @@
 // Multi-tree evaluation: all trees advance one depth level at a time; each
 // level is one trace launch over every (tree, node) of that depth followed by
-// one window-selection launch. Launch plans are cached per tree list.
+// one window-selection launch. Launch plans are cached per tree list; a new
+// plan gets its trace launch shape from the autotuner (every compiled shape
+// timed on the plan itself, the result kept per workload shape) and, when
+// configured, its launches are captured once into a HIP graph that later
+// calls replay.
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -29,10 +34,29 @@ struct Plan {
     SensorDev sd{};
     uint32_t total = 0, max_nodes = 0;
     int device = 0;
+    int shape = 0;                         // launch shape of the trace kernel
+    hipGraph_t graph = nullptr;            // the plan's launches, captured once
+    hipGraphExec_t exec = nullptr;
     ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         if (block) (void)hipFree(block);
     }
 };
+
+// Configuration for plans built from now on (mg_batch_config).
+int g_cfg_shape = -1;                      // -1: autotune
+bool g_cfg_graph = false;                  // replaying a graph measured slower than direct launches
+// Autotuned shapes per workload shape (sensor, range, map dims, sizes).
+std::map<std::vector<int64_t>, int> g_tuned;
+
+// Per-device stream that replays plan graphs, joined to the caller's stream
+// with events on both sides.
+struct Replay {
+    hipStream_t stream = nullptr;
+    hipEvent_t in = nullptr, out = nullptr;
+};
+std::map<int, Replay> g_replay;
 
 std::mutex g_mu;
 std::map<std::vector<mg_tree>, std::unique_ptr<Plan>> g_plans;
@@ -81,6 +105,8 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
     }
     P->sd = *v0.sd;
     P->device = v0.device;
+    int32_t max_tiles = 0;                 // workgroups per node of the narrowest launch shape
+    for (int k = 0; k < shape_count(); ++k) max_tiles = std::max(max_tiles, tiles_per_node(P->sd, k));
     // items grouped by global depth level, trees in order within a level
     P->level_ptr.assign(levels + 1, 0);
     std::vector<unsigned long long> items;
@@ -94,7 +120,7 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
                 items.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)ln[k]);
         }
         P->level_ptr[d + 1] = (int32_t)items.size();
-        if ((uint64_t)(P->level_ptr[d + 1] - P->level_ptr[d]) * (uint64_t)P->sd.T >= (1ull << 31))
+        if ((uint64_t)(P->level_ptr[d + 1] - P->level_ptr[d]) * (uint64_t)max_tiles >= (1ull << 31))
             return mgb::set_error(MG_E_UNSUPPORTED, "a depth level of the batch has 2^31 workgroups or more");
     }
     size_t off = 0;
@@ -157,22 +183,144 @@ int next_events(int device, hipEvent_t* t0, hipEvent_t* t1) {
     return MG_OK;
 }
 
-int run_plan(const Plan& P, hipStream_t s) {
+bool timing_on() {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    return g_timing.on;
+}
+
+// Enqueues the plan's launches on s; `timed` lets the kernel timer attach events.
+int run_plan(const Plan& P, hipStream_t s, bool timed) {
     hipError_t e = launch_batch_zero(P.dtrees, (int32_t)P.trees.size(), P.max_nodes, P.sd, s);
     if (e != hipSuccess) return hip_fail(e, "batch zero");
     for (size_t d = 0; d + 1 < P.level_ptr.size(); ++d) {
         const int32_t b = P.level_ptr[d], n = P.level_ptr[d + 1] - b;
         if (n <= 0) continue;
-        hipEvent_t t0, t1;
-        int rc = next_events(P.device, &t0, &t1);
-        if (rc != MG_OK) return rc;
-        e = launch_batch_level(P.dtrees, P.ditems + b, n, P.sd, s, t0, t1);
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (timed) {
+            int rc = next_events(P.device, &t0, &t1);
+            if (rc != MG_OK) return rc;
+        }
+        e = launch_batch_level(P.dtrees, P.ditems + b, n, P.sd, (int32_t)d, s, P.shape, t0, t1);
         if (e != hipSuccess) return hip_fail(e, "batch level");
         if (t0) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
-            g_timing.units += (int64_t)n * P.sd.T;
+            g_timing.units += (int64_t)n * tiles_per_node(P.sd, P.shape);
         }
     }
+    return MG_OK;
+}
+
+std::vector<int64_t> tune_key(const Plan& P) {
+    mgb::TreeView v;
+    mgb::tree_view(P.trees[0], &v);
+    auto bits = [](float f) { int32_t i; memcpy(&i, &f, 4); return (int64_t)i; };
+    int64_t lg = 0;
+    while ((1ull << (lg + 1)) <= P.total) ++lg;
+    return {v.params.n_az, v.params.n_el, v.params.yaw_bins, bits(v.params.fov_h_deg), bits(v.params.fov_v_deg),
+            bits(P.sd.rv), v.map->nx, v.map->ny, v.map->nz, (int64_t)P.trees.size(),
+            (int64_t)P.level_ptr.size(), lg, P.device};
+}
+
+// Times every launch shape on the plan itself (second of two runs each) and
+// keeps the fastest. Blocks on s.
+int autotune(Plan& P, hipStream_t s) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    int best = 0;
+    float best_ms = 0.f;
+    for (int k = 0; k < shape_count() && e == hipSuccess; ++k) {
+        P.shape = k;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(a, s);
+            if (e != hipSuccess) break;
+            int rc = run_plan(P, s, false);
+            if (rc != MG_OK) {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                return rc;
+            }
+            e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        }
+        if (e == hipSuccess && (k == 0 || ms < best_ms)) {
+            best = k;
+            best_ms = ms;
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    P.shape = best;
+    return MG_OK;
+}
+
+// Records the plan's launches into a graph on a private stream.
+int capture(Plan& P) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = MG_OK;
+    if (e == hipSuccess) {
+        rc = run_plan(P, cs, false);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (rc == MG_OK && e2 == hipSuccess) {
+            P.graph = g;
+            e = hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0);
+        } else {
+            if (g) (void)hipGraphDestroy(g);
+            if (rc == MG_OK) e = e2;
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != MG_OK) return rc;
+    if (e != hipSuccess) {
+        P.exec = nullptr;
+        return hip_fail(e, "graph capture");
+    }
+    return MG_OK;
+}
+
+// Replays the plan's graph ordered after the work already on s, and makes
+// later work on s wait for it.
+int replay(const Plan& P, hipStream_t s) {
+    Replay& R = g_replay[P.device];
+    hipError_t e = hipSuccess;
+    if (!R.stream) {
+        e = hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&R.in, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&R.out, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "replay stream");
+    }
+    e = hipEventRecord(R.in, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(R.stream, R.in, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(P.exec, R.stream);
+    if (e == hipSuccess) e = hipEventRecord(R.out, R.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, R.out, 0);
+    if (e != hipSuccess) return hip_fail(e, "graph replay");
+    return MG_OK;
+}
+
+// Launch shape (configured, cached or tuned now) and graph of a new plan.
+int configure(Plan& P, hipStream_t s) {
+    if (g_cfg_shape >= 0) {
+        P.shape = g_cfg_shape;
+    } else {
+        const std::vector<int64_t> key = tune_key(P);
+        auto t = g_tuned.find(key);
+        if (t != g_tuned.end()) {
+            P.shape = t->second;
+        } else {
+            int rc = autotune(P, s);
+            if (rc != MG_OK) return rc;
+            g_tuned[key] = P.shape;
+        }
+    }
+    if (g_cfg_graph) return capture(P);
     return MG_OK;
 }
 
@@ -219,11 +367,53 @@ extern "C" int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, voi
         std::unique_ptr<Plan> P;
         int rc = build_plan(key, gain, yaw_bin, depth, s, &P);
         if (rc != MG_OK) return rc;
+        if (P->device != dev) return mgb::set_error(MG_E_INVALID, "batch trees live on another device");
+        rc = configure(*P, s);
+        if (rc != MG_OK) return rc;
         it = g_plans.emplace(key, std::move(P)).first;
     }
     const Plan& P = *it->second;
     if (P.device != dev) return mgb::set_error(MG_E_INVALID, "batch trees live on another device");
-    return run_plan(P, s);
+    // the kernel timer needs the launches made one by one
+    if (!P.exec || timing_on()) return run_plan(P, s, true);
+    return replay(P, s);
+}
+
+extern "C" int mg_batch_config(int32_t shape, int32_t graph) {
+    if (shape < -1 || shape >= shape_count() || (graph != 0 && graph != 1))
+        return mgb::set_error(MG_E_INVALID, "shape must be -1 or a shape index, graph 0 or 1");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_plans.empty()) {
+        (void)hipDeviceSynchronize();          // launches of cached plans may still be queued
+        g_plans.clear();
+    }
+    g_cfg_shape = shape;
+    g_cfg_graph = graph != 0;
+    return MG_OK;
+}
+
+extern "C" int mg_trace_shapes(int32_t* count, int32_t* threads, int32_t* queue, int32_t capacity) {
+    if (!count || capacity < 0 || (capacity > 0 && (!threads || !queue)))
+        return mgb::set_error(MG_E_INVALID, "bad shape query");
+    *count = shape_count();
+    for (int k = 0; k < shape_count() && k < capacity; ++k) {
+        int th = 0, q = 0;
+        shape_of(k, &th, &q);
+        threads[k] = th;
+        queue[k] = q;
+    }
+    return MG_OK;
+}
+
+extern "C" int mg_batch_plan_info(const mg_tree* trees, int32_t n_trees, int32_t* shape, int32_t* graphed) {
+    if (!trees || n_trees < 1) return mgb::set_error(MG_E_INVALID, "bad batch arguments");
+    std::vector<mg_tree> key(trees, trees + n_trees);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) return mgb::set_error(MG_E_INVALID, "no plan for this tree list (evaluate it first)");
+    if (shape) *shape = it->second->shape;
+    if (graphed) *graphed = it->second->exec ? 1 : 0;
+    return MG_OK;
 }
 
 extern "C" int mg_timing_enable(int32_t on) {

@@ -92,16 +92,26 @@ struct BatchTree {
 // Launchers (mg_kernels.hip).
 hipError_t launch_brick(const uint8_t* dense, uint8_t* bricks, const MapDev& m, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
+// max_anc: the most ancestors any node of the launch has (the LDS holds that
+// many); every node of depth level d has exactly d.
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
-                        int32_t n_nodes, bool marginal, hipStream_t s);
+                        int32_t n_nodes, bool marginal, int32_t max_anc, hipStream_t s);
 hipError_t launch_finish(const SensorDev& sd, const TreeDev& td, const int32_t* nodes, int32_t n_nodes,
                          bool marginal, uint32_t* gain, int32_t* yaw, hipStream_t s);
 hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth, hipStream_t s);
-size_t trace_lds_bytes(const SensorDev& sd);
+// Launch shapes of the multi-tree trace kernel (shape 0 = default): rays per
+// workgroup and queue capacity per wave; LDS bytes and workgroups per node.
+int shape_count();
+void shape_of(int shape, int* threads, int* queue);
+size_t trace_lds_bytes(const SensorDev& sd, int shape, int32_t max_anc);
+int32_t tiles_per_node(const SensorDev& sd, int shape);
 hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const SensorDev& sd,
                              hipStream_t s);
-// t0/t1 (may be null): events the trace kernel's dispatch itself records at its start and end.
+// One depth level of many trees: trace with launch shape `shape`, then window
+// selection. t0/t1 (may be null): events the trace kernel's dispatch itself
+// records at its start and end.
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                              const SensorDev& sd, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                              const SensorDev& sd, int32_t max_anc, hipStream_t s, int shape = 0,
+                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 }  // namespace mgk

@@ -144,7 +144,13 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
 
 // ---------------------------------------------------------------- ray traversal
 
-constexpr int kQCap = 512;   // queued unknown voxels per wave
+// Launch shapes of the trace kernel (rays per workgroup, queued unknown
+// voxels per wave), all compiled; shape 0 is the default.
+struct Shape {
+    int threads, queue;
+};
+constexpr Shape kShapes[] = {{256, 384}, {256, 512}, {256, 256}, {128, 512}, {128, 256}, {512, 256}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 
 __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
@@ -217,8 +223,6 @@ __device__ __forceinline__ void drain_queue(uint2* __restrict__ q, int32_t n, co
     count_by_bin(q, n, marg_bins, lane);
 }
 
-// LDS carve-up shared by the trace kernels: boundary table | row table | bins
-// [2B] | ancestors | per-wave queues.
 struct TraceLDS {
     float2* bv;
     float* ts;
@@ -229,27 +233,31 @@ struct TraceLDS {
     uint16_t* lut_row;
 };
 
+// LDS carve-up: boundary table | row table | bins [2B] | guess tables |
+// per-wave queues | ancestors (as many as the launch provides for).
+template <int kTh, int kQ>
 __device__ __forceinline__ TraceLDS carve_lds(char* smem, const SensorDev& S) {
     TraceLDS L;
     L.bv = reinterpret_cast<float2*>(smem);
     L.ts = reinterpret_cast<float*>(L.bv + S.W);
     L.bins = reinterpret_cast<uint32_t*>(L.ts + S.H + 1);
-    char* tail = smem + ((reinterpret_cast<char*>(L.bins + 2 * S.B) - smem + 15) & ~static_cast<ptrdiff_t>(15));
-    L.anc = reinterpret_cast<AncLDS*>(tail);
-    L.queue = reinterpret_cast<uint2*>(tail + sizeof(AncLDS) * kMaxAnc);
-    L.lut_col = reinterpret_cast<uint16_t*>(L.queue + kQCap * (kThreads / 64));
+    L.lut_col = reinterpret_cast<uint16_t*>(L.bins + 2 * S.B);
     L.lut_row = L.lut_col + S.n_lut_col;
+    char* tail = smem + ((reinterpret_cast<char*>(L.lut_row + S.n_lut_row) - smem + 15) & ~static_cast<ptrdiff_t>(15));
+    L.queue = reinterpret_cast<uint2*>(tail);
+    L.anc = reinterpret_cast<AncLDS*>(L.queue + kQ * (kTh / 64));
     return L;
 }
 
+template <int kTh>
 __device__ __forceinline__ void load_tables(const TraceLDS& L, const SensorDev& S) {
-    for (int32_t i = threadIdx.x; i < S.W; i += kThreads) L.bv[i] = S.bv[i];
-    for (int32_t i = threadIdx.x; i <= S.H; i += kThreads) L.ts[i] = S.ts[i];
-    for (int32_t i = threadIdx.x; i < S.n_lut_col; i += kThreads) L.lut_col[i] = S.lut_col[i];
-    for (int32_t i = threadIdx.x; i < S.n_lut_row; i += kThreads) L.lut_row[i] = S.lut_row[i];
+    for (int32_t i = threadIdx.x; i < S.W; i += kTh) L.bv[i] = S.bv[i];
+    for (int32_t i = threadIdx.x; i <= S.H; i += kTh) L.ts[i] = S.ts[i];
+    for (int32_t i = threadIdx.x; i < S.n_lut_col; i += kTh) L.lut_col[i] = S.lut_col[i];
+    for (int32_t i = threadIdx.x; i < S.n_lut_row; i += kTh) L.lut_row[i] = S.lut_row[i];
 }
 
-// One workgroup = kThreads consecutive rays (tile `tile`) of one node; each
+// One workgroup = kTh consecutive rays (tile `tile`) of one node; each
 // wave owns a queue in LDS. A lane walks its ray with the Amanatides-Woo 3D
 // DDA (face-crossing parameters recomputed as (boundary - q) * (1/d); ties
 // step x, then y, then z; a voxel is visited while its entry parameter is
@@ -260,7 +268,7 @@ __device__ __forceinline__ void load_tables(const TraceLDS& L, const SensorDev& 
 // whenever the queue could overflow it is drained against the ancestors.
 // Requires the tables in LDS; ends with the tile's bins added to the node's
 // global bins.
-template <bool kMarginal>
+template <bool kMarginal, int kTh, int kQ>
 __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
                                            int32_t tile, const TraceLDS& L) {
     const int32_t tid = threadIdx.x;
@@ -269,13 +277,13 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     if (kMarginal) {
         const int32_t a0 = Tr.anc_ptr[node];
         na = Tr.anc_ptr[node + 1] - a0;
-        for (int32_t k = tid; k < na; k += kThreads) {
+        for (int32_t k = tid; k < na; k += kTh) {
             const int32_t a = Tr.anc_ids[a0 + k];
             const float4 qa = Tr.q4[a];
             const int32_t c0 = Tr.c0[a];
             int32_t c1 = c0 + S.WB;
             c1 = c1 >= S.W ? c1 - S.W : c1;
-            const float2 b0 = L.bv[c0], b1 = L.bv[c1];
+            const float2 b0 = S.bv[c0], b1 = S.bv[c1];   // global copy: LDS tables are not yet synchronised
             AncLDS A;
             A.qx = qa.x; A.qy = qa.y; A.qz = qa.z; A.c0 = c0;
             A.b0x = b0.x; A.b0y = b0.y; A.b1x = b1.x; A.b1y = b1.y;
@@ -284,11 +292,11 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             L.anc[k] = A;
         }
     }
-    for (int32_t i = tid; i < 2 * S.B; i += kThreads) L.bins[i] = 0u;
+    for (int32_t i = tid; i < 2 * S.B; i += kTh) L.bins[i] = 0u;
     __syncthreads();
 
-    uint2* q = L.queue + (tid >> 6) * kQCap;
-    const int32_t r = tile * kThreads + tid;
+    uint2* q = L.queue + (tid >> 6) * kQ;
+    const int32_t r = tile * kTh + tid;
     const bool has_ray = r < S.R;
     const int32_t rr = has_ray ? r : 0;
     const int32_t bin = S.bin_of_col[rr / S.H];
@@ -377,7 +385,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             tz = (bz - p.z) * fz;
             t = tn;
             alive = ballot(next_ok);
-        } while (alive && (!kMarginal || qn + 64 <= kQCap));
+        } while (alive && (!kMarginal || qn + 64 <= kQ));
         if (kMarginal) {
             drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, L.lut_col, L.lut_row, Tr.dpan, L.bins + S.B, lane);
             qn = 0;
@@ -387,7 +395,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     if (n_abs) atomicAdd(&L.bins[bin], n_abs);
     __syncthreads();
     uint32_t* gb = Tr.bins + (size_t)node * 2 * S.B;
-    for (int32_t i = tid; i < 2 * S.B; i += kThreads) {
+    for (int32_t i = tid; i < 2 * S.B; i += kTh) {
         const uint32_t v = L.bins[i];
         if (v) atomicAdd(&gb[i], v);
     }
@@ -396,10 +404,12 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
 template <bool kMarginal>
 __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
                                                     const int32_t* __restrict__ nodes) {
+    constexpr int kTh = kShapes[0].threads, kQ = kShapes[0].queue;
+    static_assert(kTh == kThreads, "the per-tree path tiles rays by kThreads");
     extern __shared__ char smem[];
-    const TraceLDS L = carve_lds(smem, S);
-    load_tables(L, S);
-    trace_tile<kMarginal>(M, S, Tr, nodes[blockIdx.x / S.T], blockIdx.x % S.T, L);
+    const TraceLDS L = carve_lds<kTh, kQ>(smem, S);
+    load_tables<kTh>(L, S);
+    trace_tile<kMarginal, kTh, kQ>(M, S, Tr, nodes[blockIdx.x / S.T], blockIdx.x % S.T, L);
 }
 
 // ---------------------------------------------------------------- window selection
@@ -476,11 +486,12 @@ __global__ void k_batch_zero(const BatchTree* __restrict__ trees, int32_t B2) {
 
 // One depth level of all trees at once: work item = (tree, node) from
 // `items` (tree << 32 | node), T workgroups per item.
-__global__ __launch_bounds__(kThreads) void k_trace_multi(const BatchTree* __restrict__ trees,
-                                                          const unsigned long long* __restrict__ items, SensorDev S) {
+template <int kTh, int kQ>
+__global__ __launch_bounds__(kTh) void k_trace_multi(const BatchTree* __restrict__ trees,
+                                                     const unsigned long long* __restrict__ items, SensorDev S) {
     extern __shared__ char smem[];
-    const TraceLDS L = carve_lds(smem, S);
-    load_tables(L, S);
+    const TraceLDS L = carve_lds<kTh, kQ>(smem, S);
+    load_tables<kTh>(L, S);
     const unsigned long long it = items[blockIdx.x / S.T];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
     SensorDev St = S;
@@ -488,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_multi(const BatchTree* __res
     St.rv2 = BT.rv2;
     const MapDev M = BT.map;     // copies: loaded once, not re-read through the descriptor
     const TreeDev Tr = BT.td;
-    trace_tile<true>(M, St, Tr, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
+    trace_tile<true, kTh, kQ>(M, St, Tr, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
 }
 
 // Window selection for one depth level of all trees; writes each tree's
@@ -554,17 +565,29 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t trace_lds_bytes(const SensorDev& sd) {
-    return sizeof(float2) * sd.W + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B + 16 +
-           sizeof(AncLDS) * kMaxAnc + sizeof(uint2) * kQCap * (kThreads / 64) +
-           sizeof(uint16_t) * (sd.n_lut_col + sd.n_lut_row);
+int shape_count() { return kNumShapes; }
+
+void shape_of(int shape, int* threads, int* queue) {
+    *threads = kShapes[shape].threads;
+    *queue = kShapes[shape].queue;
+}
+
+size_t trace_lds_bytes(const SensorDev& sd, int shape, int32_t max_anc) {
+    const size_t tables = sizeof(float2) * sd.W + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B +
+                          sizeof(uint16_t) * (sd.n_lut_col + sd.n_lut_row);
+    return ((tables + 15) & ~(size_t)15) + sizeof(uint2) * kShapes[shape].queue * (kShapes[shape].threads / 64) +
+           sizeof(AncLDS) * (size_t)max_anc;
+}
+
+int32_t tiles_per_node(const SensorDev& sd, int shape) {
+    return (sd.R + kShapes[shape].threads - 1) / kShapes[shape].threads;
 }
 
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
-                        int32_t n_nodes, bool marginal, hipStream_t s) {
+                        int32_t n_nodes, bool marginal, int32_t max_anc, hipStream_t s) {
     if (n_nodes <= 0) return hipSuccess;
     dim3 grid((unsigned)n_nodes * (unsigned)sd.T);
-    size_t lds = trace_lds_bytes(sd);
+    size_t lds = trace_lds_bytes(sd, 0, marginal ? max_anc : 0);
     if (marginal)
         hipLaunchKernelGGL(k_trace<true>, grid, dim3(kThreads), lds, s, m, sd, td, nodes);
     else
@@ -596,15 +619,41 @@ hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t m
     return hipGetLastError();
 }
 
-hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                              const SensorDev& sd, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    if (n_items <= 0) return hipSuccess;
-    const dim3 grid((unsigned)n_items * (unsigned)sd.T);
+namespace {
+
+template <int kTh, int kQ>
+void launch_multi(const BatchTree* trees, const unsigned long long* items, int32_t n_items, const SensorDev& sd,
+                  int32_t max_anc, hipStream_t s, hipEvent_t t0, hipEvent_t t1, int shape) {
+    SensorDev st = sd;
+    st.T = tiles_per_node(sd, shape);
+    const dim3 grid((unsigned)n_items * (unsigned)st.T);
+    const uint32_t lds = (uint32_t)trace_lds_bytes(sd, shape, max_anc);
+    auto kern = k_trace_multi<kTh, kQ>;
     if (t0 && t1)
-        hipExtLaunchKernelGGL(k_trace_multi, grid, dim3(kThreads), (uint32_t)trace_lds_bytes(sd), s, t0, t1, 0u,
-                              trees, items, sd);
+        hipExtLaunchKernelGGL(kern, grid, dim3(kTh), lds, s, t0, t1, 0u, trees, items, st);
     else
-        hipLaunchKernelGGL(k_trace_multi, grid, dim3(kThreads), trace_lds_bytes(sd), s, trees, items, sd);
+        hipLaunchKernelGGL(kern, grid, dim3(kTh), lds, s, trees, items, st);
+}
+
+template <int I>
+void launch_multi_shape(int shape, const BatchTree* trees, const unsigned long long* items, int32_t n_items,
+                        const SensorDev& sd, int32_t max_anc, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if constexpr (I < kNumShapes) {
+        if (shape == I)
+            launch_multi<kShapes[I].threads, kShapes[I].queue>(trees, items, n_items, sd, max_anc, s, t0, t1, I);
+        else
+            launch_multi_shape<I + 1>(shape, trees, items, n_items, sd, max_anc, s, t0, t1);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
+                              const SensorDev& sd, int32_t max_anc, hipStream_t s, int shape, hipEvent_t t0,
+                              hipEvent_t t1) {
+    if (n_items <= 0) return hipSuccess;
+    if (shape < 0 || shape >= kNumShapes || max_anc < 0 || max_anc > kMaxAnc) return hipErrorInvalidValue;
+    launch_multi_shape<0>(shape, trees, items, n_items, sd, max_anc, s, t0, t1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finish_multi, dim3((unsigned)n_items), dim3(kThreads), 0, s, trees, items, sd);

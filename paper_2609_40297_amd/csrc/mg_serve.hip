@@ -214,7 +214,9 @@ int mg_server_s::step() {
 
     // descriptors and the work list of this step
     size_t n_items = 0, stage = 0;
+    int32_t max_anc = 0;     // a node of depth level d has d ancestors
     for (Request* r : active) {
+        max_anc = std::max(max_anc, r->level);
         n_items += (size_t)((*r->level_ptr)[r->level + 1] - (*r->level_ptr)[r->level]);
         if (r->level + 1 == r->levels) stage += 2 * (size_t)r->n;
     }
@@ -241,7 +243,7 @@ int mg_server_s::step() {
     hipError_t e = hipMemcpyAsync(d_trees, h_trees, sizeof(BatchTree) * active.size(), hipMemcpyHostToDevice, compute);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_items, h_items, sizeof(unsigned long long) * n_items, hipMemcpyHostToDevice, compute);
-    if (e == hipSuccess) e = launch_batch_level(d_trees, d_items, (int32_t)n_items, sd, compute);
+    if (e == hipSuccess) e = launch_batch_level(d_trees, d_items, (int32_t)n_items, sd, max_anc, compute);
     size_t so = 0;
     std::vector<std::pair<Request*, size_t>> finishing;
     for (Request* r : active) {

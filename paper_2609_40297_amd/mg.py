@@ -27,7 +27,8 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_tree_buffer_pixels", "mg_tree_footprint_bytes", "mg_eval_marginal", "mg_eval_marginal_levelsync",
            "mg_eval_marginal_batch", "mg_eval_absolute", "mg_sensor_tables", "mg_last_error",
            "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait", "mg_server_stats",
-           "mg_server_destroy", "mg_timing_enable", "mg_timing_read")
+           "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
+           "mg_batch_plan_info")
 
 
 class MGError(RuntimeError):
@@ -77,6 +78,9 @@ def lib() -> C.CDLL:
         L.mg_server_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(I32),
                                       C.POINTER(I32)]
         L.mg_server_destroy.argtypes = [P]
+        L.mg_batch_config.argtypes = [I32, I32]
+        L.mg_trace_shapes.argtypes = [C.POINTER(I32), P, P, I32]
+        L.mg_batch_plan_info.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32)]
         L.mg_timing_enable.argtypes = [I32]
         L.mg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(I64), C.POINTER(I64)]
         L.mg_last_error.argtypes = []
@@ -85,7 +89,7 @@ def lib() -> C.CDLL:
                      "mg_eval_marginal_levelsync", "mg_eval_marginal_batch", "mg_eval_absolute",
                      "mg_sensor_tables", "mg_server_create", "mg_server_submit", "mg_server_poll",
                      "mg_server_wait", "mg_server_stats", "mg_server_destroy", "mg_timing_enable",
-                     "mg_timing_read"):
+                     "mg_timing_read", "mg_batch_config", "mg_trace_shapes", "mg_batch_plan_info"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -173,6 +177,28 @@ def mg_eval_marginal_batch(trees: Sequence[int], gain, yaw_bin, depth=None, stre
 
 def mg_eval_absolute(tree: int, gain, yaw_bin, stream=None):
     _check(lib().mg_eval_absolute(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin)))
+
+
+def mg_batch_config(shape: int = -1, graph: bool = False):
+    _check(lib().mg_batch_config(int(shape), 1 if graph else 0))
+
+
+def mg_trace_shapes():
+    """[(rays per workgroup, queue capacity per wave), ...] of the compiled launch shapes."""
+    n = C.c_int32()
+    _check(lib().mg_trace_shapes(C.byref(n), None, None, 0))
+    th = np.zeros(n.value, np.int32)
+    q = np.zeros(n.value, np.int32)
+    _check(lib().mg_trace_shapes(C.byref(n), _np_ptr(th), _np_ptr(q), n.value))
+    return list(zip(th.tolist(), q.tolist()))
+
+
+def mg_batch_plan_info(trees: Sequence[int]):
+    """(shape index, graphed) of the cached plan of this tree list."""
+    arr = (C.c_void_p * len(trees))(*trees)
+    sh, gr = C.c_int32(), C.c_int32()
+    _check(lib().mg_batch_plan_info(C.cast(arr, C.c_void_p), len(trees), C.byref(sh), C.byref(gr)))
+    return sh.value, bool(gr.value)
 
 
 def mg_timing_enable(on: bool):

@@ -98,3 +98,16 @@ def test_oracle_and_library_share_no_code():
         if fn.endswith((".c", ".h", ".py")):
             txt = open(os.path.join(ROOT, "oracle", fn)).read()
             assert "paper_2609_40297_amd.mg" not in txt and "mg.h" not in txt.replace("mgref.h", ""), fn
+
+
+def test_launch_shape_table_and_config_validation():
+    """Host-only: the compiled launch shapes and argument checks of mg_batch_config."""
+    from paper_2609_40297_amd import mg
+    shapes = mg.mg_trace_shapes()
+    assert len(shapes) >= 2
+    for th, q in shapes:
+        assert th % 64 == 0 and 64 <= th <= 1024 and q % 64 == 0 and q >= 128
+    for bad in [(-2, 0), (len(shapes), 0), (0, 2)]:
+        with pytest.raises(mg.MGError) as e:
+            mg._check(mg.lib().mg_batch_config(*bad))
+        assert e.value.code == mg.MG_E_INVALID

@@ -133,7 +133,9 @@ def test_kernel_timing_counts_trace_launches_and_keeps_results(mg):
     finally:
         mg.mg_timing_enable(False)
     sen = w.sensor
-    tiles = -(-sen.n_az * sen.n_el // 256)
+    shape, _ = mg.mg_batch_plan_info([T.handle])
+    threads = mg.mg_trace_shapes()[shape][0]
+    tiles = -(-sen.n_az * sen.n_el // threads)
     assert n == 2 * levels
     assert wg == 2 * T.n * tiles
     assert ms > 0.0
@@ -141,4 +143,84 @@ def test_kernel_timing_counts_trace_launches_and_keeps_results(mg):
     _check_batch(mg, [T], ref)                       # timing off again: no intervals recorded
     assert mg.mg_timing_read()[1] == 0
     T.close()
+    M.close()
+
+
+def _subset_trees(mg, n_trees=5):
+    w = W.make("batch64", n_trees=n_trees)
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    trees = [mg.Tree(M, t.pos_m, t.parent, w.sensor) for t in w.trees]
+    return M, trees
+
+
+def test_every_launch_shape_gives_identical_results(mg):
+    """Each compiled launch shape of the trace kernel, launched one by one and as a graph."""
+    M, trees = _subset_trees(mg)
+    ref = _per_tree(mg, trees)
+    shapes = mg.mg_trace_shapes()
+    log(f"[shapes] {shapes}")
+    try:
+        for k, (th, q) in enumerate(shapes):
+            for graph in (False, True):
+                mg.mg_batch_config(k, graph)
+                log(f"[shapes] shape {k} ({th} rays/WG, queue {q}) graph={graph}")
+                _check_batch(mg, trees, ref)
+                assert mg.mg_batch_plan_info([t.handle for t in trees]) == (k, graph)
+    finally:
+        mg.mg_batch_config(-1, False)
+    for T in trees:
+        T.close()
+    M.close()
+
+
+def test_graph_replays_match_eager_launches(mg):
+    """The captured plan replayed several times, with unrelated eager work and syncs in between."""
+    import torch
+    M, trees = _subset_trees(mg, 4)
+    ref = _per_tree(mg, trees)
+    n = sum(t.n for t in trees)
+    g = torch.empty(n, dtype=torch.int32, device="cuda")
+    y = torch.empty(n, dtype=torch.int32, device="cuda")
+    d = torch.empty((n, trees[0].pixels), dtype=torch.float32, device="cuda")
+    handles = [t.handle for t in trees]
+    try:
+        mg.mg_batch_config(0, True)
+        for rep in range(4):
+            g.fill_(-1)
+            y.fill_(-7)
+            d.fill_(-1.0)
+            mg.mg_eval_marginal_batch(handles, g, y, d)
+            torch.cuda.synchronize()
+            assert mg.mg_batch_plan_info(handles) == (0, True)
+            off = 0
+            for i, T in enumerate(trees):
+                assert torch.equal(g[off:off + T.n], ref[i][0]), (rep, i)
+                assert torch.equal(y[off:off + T.n], ref[i][1]), (rep, i)
+                assert torch.equal(d[off:off + T.n], ref[i][2]), (rep, i)
+                off += T.n
+            x = torch.randn(4096, device="cuda")
+            _ = (x * x).sum().item()                     # eager work between replays
+    finally:
+        mg.mg_batch_config(-1, False)
+    for T in trees:
+        T.close()
+    M.close()
+
+
+def test_autotune_chooses_a_shape_and_keeps_results(mg):
+    M, trees = _subset_trees(mg, 3)
+    ref = _per_tree(mg, trees)
+    try:
+        mg.mg_batch_config(-1, True)
+        _check_batch(mg, trees, ref)                     # first call tunes, then replays the graph
+        shape, graphed = mg.mg_batch_plan_info([t.handle for t in trees])
+        assert 0 <= shape < len(mg.mg_trace_shapes()) and graphed
+        _check_batch(mg, trees, ref)
+        mg.mg_batch_config(-1, False)                    # tuned shape reused, launches one by one
+        _check_batch(mg, trees, ref)
+        assert mg.mg_batch_plan_info([t.handle for t in trees]) == (shape, False)
+    finally:
+        mg.mg_batch_config(-1, False)
+    for T in trees:
+        T.close()
     M.close()
