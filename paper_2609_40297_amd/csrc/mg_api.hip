@@ -559,6 +559,11 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     t->scratch_gain = (uint32_t*)(base + H.o_g);
     t->scratch_yaw = (int32_t*)(base + H.o_y);
     t->sd = sensor_dev(t->sensor, sensor->range_m / map->voxel_m);
+    if (!shape_fits(t->sd, 0, std::min<int32_t>(H.maxd, kMaxAnc))) {
+        release_sensor(t->sensor);
+        return fail(MG_E_UNSUPPORTED, "sensor tables and queues need %zu bytes of LDS per workgroup, the device has %zu",
+                    trace_lds_bytes(t->sd, 0, std::min<int32_t>(H.maxd, kMaxAnc)), lds_limit());
+    }
     t->map = map;
     t->params = *sensor;
     t->n = n;

@@ -229,7 +229,10 @@ int autotune(Plan& P, hipStream_t s) {
     if (e == hipSuccess) e = hipEventCreate(&b);
     int best = 0;
     float best_ms = 0.f;
+    bool any = false;
+    const int32_t deepest = (int32_t)P.level_ptr.size() - 2;   // most ancestors of any node
     for (int k = 0; k < shape_count() && e == hipSuccess; ++k) {
+        if (!shape_fits(P.sd, k, deepest)) continue;         // needs more LDS than the device has
         P.shape = k;
         float ms = 0.f;
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
@@ -245,9 +248,10 @@ int autotune(Plan& P, hipStream_t s) {
             if (e == hipSuccess) e = hipEventSynchronize(b);
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
         }
-        if (e == hipSuccess && (k == 0 || ms < best_ms)) {
+        if (e == hipSuccess && (!any || ms < best_ms)) {
             best = k;
             best_ms = ms;
+            any = true;
         }
     }
     if (a) (void)hipEventDestroy(a);

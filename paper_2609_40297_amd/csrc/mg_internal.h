@@ -105,6 +105,8 @@ int shape_count();
 void shape_of(int shape, int* threads, int* queue);
 size_t trace_lds_bytes(const SensorDev& sd, int shape, int32_t max_anc);
 int32_t tiles_per_node(const SensorDev& sd, int shape);
+size_t lds_limit();                        // LDS bytes one workgroup may use on the current device
+bool shape_fits(const SensorDev& sd, int shape, int32_t max_anc);
 hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const SensorDev& sd,
                              hipStream_t s);
 // One depth level of many trees: trace with launch shape `shape`, then window

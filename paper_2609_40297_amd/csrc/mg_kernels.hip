@@ -91,43 +91,49 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     if (!inside) return false;
 
     // Column: pseudo-angle past the left boundary (monotone in the angle) picks a
-    // table bucket holding at most one column boundary; one comparison with that
-    // boundary decides between the bucket's two columns and a second one checks
-    // the other side. Lanes whose check fails (rounding at a bucket edge) settle
-    // with the boundary-by-boundary walk.
+    // table bucket holding at most one column boundary, giving a guess gc. The
+    // boundaries gc, gc + 1 and gc + 2 of the window are read at once (the LDS
+    // table holds the boundaries twice over, so window boundary k is entry
+    // c0 + k); the column is gc + 1 if boundary gc + 1 lies at or left of r and
+    // gc + 2 does not, gc if boundary gc does and gc + 1 does not. Lanes where
+    // neither holds (rounding at a bucket edge) settle with the
+    // boundary-by-boundary walk.
     const float u0 = A.b0x * rx + A.b0y * ry;
     float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
     pa = u0 < 0.f ? 2.f - pa : pa;
     const int32_t gc = s_lut_col[(int32_t)fminf(fmaxf(pa * S.lut_col_scale, 0.f), (float)(S.n_lut_col - 1))];
-    const bool c_up = (gc + 1 < S.WB) && left_of(s_bv[wrap(A.c0 + gc + 1, S.W)], rx, ry);
-    int32_t col = gc + (c_up ? 1 : 0);
-    const int32_t cv = c_up ? col + 1 : col;          // the boundary that is still unchecked
-    const bool cv_ok = c_up ? (cv >= S.WB || !left_of(s_bv[wrap(A.c0 + min(cv, S.WB - 1), S.W)], rx, ry))
-                            : (cv == 0 || left_of(s_bv[wrap(A.c0 + cv, S.W)], rx, ry));
-    if (ballot(!cv_ok)) {
-        if (!cv_ok) {
+    const int32_t cb = A.c0 + gc;
+    const float2 v0 = s_bv[cb], v1 = s_bv[cb + 1], v2 = s_bv[cb + 2];
+    const bool l0 = (gc == 0) | left_of(v0, rx, ry);
+    const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
+    const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
+    int32_t col = l1 ? gc + 1 : gc;
+    const bool c_ok = l1 ? !l2 : l0;
+    if (ballot(!c_ok)) {
+        if (!c_ok) {
             for (;;) {
-                if (col + 1 >= S.WB || !left_of(s_bv[wrap(A.c0 + col + 1, S.W)], rx, ry)) break;
+                if (col + 1 >= S.WB || !left_of(s_bv[A.c0 + col + 1], rx, ry)) break;
                 ++col;
             }
             for (;;) {
-                if (col == 0 || left_of(s_bv[wrap(A.c0 + col, S.W)], rx, ry)) break;
+                if (col == 0 || left_of(s_bv[A.c0 + col], rx, ry)) break;
                 --col;
             }
         }
     }
     // Row: elevation tangent picks a bucket holding at most one row boundary;
-    // same two comparisons, same fallback.
+    // the same three-boundary decision, same fallback.
     const float tg = rz * __builtin_amdgcn_rsqf(rho2);
     const int32_t gr = s_lut_row[(int32_t)fminf(fmaxf((tg - S.lut_row_lo) * S.lut_row_scale, 0.f),
                                                 (float)(S.n_lut_row - 1))];
-    const bool r_up = (gr + 1 < S.H) && (sz >= rho2 * s_ts[gr + 1]);
-    int32_t row = gr + (r_up ? 1 : 0);
-    const int32_t rv_ = r_up ? row + 1 : row;
-    const bool rv_ok = r_up ? (rv_ >= S.H || !(sz >= rho2 * s_ts[min(rv_, S.H)]))
-                            : (rv_ == 0 || sz >= rho2 * s_ts[rv_]);
-    if (ballot(!rv_ok)) {
-        if (!rv_ok) {
+    const float e0 = s_ts[gr], e1 = s_ts[gr + 1], e2 = s_ts[min(gr + 2, S.H)];
+    const bool r0 = (gr == 0) | (sz >= rho2 * e0);
+    const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
+    const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
+    int32_t row = r1 ? gr + 1 : gr;
+    const bool r_ok = r1 ? !r2 : r0;
+    if (ballot(!r_ok)) {
+        if (!r_ok) {
             for (;;) {
                 if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
                 ++row;
@@ -233,13 +239,13 @@ struct TraceLDS {
     uint16_t* lut_row;
 };
 
-// LDS carve-up: boundary table | row table | bins [2B] | guess tables |
+// LDS carve-up: boundary table (twice over) | row table | bins [2B] | guess tables |
 // per-wave queues | ancestors (as many as the launch provides for).
 template <int kTh, int kQ>
 __device__ __forceinline__ TraceLDS carve_lds(char* smem, const SensorDev& S) {
     TraceLDS L;
-    L.bv = reinterpret_cast<float2*>(smem);
-    L.ts = reinterpret_cast<float*>(L.bv + S.W);
+    L.bv = reinterpret_cast<float2*>(smem);                 // column boundaries twice over: [2W + 1]
+    L.ts = reinterpret_cast<float*>(L.bv + 2 * S.W + 1);
     L.bins = reinterpret_cast<uint32_t*>(L.ts + S.H + 1);
     L.lut_col = reinterpret_cast<uint16_t*>(L.bins + 2 * S.B);
     L.lut_row = L.lut_col + S.n_lut_col;
@@ -251,7 +257,7 @@ __device__ __forceinline__ TraceLDS carve_lds(char* smem, const SensorDev& S) {
 
 template <int kTh>
 __device__ __forceinline__ void load_tables(const TraceLDS& L, const SensorDev& S) {
-    for (int32_t i = threadIdx.x; i < S.W; i += kTh) L.bv[i] = S.bv[i];
+    for (int32_t i = threadIdx.x; i <= 2 * S.W; i += kTh) L.bv[i] = S.bv[i < S.W ? i : (i < 2 * S.W ? i - S.W : 0)];
     for (int32_t i = threadIdx.x; i <= S.H; i += kTh) L.ts[i] = S.ts[i];
     for (int32_t i = threadIdx.x; i < S.n_lut_col; i += kTh) L.lut_col[i] = S.lut_col[i];
     for (int32_t i = threadIdx.x; i < S.n_lut_row; i += kTh) L.lut_row[i] = S.lut_row[i];
@@ -573,10 +579,22 @@ void shape_of(int shape, int* threads, int* queue) {
 }
 
 size_t trace_lds_bytes(const SensorDev& sd, int shape, int32_t max_anc) {
-    const size_t tables = sizeof(float2) * sd.W + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B +
+    const size_t tables = sizeof(float2) * (2 * sd.W + 1) + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B +
                           sizeof(uint16_t) * (sd.n_lut_col + sd.n_lut_row);
     return ((tables + 15) & ~(size_t)15) + sizeof(uint2) * kShapes[shape].queue * (kShapes[shape].threads / 64) +
            sizeof(AncLDS) * (size_t)max_anc;
+}
+
+size_t lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 64u * 1024u;
+    return (size_t)v;
+}
+
+bool shape_fits(const SensorDev& sd, int shape, int32_t max_anc) {
+    return trace_lds_bytes(sd, shape, max_anc) <= lds_limit();
 }
 
 int32_t tiles_per_node(const SensorDev& sd, int shape) {
@@ -588,6 +606,7 @@ hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td,
     if (n_nodes <= 0) return hipSuccess;
     dim3 grid((unsigned)n_nodes * (unsigned)sd.T);
     size_t lds = trace_lds_bytes(sd, 0, marginal ? max_anc : 0);
+    if (lds > lds_limit()) return hipErrorInvalidConfiguration;
     if (marginal)
         hipLaunchKernelGGL(k_trace<true>, grid, dim3(kThreads), lds, s, m, sd, td, nodes);
     else
@@ -653,6 +672,7 @@ hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* 
                               hipEvent_t t1) {
     if (n_items <= 0) return hipSuccess;
     if (shape < 0 || shape >= kNumShapes || max_anc < 0 || max_anc > kMaxAnc) return hipErrorInvalidValue;
+    if (!shape_fits(sd, shape, max_anc)) return hipErrorInvalidConfiguration;
     launch_multi_shape<0>(shape, trees, items, n_items, sd, max_anc, s, t0, t1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
