@@ -107,8 +107,9 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     const bool l0 = (gc == 0) | left_of(v0, rx, ry);
     const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
     const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
-    int32_t col = l1 ? gc + 1 : gc;
-    const bool c_ok = l1 ? !l2 : l0;
+    // (and/or rather than a select, so that all three reads stay unconditional)
+    int32_t col = gc + (int32_t)l1;
+    const bool c_ok = (l1 & !l2) | (!l1 & l0);
     if (ballot(!c_ok)) {
         if (!c_ok) {
             for (;;) {
@@ -130,8 +131,8 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     const bool r0 = (gr == 0) | (sz >= rho2 * e0);
     const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
     const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
-    int32_t row = r1 ? gr + 1 : gr;
-    const bool r_ok = r1 ? !r2 : r0;
+    int32_t row = gr + (int32_t)r1;
+    const bool r_ok = (r1 & !r2) | (!r1 & r0);
     if (ballot(!r_ok)) {
         if (!r_ok) {
             for (;;) {
@@ -155,7 +156,7 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
 struct Shape {
     int threads, queue;
 };
-constexpr Shape kShapes[] = {{256, 384}, {256, 512}, {256, 256}, {128, 512}, {128, 256}, {512, 256}};
+constexpr Shape kShapes[] = {{256, 512}, {256, 384}, {256, 256}, {128, 512}, {128, 256}, {512, 256}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 
