@@ -217,10 +217,12 @@ int mg_server_destroy(mg_server server);
 int mg_timing_enable(int32_t on);
 
 /* Waits for the timed launches since the last read, returns the sum of their
- * durations (ms), their number and the workgroups they ran (any pointer may be
- * NULL), and resets the sums. At most 65536 launches may be timed between two
- * reads (MG_E_BUSY from the launch call beyond that). */
-int mg_timing_read(double* total_ms, int64_t* launches, int64_t* workgroups);
+ * durations (ms), the union of their intervals (ms during which at least one
+ * ran: launches of different groups of a batch plan overlap), their number
+ * and the workgroups they ran (any pointer may be NULL), and resets the sums.
+ * At most 65536 launches may be timed between two reads (MG_E_BUSY from the
+ * launch call beyond that). */
+int mg_timing_read(double* total_ms, double* busy_ms, int64_t* launches, int64_t* workgroups);
 
 /* Host-only diagnostics: the sensor tables the library builds (no device
  * work). dir and inv [n_az*n_el][3] (ray r = c*n_el + j), bv [n_az][2]

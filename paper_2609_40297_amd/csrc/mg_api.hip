@@ -701,6 +701,8 @@ int tree_view(mg_tree t, TreeView* v) {
     v->td = &t->dev;
     v->level_ptr = &t->level_ptr;
     v->level_nodes = &t->level_nodes_h;
+    v->parent = &t->parent_h;
+    v->depth = &t->depth_h;
     v->scratch_gain = t->scratch_gain;
     v->scratch_yaw = t->scratch_yaw;
     v->params = t->params;

@@ -1,6 +1,11 @@
-// Multi-tree evaluation: all trees advance one depth level at a time; each
-// level is one trace launch over every (tree, node) of that depth followed by
-// one window-selection launch. Launch plans are cached per tree list; a new
+// Multi-tree evaluation: trees advance one depth level at a time; each level
+// is one trace launch over every (tree, node) of that depth followed by one
+// window-selection launch. A node needs only its own ancestors, so the plan
+// splits the work into up to kGroups independent groups (whole trees, or the
+// subtrees below a shared prefix of levels when there are few trees), each
+// advancing level by level on its own stream: one group's small levels run
+// while another's are still in flight, instead of all waiting for the slowest
+// node of a global level. Launch plans are cached per tree list; a new
 // plan gets its trace launch shape from the autotuner (every compiled shape
 // timed on the plan itself, the result kept per workload shape) and, when
 // configured, its launches are captured once into a HIP graph that later
@@ -30,7 +35,14 @@ struct Plan {
     void* block = nullptr;                 // BatchTree[n_trees] | items[total]
     const BatchTree* dtrees = nullptr;
     const unsigned long long* ditems = nullptr;
-    std::vector<int32_t> level_ptr;        // items of global level d: [level_ptr[d], level_ptr[d+1])
+    // Launch records in host order: stream 0 is the caller's (the shared
+    // prefix of levels), stream g + 1 runs group g.
+    struct Launch {
+        int32_t stream, begin, count, depth;
+    };
+    std::vector<Launch> launches;
+    int32_t groups = 0;
+    int32_t levels = 0;                    // deepest level + 1 over the trees
     SensorDev sd{};
     uint32_t total = 0, max_nodes = 0;
     int device = 0;
@@ -61,6 +73,7 @@ std::map<int, Replay> g_replay;
 std::mutex g_mu;
 std::map<std::vector<mg_tree>, std::unique_ptr<Plan>> g_plans;
 constexpr size_t kMaxPlans = 64;
+constexpr int32_t kGroups = 2;             // independent groups of a plan, one stream each (2 measured best of 1/2/4/8)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -107,11 +120,79 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
     P->device = v0.device;
     int32_t max_tiles = 0;                 // workgroups per node of the narrowest launch shape
     for (int k = 0; k < shape_count(); ++k) max_tiles = std::max(max_tiles, tiles_per_node(P->sd, k));
-    // items grouped by global depth level, trees in order within a level
-    P->level_ptr.assign(levels + 1, 0);
+    // Split: with at least kGroups trees the units of work are whole trees;
+    // otherwise the levels above depth s (the first depth holding at least
+    // kGroups nodes) form a shared prefix and the units are the subtrees
+    // rooted at depth s.
+    int32_t split = 0;
+    if (nt < kGroups) {
+        split = levels;
+        for (int32_t d = 1; d < levels; ++d) {
+            int64_t cnt = 0;
+            for (int32_t i = 0; i < nt; ++i) {
+                const std::vector<int32_t>& lp = *views[i].level_ptr;
+                if (d + 1 < (int32_t)lp.size()) cnt += lp[d + 1] - lp[d];
+            }
+            if (cnt >= kGroups) {
+                split = d;
+                break;
+            }
+        }
+    }
+    // unit of every node at depth >= split: (tree, ancestor at depth split)
+    std::vector<std::vector<int32_t>> unit_of(nt);
+    std::vector<int64_t> unit_size;
+    for (int32_t i = 0; i < nt; ++i) {
+        const std::vector<int32_t>& par = *views[i].parent;
+        const std::vector<int32_t>& dep = *views[i].depth;
+        const int32_t n = views[i].n;
+        unit_of[i].assign(n, -1);
+        if (nt >= kGroups) {
+            for (int32_t k = 0; k < n; ++k) unit_of[i][k] = i;
+            unit_size.push_back(n);
+            continue;
+        }
+        for (int32_t k = 0; k < n; ++k) {            // parents precede children
+            if (dep[k] < split) continue;
+            if (dep[k] == split) {
+                unit_of[i][k] = (int32_t)unit_size.size();
+                unit_size.push_back(0);
+            } else {
+                unit_of[i][k] = unit_of[i][par[k]];
+            }
+            ++unit_size[unit_of[i][k]];
+        }
+    }
+    // units to groups, largest first onto the least loaded group
+    const int32_t G = (int32_t)std::min<size_t>(kGroups, unit_size.size());
+    std::vector<int32_t> group_of_unit(unit_size.size(), 0);
+    {
+        std::vector<int32_t> order(unit_size.size());
+        for (size_t u = 0; u < order.size(); ++u) order[u] = (int32_t)u;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return unit_size[a] > unit_size[b]; });
+        std::vector<int64_t> load(G, 0);
+        for (int32_t u : order) {
+            const int32_t g = (int32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            group_of_unit[u] = g;
+            load[g] += unit_size[u];
+        }
+    }
+    P->groups = G;
+    // items: the prefix level by level (trees in order), then every group's
+    // levels; one launch record per non-empty (stream, level)
     std::vector<unsigned long long> items;
     items.reserve(P->total);
-    for (int32_t d = 0; d < levels; ++d) {
+    auto add_launch = [&](int32_t stream, int32_t begin, int32_t d) -> int {
+        const int32_t count = (int32_t)items.size() - begin;
+        if (count == 0) return MG_OK;
+        if ((uint64_t)count * (uint64_t)max_tiles >= (1ull << 31))
+            return mgb::set_error(MG_E_UNSUPPORTED, "a depth level of the batch has 2^31 workgroups or more");
+        P->launches.push_back({stream, begin, count, d});
+        return MG_OK;
+    };
+    for (int32_t d = 0; d < split; ++d) {
+        const int32_t begin = (int32_t)items.size();
         for (int32_t i = 0; i < nt; ++i) {
             const std::vector<int32_t>& lp = *views[i].level_ptr;
             const std::vector<int32_t>& ln = *views[i].level_nodes;
@@ -119,10 +200,25 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
             for (int32_t k = lp[d]; k < lp[d + 1]; ++k)
                 items.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)ln[k]);
         }
-        P->level_ptr[d + 1] = (int32_t)items.size();
-        if ((uint64_t)(P->level_ptr[d + 1] - P->level_ptr[d]) * (uint64_t)max_tiles >= (1ull << 31))
-            return mgb::set_error(MG_E_UNSUPPORTED, "a depth level of the batch has 2^31 workgroups or more");
+        int rc = add_launch(0, begin, d);
+        if (rc != MG_OK) return rc;
     }
+    for (int32_t d = split; d < levels; ++d) {
+        for (int32_t g = 0; g < G; ++g) {
+            const int32_t begin = (int32_t)items.size();
+            for (int32_t i = 0; i < nt; ++i) {
+                const std::vector<int32_t>& lp = *views[i].level_ptr;
+                const std::vector<int32_t>& ln = *views[i].level_nodes;
+                if (d + 1 >= (int32_t)lp.size()) continue;
+                for (int32_t k = lp[d]; k < lp[d + 1]; ++k)
+                    if (group_of_unit[unit_of[i][ln[k]]] == g)
+                        items.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)ln[k]);
+            }
+            int rc = add_launch(g + 1, begin, d);
+            if (rc != MG_OK) return rc;
+        }
+    }
+    P->levels = levels;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     const size_t o_trees = take(sizeof(BatchTree) * nt);
@@ -188,24 +284,75 @@ bool timing_on() {
     return g_timing.on;
 }
 
-// Enqueues the plan's launches on s; `timed` lets the kernel timer attach events.
+// Per-device streams of the groups, with the events that fork them from and
+// join them back to the caller's stream (all default priority, non-blocking).
+struct GroupStreams {
+    hipStream_t stream[kGroups] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kGroups] = {};
+};
+std::map<int, GroupStreams> g_group_streams;
+
+int group_streams(int device, GroupStreams** out) {
+    GroupStreams& G = g_group_streams[device];
+    if (!G.fork) {
+        hipError_t e = hipEventCreateWithFlags(&G.fork, hipEventDisableTiming);
+        for (int32_t g = 0; g < kGroups && e == hipSuccess; ++g) {
+            e = hipStreamCreateWithFlags(&G.stream[g], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&G.join[g], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            for (int32_t g = 0; g < kGroups; ++g) {
+                if (G.stream[g]) (void)hipStreamDestroy(G.stream[g]);
+                if (G.join[g]) (void)hipEventDestroy(G.join[g]);
+            }
+            if (G.fork) (void)hipEventDestroy(G.fork);
+            G = GroupStreams();
+            return hip_fail(e, "group streams");
+        }
+    }
+    *out = &G;
+    return MG_OK;
+}
+
+// Enqueues the plan's launches: the shared prefix on s, then each group on its
+// own stream, forked from s and joined back to it. `timed` lets the kernel
+// timer attach events.
 int run_plan(const Plan& P, hipStream_t s, bool timed) {
     hipError_t e = launch_batch_zero(P.dtrees, (int32_t)P.trees.size(), P.max_nodes, P.sd, s);
     if (e != hipSuccess) return hip_fail(e, "batch zero");
-    for (size_t d = 0; d + 1 < P.level_ptr.size(); ++d) {
-        const int32_t b = P.level_ptr[d], n = P.level_ptr[d + 1] - b;
-        if (n <= 0) continue;
+    GroupStreams* GS = nullptr;
+    if (P.groups > 0) {
+        int rc = group_streams(P.device, &GS);
+        if (rc != MG_OK) return rc;
+    }
+    bool forked = false;
+    for (const Plan::Launch& L : P.launches) {
+        if (L.stream > 0 && !forked) {
+            e = hipEventRecord(GS->fork, s);
+            for (int32_t g = 0; g < P.groups && e == hipSuccess; ++g) e = hipStreamWaitEvent(GS->stream[g], GS->fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "group fork");
+            forked = true;
+        }
         hipEvent_t t0 = nullptr, t1 = nullptr;
         if (timed) {
             int rc = next_events(P.device, &t0, &t1);
             if (rc != MG_OK) return rc;
         }
-        e = launch_batch_level(P.dtrees, P.ditems + b, n, P.sd, (int32_t)d, s, P.shape, t0, t1);
+        hipStream_t ls = L.stream == 0 ? s : GS->stream[L.stream - 1];
+        e = launch_batch_level(P.dtrees, P.ditems + L.begin, L.count, P.sd, L.depth, ls, P.shape, t0, t1);
         if (e != hipSuccess) return hip_fail(e, "batch level");
         if (t0) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
-            g_timing.units += (int64_t)n * tiles_per_node(P.sd, P.shape);
+            g_timing.units += (int64_t)L.count * tiles_per_node(P.sd, P.shape);
         }
+    }
+    if (forked) {
+        for (int32_t g = 0; g < P.groups && e == hipSuccess; ++g) {
+            e = hipEventRecord(GS->join[g], GS->stream[g]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, GS->join[g], 0);
+        }
+        if (e != hipSuccess) return hip_fail(e, "group join");
     }
     return MG_OK;
 }
@@ -218,7 +365,7 @@ std::vector<int64_t> tune_key(const Plan& P) {
     while ((1ull << (lg + 1)) <= P.total) ++lg;
     return {v.params.n_az, v.params.n_el, v.params.yaw_bins, bits(v.params.fov_h_deg), bits(v.params.fov_v_deg),
             bits(P.sd.rv), v.map->nx, v.map->ny, v.map->nz, (int64_t)P.trees.size(),
-            (int64_t)P.level_ptr.size(), lg, P.device};
+            (int64_t)P.levels, lg, P.device};
 }
 
 // Times every launch shape on the plan itself (second of two runs each) and
@@ -230,7 +377,7 @@ int autotune(Plan& P, hipStream_t s) {
     int best = 0;
     float best_ms = 0.f;
     bool any = false;
-    const int32_t deepest = (int32_t)P.level_ptr.size() - 2;   // most ancestors of any node
+    const int32_t deepest = P.levels - 1;                     // most ancestors of any node
     for (int k = 0; k < shape_count() && e == hipSuccess; ++k) {
         if (!shape_fits(P.sd, k, deepest)) continue;         // needs more LDS than the device has
         P.shape = k;
@@ -438,21 +585,39 @@ extern "C" int mg_timing_enable(int32_t on) {
     return MG_OK;
 }
 
-extern "C" int mg_timing_read(double* total_ms, int64_t* launches, int64_t* workgroups) {
+extern "C" int mg_timing_read(double* total_ms, double* busy_ms, int64_t* launches, int64_t* workgroups) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
     double sum = 0.0;
+    std::vector<std::pair<double, double>> iv;     // launch intervals relative to the first start
     for (size_t i = 0; i < g_timing.used; ++i) {
         hipError_t e = hipEventSynchronize(g_timing.ev[i].second);
-        float ms = 0.f;
+        float ms = 0.f, a = 0.f, b = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_timing.ev[i].first, g_timing.ev[i].second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&a, g_timing.ev[0].first, g_timing.ev[i].first);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, g_timing.ev[0].first, g_timing.ev[i].second);
         if (e != hipSuccess) {
             g_timing.used = 0;
             g_timing.units = 0;
             return hip_fail(e, "timing readout");
         }
         sum += ms;
+        iv.emplace_back(a, b);
     }
+    // union of the intervals: time during which at least one timed launch ran
+    std::sort(iv.begin(), iv.end());
+    double busy = 0.0, lo = 0.0, hi = 0.0;
+    for (size_t i = 0; i < iv.size(); ++i) {
+        if (i == 0 || iv[i].first > hi) {
+            busy += hi - lo;
+            lo = iv[i].first;
+            hi = iv[i].second;
+        } else {
+            hi = std::max(hi, iv[i].second);
+        }
+    }
+    busy += hi - lo;
     if (total_ms) *total_ms = sum;
+    if (busy_ms) *busy_ms = busy;
     if (launches) *launches = (int64_t)g_timing.used;
     if (workgroups) *workgroups = g_timing.units;
     g_timing.used = 0;

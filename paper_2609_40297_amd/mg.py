@@ -82,7 +82,7 @@ def lib() -> C.CDLL:
         L.mg_trace_shapes.argtypes = [C.POINTER(I32), P, P, I32]
         L.mg_batch_plan_info.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32)]
         L.mg_timing_enable.argtypes = [I32]
-        L.mg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(I64), C.POINTER(I64)]
+        L.mg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I64), C.POINTER(I64)]
         L.mg_last_error.argtypes = []
         L.mg_last_error.restype = C.c_char_p
         for name in ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_eval_marginal",
@@ -206,10 +206,10 @@ def mg_timing_enable(on: bool):
 
 
 def mg_timing_read():
-    """(summed trace-kernel ms, timed launches, workgroups) since the last read."""
-    ms, n, wg = C.c_double(), C.c_int64(), C.c_int64()
-    _check(lib().mg_timing_read(C.byref(ms), C.byref(n), C.byref(wg)))
-    return ms.value, n.value, wg.value
+    """(summed trace-kernel ms, ms during which one ran, timed launches, workgroups) since the last read."""
+    ms, busy, n, wg = C.c_double(), C.c_double(), C.c_int64(), C.c_int64()
+    _check(lib().mg_timing_read(C.byref(ms), C.byref(busy), C.byref(n), C.byref(wg)))
+    return ms.value, busy.value, n.value, wg.value
 
 
 def mg_sensor_tables(sensor):

@@ -129,19 +129,19 @@ def test_kernel_timing_counts_trace_launches_and_keeps_results(mg):
     try:
         for _ in range(2):
             _check_batch(mg, [T], ref)
-        ms, n, wg = mg.mg_timing_read()
+        ms, busy, n, wg = mg.mg_timing_read()
     finally:
         mg.mg_timing_enable(False)
     sen = w.sensor
     shape, _ = mg.mg_batch_plan_info([T.handle])
     threads = mg.mg_trace_shapes()[shape][0]
     tiles = -(-sen.n_az * sen.n_el // threads)
-    assert n == 2 * levels
-    assert wg == 2 * T.n * tiles
-    assert ms > 0.0
-    assert mg.mg_timing_read() == (0.0, 0, 0)
+    assert n % 2 == 0 and n // 2 >= levels      # at least one launch per level (groups may split levels)
+    assert wg == 2 * T.n * tiles                # every node traced exactly once per call
+    assert ms > 0.0 and 0.0 < busy <= ms * 1.001
+    assert mg.mg_timing_read() == (0.0, 0.0, 0, 0)
     _check_batch(mg, [T], ref)                       # timing off again: no intervals recorded
-    assert mg.mg_timing_read()[1] == 0
+    assert mg.mg_timing_read()[2] == 0
     T.close()
     M.close()
 
