@@ -354,7 +354,9 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             const bool occ = st == kOccupied;
             h = occ ? t : h;
             n_abs += unk ? 1u : 0u;
-            if (kMarginal) {
+            // queueing runs only in steps where some lane of the wave is on an
+            // unknown voxel (a wave-uniform branch)
+            if (kMarginal && ballot(unk) != 0) {
                 // a lane whose unknown voxel and bin equal the previous lane's
                 // joins that lane's entry; the first lane of each run appends
                 // one entry carrying the run's length. Keys of other lanes are
