@@ -29,6 +29,13 @@ def gpu_eval_tree(mgmod, m, tree, sensor, depth=True, mode="marginal"):
         out["k_db"] = y.cpu().numpy()
         if depth:
             out["D"] = d.cpu().numpy().reshape(tree.n, sensor.n_el, sensor.w_buf)
+    if mode == "batch":                     # the multi-tree path on this one tree (autotuned, stream groups)
+        g, y, d = mgmod.eval_batch([T], depth=depth)
+        torch.cuda.synchronize()
+        out["g_db"] = mgmod.as_u32(g)
+        out["k_db"] = y.cpu().numpy()
+        if depth:
+            out["D"] = d.cpu().numpy().reshape(tree.n, sensor.n_el, sensor.w_buf)
     if mode in ("absolute", "both"):
         g, y = T.eval_absolute()
         torch.cuda.synchronize()

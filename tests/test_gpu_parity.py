@@ -38,6 +38,8 @@ def _full_parity(mg, orc, m, tree, sen, label):
     ref = orc.eval_tree(m, tree, sen, n_threads=threads())
     got = gpu_eval_tree(mg, m, tree, sen, depth=True, mode="both")
     assert_same(got, ref, keys=("g_db", "k_db", "D", "g_abs", "k_abs"))
+    batched = gpu_eval_tree(mg, m, tree, sen, depth=True, mode="batch")
+    assert_same(batched, ref, keys=("g_db", "k_db", "D"))
     return got, ref
 
 
@@ -101,6 +103,25 @@ def test_occupied_everywhere_and_unknown_everywhere(mg, orc):
     _full_parity(mg, orc, unk, tree, sen, "all-unknown")
 
 
+def test_widest_panorama_or_clean_refusal(mg, orc):
+    """The widest panorama this build accepts (4096 columns): bit-exact if the device's LDS per
+    workgroup holds its tables, otherwise MG_E_UNSUPPORTED at upload with nothing launched."""
+    w = W.make("tiny")
+    sen = W.Sensor(n_az=4096, n_el=2, fov_h_deg=90, fov_v_deg=60, range_m=3.0, yaw_bins=64)
+    tree = W.Tree(pos_m=w.trees[0].pos_m[:3].copy(), parent=np.array([-1, 0, 1], np.int32))
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    try:
+        T = mg.Tree(M, tree.pos_m, tree.parent, sen)
+    except mg.MGError as e:
+        log(f"[parity] 4096-column panorama refused: {e}")
+        assert e.code == mg.MG_E_UNSUPPORTED
+        M.close()
+        return
+    T.close()
+    M.close()
+    _full_parity(mg, orc, w.map, tree, sen, "4096 columns")
+
+
 # ----------------------------------------------------------------- full-size workloads
 
 def test_step_full_parity(mg, orc):
@@ -152,6 +173,38 @@ def test_large_sampled(mg, orc):
     log(f"[parity] large: sampled {int(mask.sum())} nodes")
     ref = orc.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads())
     assert_same(got, ref, nodes=np.flatnonzero(mask))
+
+
+def test_large_bench_configuration(mg, orc):
+    """The large workload as bench.py times it: all 8 trees in one batched call (autotuned launch
+    shape, stream groups); two leaves' ancestor chains of two trees against the oracle, and the
+    bound G_db <= G_abs with equality at the roots on every node."""
+    import torch
+    w = W.make("large")
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    trees = [mg.Tree(M, t.pos_m, t.parent, w.sensor) for t in w.trees]
+    log(f"[parity] large batched: {len(trees)} trees, {sum(t.n for t in trees)} nodes")
+    gb, yb, db = mg.eval_batch(trees, depth=True)
+    torch.cuda.synchronize()
+    off = 0
+    for i, (t, T) in enumerate(zip(w.trees, trees)):
+        ga, _ = T.eval_absolute()
+        torch.cuda.synchronize()
+        g = mg.as_u32(gb[off:off + t.n])
+        assert np.all(g <= mg.as_u32(ga)) and g[0] == mg.as_u32(ga)[0], i
+        if i in (0, 5):
+            dep = t.depth()
+            leaves = np.flatnonzero(dep == dep.max())[:2]
+            mask = orc.ancestor_closure(t.parent, leaves)
+            log(f"[parity] large tree {i}: sampled {int(mask.sum())} nodes")
+            ref = orc.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads())
+            got = dict(g_db=g, k_db=yb[off:off + t.n].cpu().numpy(),
+                       D=db[off:off + t.n].cpu().numpy().reshape(t.n, w.sensor.n_el, w.sensor.w_buf))
+            assert_same(got, ref, nodes=np.flatnonzero(mask))
+        off += t.n
+    for T in trees:
+        T.close()
+    M.close()
 
 
 # ----------------------------------------------------------------- modes and determinism
