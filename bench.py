@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--trees", type=int, default=None, help="keep only the first trees of a multi-tree workload")
     ap.add_argument("--modes", default="plain,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6)
+    ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6, help="oracle sample, rays per host thread")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -106,9 +106,21 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 3}), flush=True)
 
 
-def cpu_baseline(w, target_rays):
-    """The oracle as it stands, one thread, on ancestor-closed chains of leaves of tree 0."""
+def cpu_threads():
+    """Host threads for the oracle leg: the cores this process may use, at most 16 (one GPU's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(w, target_rays_per_thread):
+    """The oracle as it stands, with its threaded driver (nodes of a level in parallel), on an
+    ancestor-closed set of deepest leaves of tree 0 (the whole tree if the target exceeds it)."""
     from oracle import mgref
+    threads = cpu_threads()
+    target_rays = target_rays_per_thread * threads
     t = w.trees[0]
     dep = t.depth()
     order = np.argsort(-dep, kind="stable")
@@ -120,12 +132,12 @@ def cpu_baseline(w, target_rays):
         if mask.sum() * w.sensor.rays >= target_rays:
             break
     t0 = time.perf_counter()
-    mgref.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=1)
+    mgref.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads)
     dt = time.perf_counter() - t0
     rays = int(mask.sum()) * w.sensor.rays
-    return {"value": rays / dt, "unit": "rays/s", "cores": 1, "kind": "oracle",
-            "sample": f"{int(mask.sum())} nodes ({len(leaves)} deepest leaves of tree 0 and their ancestors), "
-                      f"{rays} rays, {dt:.1f} s on one thread"}
+    what = "all nodes of tree 0" if mask.all() else f"{len(leaves)} deepest leaves of tree 0 and their ancestors"
+    return {"value": rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{int(mask.sum())} nodes ({what}), {rays} rays, {dt:.1f} s on {threads} threads"}
 
 
 def serve_bench(args):
@@ -351,7 +363,7 @@ def main():
                           "overlap); avg_launch_ms = mean single-launch duration"}
     cpu = None
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle, one thread, bounded sample)")
+        log("[bench] cpu baseline (oracle on the host threads, bounded sample)")
         cpu = cpu_baseline(w, args.cpu_sample_rays)
         log(f"[bench] cpu: {cpu}")
 
