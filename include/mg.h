@@ -128,7 +128,8 @@ int mg_eval_marginal_levelsync(mg_tree tree, void* hip_stream, uint32_t* gain, i
  * concatenated in tree order (tree t's nodes start at the sum of the node
  * counts of trees < t). Results equal per-tree mg_eval_marginal calls. The
  * launch plan (tree descriptors, per-level work lists) is built on the first
- * call with a given tree list and reused. */
+ * call with a given tree list and reused. MG_E_INVALID when a tree appears
+ * twice in the list. */
 int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
                            int32_t* yaw_bin, float* depth);
 

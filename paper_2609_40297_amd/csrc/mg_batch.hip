@@ -498,6 +498,13 @@ extern "C" int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, voi
     if (!trees || n_trees < 1 || !gain || !yaw_bin) return mgb::set_error(MG_E_INVALID, "bad batch arguments");
     for (int32_t i = 0; i < n_trees; ++i)
         if (!trees[i]) return mgb::set_error(MG_E_INVALID, "NULL tree in batch");
+    {
+        // a tree listed twice would have two descriptors writing its bins and buffers
+        std::vector<mg_tree> sorted(trees, trees + n_trees);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return mgb::set_error(MG_E_INVALID, "a tree appears twice in the batch");
+    }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -102,6 +102,17 @@ def test_batch_of_the_step_tree(mg):
     M.close()
 
 
+def test_batch_rejects_a_tree_listed_twice(mg):
+    w = W.make("tiny")
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    a = mg.Tree(M, w.trees[0].pos_m, w.trees[0].parent, w.sensor)
+    with pytest.raises(mg.MGError) as e:
+        mg.eval_batch([a, a])
+    assert e.value.code == mg.MG_E_INVALID
+    a.close()
+    M.close()
+
+
 def test_batch_rejects_mixed_geometry(mg):
     w = W.make("tiny")
     M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
