@@ -33,6 +33,51 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def score_bench(mg, trees, gain, n_total, depth_sum, reps=200):
+    """Device path score (eq. 3, eq. 4, best branch) of the evaluated batch: HIP events around
+    `reps` back-to-back mg_score_branches calls on the current stream."""
+    import torch
+    dev = gain.device
+    cost = torch.empty(n_total, dtype=torch.float64, device=dev)
+    obj = torch.empty(n_total, dtype=torch.float64, device=dev)
+    best = torch.empty(len(trees), dtype=torch.int32, device=dev)
+    branch = torch.empty((len(trees), mg.MG_BRANCH_LEN), dtype=torch.int32, device=dev)
+    handles = [t.handle for t in trees]
+    for _ in range(5):
+        mg.mg_score_branches(handles, gain, 0.5, cost, obj, best, branch)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        mg.mg_score_branches(handles, gain, 0.5, cost, obj, best, branch)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    # algorithmic bytes: per node its gain (4 B), position (16 B), parent link (4 B) and cost + objective
+    # (16 B) once, each ancestor id of its root path (4 B) once; per tree the branch row (65 x 4 B)
+    alg = n_total * 40 + depth_sum * 4 + len(trees) * (mg.MG_BRANCH_LEN * 4 + 4)
+    gbs = alg / (us * 1e-6) / 1e9
+    return {"us_per_call": us, "nodes_per_s": n_total / (us * 1e-6), "launches_per_call": 2,
+            "lambda": 0.5, "algorithmic_bytes_per_call": alg,
+            "roofline": {"bound": "latency", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+            "d2h_bytes_replaced": n_total * 8, "d2h_bytes_after": len(trees) * (mg.MG_BRANCH_LEN * 4 + 4)}
+
+
+def score_oracle(w):
+    """The path-score oracle over every tree of the workload, on gains of 1 per node (its cost does
+    not depend on the values)."""
+    from oracle import paths
+    t0 = time.perf_counter()
+    for t in w.trees:
+        paths.score_paths(t.pos_m, t.parent, np.ones(t.n, np.uint32), w.map.voxel_m, 0.5)
+    dt = time.perf_counter() - t0
+    n = sum(t.n for t in w.trees)
+    return {"us_per_call": dt * 1e6, "nodes_per_s": n / dt, "cores": 1, "kind": "oracle",
+            "sample": f"all {len(w.trees)} trees, {n} nodes, one thread"}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -361,10 +406,16 @@ def main():
                 "timing": "HIP events recorded by each trace dispatch over the timed steps; achieved = "
                           "algorithmic bytes / union of the launch intervals (launches of the two groups "
                           "overlap); avg_launch_ms = mean single-launch duration"}
+    score = None
+    if "batched" in results:
+        score = score_bench(mg, trees, g_all, n_total, int(sum(t.depth().sum() for t in w.trees)))
+        log(f"[bench] path score: {score}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on the host threads, bounded sample)")
         cpu = cpu_baseline(w, args.cpu_sample_rays)
+        if score is not None:
+            cpu["path_score"] = score_oracle(w)
         log(f"[bench] cpu: {cpu}")
 
     line = {
@@ -389,6 +440,7 @@ def main():
         "modes": results,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "path_score": score,
     }
     print(json.dumps(line), flush=True)
     for T in trees:

@@ -43,6 +43,10 @@ enum {
     MG_E_UNSUPPORTED = -5   /* valid input outside the sizes this build handles */
 };
 
+/* Longest root path of a tree (depth <= 64): the row length of the branch
+ * output of mg_score_branches. */
+#define MG_BRANCH_LEN 65
+
 typedef struct mg_map_s* mg_map;
 typedef struct mg_tree_s* mg_tree;
 
@@ -129,9 +133,26 @@ int mg_eval_marginal_levelsync(mg_tree tree, void* hip_stream, uint32_t* gain, i
  * counts of trees < t). Results equal per-tree mg_eval_marginal calls. The
  * launch plan (tree descriptors, per-level work lists) is built on the first
  * call with a given tree list and reused. MG_E_INVALID when a tree appears
- * twice in the list. */
+ * twice in the list; MG_E_UNSUPPORTED for more than 65535 trees. */
 int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
                            int32_t* yaw_bin, float* depth);
+
+/* Path score of every node of a batch (Sec. III-C): traversal cost
+ * c(n) = c(Pa(n)) + |p_n - p_Pa(n)| in metres (eq. 3) and exponential
+ * objective o(n) = o(Pa(n)) + g(n) exp(-lambda c(n)) (eq. 4), with g(n) the
+ * gain count times the voxel volume (m^3) and c(root) = 0, o(root) = g(root);
+ * float64 on the float32 positions. best[t] is tree t's node of largest o
+ * (smallest id on ties): the end of its best branch. branch (may be NULL):
+ * DEVICE int32 [n_trees][MG_BRANCH_LEN], row t the node ids of that branch
+ * from the root to best[t], then -1 to the end of the row; the first node
+ * after the root is the segment a planner executes. The tree list must have a
+ * plan (a prior
+ * mg_eval_marginal_batch call); gain is the DEVICE uint32 array of gains in
+ * the batch's concatenated order (usually that call's output), enqueued on
+ * hip_stream after it. cost (may be NULL) and objective: DEVICE double [sum of
+ * n]; best: DEVICE int32 [n_trees]. MG_E_INVALID for lambda < 0 or no plan. */
+int mg_score_branches(const mg_tree* trees, int32_t n_trees, void* hip_stream, const uint32_t* gain, double lambda,
+                      double* cost, double* objective, int32_t* best, int32_t* branch);
 
 /* Launch configuration of mg_eval_marginal_batch for plans built after this
  * call (cached plans are dropped, after the device has finished their work).

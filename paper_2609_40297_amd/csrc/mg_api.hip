@@ -428,10 +428,10 @@ namespace mgb {
 // Host side of a tree upload: validation and every array the device needs.
 struct HostTree {
     int32_t n = 0, maxd = 0;
-    std::vector<float4> q4;
+    std::vector<float4> q4, pm;
     std::vector<int32_t> depth, level_ptr, level_nodes, anc_ptr, anc_ids, child_ptr, child_ids, parent;
     // device block layout
-    size_t o_q4 = 0, o_ap = 0, o_ai = 0, o_ln = 0, o_cp = 0, o_ci = 0, o_c0 = 0, o_g = 0, o_y = 0, o_bins = 0,
+    size_t o_q4 = 0, o_pm = 0, o_ap = 0, o_ai = 0, o_ln = 0, o_cp = 0, o_ci = 0, o_c0 = 0, o_g = 0, o_y = 0, o_bins = 0,
            o_dpan = 0, total = 0;
 };
 
@@ -463,6 +463,7 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
         if (H->depth[i] > kMaxAnc) return fail(MG_E_INVALID, "node %d is deeper than %d", i, kMaxAnc);
     }
     H->q4.resize(n);
+    H->pm.resize(n);
     const int32_t dims[3] = {map->dev.nx, map->dev.ny, map->dev.nz};
     for (int32_t i = 0; i < n; ++i) {
         float qv[3];
@@ -473,6 +474,7 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
             qv[a] = v;
         }
         H->q4[i] = make_float4(qv[0], qv[1], qv[2], 0.f);
+        H->pm[i] = make_float4(pos_m[3 * i], pos_m[3 * i + 1], pos_m[3 * i + 2], 0.f);
     }
     H->maxd = 0;
     for (int32_t i = 0; i < n; ++i) H->maxd = std::max(H->maxd, H->depth[i]);
@@ -505,6 +507,7 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     H->o_q4 = take(sizeof(float4) * n);
+    H->o_pm = take(sizeof(float4) * n);
     H->o_ap = take(sizeof(int32_t) * (n + 1));
     H->o_ai = take(sizeof(int32_t) * H->anc_ids.size());
     H->o_ln = take(sizeof(int32_t) * n);
@@ -535,6 +538,7 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     };
     std::vector<int32_t> zeros_c0(n, 0);
     hipError_t e = up(H.o_q4, H.q4.data(), sizeof(float4) * n);
+    if (e == hipSuccess) e = up(H.o_pm, H.pm.data(), sizeof(float4) * n);
     if (e == hipSuccess) e = up(H.o_ap, H.anc_ptr.data(), sizeof(int32_t) * (n + 1));
     if (e == hipSuccess) e = up(H.o_ai, H.anc_ids.data(), sizeof(int32_t) * H.anc_ids.size());
     if (e == hipSuccess) e = up(H.o_ln, H.level_nodes.data(), sizeof(int32_t) * n);
@@ -547,6 +551,7 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
         return fail(MG_E_DEVICE, "tree upload: %s", hipGetErrorString(e));
     }
     t->dev.q4 = (const float4*)(base + H.o_q4);
+    t->dev.pm = (const float4*)(base + H.o_pm);
     t->dev.anc_ptr = (const int32_t*)(base + H.o_ap);
     t->dev.anc_ids = (const int32_t*)(base + H.o_ai);
     t->dev.level_nodes = (const int32_t*)(base + H.o_ln);
@@ -706,6 +711,7 @@ int tree_view(mg_tree t, TreeView* v) {
     v->scratch_gain = t->scratch_gain;
     v->scratch_yaw = t->scratch_yaw;
     v->params = t->params;
+    v->voxel_m = t->map->voxel_m;
     v->n = t->n;
     v->levels = t->levels;
     v->device = t->device;

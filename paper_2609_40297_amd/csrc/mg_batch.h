@@ -18,6 +18,7 @@ struct TreeView {
     uint32_t* scratch_gain;                    // device outputs inside the tree's block
     int32_t* scratch_yaw;
     mg_sensor params;
+    float voxel_m;                             // edge of the tree's map voxels (metres)
     int32_t n, levels, device;
 };
 

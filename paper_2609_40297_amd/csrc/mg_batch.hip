@@ -107,6 +107,8 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
         bt[i].td = *v.td;
         bt[i].rv = v.sd->rv;
         bt[i].rv2 = v.sd->rv2;
+        bt[i].vox3 = (double)v.voxel_m * (double)v.voxel_m * (double)v.voxel_m;
+        bt[i].out_off = P->total;
         bt[i].gain = gain + P->total;
         bt[i].yaw = yaw + P->total;
         bt[i].depth = depth ? depth + (size_t)P->total * v.sd->H * v.sd->WB : nullptr;
@@ -496,6 +498,7 @@ void forget_tree(mg_tree t) {
 extern "C" int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
                                       int32_t* yaw_bin, float* depth) {
     if (!trees || n_trees < 1 || !gain || !yaw_bin) return mgb::set_error(MG_E_INVALID, "bad batch arguments");
+    if (n_trees > 65535) return mgb::set_error(MG_E_UNSUPPORTED, "more than 65535 trees in one batch");
     for (int32_t i = 0; i < n_trees; ++i)
         if (!trees[i]) return mgb::set_error(MG_E_INVALID, "NULL tree in batch");
     {
@@ -535,6 +538,27 @@ extern "C" int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, voi
     // the kernel timer needs the launches made one by one
     if (!P.exec || timing_on()) return run_plan(P, s, true);
     return replay(P, s);
+}
+
+extern "C" int mg_score_branches(const mg_tree* trees, int32_t n_trees, void* hip_stream, const uint32_t* gain,
+                                 double lambda, double* cost, double* objective, int32_t* best, int32_t* branch) {
+    if (!trees || n_trees < 1 || !gain || !objective || !best)
+        return mgb::set_error(MG_E_INVALID, "bad scoring arguments");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return mgb::set_error(MG_E_INVALID, "lambda must be >= 0");
+    std::vector<mg_tree> key(trees, trees + n_trees);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end())
+        return mgb::set_error(MG_E_INVALID, "no plan for this tree list (evaluate it with mg_eval_marginal_batch first)");
+    const Plan& P = *it->second;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (P.device != dev) return mgb::set_error(MG_E_INVALID, "batch trees live on another device");
+    e = launch_score(P.dtrees, n_trees, P.max_nodes, gain, lambda, cost, objective, best, branch,
+                     (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "path score");
+    return MG_OK;
 }
 
 extern "C" int mg_batch_config(int32_t shape, int32_t graph) {

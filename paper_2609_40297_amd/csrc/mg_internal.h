@@ -67,6 +67,7 @@ struct SensorDev {
 // node's buffer is the window slice starting at column c0[n].
 struct TreeDev {
     const float4* q4;          // [n] position in voxel units
+    const float4* pm;          // [n] position in metres, as given
     const int32_t* anc_ptr;    // [n+1] CSR into anc_ids
     const int32_t* anc_ids;    // ancestors, nearest first
     const int32_t* level_nodes;// [n] nodes sorted by depth
@@ -84,6 +85,8 @@ struct BatchTree {
     MapDev map;
     TreeDev td;
     float rv, rv2;
+    double vox3;               // voxel volume (m^3): a gain count times this is a volume
+    uint32_t out_off;          // first node of this tree in the concatenated outputs
     uint32_t* gain;            // [n]
     int32_t* yaw;              // [n]
     float* depth;              // [n][H][WB] or NULL
@@ -107,6 +110,9 @@ size_t trace_lds_bytes(const SensorDev& sd, int shape, int32_t max_anc);
 int32_t tiles_per_node(const SensorDev& sd, int shape);
 size_t lds_limit();                        // LDS bytes one workgroup may use on the current device
 bool shape_fits(const SensorDev& sd, int shape, int32_t max_anc);
+// Path score of every node of the trees (eq. 3, eq. 4) and each tree's best node.
+hipError_t launch_score(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const uint32_t* gain,
+                        double lambda, double* cost, double* obj, int32_t* best, int32_t* branch, hipStream_t s);
 hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const SensorDev& sd,
                              hipStream_t s);
 // One depth level of many trees: trace with launch shape `shape`, then window

@@ -630,6 +630,88 @@ hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- path score (eq. 3, eq. 4)
+
+// One thread per node of one tree (grid: blocks x trees). The traversal cost
+// (eq. 3) and the exponential objective (eq. 4) are summed from the root down
+// the node's ancestor list (nearest first, so walked backwards), in the order
+// the recursions take: c += |p_m - p_prev| and o += g(m) v^3 exp(-lambda c),
+// in float64 on the float32 positions in metres.
+__global__ void k_score(const BatchTree* __restrict__ trees, const uint32_t* __restrict__ gain, double lambda,
+                        double* __restrict__ cost, double* __restrict__ obj) {
+    const BatchTree& T = trees[blockIdx.y];
+    const int32_t node = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (node >= T.td.n) return;
+    const uint32_t* g = gain + T.out_off;
+    const int32_t a0 = T.td.anc_ptr[node], a1 = T.td.anc_ptr[node + 1];
+    int32_t prev = a1 > a0 ? T.td.anc_ids[a1 - 1] : node;      // the root
+    double c = 0.0;
+    double o = (double)g[prev] * T.vox3;
+    for (int32_t k = a1 - 2; k >= a0 - 1; --k) {
+        const int32_t m = k >= a0 ? T.td.anc_ids[k] : node;
+        const float4 pa = T.td.pm[prev], pb = T.td.pm[m];
+        const double dx = (double)pb.x - (double)pa.x;
+        const double dy = (double)pb.y - (double)pa.y;
+        const double dz = (double)pb.z - (double)pa.z;
+        c = c + sqrt(dx * dx + dy * dy + dz * dz);
+        o = o + (double)g[m] * T.vox3 * exp(-lambda * c);
+        prev = m;
+    }
+    if (cost) cost[T.out_off + node] = c;
+    obj[T.out_off + node] = o;
+}
+
+// One workgroup per tree: the node of largest objective, smallest id on ties,
+// and (if asked) its root path, root first, padded with -1.
+__global__ __launch_bounds__(kThreads) void k_best(const BatchTree* __restrict__ trees,
+                                                   const double* __restrict__ obj, int32_t* __restrict__ best,
+                                                   int32_t* __restrict__ branch) {
+    __shared__ double s_o[kThreads];
+    __shared__ int32_t s_i[kThreads];
+    const BatchTree& T = trees[blockIdx.x];
+    const double* o = obj + T.out_off;
+    double bo = 0.0;
+    int32_t bi = -1;
+    for (int32_t i = threadIdx.x; i < T.td.n; i += kThreads)
+        if (bi < 0 || o[i] > bo) {           // ids ascend, so a later equal value never wins
+            bo = o[i];
+            bi = i;
+        }
+    s_o[threadIdx.x] = bo;
+    s_i[threadIdx.x] = bi;
+    __syncthreads();
+    for (int32_t off = kThreads / 2; off > 0; off >>= 1) {
+        if ((int32_t)threadIdx.x < off) {
+            const double po = s_o[threadIdx.x + off];
+            const int32_t pi = s_i[threadIdx.x + off];
+            const double mo = s_o[threadIdx.x];
+            const int32_t mi = s_i[threadIdx.x];
+            if (pi >= 0 && (mi < 0 || po > mo || (po == mo && pi < mi))) {
+                s_o[threadIdx.x] = po;
+                s_i[threadIdx.x] = pi;
+            }
+        }
+        __syncthreads();
+    }
+    const int32_t b = s_i[0];
+    if (threadIdx.x == 0) best[blockIdx.x] = b;
+    if (branch && threadIdx.x < kMaxAnc + 1) {
+        const int32_t a0 = T.td.anc_ptr[b], d = T.td.anc_ptr[b + 1] - a0;     // ancestors, nearest first
+        const int32_t t = (int32_t)threadIdx.x;
+        branch[(size_t)blockIdx.x * (kMaxAnc + 1) + t] = t < d ? T.td.anc_ids[a0 + d - 1 - t] : t == d ? b : -1;
+    }
+}
+
+hipError_t launch_score(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const uint32_t* gain,
+                        double lambda, double* cost, double* obj, int32_t* best, int32_t* branch, hipStream_t s) {
+    hipLaunchKernelGGL(k_score, dim3((unsigned)grid_for(max_nodes, 256), (unsigned)n_trees), dim3(256), 0, s, trees,
+                       gain, lambda, cost, obj);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_best, dim3((unsigned)n_trees), dim3(kThreads), 0, s, trees, obj, best, branch);
+    return hipGetLastError();
+}
+
 }  // namespace mgk
 
 namespace mgk {

@@ -28,7 +28,7 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_eval_marginal_batch", "mg_eval_absolute", "mg_sensor_tables", "mg_last_error",
            "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait", "mg_server_stats",
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
-           "mg_batch_plan_info")
+           "mg_batch_plan_info", "mg_score_branches")
 
 
 class MGError(RuntimeError):
@@ -81,6 +81,7 @@ def lib() -> C.CDLL:
         L.mg_batch_config.argtypes = [I32, I32]
         L.mg_trace_shapes.argtypes = [C.POINTER(I32), P, P, I32]
         L.mg_batch_plan_info.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32)]
+        L.mg_score_branches.argtypes = [P, I32, P, P, C.c_double, P, P, P, P]
         L.mg_timing_enable.argtypes = [I32]
         L.mg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I64), C.POINTER(I64)]
         L.mg_last_error.argtypes = []
@@ -89,7 +90,8 @@ def lib() -> C.CDLL:
                      "mg_eval_marginal_levelsync", "mg_eval_marginal_batch", "mg_eval_absolute",
                      "mg_sensor_tables", "mg_server_create", "mg_server_submit", "mg_server_poll",
                      "mg_server_wait", "mg_server_stats", "mg_server_destroy", "mg_timing_enable",
-                     "mg_timing_read", "mg_batch_config", "mg_trace_shapes", "mg_batch_plan_info"):
+                     "mg_timing_read", "mg_batch_config", "mg_trace_shapes", "mg_batch_plan_info",
+                     "mg_score_branches"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -177,6 +179,28 @@ def mg_eval_marginal_batch(trees: Sequence[int], gain, yaw_bin, depth=None, stre
 
 def mg_eval_absolute(tree: int, gain, yaw_bin, stream=None):
     _check(lib().mg_eval_absolute(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin)))
+
+
+MG_BRANCH_LEN = 65
+
+
+def mg_score_branches(trees: Sequence[int], gain, lam: float, cost, objective, best, branch=None, stream=None):
+    arr = (C.c_void_p * len(trees))(*trees)
+    _check(lib().mg_score_branches(C.cast(arr, C.c_void_p), len(trees), _stream(stream), _dev_ptr(gain), float(lam),
+                                   _dev_ptr(cost), _dev_ptr(objective), _dev_ptr(best), _dev_ptr(branch)))
+
+
+def score_batch(trees, gain, lam=0.5, stream=None):
+    """Device path score of a batch already evaluated: (cost, objective, best, branch) tensors."""
+    import torch
+    n = sum(t.n for t in trees)
+    dev = gain.device
+    cost = torch.empty(n, dtype=torch.float64, device=dev)
+    obj = torch.empty(n, dtype=torch.float64, device=dev)
+    best = torch.empty(len(trees), dtype=torch.int32, device=dev)
+    branch = torch.empty((len(trees), MG_BRANCH_LEN), dtype=torch.int32, device=dev)
+    mg_score_branches([t.handle for t in trees], gain, lam, cost, obj, best, branch, stream)
+    return cost, obj, best, branch
 
 
 def mg_batch_config(shape: int = -1, graph: bool = False):
