@@ -92,6 +92,7 @@ def parse():
     ap.add_argument("--trees", type=int, default=None, help="keep only the first trees of a multi-tree workload")
     ap.add_argument("--modes", default="plain,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sp-steps", type=int, default=5, help="timed single-parent (g_sp) passes; 0 skips")
     ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6, help="oracle sample, rays per host thread")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (calibrates HBM byte counters) and exit")
@@ -406,6 +407,23 @@ def main():
                 "timing": "HIP events recorded by each trace dispatch over the timed steps; achieved = "
                           "algorithmic bytes / union of the launch intervals (launches of the two groups "
                           "overlap); avg_launch_ms = mean single-launch duration"}
+    sp = None
+    if args.sp_steps > 0:
+        # single-parent gain g_sp (the comparison gain of Fig. 4) on the same trees, per-tree path
+        g_sp = torch.empty(max(t.n for t in trees), dtype=torch.int32, device=dev)
+        y_sp = torch.empty_like(g_sp)
+        for T in trees:
+            mg.mg_eval_single_parent(T.handle, g_sp, y_sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.sp_steps):
+            for T in trees:
+                mg.mg_eval_single_parent(T.handle, g_sp, y_sp)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.sp_steps
+        sp = {"rays_per_s": rays_per_step / dt, "ms_per_step": dt * 1e3, "steps": args.sp_steps,
+              "path": "mg_eval_single_parent, tree after tree"}
+        log(f"[bench] single parent: {sp}")
     score = None
     if "batched" in results:
         score = score_bench(mg, trees, g_all, n_total, int(sum(t.depth().sum() for t in w.trees)))
@@ -441,6 +459,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "path_score": score,
+        "single_parent": sp,
     }
     print(json.dumps(line), flush=True)
     for T in trees:

@@ -177,6 +177,13 @@ int mg_trace_shapes(int32_t* count, int32_t* threads, int32_t* queue, int32_t ca
  * of this tree list. MG_E_INVALID when the list has no plan yet. */
 int mg_batch_plan_info(const mg_tree* trees, int32_t n_trees, int32_t* shape, int32_t* graphed);
 
+/* Single-parent gain g_sp (the comparison gain of Sec. V-A, Fig. 4): as
+ * mg_eval_marginal, but each node is conditioned on its parent's depth buffer
+ * only; the parent's window and buffer are its own single-parent results.
+ * Same outputs and errors as mg_eval_marginal; it overwrites the tree's
+ * buffers, so a later path score or descendant evaluation sees these. */
+int mg_eval_single_parent(mg_tree tree, void* hip_stream, uint32_t* gain, int32_t* yaw_bin, float* depth);
+
 /* Absolute gain of every node (eq. 1 maximised over the yaw windows), no
  * conditioning and no level order: one flat launch over all nodes.
  *   gain DEVICE uint32[n], yaw_bin DEVICE int32[n]. */

@@ -561,6 +561,7 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     t->dev.bins = (uint32_t*)(base + H.o_bins);
     t->dev.dpan = (float*)(base + H.o_dpan);
     t->dev.n = n;
+    t->dev.anc_cap = kMaxAnc;
     t->scratch_gain = (uint32_t*)(base + H.o_g);
     t->scratch_yaw = (int32_t*)(base + H.o_y);
     t->sd = sensor_dev(t->sensor, sensor->range_m / map->voxel_m);
@@ -645,13 +646,15 @@ int check_device(mg_tree t) {
 // Depth-ordered evaluation: for each level, trace all its nodes' rays, then
 // select their windows; level d+1 reads the buffers and windows of levels <= d.
 int eval_levels(mg_tree t, hipStream_t s, uint32_t* gain, int32_t* yaw, float* depth, uint32_t* host_gain,
-                int32_t* host_yaw) {
-    HIP_TRY(launch_zero_u32(t->dev.bins, (size_t)2 * t->sd.B * t->n, s));
+                int32_t* host_yaw, int32_t anc_cap = kMaxAnc) {
+    TreeDev td = t->dev;
+    td.anc_cap = anc_cap;
+    HIP_TRY(launch_zero_u32(td.bins, (size_t)2 * t->sd.B * t->n, s));
     for (int32_t d = 0; d < t->levels; ++d) {
         const int32_t b = t->level_ptr[d], cnt = t->level_ptr[d + 1] - b;
-        const int32_t* nodes = t->dev.level_nodes + b;
-        HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, nodes, cnt, true, d, s));
-        HIP_TRY(launch_finish(t->sd, t->dev, nodes, cnt, true, gain, yaw, s));
+        const int32_t* nodes = td.level_nodes + b;
+        HIP_TRY(launch_trace(t->map->dev, t->sd, td, nodes, cnt, true, std::min(d, anc_cap), s));
+        HIP_TRY(launch_finish(t->sd, td, nodes, cnt, true, gain, yaw, s));
         if (host_gain) {
             // results of this level back to the host before the next level (Sec. IV-C)
             HIP_TRY(hipMemcpyAsync(host_gain, gain, sizeof(uint32_t) * t->n, hipMemcpyDeviceToHost, s));
@@ -670,6 +673,13 @@ extern "C" int mg_eval_marginal(mg_tree t, void* hip_stream, uint32_t* gain, int
     int rc = check_device(t);
     if (rc != MG_OK) return rc;
     return eval_levels(t, (hipStream_t)hip_stream, gain, yaw_bin, depth, nullptr, nullptr);
+}
+
+extern "C" int mg_eval_single_parent(mg_tree t, void* hip_stream, uint32_t* gain, int32_t* yaw_bin, float* depth) {
+    if (!t || !gain || !yaw_bin) return fail(MG_E_INVALID, "tree/gain/yaw_bin is NULL");
+    int rc = check_device(t);
+    if (rc != MG_OK) return rc;
+    return eval_levels(t, (hipStream_t)hip_stream, gain, yaw_bin, depth, nullptr, nullptr, 1);
 }
 
 extern "C" int mg_eval_marginal_levelsync(mg_tree t, void* hip_stream, uint32_t* gain, int32_t* yaw_bin,

@@ -77,6 +77,7 @@ struct TreeDev {
     float* dpan;               // [n][R]
     int32_t* c0;               // [n]
     int32_t n;
+    int32_t anc_cap;           // nearest ancestors that condition a node (kMaxAnc: all; 1: parent only)
 };
 
 // One tree of a multi-tree launch: its map and node data, its range in voxel

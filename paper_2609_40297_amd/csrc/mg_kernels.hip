@@ -283,7 +283,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     int32_t na = 0;
     if (kMarginal) {
         const int32_t a0 = Tr.anc_ptr[node];
-        na = Tr.anc_ptr[node + 1] - a0;
+        na = min(Tr.anc_ptr[node + 1] - a0, Tr.anc_cap);     // the list is nearest first
         for (int32_t k = tid; k < na; k += kTh) {
             const int32_t a = Tr.anc_ids[a0 + k];
             const float4 qa = Tr.q4[a];

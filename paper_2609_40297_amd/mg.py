@@ -25,7 +25,7 @@ _NAMES = {-1: "MG_E_INVALID", -2: "MG_E_NOMEM", -3: "MG_E_DEVICE", -4: "MG_E_BUS
 # Every entry point declared in include/mg.h.
 EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_tree_nodes",
            "mg_tree_buffer_pixels", "mg_tree_footprint_bytes", "mg_eval_marginal", "mg_eval_marginal_levelsync",
-           "mg_eval_marginal_batch", "mg_eval_absolute", "mg_sensor_tables", "mg_last_error",
+           "mg_eval_marginal_batch", "mg_eval_absolute", "mg_eval_single_parent", "mg_sensor_tables", "mg_last_error",
            "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait", "mg_server_stats",
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
            "mg_batch_plan_info", "mg_score_branches")
@@ -67,6 +67,7 @@ def lib() -> C.CDLL:
         L.mg_tree_footprint_bytes.argtypes = [P]
         L.mg_tree_footprint_bytes.restype = I64
         L.mg_eval_marginal.argtypes = [P, P, P, P, P]
+        L.mg_eval_single_parent.argtypes = [P, P, P, P, P]
         L.mg_eval_marginal_levelsync.argtypes = [P, P, P, P, P, P, P]
         L.mg_eval_marginal_batch.argtypes = [P, I32, P, P, P, P]
         L.mg_eval_absolute.argtypes = [P, P, P, P]
@@ -88,6 +89,7 @@ def lib() -> C.CDLL:
         L.mg_last_error.restype = C.c_char_p
         for name in ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_eval_marginal",
                      "mg_eval_marginal_levelsync", "mg_eval_marginal_batch", "mg_eval_absolute",
+                     "mg_eval_single_parent",
                      "mg_sensor_tables", "mg_server_create", "mg_server_submit", "mg_server_poll",
                      "mg_server_wait", "mg_server_stats", "mg_server_destroy", "mg_timing_enable",
                      "mg_timing_read", "mg_batch_config", "mg_trace_shapes", "mg_batch_plan_info",
@@ -161,6 +163,11 @@ def mg_tree_footprint_bytes(handle: int) -> int:
 def mg_eval_marginal(tree: int, gain, yaw_bin, depth=None, stream=None):
     _check(lib().mg_eval_marginal(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin),
                                   _dev_ptr(depth)))
+
+
+def mg_eval_single_parent(tree: int, gain, yaw_bin, depth=None, stream=None):
+    _check(lib().mg_eval_single_parent(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin),
+                                       _dev_ptr(depth)))
 
 
 def mg_eval_marginal_levelsync(tree: int, host_gain: np.ndarray, host_yaw: np.ndarray, gain=None, yaw_bin=None,
@@ -293,6 +300,11 @@ class Tree:
     def eval_marginal(self, depth=False, stream=None):
         g, y, d = self.outputs(depth)
         mg_eval_marginal(self.handle, g, y, d, stream)
+        return g, y, d
+
+    def eval_single_parent(self, depth=False, stream=None):
+        g, y, d = self.outputs(depth)
+        mg_eval_single_parent(self.handle, g, y, d, stream)
         return g, y, d
 
     def eval_absolute(self, stream=None):

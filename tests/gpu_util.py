@@ -36,6 +36,13 @@ def gpu_eval_tree(mgmod, m, tree, sensor, depth=True, mode="marginal"):
         out["k_db"] = y.cpu().numpy()
         if depth:
             out["D"] = d.cpu().numpy().reshape(tree.n, sensor.n_el, sensor.w_buf)
+    if mode == "single_parent":             # g_sp: parent-only conditioning
+        g, y, d = T.eval_single_parent(depth=depth)
+        torch.cuda.synchronize()
+        out["g_db"] = mgmod.as_u32(g)
+        out["k_db"] = y.cpu().numpy()
+        if depth:
+            out["D"] = d.cpu().numpy().reshape(tree.n, sensor.n_el, sensor.w_buf)
     if mode in ("absolute", "both"):
         g, y = T.eval_absolute()
         torch.cuda.synchronize()

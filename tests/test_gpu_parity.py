@@ -131,6 +131,28 @@ def test_step_full_parity(mg, orc):
     assert np.all(got["g_db"] <= got["g_abs"]) and got["g_db"][0] == got["g_abs"][0]
 
 
+@pytest.mark.parametrize("case", ["tiny", "micro0", "micro1", "micro2", "step"])
+def test_single_parent_full(mg, orc, case):
+    """g_sp (parent-only conditioning, the comparison gain of Fig. 4) against the oracle with one
+    ancestor, every node; equal to the marginal gain where the parent is the only ancestor."""
+    if case == "tiny" or case == "step":
+        w = W.make(case)
+        m, tree, sen = w.map, w.trees[0], w.sensor
+    else:
+        k = int(case[-1])
+        m, tree, sen = W.random_micro(600 + k, dims=(17, 13, 9), n_nodes=14, max_depth=5, range_vox=9.0,
+                                      p_occ=0.06, p_free=0.45, n_az=[16, 100, 24][k], n_el=[6, 7, 5][k],
+                                      yaw_bins=[8, 36, 12][k])
+    log(f"[parity] single parent {case}: n={tree.n}")
+    ref = orc.eval_tree(m, tree, sen, max_anc=1, n_threads=threads())
+    got = gpu_eval_tree(mg, m, tree, sen, depth=True, mode="single_parent")
+    assert_same(got, ref)
+    full = gpu_eval_tree(mg, m, tree, sen, depth=False, mode="marginal")
+    dep = tree.depth()
+    assert np.array_equal(got["g_db"][dep <= 1], full["g_db"][dep <= 1])
+    assert np.all(got["g_db"][dep == 2] >= full["g_db"][dep == 2])
+
+
 def test_batch64_subset(mg, orc):
     """Four trees of the 64-tree workload: batch call == per-tree calls == oracle (sampled)."""
     import torch
