@@ -117,9 +117,9 @@ int mgref_sensor_tables(const mgref_sensor_params* p, float* dir, float* inv, fl
  * the range limit Rv and the ray is still inside the grid. Unknown and free
  * voxels let the ray through; the first occupied voxel ends it and its entry
  * t is the first-hit depth; without a hit the depth is Rv (Sec. IV-A). */
-int mgref_trace_ray(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz,
-                    const float q[3], const float d[3], const float inv[3], float rv,
-                    int32_t cap, uint32_t* ids, uint8_t* st, float* tenter, float* h) {
+int mgref_trace_ray_exit(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz,
+                         const float q[3], const float d[3], const float inv[3], float rv,
+                         int32_t cap, uint32_t* ids, uint8_t* st, float* tenter, float* texit, float* h) {
     int32_t n[3] = {nx, ny, nz};
     int32_t i[3], step[3], nb[3];
     float tn[3];
@@ -142,17 +142,24 @@ int mgref_trace_ray(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz,
         st[count] = s;
         tenter[count] = t;
         ++count;
-        if (s == S_OCC) { *h = t; break; }
+        if (s == S_OCC) { *h = t; if (texit) texit[count - 1] = t; break; }
         int a;
         if (tn[0] <= tn[1] && tn[0] <= tn[2]) a = 0;
         else if (tn[1] <= tn[2]) a = 1;
         else a = 2;
+        if (texit) texit[count - 1] = tn[a];      /* the voxel is left where the next one is entered */
         t = tn[a];
         i[a] += step[a];
         nb[a] += step[a];
         tn[a] = ((float)nb[a] - q[a]) * inv[a];
     }
     return count;
+}
+
+int mgref_trace_ray(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz,
+                    const float q[3], const float d[3], const float inv[3], float rv,
+                    int32_t cap, uint32_t* ids, uint8_t* st, float* tenter, float* h) {
+    return mgref_trace_ray_exit(states, nx, ny, nz, q, d, inv, rv, cap, ids, st, tenter, NULL, h);
 }
 
 /* ------------------------------------------------------------------ ancestor test */

@@ -87,6 +87,13 @@ int mgref_trace_ray(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz,
                     const float q[3], const float d[3], const float inv[3], float rv,
                     int32_t cap, uint32_t* ids, uint8_t* st, float* tenter, float* h);
 
+/* The same traversal; texit[v] (if not NULL) also receives the parameter at
+ * which visit v's voxel is left: the next voxel's entry, which may lie at or
+ * beyond Rv or outside the grid (for an occupied voxel, its own entry). */
+int mgref_trace_ray_exit(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz,
+                         const float q[3], const float d[3], const float inv[3], float rv,
+                         int32_t cap, uint32_t* ids, uint8_t* st, float* tenter, float* texit, float* h);
+
 /* obs(a, x) for the voxel (ix,iy,iz): 1 when ancestor a (position qa in
  * voxel units, window start column c0a, buffer Da[n_el][w_buf]) observes it. */
 int mgref_obs(const mgref_sensor* s, const float qa[3], int32_t c0a, const float* Da,

@@ -1,6 +1,6 @@
 """ctypes wrapper of the oracle library ``libmgref.so`` (test infrastructure only).
 
-``build()`` compiles ``mgref.c`` with gcc (-O2 -ffp-contract=off, no fast-math)
+``build()`` compiles ``mgref.c`` and ``ivlref.c`` (the interval mode) with gcc (-O2 -ffp-contract=off, no fast-math)
 into this directory. The wrapper takes numpy arrays and workload objects and
 returns numpy arrays; it does no arithmetic of its own.
 """
@@ -14,7 +14,7 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "mgref.c")
+SRC = [os.path.join(HERE, "mgref.c"), os.path.join(HERE, "ivlref.c")]
 LIB = os.path.join(HERE, "libmgref.so")
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
@@ -24,7 +24,7 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast
 def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, *SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
