@@ -184,6 +184,44 @@ int mg_batch_plan_info(const mg_tree* trees, int32_t n_trees, int32_t* shape, in
  * buffers, so a later path score or descendant evaluation sees these. */
 int mg_eval_single_parent(mg_tree tree, void* hip_stream, uint32_t* gain, int32_t* yaw_bin, float* depth);
 
+/* Marginal gain with the paper's own ancestor test (Sec. IV-A, IV-B,
+ * eq. 5-7), "interval mode". Each node keeps a pinhole depth buffer of
+ * wd x hd pixels at its chosen yaw (wd, hd <= 0: the resolution rule of
+ * Sec. IV-A, ceil(2 d_max tan(fov/2) / v) per axis), holding the camera-frame
+ * z (voxel units) of the first occupied voxel through each pixel centre, or
+ * of the ray's end at the range limit. A candidate ray is moved into every
+ * ancestor's camera frame, clipped to z in [1/64, Rv], projected (eq. 5),
+ * clipped to the buffer (Liang-Barsky) and walked pixel by pixel (2D DDA)
+ * with inverse depth linear in screen space (eq. 6); where z <= the stored
+ * depth it is observed, which gives each ancestor's overlap intervals in t
+ * (eq. 7); the intervals of all ancestors are merged. An unknown voxel counts
+ * unless the midpoint of its chord [t_enter, min(t_exit, Rv)] lies in a
+ * merged interval. Camera frame of yaw psi: x = (sin, -cos, 0), y = (0, 0, -1),
+ * z = (cos, sin, 0); window k's yaw is az_offset + (k + w/2) * 360 / B.
+ * Candidate rays, bins and windows are those of mg_eval_marginal.
+ *   gain DEVICE uint32[n], yaw_bin DEVICE int32[n], depth DEVICE float
+ *   [n][hd][wd] or NULL. The first call on a tree (or a call with another
+ *   buffer size) allocates the tree's buffers and copies the camera tables
+ *   synchronously; later calls allocate nothing and run on hip_stream.
+ *   MG_E_UNSUPPORTED for a side above 4096 pixels. It overwrites the tree's
+ *   bins and windows (not its panorama buffers). */
+int mg_eval_interval(mg_tree tree, void* hip_stream, int32_t wd, int32_t hd, uint32_t* gain, int32_t* yaw_bin,
+                     float* depth);
+
+/* Merged overlap intervals the interval mode keeps per ray (0..16; -1 restores
+ * the default 16). A ray whose merged list would need more takes an exact
+ * slow path (each unknown voxel tests every ancestor's intervals), so results
+ * do not depend on it; small values exercise that path. Host only. */
+int mg_interval_config(int32_t cap);
+
+/* Host copy of the interval-mode camera for a sensor and voxel size (for
+ * tests): wh[2] = (wd, hd) after the resolution rule, intr[6] = (fx, fy, cx,
+ * cy, z_near, Rv), pdir [hd][wd][3] unit camera-frame pixel-centre
+ * directions, cs [yaw_bins][2] cos and sin of each window's yaw. Pointers
+ * other than wh may be NULL. */
+int mg_interval_tables(const mg_sensor* sensor, float voxel_m, int32_t wd, int32_t hd, int32_t* wh, float* intr,
+                       float* pdir, float* cs);
+
 /* Absolute gain of every node (eq. 1 maximised over the yaw windows), no
  * conditioning and no level order: one flat launch over all nodes.
  *   gain DEVICE uint32[n], yaw_bin DEVICE int32[n]. */

@@ -621,6 +621,7 @@ extern "C" int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* par
 extern "C" int mg_tree_destroy(mg_tree t) {
     if (!t) return fail(MG_E_INVALID, "tree is NULL");
     mgb::forget_tree(t);
+    mgb::forget_interval(t);
     if (t->owns_block) (void)hipFree(t->block);
     release_sensor(t->sensor);
     t->map->trees--;

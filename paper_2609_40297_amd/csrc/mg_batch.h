@@ -33,5 +33,6 @@ int prepare(mg_map map, const float* pos_m, const int32_t* parent, int32_t n, co
 size_t block_bytes(const HostTree& H);
 int upload_into(mg_map map, const HostTree& H, const mg_sensor* sensor, hipStream_t s, void* block, mg_tree* out);
 void forget_tree(mg_tree t);               // mg_batch.hip: drop cached launch plans that use t
+void forget_interval(mg_tree t);           // mg_interval.hip: free t's interval-mode buffers
 
 }  // namespace mgb

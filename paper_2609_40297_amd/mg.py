@@ -28,7 +28,9 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_eval_marginal_batch", "mg_eval_absolute", "mg_eval_single_parent", "mg_sensor_tables", "mg_last_error",
            "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait", "mg_server_stats",
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
-           "mg_batch_plan_info", "mg_score_branches")
+           "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
+                     "mg_interval_config",
+           "mg_interval_config")
 
 
 class MGError(RuntimeError):
@@ -68,6 +70,9 @@ def lib() -> C.CDLL:
         L.mg_tree_footprint_bytes.restype = I64
         L.mg_eval_marginal.argtypes = [P, P, P, P, P]
         L.mg_eval_single_parent.argtypes = [P, P, P, P, P]
+        L.mg_eval_interval.argtypes = [P, P, I32, I32, P, P, P]
+        L.mg_interval_config.argtypes = [I32]
+        L.mg_interval_tables.argtypes = [C.POINTER(mg_sensor), C.c_float, I32, I32, P, P, P, P]
         L.mg_eval_marginal_levelsync.argtypes = [P, P, P, P, P, P, P]
         L.mg_eval_marginal_batch.argtypes = [P, I32, P, P, P, P]
         L.mg_eval_absolute.argtypes = [P, P, P, P]
@@ -89,7 +94,7 @@ def lib() -> C.CDLL:
         L.mg_last_error.restype = C.c_char_p
         for name in ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_eval_marginal",
                      "mg_eval_marginal_levelsync", "mg_eval_marginal_batch", "mg_eval_absolute",
-                     "mg_eval_single_parent",
+                     "mg_eval_single_parent", "mg_eval_interval", "mg_interval_tables",
                      "mg_sensor_tables", "mg_server_create", "mg_server_submit", "mg_server_poll",
                      "mg_server_wait", "mg_server_stats", "mg_server_destroy", "mg_timing_enable",
                      "mg_timing_read", "mg_batch_config", "mg_trace_shapes", "mg_batch_plan_info",
@@ -163,6 +168,29 @@ def mg_tree_footprint_bytes(handle: int) -> int:
 def mg_eval_marginal(tree: int, gain, yaw_bin, depth=None, stream=None):
     _check(lib().mg_eval_marginal(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin),
                                   _dev_ptr(depth)))
+
+
+def mg_eval_interval(tree: int, wd: int, hd: int, gain, yaw_bin, depth=None, stream=None):
+    _check(lib().mg_eval_interval(C.c_void_p(tree), _stream(stream), int(wd), int(hd), _dev_ptr(gain),
+                                  _dev_ptr(yaw_bin), _dev_ptr(depth)))
+
+
+def mg_interval_config(cap: int = -1):
+    _check(lib().mg_interval_config(int(cap)))
+
+
+def interval_tables(sensor, voxel_m, wd=0, hd=0):
+    """Host tables of the interval-mode camera: (wd, hd, intr[6], pdir[hd, wd, 3], cs[B, 2])."""
+    s = make_sensor(sensor)
+    wh = np.zeros(2, np.int32)
+    _check(lib().mg_interval_tables(C.byref(s), float(voxel_m), int(wd), int(hd), _np_ptr(wh), None, None, None))
+    W, H = int(wh[0]), int(wh[1])
+    intr = np.zeros(6, np.float32)
+    pdir = np.zeros((H, W, 3), np.float32)
+    cs = np.zeros((s.yaw_bins, 2), np.float32)
+    _check(lib().mg_interval_tables(C.byref(s), float(voxel_m), int(wd), int(hd), _np_ptr(wh), _np_ptr(intr),
+                                    _np_ptr(pdir), _np_ptr(cs)))
+    return W, H, intr, pdir, cs
 
 
 def mg_eval_single_parent(tree: int, gain, yaw_bin, depth=None, stream=None):
@@ -262,6 +290,7 @@ class Map:
     def __init__(self, states: np.ndarray, voxel_m: float, origin_m=(0.0, 0.0, 0.0), stream=None):
         self.handle = mg_map_create(states, voxel_m, origin_m, stream)
         self.shape = tuple(np.asarray(states).shape)
+        self.voxel_m = float(np.float32(voxel_m))
 
     def close(self):
         if self.handle:
@@ -300,6 +329,15 @@ class Tree:
     def eval_marginal(self, depth=False, stream=None):
         g, y, d = self.outputs(depth)
         mg_eval_marginal(self.handle, g, y, d, stream)
+        return g, y, d
+
+    def eval_interval(self, wd=0, hd=0, depth=False, stream=None):
+        """Interval mode (the paper's pinhole buffers and overlap intervals): (gain, yaw, depth or None)."""
+        import torch
+        W, H, _, _, _ = interval_tables(self.sensor, self.map.voxel_m, wd, hd)
+        g, y, _ = self.outputs(False)
+        d = torch.empty((self.n, H, W), dtype=torch.float32, device=g.device) if depth else None
+        mg_eval_interval(self.handle, W, H, g, y, d, stream)
         return g, y, d
 
     def eval_single_parent(self, depth=False, stream=None):

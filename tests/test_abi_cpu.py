@@ -63,6 +63,20 @@ def test_sensor_tables_equal_oracle_bitwise(mglib, oracle_lib, sen):
         assert a[k].tobytes() == b[k].tobytes(), k
 
 
+@pytest.mark.parametrize("sen,v,wd,hd", [(W.SENSOR_TINY, 0.2, 0, 0), (W.SENSOR_STEP, 0.1, 0, 0),
+                                         (W.SENSOR_LARGE, 0.05, 0, 0), (W.SENSOR_STEP, 0.1, 37, 21),
+                                         (dict(n_az=100, n_el=7, fov_h_deg=90, fov_v_deg=50, range_m=3.0,
+                                               yaw_bins=36, az_offset_deg=12.5), 0.25, 0, 0)])
+def test_interval_camera_equals_oracle_bitwise(mglib, oracle_lib, sen, v, wd, hd):
+    from oracle import ivlref
+    s = W.Sensor(**sen)
+    a = mglib.interval_tables(s, v, wd, hd)
+    b = ivlref.camera_tables(s, v, wd, hd)
+    assert a[:2] == b[:2]
+    for x, y in zip(a[2:], b[2:]):
+        assert x.tobytes() == y.tobytes()
+
+
 def test_host_validation_errors(mglib):
     mg = mglib
     st = np.zeros((4, 4, 4), np.uint8)

@@ -1,0 +1,133 @@
+"""GPU parity of the interval mode (mg_eval_interval) against its oracle (oracle/ivlref.c).
+
+Gains, windows and the pinhole depth buffers (float bits) must match the
+oracle exactly: both sides take every decision in binary32 in the same order.
+The merged-interval capacity per ray is varied (0, 1 and the default), which
+sends rays through the exact slow path; results must not change.
+"""
+import numpy as np
+import pytest
+
+from paper_2609_40297_amd import workloads as W
+from tests.gpu_util import log, threads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_40297_amd import mg as mgmod
+    mgmod.lib()
+    return mgmod
+
+
+@pytest.fixture(scope="module")
+def ivl():
+    from oracle import ivlref, mgref
+    if not __import__("os").path.exists(mgref.LIB):
+        mgref.build()
+    return ivlref
+
+
+def _gpu_interval(mg, m, tree, sen, wd=0, hd=0, caps=(-1,)):
+    import torch
+    M = mg.Map(m.states, m.voxel_m, m.origin_m)
+    T = mg.Tree(M, tree.pos_m, tree.parent, sen)
+    outs = []
+    try:
+        for cap in caps:
+            mg.mg_interval_config(cap)
+            g, y, d = T.eval_interval(wd, hd, depth=True)
+            torch.cuda.synchronize()
+            outs.append(dict(g_db=mg.as_u32(g), k_db=y.cpu().numpy(), D=d.cpu().numpy()))
+    finally:
+        mg.mg_interval_config(-1)
+        T.close()
+        M.close()
+    return outs
+
+
+def _same(got, ref, nodes=None):
+    sel = slice(None) if nodes is None else np.asarray(nodes)
+    assert np.array_equal(got["g_db"][sel].astype(np.int64), ref["g_db"][sel].astype(np.int64)), \
+        np.flatnonzero(got["g_db"][sel] != ref["g_db"][sel])[:8]
+    assert np.array_equal(got["k_db"][sel], ref["k_db"][sel])
+    a, b = got["D"][sel], ref["D"][sel]
+    assert a.shape == b.shape and a.tobytes() == b.tobytes(), np.argwhere(a != b)[:5]
+
+
+def test_interval_tiny_full(mg, ivl):
+    w = W.make("tiny")
+    log("[interval] tiny, resolution rule")
+    ref = ivl.eval_tree(w.map, w.trees[0], w.sensor, n_threads=threads())
+    for got in _gpu_interval(mg, w.map, w.trees[0], w.sensor, caps=(-1, 0, 1, 3)):
+        _same(got, ref)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_interval_random_micro_full(mg, ivl, seed):
+    sens = [dict(n_az=16, n_el=6, yaw_bins=8), dict(n_az=100, n_el=7, yaw_bins=36),
+            dict(n_az=24, n_el=5, yaw_bins=12), dict(n_az=48, n_el=9, yaw_bins=12)]
+    sizes = [(0, 0), (13, 7), (31, 17), (8, 40)]
+    m, tree, sen = W.random_micro(700 + seed, dims=(19, 15, 10), n_nodes=14, max_depth=5, range_vox=9.0,
+                                  p_occ=0.06, p_free=0.45, **sens[seed])
+    wd, hd = sizes[seed]
+    log(f"[interval] micro{seed}: n={tree.n} buffer {wd}x{hd}")
+    ref = ivl.eval_tree(m, tree, sen, wd=wd, hd=hd, n_threads=threads())
+    for got in _gpu_interval(mg, m, tree, sen, wd, hd, caps=(-1, 0, 2)):
+        _same(got, ref)
+
+
+def test_interval_degenerate_trees(mg, ivl):
+    """One node; a 20-deep chain; a node repeated at its parent's position; unknown everywhere."""
+    st = np.full((20, 24, 24), W.UNK, np.uint8)
+    m = W.Map(states=st, voxel_m=0.5, origin_m=np.array([1.0, -2.0, 0.5], np.float32))
+    sen = W.Sensor(n_az=32, n_el=6, fov_h_deg=90.0, fov_v_deg=60.0, range_m=4.0, yaw_bins=8)
+    o = m.origin_m
+    one = W.Tree(pos_m=(o + np.array([[6.1, 6.2, 5.3]], np.float32)).astype(np.float32),
+                 parent=np.array([-1], np.int32))
+    k = 20
+    chain = W.Tree(pos_m=(o + np.stack([np.linspace(1, 10, k), np.full(k, 6.0), np.linspace(2, 8, k)], 1)
+                          ).astype(np.float32), parent=np.arange(-1, k - 1, dtype=np.int32))
+    rep = W.Tree(pos_m=(o + np.array([[6.25, 6.25, 5.25]] * 3, np.float32)).astype(np.float32),
+                 parent=np.array([-1, 0, 1], np.int32))
+    for name, tree in (("one", one), ("chain", chain), ("repeat", rep)):
+        log(f"[interval] {name}")
+        ref = ivl.eval_tree(m, tree, sen, n_threads=threads())
+        for got in _gpu_interval(mg, m, tree, sen, caps=(-1, 0)):
+            _same(got, ref)
+
+
+def test_interval_step_sampled(mg, ivl):
+    """500-node planner step (160 x 93 buffers by the resolution rule): the ancestor chains of three
+    deepest leaves against the oracle; the whole tree evaluated on the GPU."""
+    from oracle import mgref
+    w = W.make("step")
+    t = w.trees[0]
+    dep = t.depth()
+    leaves = np.flatnonzero(dep == dep.max())[:3]
+    mask = mgref.ancestor_closure(t.parent, leaves)
+    sel = np.flatnonzero(mask)
+    log(f"[interval] step: n={t.n}, sampled {sel.size} nodes")
+    ref = ivl.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads())
+    got = _gpu_interval(mg, w.map, t, w.sensor)[0]
+    assert got["D"].shape == (t.n, 93, 160)
+    _same(got, ref, nodes=sel)
+
+
+def test_interval_rejects_bad_sizes(mg):
+    w = W.make("tiny")
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    T = mg.Tree(M, w.trees[0].pos_m, w.trees[0].parent, w.sensor)
+    import torch
+    g = torch.empty(T.n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(g)
+    with pytest.raises(mg.MGError):
+        mg.mg_eval_interval(T.handle, 5000, 10, g, y)
+    with pytest.raises(mg.MGError):
+        mg.mg_interval_config(17)
+    T.close()
+    M.close()
