@@ -93,6 +93,7 @@ def parse():
     ap.add_argument("--modes", default="plain,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sp-steps", type=int, default=5, help="timed single-parent (g_sp) passes; 0 skips")
+    ap.add_argument("--ivl-steps", type=int, default=3, help="timed interval-mode passes; 0 skips")
     ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6, help="oracle sample, rays per host thread")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (calibrates HBM byte counters) and exit")
@@ -424,6 +425,33 @@ def main():
         sp = {"rays_per_s": rays_per_step / dt, "ms_per_step": dt * 1e3, "steps": args.sp_steps,
               "path": "mg_eval_single_parent, tree after tree"}
         log(f"[bench] single parent: {sp}")
+    ivl = None
+    if args.ivl_steps > 0:
+        # interval mode (the paper's pinhole buffers and overlap intervals), per-tree level path
+        wd, hd, _, _, _ = mg.interval_tables(sen, w.map.voxel_m)
+        g_iv = torch.empty(max(t.n for t in trees), dtype=torch.int32, device=dev)
+        y_iv = torch.empty_like(g_iv)
+        for T in trees:                        # first call allocates the buffers
+            mg.mg_eval_interval(T.handle, wd, hd, g_iv, y_iv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.ivl_steps):
+            for T in trees:
+                mg.mg_eval_interval(T.handle, wd, hd, g_iv, y_iv)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.ivl_steps
+        ivl = {"rays_per_s": rays_per_step / dt, "ms_per_step": dt * 1e3, "steps": args.ivl_steps,
+               "buffer": f"{wd}x{hd}", "path": "mg_eval_interval, tree after tree"}
+        wci = work_counts((args.workload if args.trees is None else f"{args.workload}:{args.trees}") + "/interval")
+        if wci is not None:
+            # algorithmic bytes: 1 B per voxel visit, 4 B per pixel walked in an ancestor buffer, 4 B per
+            # rendered pixel, 2 x B x 4 B of bins per node; divided by the whole call's time
+            alg = wci["visits"] + 4 * wci["pixel_steps"] + 4 * wci["nodes"] * wci["wd"] * wci["hd"] + \
+                n_total * 2 * sen.yaw_bins * 4
+            ivl["algorithmic_bytes_per_step"] = alg
+            ivl["achieved_GBps_whole_call"] = alg / dt / 1e9
+            ivl["pixel_steps_per_ray"] = wci["pixel_steps"] / wci["rays"]
+        log(f"[bench] interval: {ivl}")
     score = None
     if "batched" in results:
         score = score_bench(mg, trees, g_all, n_total, int(sum(t.depth().sum() for t in w.trees)))
@@ -460,6 +488,7 @@ def main():
         "cpu_baseline": cpu,
         "path_score": score,
         "single_parent": sp,
+        "interval": ivl,
     }
     print(json.dumps(line), flush=True)
     for T in trees:

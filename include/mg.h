@@ -208,10 +208,11 @@ int mg_eval_single_parent(mg_tree tree, void* hip_stream, uint32_t* gain, int32_
 int mg_eval_interval(mg_tree tree, void* hip_stream, int32_t wd, int32_t hd, uint32_t* gain, int32_t* yaw_bin,
                      float* depth);
 
-/* Merged overlap intervals the interval mode keeps per ray (0..16; -1 restores
- * the default 16). A ray whose merged list would need more takes an exact
- * slow path (each unknown voxel tests every ancestor's intervals), so results
- * do not depend on it; small values exercise that path. Host only. */
+/* Merged overlap intervals the interval mode holds per ray (1..16; -1
+ * restores the default 16). A ray whose union has more components is
+ * evaluated in windows of that many (the ancestors' intervals are regenerated
+ * for each window), so results do not depend on it; small values exercise
+ * that path. Host only. */
 int mg_interval_config(int32_t cap);
 
 /* Host copy of the interval-mode camera for a sensor and voxel size (for

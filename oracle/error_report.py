@@ -6,8 +6,11 @@ window, Sec. V-A's fixed-yaw protocol), X_set (eq. 2 as a set), G_abs
 (absolute) and g_sp (single-parent conditioning). Reports, per depth, the mean
 ratios G_db/X_ray, G_sp/X_ray and G_abs/X_ray (the analogue of Fig. 4b), and
 over all nodes the least-squares slope (through the origin) and R^2 of G_db
-against X_ray (the statistic form of Sec. V-A). Test infrastructure: calls
-only the oracle and the workload generator.
+against X_ray (the statistic form of Sec. V-A). The same statistics are
+reported for the interval mode (oracle/ivlref.c: pinhole buffers and overlap
+intervals, the paper's own test), against X_ray at the interval mode's own
+windows. Test infrastructure: calls only the oracle and the workload
+generator.
 
 The exact pass covers every node of tiny and step and seeded node
 subsamples (with their ancestor chains) of batch64, large and serve16.
@@ -23,7 +26,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-from oracle import mgref  # noqa: E402
+from oracle import ivlref, mgref  # noqa: E402
 from paper_2609_40297_amd import workloads as W  # noqa: E402
 
 
@@ -46,6 +49,30 @@ def _compare(rows):
                               dbset_over_exactset=float(np.mean(gs[m] / np.maximum(xs[m], 1)))))
     return dict(compared=int(sel.sum()), slope=slope, r2=r2, mean_db_over_exact=float(np.mean(g[sel] / x[sel])),
                 overestimate_pct=float(100.0 * (np.sum(g[sel]) / np.sum(x[sel]) - 1.0)), per_depth=per_depth)
+
+
+def _fit(dep, g, x):
+    """Slope through the origin, R^2 and per-depth mean ratio of g against x (nodes with x > 0)."""
+    dep, g, x = (np.asarray(c, dtype=np.float64) for c in (dep, g, x))
+    sel = x > 0
+    slope = float(np.sum(g[sel] * x[sel]) / np.sum(x[sel] * x[sel]))
+    resid = g[sel] - slope * x[sel]
+    r2 = float(1.0 - np.sum(resid ** 2) / np.sum((g[sel] - g[sel].mean()) ** 2))
+    per_depth = [dict(depth=d, nodes=int(((dep == d) & sel).sum()),
+                      over_exact=float(np.mean(g[(dep == d) & sel] / x[(dep == d) & sel])))
+                 for d in range(int(dep.max()) + 1) if ((dep == d) & sel).any()]
+    return dict(compared=int(sel.sum()), slope=slope, r2=r2,
+                overestimate_pct=float(100.0 * (np.sum(g[sel]) / np.sum(x[sel]) - 1.0)), per_depth=per_depth)
+
+
+def _interval_rows(m, t, sensor, mask, n_threads):
+    """(depth, G_ivl, X_ray at the interval mode's windows) of the nodes in `mask` or all."""
+    ivl = ivlref.eval_tree(m, t, sensor, mask=mask, n_threads=n_threads)
+    blind = np.zeros((t.n, sensor.n_el, sensor.w_buf), np.float32)
+    ex = mgref.exact(m, t, sensor, ivl["k_db"], blind, mask=mask)
+    dep = t.depth()
+    idx = np.arange(t.n) if mask is None else np.nonzero(mask)[0]
+    return [(dep[i], ivl["g_db"][i], ex["X_ray"][i]) for i in idx], (ivl["wd"], ivl["hd"])
 
 
 def _tree_rows(m, t, sensor, mask, n_threads):
@@ -74,7 +101,7 @@ PLANS = {"tiny": (1, None), "step": (1, None), "batch64": (8, 32), "large": (1, 
 def report(name, n_threads=None):
     n_threads = n_threads or os.cpu_count() or 1
     n_trees, per_tree = PLANS[name]
-    rows, evaluated = [], 0
+    rows, irows, evaluated, buf = [], [], 0, None
     if name == "serve16":
         jobs = []
         for _, r, seed, n, d in W.serve_requests(n_trees):
@@ -86,11 +113,14 @@ def report(name, n_threads=None):
     for j, (m, t, sensor) in enumerate(jobs):
         mask = None if per_tree is None else _sample_mask(t, per_tree, 7000 + j)
         rows += _tree_rows(m, t, sensor, mask, n_threads)
+        r, buf = _interval_rows(m, t, sensor, mask, n_threads)
+        irows += r
         evaluated += t.n if mask is None else int(mask.sum())
     out = dict(workload=name, trees=len(jobs), nodes_evaluated=evaluated,
                sample="all nodes" if per_tree is None else
                f"{per_tree} seeded nodes per tree (seeds 7000+tree) and their ancestors")
     out.update(_compare(rows))
+    out["interval"] = dict(buffer=f"{buf[0]}x{buf[1]}", **_fit(*zip(*irows)))
     return out
 
 

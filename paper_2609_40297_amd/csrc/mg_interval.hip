@@ -20,9 +20,11 @@
 // kernel; the nodes of the level then render their buffers at the chosen yaw.
 //
 // The merged list lives in registers/scratch with room for kIvlCap intervals
-// per ray. A ray whose union needs more switches to an exact slow path: every
-// unknown voxel regenerates the ancestors' intervals and tests membership, so
-// results never depend on the capacity.
+// per ray, as a window of the union: it holds the union's components from t0
+// on, exactly up to a cut tcut (the start of the first interval it had no room
+// for). A voxel past the cut moves the window (t0 = tcut) and regenerates the
+// ancestors' intervals, so results never depend on the capacity; most rays
+// need a single window.
 //
 // Camera frame of yaw psi: x right = (sin psi, -cos psi, 0), y down =
 // (0, 0, -1), z forward = (cos psi, sin psi, 0), in voxel units. The yaw of
@@ -52,7 +54,8 @@ constexpr int kMaxSide = 4096;     // buffer width / height limit
 struct Cam {
     const float4* pdir;   // [hd*wd] unit camera-frame direction of pixel (i, j) at j*wd + i
     const float2* cs;     // [B] cos, sin of the yaw of window k
-    float* dpin;          // [n][hd*wd] the nodes' depth buffers
+    float* dpin;          // [n][hd*wd] the nodes' depth buffers (camera z)
+    float* winv;          // [n][hd*wd] their inverse depths 1/z (0 where z = 0)
     int32_t wd, hd, npx;
     float fx, fy, cx, cy, znear, rv;
 };
@@ -129,16 +132,15 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
     float su = si ? ((float)bu - uA) * iu : inf;
     float sv = sj ? ((float)bv - vA) * iv : inf;
     float sa = s0;
-    const float* __restrict__ Da = C.dpin + (size_t)A.node * (size_t)C.npx;
+    const float* __restrict__ Wa = C.winv + (size_t)A.node * (size_t)C.npx;
     float olo = 0.0f, ohi = 0.0f;
     bool open = false;
     for (int32_t it = 0; it < C.wd + C.hd + 2; ++it) {
         float e = su < sv ? su : sv;
         e = e < s1 ? e : s1;
-        const float Dp = Da[(size_t)j * C.wd + i];
-        if (Dp > 0.0f) {
+        const float wD = Wa[(size_t)j * C.wd + i];    // 1/D, or 0 for D = 0 (nothing observed)
+        if (wD > 0.0f) {
             // the part of [sa, e] where w(s) >= 1/D, i.e. z(s) <= D
-            const float wD = 1.0f / Dp;
             float lo = sa, hi = e;
             bool ok = true;
             if (wb == wa) {
@@ -176,14 +178,22 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
     return open ? sink(olo, ohi) : false;
 }
 
-// Sorted union of intervals, at most cap (<= kIvlCap); `over` once the union would need more.
-struct Merged {
+// Window of the union of intervals: its components that reach t0 or later,
+// sorted, at most cap (<= kIvlCap) of them. An interval that would need a
+// further component is dropped and lowers tcut to its start (so is the last
+// component when an earlier one is inserted into a full list); every
+// interval dropped starts at or after tcut, so membership of any t in
+// [t0, tcut) is exact. Intervals starting at or after tcut stop the
+// ancestor's walk (the rest of its intervals start later still).
+struct Window {
     float lo[kIvlCap], hi[kIvlCap];
     int32_t m = 0, cap = kIvlCap;
-    bool over = false;
+    float t0 = -__builtin_inff(), tcut = __builtin_inff();
     __device__ bool operator()(float a, float b) {
+        if (a >= tcut) return true;
+        if (b < t0) return false;
         int32_t i = 0;
-        while (i < m && hi[i] < a) ++i;          // intervals that end before a
+        while (i < m && hi[i] < a) ++i;          // components that end before a
         int32_t j = i;
         float nlo = a, nhi = b;
         while (j < m && lo[j] <= b) {            // overlapping or touching ones join
@@ -193,9 +203,13 @@ struct Merged {
         }
         const int32_t removed = j - i;
         if (removed == 0) {
-            if (m >= cap) {
-                over = true;
-                return true;
+            if (m == cap) {
+                if (i == m) {                    // after every kept component
+                    tcut = a;
+                    return true;
+                }
+                tcut = lo[m - 1];                // the last component makes room
+                --m;
             }
             for (int32_t k = m; k > i; --k) {
                 lo[k] = lo[k - 1];
@@ -212,17 +226,6 @@ struct Merged {
         lo[i] = nlo;
         hi[i] = nhi;
         return false;
-    }
-};
-
-// Is t inside an interval of one ancestor? Intervals arrive sorted, so the
-// walk stops at the first that contains t or starts past it.
-struct Member {
-    float t;
-    bool found = false;
-    __device__ bool operator()(float a, float b) {
-        if (a <= t && t <= b) found = true;
-        return found || a > t;
     }
 };
 
@@ -257,9 +260,9 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_trace(MapDev M, SensorDev S
         const float4 p = Tr.q4[node];
         const float4 d = S.d4[r];
         const float4 inv = S.iv4[r];
-        Merged U;
+        Window U;
         U.cap = cap;
-        for (int32_t k = 0; k < na && !U.over; ++k) anc_intervals(C, p.x, p.y, p.z, d.x, d.y, d.z, s_anc[k], U);
+        for (int32_t k = 0; k < na; ++k) anc_intervals(C, p.x, p.y, p.z, d.x, d.y, d.z, s_anc[k], U);
         // 3D DDA (Amanatides-Woo; crossings recomputed as (b - q) / d; ties x, y, z)
         int32_t ix = (int32_t)floorf(p.x), iy = (int32_t)floorf(p.y), iz = (int32_t)floorf(p.z);
         const int32_t sx = d.x > 0.f ? 1 : (d.x < 0.f ? -1 : 0);
@@ -284,17 +287,15 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_trace(MapDev M, SensorDev S
                 ++n_abs;
                 const float tex = tn < S.rv ? tn : S.rv;
                 const float tm = 0.5f * (t + tex);
-                bool covered = false;
-                if (U.over) {
-                    for (int32_t k = 0; k < na && !covered; ++k) {
-                        Member mb{tm};
-                        anc_intervals(C, p.x, p.y, p.z, d.x, d.y, d.z, s_anc[k], mb);
-                        covered = mb.found;
-                    }
-                } else {
-                    while (ptr < U.m && U.hi[ptr] < tm) ++ptr;
-                    covered = ptr < U.m && U.lo[ptr] <= tm;
+                while (tm >= U.tcut) {               // move the window past the cut
+                    U.t0 = U.tcut;
+                    U.tcut = inf;
+                    U.m = 0;
+                    for (int32_t k = 0; k < na; ++k) anc_intervals(C, p.x, p.y, p.z, d.x, d.y, d.z, s_anc[k], U);
+                    ptr = 0;
                 }
+                while (ptr < U.m && U.hi[ptr] < tm) ++ptr;
+                const bool covered = ptr < U.m && U.lo[ptr] <= tm;
                 n_marg += covered ? 0u : 1u;
             }
             t = tn;
@@ -367,7 +368,9 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_render(MapDev M, Cam C, Tre
         nb[ax] += st[ax];
         tn[ax] = ((float)nb[ax] - qv[ax]) * iv[ax];
     }
-    C.dpin[(size_t)node * (size_t)C.npx + px] = h * pd.z;
+    const float z = h * pd.z;
+    C.dpin[(size_t)node * (size_t)C.npx + px] = z;
+    C.winv[(size_t)node * (size_t)C.npx + px] = z > 0.0f ? 1.0f / z : 0.0f;
 }
 
 // ---------------------------------------------------------------- host
@@ -439,13 +442,13 @@ int build_camera(const mg_sensor& p, float voxel_m, int32_t wd, int32_t hd, Host
 // Per-tree device state of the interval mode, made on the first call.
 struct State {
     int32_t wd = 0, hd = 0;
-    void* block = nullptr;   // pdir | cs | dpin
+    void* block = nullptr;   // pdir | cs | dpin | winv
     Cam cam{};
 };
 
 std::mutex g_mu;
 std::map<mg_tree, State> g_state;
-int32_t g_cap = kIvlCap;     // merged intervals kept per ray before the slow path
+int32_t g_cap = kIvlCap;     // union components held per ray (window size)
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -466,7 +469,8 @@ void forget_interval(mg_tree t) {
 }  // namespace mgb
 
 extern "C" int mg_interval_config(int32_t cap) {
-    if (cap < -1 || cap > mgi::kIvlCap) return mgb::set_error(MG_E_INVALID, "interval capacity outside -1..16");
+    if (cap == 0 || cap < -1 || cap > mgi::kIvlCap)
+        return mgb::set_error(MG_E_INVALID, "interval capacity outside 1..16 (or -1)");
     std::lock_guard<std::mutex> lk(mgi::g_mu);
     mgi::g_cap = cap < 0 ? mgi::kIvlCap : cap;
     return MG_OK;
@@ -530,7 +534,8 @@ extern "C" int mg_eval_interval(mg_tree t, void* hip_stream, int32_t wd, int32_t
             }
             const size_t o_cs = align256(sizeof(float4) * npx);
             const size_t o_d = o_cs + align256(sizeof(float2) * H.cs.size());
-            const size_t total = o_d + sizeof(float) * npx * (size_t)v.n;
+            const size_t o_w = o_d + align256(sizeof(float) * npx * (size_t)v.n);
+            const size_t total = o_w + sizeof(float) * npx * (size_t)v.n;
             e = hipMalloc(&st.block, total);
             if (e != hipSuccess) {
                 st.block = nullptr;
@@ -545,6 +550,7 @@ extern "C" int mg_eval_interval(mg_tree t, void* hip_stream, int32_t wd, int32_t
             st.cam.pdir = (const float4*)base;
             st.cam.cs = (const float2*)(base + o_cs);
             st.cam.dpin = (float*)(base + o_d);
+            st.cam.winv = (float*)(base + o_w);
             st.cam.wd = H.wd;
             st.cam.hd = H.hd;
             st.cam.npx = (int32_t)npx;

@@ -4,9 +4,12 @@ visits V (voxels visited by the DDA), unk_visits U (unknown ones), anc_tests T
 (ancestor tests, parent first, stopping at the first that observes), rays R.
 These are the numerators of the roofline figures (algorithmic bytes per ray:
 V/R grid gathers of 1 byte, T/R depth reads of 4 bytes, one 4-byte first-hit
-write). Calls only the oracle and the workload generator.
+write). Entries named "<workload>/interval" hold the interval mode's work:
+V, U, pixel_steps (pixels walked by the 2D DDAs, one 4-byte depth read
+each), merged intervals, and the buffer size. Calls only the oracle and the
+workload generator.
 
-Usage: python tests/golden/make_work_counts.py [workload ...]
+Usage: python tests/golden/make_work_counts.py [workload[/interval] ...]
 """
 import json
 import os
@@ -15,7 +18,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import mgref  # noqa: E402
+from oracle import ivlref, mgref  # noqa: E402
 from paper_2609_40297_amd import workloads as W  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "work_counts.json")
@@ -33,11 +36,27 @@ def count(name, n_trees=None):
     return tot
 
 
+def count_interval(name, n_trees=None):
+    w = W.make(name, n_trees=n_trees)
+    tot = dict(visits=0, unk_visits=0, pixel_steps=0, intervals=0, max_merged=0, rays=0, nodes=0)
+    for t in w.trees:
+        o = ivlref.eval_tree(w.map, t, w.sensor, n_threads=os.cpu_count() or 1)
+        for k in ("visits", "unk_visits", "pixel_steps", "intervals"):
+            tot[k] += int(o["counters"][k])
+        tot["max_merged"] = max(tot["max_merged"], int(o["counters"]["max_merged"]))
+        tot["rays"] += t.n * w.sensor.rays
+        tot["nodes"] += t.n
+        tot["wd"], tot["hd"] = int(o["wd"]), int(o["hd"])
+    return tot
+
+
 if __name__ == "__main__":
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for arg in sys.argv[1:] or ["tiny", "step"]:
-        name, _, nt = arg.partition(":")
-        data[arg] = count(name, int(nt) if nt else None)
+        base, _, mode = arg.partition("/")
+        name, _, nt = base.partition(":")
+        fn = count_interval if mode == "interval" else count
+        data[arg] = fn(name, int(nt) if nt else None)
         print(arg, data[arg], flush=True)
         with open(OUT, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)

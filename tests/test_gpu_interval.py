@@ -2,8 +2,9 @@
 
 Gains, windows and the pinhole depth buffers (float bits) must match the
 oracle exactly: both sides take every decision in binary32 in the same order.
-The merged-interval capacity per ray is varied (0, 1 and the default), which
-sends rays through the exact slow path; results must not change.
+The merged-interval capacity per ray is varied (1, 2, 3 and the default 16),
+which makes rays evaluate their union in several windows; results must not
+change.
 """
 import numpy as np
 import pytest
@@ -63,7 +64,7 @@ def test_interval_tiny_full(mg, ivl):
     w = W.make("tiny")
     log("[interval] tiny, resolution rule")
     ref = ivl.eval_tree(w.map, w.trees[0], w.sensor, n_threads=threads())
-    for got in _gpu_interval(mg, w.map, w.trees[0], w.sensor, caps=(-1, 0, 1, 3)):
+    for got in _gpu_interval(mg, w.map, w.trees[0], w.sensor, caps=(-1, 1, 2, 3)):
         _same(got, ref)
 
 
@@ -77,7 +78,7 @@ def test_interval_random_micro_full(mg, ivl, seed):
     wd, hd = sizes[seed]
     log(f"[interval] micro{seed}: n={tree.n} buffer {wd}x{hd}")
     ref = ivl.eval_tree(m, tree, sen, wd=wd, hd=hd, n_threads=threads())
-    for got in _gpu_interval(mg, m, tree, sen, wd, hd, caps=(-1, 0, 2)):
+    for got in _gpu_interval(mg, m, tree, sen, wd, hd, caps=(-1, 1, 2)):
         _same(got, ref)
 
 
@@ -97,7 +98,7 @@ def test_interval_degenerate_trees(mg, ivl):
     for name, tree in (("one", one), ("chain", chain), ("repeat", rep)):
         log(f"[interval] {name}")
         ref = ivl.eval_tree(m, tree, sen, n_threads=threads())
-        for got in _gpu_interval(mg, m, tree, sen, caps=(-1, 0)):
+        for got in _gpu_interval(mg, m, tree, sen, caps=(-1, 1)):
             _same(got, ref)
 
 
@@ -113,9 +114,9 @@ def test_interval_step_sampled(mg, ivl):
     sel = np.flatnonzero(mask)
     log(f"[interval] step: n={t.n}, sampled {sel.size} nodes")
     ref = ivl.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads())
-    got = _gpu_interval(mg, w.map, t, w.sensor)[0]
-    assert got["D"].shape == (t.n, 93, 160)
-    _same(got, ref, nodes=sel)
+    for got in _gpu_interval(mg, w.map, t, w.sensor, caps=(-1, 2)):
+        assert got["D"].shape == (t.n, 93, 160)
+        _same(got, ref, nodes=sel)
 
 
 def test_interval_rejects_bad_sizes(mg):
@@ -129,5 +130,7 @@ def test_interval_rejects_bad_sizes(mg):
         mg.mg_eval_interval(T.handle, 5000, 10, g, y)
     with pytest.raises(mg.MGError):
         mg.mg_interval_config(17)
+    with pytest.raises(mg.MGError):
+        mg.mg_interval_config(0)
     T.close()
     M.close()
