@@ -5,14 +5,15 @@
 // (Sec. IV-A). A pixel holds the camera-frame z of the first occupied voxel on
 // the ray through its centre, or of the ray's end at the range limit.
 //
-// A candidate ray r(t) = q + t d, 0 <= t <= Rv (one thread per panorama ray)
-// is moved into every ancestor's camera frame, clipped to the valid depth
-// range z_near <= z <= Rv (z is linear in t), projected with eq. (5), clipped
-// to the buffer with the Liang-Barsky algorithm and walked pixel by pixel with
-// a 2D DDA. Inverse depth is linear in screen space (eq. 6), so the part of a
-// pixel's span where z <= the stored depth is found by solving one linear
-// equation, and is mapped back to t perspective-correctly; the spans form the
-// ancestor's overlap intervals (eq. 7). Intervals of all ancestors are merged
+// A candidate ray r(t) = q + t d (one thread per panorama ray) is taken up to
+// its own first hit h <= Rv (nothing past it is counted), moved into every
+// ancestor's camera frame, clipped to the valid depth range z_near <= z <= Rv
+// (z is linear in t), projected with eq. (5), clipped to the buffer with the
+// Liang-Barsky algorithm and walked pixel by pixel with a 2D DDA. Inverse
+// depth is linear in screen space (eq. 6), so the part of a pixel's span where
+// z <= the stored depth is found by solving one linear equation; each maximal
+// observed run of the screen parameter s is one of the ancestor's overlap
+// intervals (eq. 7), mapped back to t perspective-correctly. Intervals of all ancestors are merged
 // into one sorted list of disjoint intervals per ray. The 3D DDA then counts
 // an unknown voxel towards the absolute bin of the ray's column, and towards
 // the marginal bin unless the midpoint of its chord [t_enter, min(t_exit, Rv)]
@@ -74,12 +75,13 @@ __device__ __forceinline__ float t_of_s(float s, float wa, float wb, float tlo, 
     return tlo + lam * (thi - tlo);
 }
 
-// Overlap intervals of ancestor A on the ray from qn along d, in increasing t,
-// intervals that start at or before the end of the previous one joined to it.
-// Each finished interval goes to sink(lo, hi); a sink returning true stops the
-// walk (and this function returns true).
+// Overlap intervals of ancestor A on the ray from qn along d, 0 <= t <= tmax,
+// in increasing t: observed runs of s (a run starting at or before the end of
+// the open one joins it), each mapped to [t(lo), t(hi)] when it closes and
+// given to sink(lo, hi); a sink returning true stops the walk (and this
+// function returns true).
 template <class Sink>
-__device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float dx, float dy, float dz,
+__device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float dx, float dy, float dz, float tmax,
                               const Anc& A, Sink& sink) {
     const float c = A.c, s = A.s;
     const float ox = qx - A.qx, oy = qy - A.qy, oz = qz - A.qz;
@@ -89,12 +91,12 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
     if (Dz == 0.0f) {
         if (!(P0z >= C.znear && P0z <= C.rv)) return false;
         tlo = 0.0f;
-        thi = C.rv;
+        thi = tmax;
     } else {
         const float t1 = (C.znear - P0z) / Dz, t2 = (C.rv - P0z) / Dz;
         const float a = t1 < t2 ? t1 : t2, b = t1 < t2 ? t2 : t1;
         tlo = a > 0.0f ? a : 0.0f;
-        thi = b < C.rv ? b : C.rv;
+        thi = b < tmax ? b : tmax;
     }
     if (!(tlo < thi)) return false;
     const float Ax = P0x + tlo * Dx, Ay = P0y + tlo * Dy, Az = P0z + tlo * Dz;
@@ -103,6 +105,7 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
     const float uA = C.fx * Ax / Az + C.cx, vA = C.fy * Ay / Az + C.cy;
     const float uB = C.fx * Bx / Bz + C.cx, vB = C.fy * By / Bz + C.cy;
     const float wa = 1.0f / Az, wb = 1.0f / Bz;
+    const float rden = wb != wa ? 1.0f / (wb - wa) : 0.0f;
     // Liang-Barsky against u >= 0, u <= W_D, v >= 0, v <= H_D
     const float du = uB - uA, dv = vB - vA;
     const float pp[4] = {-du, du, -dv, dv};
@@ -146,18 +149,17 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
             if (wb == wa) {
                 ok = wa >= wD;
             } else {
-                const float ss = (wD - wa) / (wb - wa);
+                const float ss = (wD - wa) * rden;
                 if (wb > wa) lo = sa > ss ? sa : ss;
                 else hi = e < ss ? e : ss;
             }
             if (ok && lo <= hi) {
-                const float tl = t_of_s(lo, wa, wb, tlo, thi), th = t_of_s(hi, wa, wb, tlo, thi);
-                if (open && tl <= ohi) {
-                    ohi = th > ohi ? th : ohi;
+                if (open && lo <= ohi) {
+                    ohi = hi > ohi ? hi : ohi;
                 } else {
-                    if (open && sink(olo, ohi)) return true;
-                    olo = tl;
-                    ohi = th;
+                    if (open && sink(t_of_s(olo, wa, wb, tlo, thi), t_of_s(ohi, wa, wb, tlo, thi))) return true;
+                    olo = lo;
+                    ohi = hi;
                     open = true;
                 }
             }
@@ -175,7 +177,7 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
         sa = e;
         if (i < 0 || i >= C.wd || j < 0 || j >= C.hd) break;
     }
-    return open ? sink(olo, ohi) : false;
+    return open ? sink(t_of_s(olo, wa, wb, tlo, thi), t_of_s(ohi, wa, wb, tlo, thi)) : false;
 }
 
 // Window of the union of intervals: its components that reach t0 or later,
@@ -260,19 +262,43 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_trace(MapDev M, SensorDev S
         const float4 p = Tr.q4[node];
         const float4 d = S.d4[r];
         const float4 inv = S.iv4[r];
-        Window U;
-        U.cap = cap;
-        for (int32_t k = 0; k < na; ++k) anc_intervals(C, p.x, p.y, p.z, d.x, d.y, d.z, s_anc[k], U);
-        // 3D DDA (Amanatides-Woo; crossings recomputed as (b - q) / d; ties x, y, z)
-        int32_t ix = (int32_t)floorf(p.x), iy = (int32_t)floorf(p.y), iz = (int32_t)floorf(p.z);
+        // 3D DDA (Amanatides-Woo; crossings recomputed as (b - q) / d; ties x, y, z),
+        // first to the ray's first hit h, then again counting
+        const int32_t ix0 = (int32_t)floorf(p.x), iy0 = (int32_t)floorf(p.y), iz0 = (int32_t)floorf(p.z);
         const int32_t sx = d.x > 0.f ? 1 : (d.x < 0.f ? -1 : 0);
         const int32_t sy = d.y > 0.f ? 1 : (d.y < 0.f ? -1 : 0);
         const int32_t sz = d.z > 0.f ? 1 : (d.z < 0.f ? -1 : 0);
-        int32_t bx = sx > 0 ? ix + 1 : ix, by = sy > 0 ? iy + 1 : iy, bz = sz > 0 ? iz + 1 : iz;
+        const int32_t bx0 = sx > 0 ? ix0 + 1 : ix0, by0 = sy > 0 ? iy0 + 1 : iy0, bz0 = sz > 0 ? iz0 + 1 : iz0;
         const float inf = __builtin_inff();
-        float tx = sx ? ((float)bx - p.x) * inv.x : inf;
-        float ty = sy ? ((float)by - p.y) * inv.y : inf;
-        float tz = sz ? ((float)bz - p.z) * inv.z : inf;
+        const float tx0 = sx ? ((float)bx0 - p.x) * inv.x : inf;
+        const float ty0 = sy ? ((float)by0 - p.y) * inv.y : inf;
+        const float tz0 = sz ? ((float)bz0 - p.z) * inv.z : inf;
+        float h = S.rv;
+        {
+            int32_t ix = ix0, iy = iy0, iz = iz0, bx = bx0, by = by0, bz = bz0;
+            float tx = tx0, ty = ty0, tz = tz0, t = 0.0f;
+            for (;;) {
+                if (ix < 0 || ix >= M.nx || iy < 0 || iy >= M.ny || iz < 0 || iz >= M.nz) break;
+                if (!(t < S.rv)) break;
+                if (M.bricks[voxel_addr(ix, iy, iz, M)] == kOccupied) {
+                    h = t;
+                    break;
+                }
+                const int ax = (tx <= ty && tx <= tz) ? 0 : (ty <= tz ? 1 : 2);
+                if (ax == 0) {
+                    t = tx; ix += sx; bx += sx; tx = ((float)bx - p.x) * inv.x;
+                } else if (ax == 1) {
+                    t = ty; iy += sy; by += sy; ty = ((float)by - p.y) * inv.y;
+                } else {
+                    t = tz; iz += sz; bz += sz; tz = ((float)bz - p.z) * inv.z;
+                }
+            }
+        }
+        Window U;
+        U.cap = cap;
+        for (int32_t k = 0; k < na; ++k) anc_intervals(C, p.x, p.y, p.z, d.x, d.y, d.z, h, s_anc[k], U);
+        int32_t ix = ix0, iy = iy0, iz = iz0, bx = bx0, by = by0, bz = bz0;
+        float tx = tx0, ty = ty0, tz = tz0;
         float t = 0.0f;
         uint32_t n_abs = 0, n_marg = 0;
         int32_t ptr = 0;
@@ -291,7 +317,7 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_trace(MapDev M, SensorDev S
                     U.t0 = U.tcut;
                     U.tcut = inf;
                     U.m = 0;
-                    for (int32_t k = 0; k < na; ++k) anc_intervals(C, p.x, p.y, p.z, d.x, d.y, d.z, s_anc[k], U);
+                    for (int32_t k = 0; k < na; ++k) anc_intervals(C, p.x, p.y, p.z, d.x, d.y, d.z, h, s_anc[k], U);
                     ptr = 0;
                 }
                 while (ptr < U.m && U.hi[ptr] < tm) ++ptr;
