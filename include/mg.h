@@ -86,6 +86,39 @@ int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, flo
 /* Frees the map. MG_E_BUSY while trees created on it still exist. */
 int mg_map_destroy(mg_map map);
 
+/* Map from a truncated signed distance field (the planners' volumetric map,
+ * which Sec. IV converts into a contiguous grid on the GPU). distance (metres)
+ * and weight: DEVICE float [nz][ny][nx], x fastest, read on hip_stream. A
+ * voxel is unknown unless weight >= min_weight, occupied when
+ * distance <= surface_m, free otherwise (comparisons with NaN are false: a
+ * NaN weight is unknown, a NaN distance free). One pass reads 8 B and writes
+ * the bricked byte per voxel; the call returns after it finished. Same
+ * geometry rules and errors as mg_map_create; MG_E_INVALID for a non-finite
+ * surface_m or min_weight. */
+int mg_map_create_tsdf(const float* distance, const float* weight, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
+                       const float origin_m[3], float surface_m, float min_weight, void* hip_stream, mg_map* out);
+
+/* Replaces the states of a box of voxels [lo, lo + size) (HOST int32[3]
+ * each) by the conversion above of its TSDF, distance and weight DEVICE float
+ * [size_z][size_y][size_x], x fastest. Enqueued on hip_stream; evaluations
+ * that must see the update go on the same stream (or are ordered after it).
+ * MG_E_INVALID when the box leaves the grid. */
+int mg_map_update_tsdf(mg_map map, void* hip_stream, const float* distance, const float* weight, const int32_t lo[3],
+                       const int32_t size[3], float surface_m, float min_weight);
+
+/* New states for listed voxels between replans: voxel_ids DEVICE uint32
+ * [count] (linear ids x + nx (y + ny z), distinct; for repeated ids the
+ * state written is one of theirs), states DEVICE uint8 [count] in {0, 1, 2}.
+ * An id outside the grid or a larger state is skipped and counted into
+ * *rejected (DEVICE uint32, zeroed first; may be NULL). Enqueued on
+ * hip_stream. */
+int mg_map_update(mg_map map, void* hip_stream, const uint32_t* voxel_ids, const uint8_t* states, int32_t count,
+                  uint32_t* rejected);
+
+/* Dense copy of the map's states: DEVICE uint8 [nz][ny][nx], x fastest,
+ * enqueued on hip_stream. */
+int mg_map_read(mg_map map, void* hip_stream, uint8_t* states);
+
 /* Candidate tree (Sec. III-A: nodes with positions; Sec. IV-D: the whole tree
  * is built first, then evaluated).
  *   pos_m: HOST array [n][3] in metres; parent: HOST array [n] with

@@ -335,39 +335,43 @@ struct mg_map_s {
     std::atomic<int> trees{0};
 };
 
-extern "C" int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
-                             const float origin_m[3], void* hip_stream, mg_map* out) {
-    if (!out) return fail(MG_E_INVALID, "out is NULL");
-    *out = nullptr;
-    if (!states || !origin_m) return fail(MG_E_INVALID, "states/origin is NULL");
+namespace {
+
+int32_t bricks_for(int32_t n) {     // power of two holding at least n + 1 voxels
+    int32_t nb = 1;
+    while (nb * 8 < n + 1) nb *= 2;
+    return nb;
+}
+
+// Host-only validation of a map's geometry (no device call).
+int check_geometry(int32_t nx, int32_t ny, int32_t nz, float voxel_m, const float origin_m[3]) {
+    if (!origin_m) return fail(MG_E_INVALID, "origin is NULL");
     if (nx < 1 || ny < 1 || nz < 1 || nx > 8192 || ny > 8192 || nz > 8192)
         return fail(MG_E_INVALID, "grid dims must be in [1, 8192]");
     if (!(voxel_m > 0.0f) || !std::isfinite(voxel_m)) return fail(MG_E_INVALID, "voxel_m must be positive");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(origin_m[a])) return fail(MG_E_INVALID, "origin must be finite");
-    const size_t nvox = (size_t)nx * ny * nz;
-    if (nvox >= (1ull << 32)) return fail(MG_E_INVALID, "grid has 2^32 voxels or more");
-    // power-of-two brick counts holding at least n + 1 voxels per axis
-    auto bricks_for = [](int32_t n) {
-        int32_t nb = 1;
-        while (nb * 8 < n + 1) nb *= 2;
-        return nb;
-    };
+    if ((size_t)nx * ny * nz >= (1ull << 32)) return fail(MG_E_INVALID, "grid has 2^32 voxels or more");
+    const int32_t nbx = bricks_for(nx), nby = bricks_for(ny), nbz = bricks_for(nz);
+    if ((size_t)nbx * nby * nbz * 512u > (1ull << 32) - 256)
+        return fail(MG_E_UNSUPPORTED, "bricked grid (%d x %d x %d bricks) exceeds 2^32 - 256 bytes", nbx, nby, nbz);
+    return MG_OK;
+}
+
+// Lays out the padded bricked grid (power-of-two brick counts holding at
+// least n + 1 voxels per axis) and allocates it.
+int map_alloc(int32_t nx, int32_t ny, int32_t nz, float voxel_m, const float origin_m[3],
+              std::unique_ptr<mg_map_s>* out) {
+    int rc0 = check_geometry(nx, ny, nz, voxel_m, origin_m);
+    if (rc0 != MG_OK) return rc0;
     const int32_t nbx = bricks_for(nx), nby = bricks_for(ny), nbz = bricks_for(nz);
     const size_t padded = (size_t)nbx * nby * nbz * 512u;
-    if (padded > (1ull << 32) - 256)
-        return fail(MG_E_UNSUPPORTED, "bricked grid (%d x %d x %d bricks) exceeds 2^32 - 256 bytes", nbx, nby, nbz);
-    for (size_t i = 0; i < nvox; ++i)
-        if (states[i] > 2) return fail(MG_E_INVALID, "voxel %zu has state %u (expected 0, 1 or 2)", i, states[i]);
-
-    hipStream_t s = (hipStream_t)hip_stream;
     std::unique_ptr<mg_map_s> m(new (std::nothrow) mg_map_s());
     if (!m) return fail(MG_E_NOMEM, "host allocation failed");
     HIP_TRY(hipGetDevice(&m->device));
-    uint8_t* dense = nullptr;
-    HIP_TRY(hipMalloc(&dense, nvox));
     hipError_t e = hipMalloc(&m->bricks, padded);
-    if (e == hipSuccess) e = hipMemcpyAsync(dense, states, nvox, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "map allocation: %s", hipGetErrorString(e));
     m->dev.bricks = m->bricks;
     m->dev.nx = nx; m->dev.ny = ny; m->dev.nz = nz;
     m->dev.nbx = nbx; m->dev.nby = nby; m->dev.nbz = nbz;
@@ -378,6 +382,32 @@ extern "C" int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int3
     m->dev.shy = 6u + log2i(nbx);
     m->dev.shz = 6u + log2i(nbx) + log2i(nby);
     m->dev.outside = voxel_addr(8 * nbx - 1, 0, 0, m->dev);
+    m->voxel_m = voxel_m;
+    for (int a = 0; a < 3; ++a) m->origin[a] = origin_m[a];
+    m->bytes = padded;
+    *out = std::move(m);
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
+                             const float origin_m[3], void* hip_stream, mg_map* out) {
+    if (!out) return fail(MG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!states) return fail(MG_E_INVALID, "states is NULL");
+    int rc = check_geometry(nx, ny, nz, voxel_m, origin_m);
+    if (rc != MG_OK) return rc;
+    const size_t nvox = (size_t)nx * ny * nz;
+    for (size_t i = 0; i < nvox; ++i)
+        if (states[i] > 2) return fail(MG_E_INVALID, "voxel %zu has state %u (expected 0, 1 or 2)", i, states[i]);
+    std::unique_ptr<mg_map_s> m;
+    rc = map_alloc(nx, ny, nz, voxel_m, origin_m, &m);
+    if (rc != MG_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint8_t* dense = nullptr;
+    hipError_t e = hipMalloc(&dense, nvox);
+    if (e == hipSuccess) e = hipMemcpyAsync(dense, states, nvox, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_brick(dense, m->bricks, m->dev, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dense);
@@ -385,10 +415,75 @@ extern "C" int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int3
         (void)hipFree(m->bricks);
         return fail(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "map upload: %s", hipGetErrorString(e));
     }
-    m->voxel_m = voxel_m;
-    for (int a = 0; a < 3; ++a) m->origin[a] = origin_m[a];
-    m->bytes = padded;
     *out = m.release();
+    return MG_OK;
+}
+
+extern "C" int mg_map_create_tsdf(const float* distance, const float* weight, int32_t nx, int32_t ny, int32_t nz,
+                                  float voxel_m, const float origin_m[3], float surface_m, float min_weight,
+                                  void* hip_stream, mg_map* out) {
+    if (!out) return fail(MG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!distance || !weight) return fail(MG_E_INVALID, "distance/weight is NULL");
+    if (!std::isfinite(surface_m) || !std::isfinite(min_weight))
+        return fail(MG_E_INVALID, "surface_m and min_weight must be finite");
+    int rc = check_geometry(nx, ny, nz, voxel_m, origin_m);
+    if (rc != MG_OK) return rc;
+    std::unique_ptr<mg_map_s> m;
+    rc = map_alloc(nx, ny, nz, voxel_m, origin_m, &m);
+    if (rc != MG_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = launch_tsdf_grid(distance, weight, m->dev, surface_m, min_weight, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(m->bricks);
+        return fail(MG_E_DEVICE, "TSDF conversion: %s", hipGetErrorString(e));
+    }
+    *out = m.release();
+    return MG_OK;
+}
+
+extern "C" int mg_map_update_tsdf(mg_map map, void* hip_stream, const float* distance, const float* weight,
+                                  const int32_t lo[3], const int32_t size[3], float surface_m, float min_weight) {
+    if (!map || !lo || !size) return fail(MG_E_INVALID, "NULL argument");
+    if ((!distance || !weight) && (int64_t)size[0] * size[1] * size[2] != 0)
+        return fail(MG_E_INVALID, "distance/weight is NULL");
+    if (!std::isfinite(surface_m) || !std::isfinite(min_weight))
+        return fail(MG_E_INVALID, "surface_m and min_weight must be finite");
+    const int32_t dims[3] = {map->dev.nx, map->dev.ny, map->dev.nz};
+    bool whole = true;
+    for (int a = 0; a < 3; ++a) {
+        if (lo[a] < 0 || size[a] < 0 || (int64_t)lo[a] + size[a] > dims[a])
+            return fail(MG_E_INVALID, "box [%d, %d) on axis %d leaves the grid (%d)", lo[a], lo[a] + size[a], a, dims[a]);
+        whole = whole && lo[a] == 0 && size[a] == dims[a];
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != map->device) return fail(MG_E_INVALID, "the map lives on another device");
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(whole ? launch_tsdf_grid(distance, weight, map->dev, surface_m, min_weight, s)
+                  : launch_tsdf_box(distance, weight, map->dev, lo, size, surface_m, min_weight, s));
+    return MG_OK;
+}
+
+extern "C" int mg_map_update(mg_map map, void* hip_stream, const uint32_t* voxel_ids, const uint8_t* states,
+                             int32_t count, uint32_t* rejected) {
+    if (!map || count < 0 || (count > 0 && (!voxel_ids || !states))) return fail(MG_E_INVALID, "bad update arguments");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != map->device) return fail(MG_E_INVALID, "the map lives on another device");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (rejected) HIP_TRY(launch_zero_u32(rejected, 1, s));
+    HIP_TRY(launch_map_scatter(voxel_ids, states, (uint32_t)count, map->dev, rejected, s));
+    return MG_OK;
+}
+
+extern "C" int mg_map_read(mg_map map, void* hip_stream, uint8_t* states) {
+    if (!map || !states) return fail(MG_E_INVALID, "map/states is NULL");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != map->device) return fail(MG_E_INVALID, "the map lives on another device");
+    HIP_TRY(launch_unbrick(map->dev, states, (hipStream_t)hip_stream));
     return MG_OK;
 }
 

@@ -96,6 +96,15 @@ struct BatchTree {
 // Launchers (mg_kernels.hip).
 hipError_t launch_brick(const uint8_t* dense, uint8_t* bricks, const MapDev& m, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
+// Map contents (mg_map.hip): TSDF conversion of the whole grid or of a box,
+// listed voxel updates, and a dense copy of the states.
+hipError_t launch_tsdf_grid(const float* dist, const float* weight, const MapDev& m, float surface, float min_weight,
+                            hipStream_t s);
+hipError_t launch_tsdf_box(const float* dist, const float* weight, const MapDev& m, const int32_t lo[3],
+                           const int32_t size[3], float surface, float min_weight, hipStream_t s);
+hipError_t launch_map_scatter(const uint32_t* ids, const uint8_t* states, uint32_t count, const MapDev& m,
+                              uint32_t* rejected, hipStream_t s);
+hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s);
 // max_anc: the most ancestors any node of the launch has (the LDS holds that
 // many); every node of depth level d has exactly d.
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,

@@ -29,8 +29,9 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait", "mg_server_stats",
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
-                     "mg_interval_config",
-           "mg_interval_config")
+                     "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update",
+                     "mg_map_read",
+           "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read")
 
 
 class MGError(RuntimeError):
@@ -71,6 +72,10 @@ def lib() -> C.CDLL:
         L.mg_eval_marginal.argtypes = [P, P, P, P, P]
         L.mg_eval_single_parent.argtypes = [P, P, P, P, P]
         L.mg_eval_interval.argtypes = [P, P, I32, I32, P, P, P]
+        L.mg_map_create_tsdf.argtypes = [P, P, I32, I32, I32, C.c_float, P, C.c_float, C.c_float, P, C.POINTER(P)]
+        L.mg_map_update_tsdf.argtypes = [P, P, P, P, P, P, C.c_float, C.c_float]
+        L.mg_map_update.argtypes = [P, P, P, P, I32, P]
+        L.mg_map_read.argtypes = [P, P, P]
         L.mg_interval_config.argtypes = [I32]
         L.mg_interval_tables.argtypes = [C.POINTER(mg_sensor), C.c_float, I32, I32, P, P, P, P]
         L.mg_eval_marginal_levelsync.argtypes = [P, P, P, P, P, P, P]
@@ -284,13 +289,56 @@ def mg_sensor_tables(sensor):
 
 # ----------------------------------------------------------------- owning wrappers
 
+def mg_map_create_tsdf(distance, weight, voxel_m, origin_m, surface_m, min_weight, stream=None) -> int:
+    """distance, weight: device float32 tensors [nz, ny, nx]."""
+    nz, ny, nx = (int(v) for v in distance.shape)
+    org = np.ascontiguousarray(origin_m, dtype=np.float32)
+    out = C.c_void_p()
+    _check(lib().mg_map_create_tsdf(_dev_ptr(distance), _dev_ptr(weight), nx, ny, nz, float(voxel_m), _np_ptr(org),
+                                    float(surface_m), float(min_weight), _stream(stream), C.byref(out)))
+    return out.value
+
+
+def mg_map_update_tsdf(m: int, distance, weight, lo, surface_m, min_weight, stream=None):
+    """distance, weight: device float32 tensors [sz, sy, sx] for the box starting at lo = (x, y, z)."""
+    sz, sy, sx = (int(v) for v in distance.shape)
+    lo_a = np.ascontiguousarray(lo, dtype=np.int32)
+    size_a = np.array([sx, sy, sz], np.int32)
+    _check(lib().mg_map_update_tsdf(C.c_void_p(m), _stream(stream), _dev_ptr(distance), _dev_ptr(weight),
+                                    _np_ptr(lo_a), _np_ptr(size_a), float(surface_m), float(min_weight)))
+
+
+def mg_map_update(m: int, voxel_ids, states, rejected=None, stream=None):
+    """voxel_ids: device int32/uint32 tensor, states: device uint8 tensor, rejected: device int32 [1] or None."""
+    _check(lib().mg_map_update(C.c_void_p(m), _stream(stream), _dev_ptr(voxel_ids), _dev_ptr(states),
+                               int(voxel_ids.numel()), _dev_ptr(rejected)))
+
+
+def mg_map_read(m: int, states, stream=None):
+    _check(lib().mg_map_read(C.c_void_p(m), _stream(stream), _dev_ptr(states)))
+
+
 class Map:
     """Device-resident occupancy grid (wraps mg_map_create / mg_map_destroy)."""
 
-    def __init__(self, states: np.ndarray, voxel_m: float, origin_m=(0.0, 0.0, 0.0), stream=None):
-        self.handle = mg_map_create(states, voxel_m, origin_m, stream)
+    def __init__(self, states: np.ndarray, voxel_m: float, origin_m=(0.0, 0.0, 0.0), stream=None, handle=None):
+        self.handle = handle if handle is not None else mg_map_create(states, voxel_m, origin_m, stream)
         self.shape = tuple(np.asarray(states).shape)
         self.voxel_m = float(np.float32(voxel_m))
+
+    @classmethod
+    def from_tsdf(cls, distance, weight, voxel_m, origin_m=(0.0, 0.0, 0.0), surface_m=0.0, min_weight=1e-3,
+                  stream=None):
+        """Map converted on the device from a TSDF (device float32 tensors [nz, ny, nx])."""
+        h = mg_map_create_tsdf(distance, weight, voxel_m, origin_m, surface_m, min_weight, stream)
+        return cls(np.empty(tuple(distance.shape), np.uint8), voxel_m, origin_m, handle=h)
+
+    def read(self, stream=None):
+        """Device uint8 tensor [nz, ny, nx] with the map's states."""
+        import torch
+        out = torch.empty(self.shape, dtype=torch.uint8, device="cuda")
+        mg_map_read(self.handle, out, stream)
+        return out
 
     def close(self):
         if self.handle:
