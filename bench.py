@@ -65,6 +65,43 @@ def score_bench(mg, trees, gain, n_total, depth_sum, reps=200):
             "d2h_bytes_replaced": n_total * 8, "d2h_bytes_after": len(trees) * (mg.MG_BRANCH_LEN * 4 + 4)}
 
 
+def map_bench(mg, dims=(512, 512, 128), voxel_m=0.05, reps=20, n_updates=1 << 20):
+    """Map conversion and deltas on the grid of the large configuration: a whole-grid TSDF update
+    (reads 8 B, writes the bricked byte per voxel) and listed voxel updates, timed with HIP events
+    over `reps` calls on the current stream; inputs resident on the device, seeded."""
+    import torch
+    nx, ny, nz = dims
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1234)
+    dist = torch.randn((nz, ny, nx), generator=g, device="cuda") * 0.4 + 0.3
+    wgt = torch.rand((nz, ny, nx), generator=g, device="cuda") * 3.0
+    M = mg.Map.from_tsdf(dist, wgt, voxel_m, (0.0, 0.0, 0.0), surface_m=0.05, min_weight=1.0)
+    ids = torch.randint(0, nx * ny * nz, (n_updates,), generator=g, device="cuda", dtype=torch.int32)
+    new = torch.randint(0, 3, (n_updates,), generator=g, device="cuda", dtype=torch.uint8)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    out = {"grid": f"{nx}x{ny}x{nz}", "voxels": nx * ny * nz}
+    for name, fn in (("tsdf_update", lambda: mg.mg_map_update_tsdf(M.handle, dist, wgt, (0, 0, 0), 0.05, 1.0)),
+                     ("voxel_updates", lambda: mg.mg_map_update(M.handle, ids, new))):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_us"] = e0.elapsed_time(e1) * 1e3 / reps
+    M.close()
+    nb = [((n + 7) // 8) for n in dims]
+    alg = 8 * nx * ny * nz + nb[0] * nb[1] * nb[2] * 512       # TSDF in, bricks holding grid voxels out
+    gbs = alg / (out["tsdf_update_us"] * 1e-6) / 1e9
+    out["tsdf_voxels_per_s"] = nx * ny * nz / (out["tsdf_update_us"] * 1e-6)
+    out["tsdf_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": alg}
+    out["voxel_updates_per_s"] = n_updates / (out["voxel_updates_us"] * 1e-6)
+    return out
+
+
 def score_oracle(w):
     """The path-score oracle over every tree of the workload, on gains of 1 per node (its cost does
     not depend on the values)."""
@@ -94,6 +131,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sp-steps", type=int, default=5, help="timed single-parent (g_sp) passes; 0 skips")
     ap.add_argument("--ivl-steps", type=int, default=3, help="timed interval-mode passes; 0 skips")
+    ap.add_argument("--no-map-bench", dest="map_bench", action="store_false",
+                    help="skip the map conversion / update timing")
     ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6, help="oracle sample, rays per host thread")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (calibrates HBM byte counters) and exit")
@@ -452,6 +491,9 @@ def main():
             ivl["achieved_GBps_whole_call"] = alg / dt / 1e9
             ivl["pixel_steps_per_ray"] = wci["pixel_steps"] / wci["rays"]
         log(f"[bench] interval: {ivl}")
+    mapb = map_bench(mg) if args.map_bench else None
+    if mapb:
+        log(f"[bench] maps: {mapb}")
     score = None
     if "batched" in results:
         score = score_bench(mg, trees, g_all, n_total, int(sum(t.depth().sum() for t in w.trees)))
@@ -489,6 +531,7 @@ def main():
         "path_score": score,
         "single_parent": sp,
         "interval": ivl,
+        "maps": mapb,
     }
     print(json.dumps(line), flush=True)
     for T in trees:

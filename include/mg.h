@@ -256,6 +256,20 @@ int mg_interval_config(int32_t cap);
 int mg_interval_tables(const mg_sensor* sensor, float voxel_m, int32_t wd, int32_t hd, int32_t* wh, float* intr,
                        float* pdir, float* cs);
 
+/* Exact marginal gain with voxel hash sets (eq. 2; the exact comparison of
+ * Sec. V-A, there computed with hash maps on the CPU) at given windows:
+ * yaw_bin DEVICE int32[n] (e.g. from mg_eval_marginal). I(n) is the set of
+ * unknown voxels met by the rays of node n's window; outputs DEVICE
+ * uint32[n]: x_ray = unknown incidences of those rays whose voxel is in no
+ * ancestor's I (the per-incidence counterpart of the depth-buffer gain),
+ * x_set = |I(n) minus the ancestors' I| (may be NULL), a_set = |I(n)| (may be
+ * NULL). Synchronises hip_stream twice (windows checked on the host, tables
+ * sized from a first pass) and may grow the tree's table pool (about 8 bytes
+ * per unknown incidence of the windows). MG_E_INVALID for a window outside
+ * [0, yaw_bins). */
+int mg_eval_exact(mg_tree tree, void* hip_stream, const int32_t* yaw_bin, uint32_t* x_ray, uint32_t* x_set,
+                  uint32_t* a_set);
+
 /* Absolute gain of every node (eq. 1 maximised over the yaw windows), no
  * conditioning and no level order: one flat launch over all nodes.
  *   gain DEVICE uint32[n], yaw_bin DEVICE int32[n]. */

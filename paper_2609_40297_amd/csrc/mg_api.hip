@@ -433,7 +433,8 @@ extern "C" int mg_map_create_tsdf(const float* distance, const float* weight, in
     rc = map_alloc(nx, ny, nz, voxel_m, origin_m, &m);
     if (rc != MG_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    hipError_t e = launch_tsdf_grid(distance, weight, m->dev, surface_m, min_weight, s);
+    hipError_t e = launch_fill_outside(m->dev, s);
+    if (e == hipSuccess) e = launch_tsdf_grid(distance, weight, m->dev, surface_m, min_weight, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(m->bricks);
@@ -717,6 +718,7 @@ extern "C" int mg_tree_destroy(mg_tree t) {
     if (!t) return fail(MG_E_INVALID, "tree is NULL");
     mgb::forget_tree(t);
     mgb::forget_interval(t);
+    mgb::forget_exact(t);
     if (t->owns_block) (void)hipFree(t->block);
     release_sensor(t->sensor);
     t->map->trees--;

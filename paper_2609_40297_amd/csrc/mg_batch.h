@@ -34,5 +34,6 @@ size_t block_bytes(const HostTree& H);
 int upload_into(mg_map map, const HostTree& H, const mg_sensor* sensor, hipStream_t s, void* block, mg_tree* out);
 void forget_tree(mg_tree t);               // mg_batch.hip: drop cached launch plans that use t
 void forget_interval(mg_tree t);           // mg_interval.hip: free t's interval-mode buffers
+void forget_exact(mg_tree t);              // mg_exact.hip: free t's hash tables
 
 }  // namespace mgb

@@ -105,6 +105,7 @@ hipError_t launch_tsdf_box(const float* dist, const float* weight, const MapDev&
 hipError_t launch_map_scatter(const uint32_t* ids, const uint8_t* states, uint32_t count, const MapDev& m,
                               uint32_t* rejected, hipStream_t s);
 hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s);
+hipError_t launch_fill_outside(const MapDev& m, hipStream_t s);
 // max_anc: the most ancestors any node of the launch has (the LDS holds that
 // many); every node of depth level d has exactly d.
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,

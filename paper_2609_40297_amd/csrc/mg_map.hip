@@ -19,10 +19,12 @@ __device__ __forceinline__ uint8_t tsdf_state(float d, float w, float surface, f
     return !(w >= min_weight) ? (uint8_t)kUnknown : (d <= surface ? (uint8_t)kOccupied : (uint8_t)kFree);
 }
 
-// Whole grid: one workgroup per run of up to 32 bricks along x at one (by, bz).
-// Each of the 64 (y, z) rows of the run is read coalesced along x, the states
-// are assembled in LDS in brick order, and the run's bricks (contiguous in
-// memory) are written out in 16-byte stores. Padding voxels get kOutside.
+// Whole grid: one workgroup per run of up to 32 bricks along x at one (by, bz),
+// over the bricks that hold grid voxels (bricks wholly in the padding keep
+// kOutside from the map's creation). Each of the 64 (y, z) rows of the run is
+// read coalesced along x, the states are assembled in LDS in brick order, and
+// the run's bricks (contiguous in memory) are written out in 16-byte stores.
+// Padding voxels inside these bricks get kOutside.
 constexpr int kTileBricks = 32;
 
 __global__ __launch_bounds__(256) void k_tsdf_grid(const float* __restrict__ dist, const float* __restrict__ weight,
@@ -102,10 +104,24 @@ unsigned blocks_for(size_t n) {
 }
 }  // namespace
 
+// Every byte of the padded grid set to kOutside (a new map, before conversion).
+__global__ void k_fill_outside(uint4* __restrict__ p, size_t n16) {
+    const uint32_t o = kOutside * 0x01010101u;
+    const uint4 v = make_uint4(o, o, o, o);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_outside(const MapDev& m, hipStream_t s) {
+    const size_t n16 = (size_t)m.nbx * m.nby * m.nbz * 32u;
+    hipLaunchKernelGGL(k_fill_outside, dim3(blocks_for(n16)), dim3(256), 0, s, (uint4*)m.bricks, n16);
+    return hipGetLastError();
+}
+
 hipError_t launch_tsdf_grid(const float* dist, const float* weight, const MapDev& m, float surface, float min_weight,
                             hipStream_t s) {
     const int32_t tb = m.nbx < kTileBricks ? m.nbx : kTileBricks;
-    const dim3 grid((unsigned)(m.nbx / tb), (unsigned)m.nby, (unsigned)m.nbz);
+    const int32_t ux = (m.nx + 7) / 8, uy = (m.ny + 7) / 8, uz = (m.nz + 7) / 8;   // bricks holding grid voxels
+    const dim3 grid((unsigned)((ux + tb - 1) / tb), (unsigned)uy, (unsigned)uz);
     hipLaunchKernelGGL(k_tsdf_grid, grid, dim3(256), 0, s, dist, weight, (uint8_t*)m.bricks, m, surface, min_weight);
     return hipGetLastError();
 }

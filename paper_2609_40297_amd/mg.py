@@ -30,8 +30,9 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
                      "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update",
-                     "mg_map_read",
-           "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read")
+                     "mg_map_read", "mg_eval_exact",
+           "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read",
+           "mg_eval_exact")
 
 
 class MGError(RuntimeError):
@@ -76,6 +77,7 @@ def lib() -> C.CDLL:
         L.mg_map_update_tsdf.argtypes = [P, P, P, P, P, P, C.c_float, C.c_float]
         L.mg_map_update.argtypes = [P, P, P, P, I32, P]
         L.mg_map_read.argtypes = [P, P, P]
+        L.mg_eval_exact.argtypes = [P, P, P, P, P, P]
         L.mg_interval_config.argtypes = [I32]
         L.mg_interval_tables.argtypes = [C.POINTER(mg_sensor), C.c_float, I32, I32, P, P, P, P]
         L.mg_eval_marginal_levelsync.argtypes = [P, P, P, P, P, P, P]
@@ -196,6 +198,11 @@ def interval_tables(sensor, voxel_m, wd=0, hd=0):
     _check(lib().mg_interval_tables(C.byref(s), float(voxel_m), int(wd), int(hd), _np_ptr(wh), _np_ptr(intr),
                                     _np_ptr(pdir), _np_ptr(cs)))
     return W, H, intr, pdir, cs
+
+
+def mg_eval_exact(tree: int, yaw_bin, x_ray, x_set=None, a_set=None, stream=None):
+    _check(lib().mg_eval_exact(C.c_void_p(tree), _stream(stream), _dev_ptr(yaw_bin), _dev_ptr(x_ray), _dev_ptr(x_set),
+                               _dev_ptr(a_set)))
 
 
 def mg_eval_single_parent(tree: int, gain, yaw_bin, depth=None, stream=None):
@@ -378,6 +385,15 @@ class Tree:
         g, y, d = self.outputs(depth)
         mg_eval_marginal(self.handle, g, y, d, stream)
         return g, y, d
+
+    def eval_exact(self, yaw_bin, stream=None):
+        """Exact marginal gain with hash sets at the windows yaw_bin (device int32 [n]): (x_ray, x_set, a_set)."""
+        import torch
+        xr = torch.empty(self.n, dtype=torch.int32, device=yaw_bin.device)
+        xs = torch.empty_like(xr)
+        a = torch.empty_like(xr)
+        mg_eval_exact(self.handle, yaw_bin, xr, xs, a, stream)
+        return xr, xs, a
 
     def eval_interval(self, wd=0, hd=0, depth=False, stream=None):
         """Interval mode (the paper's pinhole buffers and overlap intervals): (gain, yaw, depth or None)."""

@@ -1,0 +1,83 @@
+"""GPU parity of the exact hash-set marginal gain (mg_eval_exact) against the oracle's exact
+pass (oracle/mgref.c, sorted voxel sets): X_ray, X_set and A_set at the depth-buffer method's
+windows, integer-exact."""
+import numpy as np
+import pytest
+
+from paper_2609_40297_amd import workloads as W
+from tests.gpu_util import log, threads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_40297_amd import mg as mgmod
+    mgmod.lib()
+    return mgmod
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import mgref
+    if not __import__("os").path.exists(mgref.LIB):
+        mgref.build()
+    return mgref
+
+
+def _check(mg, orc, m, tree, sen, label, mask=None):
+    import torch
+    M = mg.Map(m.states, m.voxel_m, m.origin_m)
+    T = mg.Tree(M, tree.pos_m, tree.parent, sen)
+    g, y, d = T.eval_marginal(depth=True)
+    xr, xs, a = T.eval_exact(y)
+    torch.cuda.synchronize()
+    k = y.cpu().numpy()
+    D = d.cpu().numpy().reshape(tree.n, sen.n_el, sen.w_buf)
+    ref = orc.exact(m, tree, sen, k, D, mask=mask)
+    sel = np.arange(tree.n) if mask is None else np.flatnonzero(mask)
+    log(f"[exact] {label}: n={tree.n}, compared {sel.size}, X_ray sum {int(ref['X_ray'][sel].sum())}")
+    for name, got in (("X_ray", xr), ("X_set", xs), ("A_set", a)):
+        assert np.array_equal(mg.as_u32(got)[sel], ref[name][sel]), name
+    T.close()
+    M.close()
+    return ref
+
+
+def test_exact_tiny(mg, orc):
+    w = W.make("tiny")
+    ref = _check(mg, orc, w.map, w.trees[0], w.sensor, "tiny")
+    assert ref["X_set"][0] == ref["A_set"][0]                  # the root has no ancestors
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_exact_random_micro(mg, orc, seed):
+    sens = [dict(n_az=16, n_el=6, yaw_bins=8), dict(n_az=100, n_el=7, yaw_bins=36),
+            dict(n_az=24, n_el=5, yaw_bins=12)]
+    m, tree, sen = W.random_micro(800 + seed, dims=(17, 13, 9), n_nodes=12, max_depth=4, range_vox=9.0,
+                                  p_occ=0.06, p_free=0.45, **sens[seed])
+    _check(mg, orc, m, tree, sen, f"micro{seed}")
+
+
+def test_exact_step_sampled(mg, orc):
+    w = W.make("step")
+    t = w.trees[0]
+    dep = t.depth()
+    leaves = np.flatnonzero(dep == dep.max())[:3]
+    mask = orc.ancestor_closure(t.parent, leaves)
+    _check(mg, orc, w.map, t, w.sensor, "step", mask=mask)
+
+
+def test_exact_rejects_bad_windows(mg):
+    import torch
+    w = W.make("tiny")
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    T = mg.Tree(M, w.trees[0].pos_m, w.trees[0].parent, w.sensor)
+    y = torch.full((T.n,), w.sensor.yaw_bins, dtype=torch.int32, device="cuda")
+    with pytest.raises(mg.MGError):
+        T.eval_exact(y)
+    T.close()
+    M.close()
