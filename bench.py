@@ -131,6 +131,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sp-steps", type=int, default=5, help="timed single-parent (g_sp) passes; 0 skips")
     ap.add_argument("--ivl-steps", type=int, default=3, help="timed interval-mode passes; 0 skips")
+    ap.add_argument("--exact-steps", type=int, default=3, help="timed exact hash-set passes; 0 skips")
     ap.add_argument("--no-map-bench", dest="map_bench", action="store_false",
                     help="skip the map conversion / update timing")
     ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6, help="oracle sample, rays per host thread")
@@ -491,6 +492,30 @@ def main():
             ivl["achieved_GBps_whole_call"] = alg / dt / 1e9
             ivl["pixel_steps_per_ray"] = wci["pixel_steps"] / wci["rays"]
         log(f"[bench] interval: {ivl}")
+    exact = None
+    if args.exact_steps > 0 and "batched" in results:
+        # exact marginal gain with device hash sets at the depth-buffer windows just computed
+        # (the exact comparison of Sec. V-A), per tree: X_ray, X_set, A_set
+        xr = torch.empty(max(t.n for t in trees), dtype=torch.int32, device=dev)
+        xs, xa = torch.empty_like(xr), torch.empty_like(xr)
+        ys = []
+        off = 0
+        for T in trees:
+            ys.append(y_all[off:off + T.n])
+            off += T.n
+        for T, yk in zip(trees, ys):
+            mg.mg_eval_exact(T.handle, yk, xr, xs, xa)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.exact_steps):
+            for T, yk in zip(trees, ys):
+                mg.mg_eval_exact(T.handle, yk, xr, xs, xa)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.exact_steps
+        exact = {"ms_per_step": dt * 1e3, "window_rays_per_s": n_total * sen.n_el * sen.w_buf / dt,
+                 "steps": args.exact_steps, "over_depth_buffer": dt * 1e3 / results["batched"]["ms_per_step"],
+                 "path": "mg_eval_exact per tree (hash sets of the window rays' unknown voxels; X_ray, X_set, A_set)"}
+        log(f"[bench] exact: {exact}")
     mapb = map_bench(mg) if args.map_bench else None
     if mapb:
         log(f"[bench] maps: {mapb}")
@@ -532,6 +557,7 @@ def main():
         "single_parent": sp,
         "interval": ivl,
         "maps": mapb,
+        "exact": exact,
     }
     print(json.dumps(line), flush=True)
     for T in trees:
