@@ -306,6 +306,16 @@ int mg_server_create(const mg_server_config* cfg, mg_server* out);
 int mg_server_submit(mg_server server, mg_map map, const float* pos_m, const int32_t* parent, int32_t n,
                      uint32_t* gain, int32_t* yaw_bin, int64_t* ticket);
 
+/* Queues a map update between replans: voxel_ids HOST uint32 [count] (linear
+ * ids x + nx (y + ny z), distinct), states HOST uint8 [count] in {0, 1, 2};
+ * both copied. The update is applied once it reaches the head of the queue
+ * and no in-flight request uses the map, so requests submitted before it see
+ * the old map and requests submitted after it the new one. *ticket works with
+ * mg_server_poll / mg_server_wait like a request's. MG_E_INVALID for an id
+ * outside the grid or a larger state. Thread-safe. */
+int mg_server_map_update(mg_server server, mg_map map, const uint32_t* voxel_ids, const uint8_t* states,
+                         int32_t count, int64_t* ticket);
+
 /* Non-blocking: *status = 0 while pending, 1 when done, or the request's
  * negative error code. Once reported done (or failed) the ticket is retired;
  * latency_us (may be NULL) receives submit-to-result time in microseconds. */

@@ -826,4 +826,6 @@ int tree_view(mg_tree t, TreeView* v) {
     return MG_OK;
 }
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+const mgk::MapDev* map_dev(mg_map m) { return &m->dev; }
+size_t map_voxel_count(mg_map m) { return (size_t)m->dev.nx * m->dev.ny * m->dev.nz; }
 }  // namespace mgb

@@ -23,6 +23,8 @@ struct TreeView {
 };
 
 int tree_view(mg_tree t, TreeView* v);     // mg_api.hip
+const mgk::MapDev* map_dev(mg_map m);      // mg_api.hip
+size_t map_voxel_count(mg_map m);          // mg_api.hip
 int set_error(int code, const char* msg);  // mg_api.hip
 
 // Tree uploads into memory the caller provides (mg_api.hip), for the server's arena.

@@ -8,6 +8,11 @@
 // fits in the server's device arena (admission by device-memory footprint);
 // a finished request's results are copied to the caller's host arrays and its
 // arena block is released. Nothing on the request path allocates device memory.
+//
+// Map updates between replans are queued with the requests. An update is
+// applied when it reaches the head of the queue and no in-flight request
+// uses its map: requests submitted before it see the old map, requests
+// submitted after it the new one.
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 
@@ -77,7 +82,10 @@ class Arena {
 
 struct Request {
     int64_t ticket = 0;
+    int kind = 0;                    // 0 a tree to evaluate, 1 a map update
     mg_map map = nullptr;
+    std::vector<uint32_t> upd_ids;   // map update: voxel ids and new states (host copies)
+    std::vector<uint8_t> upd_states;
     mgb::HostTree* host = nullptr;
     int32_t n = 0;
     uint32_t* out_gain = nullptr;    // caller's host arrays
@@ -126,14 +134,41 @@ struct mg_server_s {
     size_t cap_trees = 0, cap_items = 0;
     uint32_t* h_stage = nullptr;        // pinned: gain then yaw of finished requests
     size_t cap_stage = 0;
+    uint32_t* d_upd = nullptr;          // map updates: ids, then states (device), grown on demand
+    size_t cap_upd = 0;
     // statistics
     int64_t steps = 0, completed = 0;
     double rays_done = 0.0;
 
     int grow(size_t trees, size_t items, size_t stage_words);
+    int apply_update(Request* r);
     void run();
     int step();
 };
+
+// Applies a queued map update on the compute stream (after every earlier
+// launch on it) and waits for it, so the host copies can be released.
+int mg_server_s::apply_update(Request* r) {
+    const size_t n = r->upd_ids.size();
+    if (n == 0) return MG_OK;
+    const size_t words = n + (n + 3) / 4;
+    hipError_t e = hipSuccess;
+    if (words > cap_upd) {
+        (void)hipFree(d_upd);
+        d_upd = nullptr;
+        cap_upd = 0;
+        e = hipMalloc(&d_upd, sizeof(uint32_t) * std::max(words, (size_t)1024));
+        if (e != hipSuccess) return hip_fail(e, "server map update staging");
+        cap_upd = std::max(words, (size_t)1024);
+    }
+    uint8_t* d_states = (uint8_t*)(d_upd + n);
+    e = hipMemcpyAsync(d_upd, r->upd_ids.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, compute);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_states, r->upd_states.data(), n, hipMemcpyHostToDevice, compute);
+    if (e == hipSuccess) e = launch_map_scatter(d_upd, d_states, (uint32_t)n, *mgb::map_dev(r->map), nullptr, compute);
+    if (e == hipSuccess) e = hipStreamSynchronize(compute);
+    if (e != hipSuccess) return hip_fail(e, "server map update");
+    return MG_OK;
+}
 
 int mg_server_s::grow(size_t trees, size_t items, size_t stage_words) {
     hipError_t e = hipSuccess;
@@ -177,8 +212,29 @@ int mg_server_s::step() {
         Request* r = nullptr;
         {
             std::lock_guard<std::mutex> lk(mu);
-            if (queue.empty() || (int32_t)inflight.size() >= cfg.max_inflight) break;
+            if (queue.empty()) break;
             r = queue.front();
+            if (r->kind == 1) {
+                // a map update waits for the in-flight requests on its map
+                if (std::any_of(inflight.begin(), inflight.end(), [&](Request* q) { return q->map == r->map; })) break;
+                queue.pop_front();
+            }
+        }
+        if (r->kind == 1) {
+            const int urc = apply_update(r);
+            std::lock_guard<std::mutex> lk(mu);
+            r->upd_ids = std::vector<uint32_t>();
+            r->upd_states = std::vector<uint8_t>();
+            r->rc = urc;
+            r->state = 2;
+            r->t_done = Clock::now();
+            cv_done.notify_all();
+            if (urc != MG_OK) return urc;
+            continue;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if ((int32_t)inflight.size() >= cfg.max_inflight) break;
             size_t off = 0;
             if (!arena.alloc(r->bytes, &off)) break;
             r->arena_off = off;
@@ -375,6 +431,32 @@ static int finish_ticket(mg_server s, std::unique_lock<std::mutex>& lk, int64_t 
     return rc;
 }
 
+extern "C" int mg_server_map_update(mg_server s, mg_map map, const uint32_t* voxel_ids, const uint8_t* states,
+                                    int32_t count, int64_t* ticket) {
+    if (!s || !map || !ticket || count < 0 || (count > 0 && (!voxel_ids || !states)))
+        return mgb::set_error(MG_E_INVALID, "bad map update arguments");
+    const size_t nvox = mgb::map_voxel_count(map);
+    for (int32_t i = 0; i < count; ++i)
+        if (voxel_ids[i] >= nvox || states[i] > 2)
+            return mgb::set_error(MG_E_INVALID, "map update lists a voxel outside the grid or a state above 2");
+    std::unique_ptr<Request> r(new (std::nothrow) Request());
+    if (!r) return mgb::set_error(MG_E_NOMEM, "host allocation failed");
+    r->kind = 1;
+    r->map = map;
+    r->upd_ids.assign(voxel_ids, voxel_ids + count);
+    r->upd_states.assign(states, states + count);
+    r->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->fatal != MG_OK) return mgb::set_error(s->fatal, s->fatal_msg.c_str());
+    if (s->stop) return mgb::set_error(MG_E_BUSY, "server is shutting down");
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->queue.push_back(r.get());
+    s->all.emplace(r->ticket, std::move(r));
+    s->cv_work.notify_one();
+    return MG_OK;
+}
+
 extern "C" int mg_server_poll(mg_server s, int64_t ticket, int32_t* status, double* latency_us) {
     if (!s || !status) return mgb::set_error(MG_E_INVALID, "server/status is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
@@ -428,6 +510,7 @@ extern "C" int mg_server_destroy(mg_server s) {
     (void)hipHostFree(s->h_trees);
     (void)hipHostFree(s->h_items);
     (void)hipHostFree(s->h_stage);
+    (void)hipFree(s->d_upd);
     (void)hipFree(s->arena_mem);
     (void)hipStreamDestroy(s->compute);
     (void)hipStreamDestroy(s->upload);

@@ -30,9 +30,9 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
                      "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update",
-                     "mg_map_read", "mg_eval_exact",
+                     "mg_map_read", "mg_eval_exact", "mg_server_map_update",
            "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read",
-           "mg_eval_exact")
+           "mg_eval_exact", "mg_server_map_update")
 
 
 class MGError(RuntimeError):
@@ -86,6 +86,7 @@ def lib() -> C.CDLL:
         L.mg_sensor_tables.argtypes = [C.POINTER(mg_sensor), P, P, P, P, P, P]
         L.mg_server_create.argtypes = [C.POINTER(mg_server_config), C.POINTER(P)]
         L.mg_server_submit.argtypes = [P, P, P, P, I32, P, P, C.POINTER(I64)]
+        L.mg_server_map_update.argtypes = [P, P, P, P, I32, C.POINTER(I64)]
         L.mg_server_poll.argtypes = [P, I64, C.POINTER(I32), C.POINTER(C.c_double)]
         L.mg_server_wait.argtypes = [P, I64, C.POINTER(C.c_double)]
         L.mg_server_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(I32),
@@ -462,6 +463,16 @@ class Server:
         _check(lib().mg_server_submit(C.c_void_p(self.handle), C.c_void_p(m.handle), _np_ptr(pos), _np_ptr(par), n,
                                       _np_ptr(g), _np_ptr(y), C.byref(t)))
         self._keep[t.value] = (g, y)
+        return t.value
+
+    def map_update(self, m: Map, voxel_ids, states) -> int:
+        """Queues new states for listed voxels of map m (applied after the requests submitted before it)."""
+        ids = np.ascontiguousarray(voxel_ids, dtype=np.uint32)
+        st = np.ascontiguousarray(states, dtype=np.uint8)
+        t = C.c_int64()
+        _check(lib().mg_server_map_update(C.c_void_p(self.handle), C.c_void_p(m.handle), _np_ptr(ids), _np_ptr(st),
+                                          int(ids.size), C.byref(t)))
+        self._keep[t.value] = (None, None)
         return t.value
 
     def poll(self, ticket: int):

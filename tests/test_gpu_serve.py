@@ -114,3 +114,57 @@ def test_bad_requests_do_not_disturb_others(mg, scene):
     tiny.close()
     _check([S.wait(t)[:2] for t in tickets], ref)
     S.close()
+
+
+def test_map_updates_are_ordered_with_requests(mg):
+    """Requests submitted before a map update see the old map, those after it the new one,
+    whatever is in flight; each equals a plain evaluation on a map uploaded with that content."""
+    import torch
+    from oracle import maps
+    w = W.make("tiny")
+    sen = w.sensor
+    st0 = w.map.states
+    rng = np.random.Generator(np.random.PCG64(77))
+    unk = np.flatnonzero(st0.reshape(-1) == W.UNK)
+    ids1 = rng.choice(unk, unk.size // 4, replace=False).astype(np.uint32)
+    new1 = rng.choice(np.array([W.FREE, W.OCC], np.uint8), ids1.size, p=[0.85, 0.15])
+    st1, _ = maps.apply_updates(st0, ids1, new1)
+    ids2 = rng.choice(st0.size, 3000, replace=False).astype(np.uint32)
+    new2 = rng.integers(0, 3, ids2.size).astype(np.uint8)
+    st2, _ = maps.apply_updates(st1, ids2, new2)
+    t0 = w.trees[0]
+    trees = [(t0.pos_m, t0.parent), (t0.pos_m[:7].copy(), t0.parent[:7].copy())]
+
+    def plain(states, pos, par):
+        M = mg.Map(states, w.map.voxel_m, w.map.origin_m)
+        T = mg.Tree(M, pos, par, sen)
+        g, y, _ = T.eval_marginal()
+        torch.cuda.synchronize()
+        out = (mg.as_u32(g), y.cpu().numpy())
+        T.close()
+        M.close()
+        return out
+
+    expect = {k: [plain(s, *tr) for tr in trees] for k, s in ((0, st0), (1, st1), (2, st2))}
+    Ms = mg.Map(st0, w.map.voxel_m, w.map.origin_m)
+    S = mg.Server(sen, max_inflight=3, arena_bytes=1 << 30)
+    plan = [("req", 0), ("req", 1), ("upd", (ids1, new1)), ("req", 0), ("req", 1), ("req", 0),
+            ("upd", (ids2, new2)), ("req", 1), ("req", 0)]
+    version, tickets = 0, []
+    for kind, arg in plan:
+        if kind == "upd":
+            tickets.append(("upd", S.map_update(Ms, *arg), None))
+            version += 1
+        else:
+            tickets.append(("req", S.submit(Ms, *trees[arg]), (version, arg)))
+    for kind, t, info in tickets:
+        if kind == "upd":
+            S.wait(t)
+            continue
+        g, y, _ = S.wait(t)
+        eg, ey = expect[info[0]][info[1]]
+        assert np.array_equal(g, eg) and np.array_equal(y, ey), info
+    with pytest.raises(mg.MGError):
+        S.map_update(Ms, np.array([st0.size], np.uint32), np.array([1], np.uint8))
+    S.close()
+    Ms.close()
