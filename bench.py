@@ -293,6 +293,24 @@ def serve_bench(args):
     for t in tickets:
         S.wait(t)
     sat_served = time.perf_counter() - t0
+    # served with map updates between replans: after each request, 10k voxels of its robot's map change
+    # (queued with the requests, so later requests of that robot see them)
+    rng = np.random.Generator(np.random.PCG64(4242))
+    upd = []
+    for i in range(len(trees)):
+        st = maps[robot_of[i]].states
+        ids = rng.choice(st.size, 10000, replace=False).astype(np.uint32)
+        upd.append((ids, rng.integers(0, 3, ids.size).astype(np.uint8)))
+    tickets, utickets = [], []
+    t0 = time.perf_counter()
+    for i in range(len(trees)):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        tickets.append(S.submit(dev_maps[robot_of[i]], trees[i].pos_m, trees[i].parent))
+        utickets.append(S.map_update(dev_maps[robot_of[i]], *upd[i]))
+    with_upd = [S.wait(t)[2] / 1e3 for t in tickets]
+    for t in utickets:
+        S.wait(t)
     S.close()
     t0 = time.perf_counter()
     for i in range(len(trees)):
@@ -304,6 +322,9 @@ def serve_bench(args):
                   "saturated_rays_per_s": total_rays / sat_plain},
         "served": {"p50_ms": float(np.percentile(lat_served, 50)), "p99_ms": float(np.percentile(lat_served, 99)),
                    "saturated_rays_per_s": total_rays / sat_served},
+        "served_with_map_updates": {"p50_ms": float(np.percentile(with_upd, 50)),
+                                    "p99_ms": float(np.percentile(with_upd, 99)),
+                                    "updates": len(utickets), "voxels_per_update": 10000},
     }
     log(f"[bench] serve16: {res}")
     line = {
