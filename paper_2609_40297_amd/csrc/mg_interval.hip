@@ -138,44 +138,45 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
     const float* __restrict__ Wa = C.winv + (size_t)A.node * (size_t)C.npx;
     float olo = 0.0f, ohi = 0.0f;
     bool open = false;
+    int32_t off = j * C.wd + i;               // the pixel's offset, kept up to date by the steps
+    const int32_t voff = sj * C.wd;
+    float wD = Wa[off];                       // 1/D, or 0 for D = 0 (nothing observed)
     for (int32_t it = 0; it < C.wd + C.hd + 2; ++it) {
         float e = su < sv ? su : sv;
         e = e < s1 ? e : s1;
-        const float wD = Wa[(size_t)j * C.wd + i];    // 1/D, or 0 for D = 0 (nothing observed)
-        if (wD > 0.0f) {
-            // the part of [sa, e] where w(s) >= 1/D, i.e. z(s) <= D
-            float lo = sa, hi = e;
-            bool ok = true;
-            if (wb == wa) {
-                ok = wa >= wD;
-            } else {
-                const float ss = (wD - wa) * rden;
-                if (wb > wa) lo = sa > ss ? sa : ss;
-                else hi = e < ss ? e : ss;
-            }
-            if (ok && lo <= hi) {
-                if (open && lo <= ohi) {
-                    ohi = hi > ohi ? hi : ohi;
-                } else {
-                    if (open && sink(t_of_s(olo, wa, wb, tlo, thi), t_of_s(ohi, wa, wb, tlo, thi))) return true;
-                    olo = lo;
-                    ohi = hi;
-                    open = true;
-                }
-            }
+        // the next pixel first, so that its load is in flight while this one is processed
+        const bool stepu = su <= sv;
+        const int32_t ni = stepu ? i + si : i, nj = stepu ? j : j + sj;
+        const bool more = (e < s1) & ((uint32_t)ni < (uint32_t)C.wd) & ((uint32_t)nj < (uint32_t)C.hd);
+        const int32_t noff = more ? off + (stepu ? si : voff) : off;
+        const float wN = Wa[noff];
+        // the part [lo, hi] of [sa, e] where w(s) >= 1/D, i.e. z(s) <= D (w is
+        // linear in s; with w constant the whole span or nothing)
+        const float ss = (wD - wa) * rden;
+        const float lo = wb > wa ? (sa > ss ? sa : ss) : sa;
+        const float hi = wb < wa ? (e < ss ? e : ss) : e;
+        const bool ok = (wD > 0.0f) & ((wb != wa) | (wa >= wD)) & (lo <= hi);
+        const bool join = ok & open & (lo <= ohi);     // continues the open run
+        ohi = join ? (hi > ohi ? hi : ohi) : ohi;
+        if (ok & !join) {                              // a new run: the open one is finished
+            if (open && sink(t_of_s(olo, wa, wb, tlo, thi), t_of_s(ohi, wa, wb, tlo, thi))) return true;
+            olo = lo;
+            ohi = hi;
+            open = true;
         }
-        if (!(e < s1)) break;
-        if (su <= sv) {
-            i += si;
+        if (!more) break;
+        i = ni;
+        j = nj;
+        off = noff;
+        if (stepu) {
             bu += si;
             su = ((float)bu - uA) * iu;
         } else {
-            j += sj;
             bv += sj;
             sv = ((float)bv - vA) * iv;
         }
         sa = e;
-        if (i < 0 || i >= C.wd || j < 0 || j >= C.hd) break;
+        wD = wN;
     }
     return open ? sink(t_of_s(olo, wa, wb, tlo, thi), t_of_s(ohi, wa, wb, tlo, thi)) : false;
 }
