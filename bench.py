@@ -227,6 +227,40 @@ def cpu_baseline(w, target_rays_per_thread):
             "sample": f"{int(mask.sum())} nodes ({what}), {rays} rays, {dt:.1f} s on {threads} threads"}
 
 
+def next_row_oracles(w, threads):
+    """The oracles of the next-row paths, each on a bounded sample, for context beside the device
+    figures: the interval mode and the exact sets on the three deepest leaves of tree 0 and their
+    ancestors (the exact pass at the depth-buffer windows of the same nodes), the TSDF conversion
+    on a 512x512x128 grid."""
+    from oracle import ivlref, maps, mgref
+    t = w.trees[0]
+    dep = t.depth()
+    leaves = [int(i) for i in np.flatnonzero(dep == dep.max())[:3]]
+    mask = mgref.ancestor_closure(t.parent, leaves)
+    nodes = int(mask.sum())
+    out = {}
+    t0 = time.perf_counter()
+    ivlref.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads)
+    dt = time.perf_counter() - t0
+    out["interval"] = {"value": nodes * w.sensor.rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+                       "sample": f"{nodes} nodes (3 deepest leaves of tree 0 and their ancestors), {dt:.2f} s"}
+    ref = mgref.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads)
+    t0 = time.perf_counter()
+    mgref.exact(w.map, t, w.sensor, ref["k_db"], ref["D"], mask=mask)
+    dt = time.perf_counter() - t0
+    out["exact"] = {"value": nodes * w.sensor.n_el * w.sensor.w_buf / dt, "unit": "window rays/s", "cores": 1,
+                    "kind": "oracle", "sample": f"the same {nodes} nodes, sorted voxel sets, {dt:.2f} s"}
+    rng = np.random.Generator(np.random.PCG64(5))
+    d = rng.normal(0.3, 0.4, (128, 512, 512)).astype(np.float32)
+    wt = rng.uniform(0, 3, d.shape).astype(np.float32)
+    t0 = time.perf_counter()
+    maps.tsdf_states(d, wt, 0.05, 1.0)
+    dt = time.perf_counter() - t0
+    out["tsdf"] = {"value": d.size / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+                   "sample": f"512x512x128 grid, {dt:.2f} s"}
+    return out
+
+
 def serve_bench(args):
     """16 robots, Poisson replanning requests at 20 Hz (seeded), replayed in real time.
 
@@ -550,6 +584,7 @@ def main():
         cpu = cpu_baseline(w, args.cpu_sample_rays)
         if score is not None:
             cpu["path_score"] = score_oracle(w)
+            cpu.update(next_row_oracles(w, cpu_threads()))
         log(f"[bench] cpu: {cpu}")
 
     line = {
