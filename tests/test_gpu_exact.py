@@ -81,3 +81,13 @@ def test_exact_rejects_bad_windows(mg):
         T.eval_exact(y)
     T.close()
     M.close()
+
+
+def test_exact_deepest_chain(mg, orc):
+    """A 64-node chain: the last node probes 63 ancestors' sets."""
+    w = W.make("tiny")
+    p = w.trees[0].pos_m
+    chain_pos = np.repeat(p[:4], 17, axis=0)[:64] + np.float32(0.013) * np.arange(64, dtype=np.float32)[:, None]
+    chain_pos = np.clip(chain_pos, 0.05, w.map.extent_m.astype(np.float32) - 0.05).astype(np.float32)
+    chain = W.Tree(pos_m=chain_pos, parent=np.arange(-1, 63, dtype=np.int32))
+    _check(mg, orc, w.map, chain, w.sensor, "chain63")

@@ -134,3 +134,32 @@ def test_interval_rejects_bad_sizes(mg):
         mg.mg_interval_config(0)
     T.close()
     M.close()
+
+
+def test_interval_deepest_chain(mg, ivl):
+    """A 64-node chain (depth 63: 63 ancestors for the last node) on the tiny map."""
+    w = W.make("tiny")
+    p = w.trees[0].pos_m
+    chain_pos = np.repeat(p[:4], 17, axis=0)[:64] + np.float32(0.013) * np.arange(64, dtype=np.float32)[:, None]
+    chain_pos = np.clip(chain_pos, 0.05, w.map.extent_m.astype(np.float32) - 0.05).astype(np.float32)
+    chain = W.Tree(pos_m=chain_pos, parent=np.arange(-1, 63, dtype=np.int32))
+    ref = ivl.eval_tree(w.map, chain, w.sensor, n_threads=threads())
+    for got in _gpu_interval(mg, w.map, chain, w.sensor, caps=(-1, 2)):
+        _same(got, ref)
+
+
+def test_interval_large_sampled(mg, ivl):
+    """Large map (512x512x128 at 0.05 m, 720x120 rays, 15 m; 600x347 buffers): one mid-depth
+    node's ancestor chain against the oracle, the whole 3000-node tree on the GPU."""
+    from oracle import mgref
+    w = W.make("large", n_trees=1)
+    t = w.trees[0]
+    dep = t.depth()
+    node = int(np.flatnonzero(dep == 5)[0])
+    mask = mgref.ancestor_closure(t.parent, [node])
+    sel = np.flatnonzero(mask)
+    log(f"[interval] large: n={t.n}, sampled {sel.size} nodes")
+    ref = ivl.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads())
+    got = _gpu_interval(mg, w.map, t, w.sensor)[0]
+    assert got["D"].shape == (t.n, 347, 600)
+    _same(got, ref, nodes=sel)
