@@ -1,6 +1,6 @@
 // Map contents on the device: conversion of a truncated signed distance field
-// (the volumetric map the paper's planners keep, Sec. IV "converted into a
-// contiguous representation") into the bricked occupancy grid, and in-place
+// (the volumetric map the paper's planners keep; Sec. IV turns it into a
+// contiguous grid on the GPU) into the bricked occupancy grid, and in-place
 // updates between replans (a box of the TSDF, or a list of voxels).
 //
 // Occupancy of a voxel from its TSDF distance d (metres) and weight w:
