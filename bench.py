@@ -97,7 +97,9 @@ def map_bench(mg, dims=(512, 512, 128), voxel_m=0.05, reps=20, n_updates=1 << 20
     gbs = alg / (out["tsdf_update_us"] * 1e-6) / 1e9
     out["tsdf_voxels_per_s"] = nx * ny * nz / (out["tsdf_update_us"] * 1e-6)
     out["tsdf_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": alg}
+                            "frac": gbs / HBM_PEAK_GBS,
+                            "traffic": summary_traffic(TSDF_TRAFFIC_SUMMARY, TSDF_SOURCES) if dims == (512, 512, 128)
+                            else None, "algorithmic_bytes": alg}
     out["voxel_updates_per_s"] = n_updates / (out["voxel_updates_us"] * 1e-6)
     return out
 
@@ -132,6 +134,8 @@ def parse():
     ap.add_argument("--sp-steps", type=int, default=5, help="timed single-parent (g_sp) passes; 0 skips")
     ap.add_argument("--ivl-steps", type=int, default=3, help="timed interval-mode passes; 0 skips")
     ap.add_argument("--exact-steps", type=int, default=3, help="timed exact hash-set passes; 0 skips")
+    ap.add_argument("--map-bench-only", action="store_true",
+                    help="only run the map conversion / update timing (3 calls each) and exit")
     ap.add_argument("--no-map-bench", dest="map_bench", action="store_false",
                     help="skip the map conversion / update timing")
     ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6, help="oracle sample, rays per host thread")
@@ -154,31 +158,40 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_multi_step_traffic.md"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_40297_amd", "csrc", f) for f in ("mg_kernels.hip", "mg_batch.hip")]
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per trace launch from the committed counter summary, or None.
+def summary_traffic(path, sources):
+    """HBM bytes per launch from a committed counter summary, or None.
 
-    The summary records the SHA-256 of the kernel and scheduler sources it was
-    taken with; when they have changed since, the figure no longer applies."""
-    if workload != "step" or not os.path.exists(TRAFFIC_SUMMARY):
+    The summary records the SHA-256 of the sources it was taken with; when they
+    have changed since, the figure no longer applies."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_SUMMARY) as f:
+    with open(path) as f:
         for ln in f:
             if ln.startswith("- ") and ":" in ln:
                 k, v = ln[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != kernel_source_hash() or "hbm_bytes_per_launch" not in vals:
+    if vals.get("kernel_source_sha256") != kernel_source_hash(sources) or "hbm_bytes_per_launch" not in vals:
         return None
     return float(vals["hbm_bytes_per_launch"])
+
+
+def measured_traffic(workload):
+    """HBM bytes per trace launch of the step workload (committed counter summary), or None."""
+    return summary_traffic(TRAFFIC_SUMMARY, KERNEL_SOURCES) if workload == "step" else None
+
+
+TSDF_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tsdf_grid_512x512x128_traffic.md")
+TSDF_SOURCES = [os.path.join(ROOT, "paper_2609_40297_amd", "csrc", "mg_map.hip")]
 
 
 def copy_probe(mib):
@@ -396,6 +409,12 @@ def main():
         sys.exit(2)
     if args.copy_probe_mib:
         return copy_probe(args.copy_probe_mib)
+    if args.map_bench_only:
+        import torch
+        from paper_2609_40297_amd import mg
+        torch.cuda.set_device(0)
+        print(json.dumps({"maps": map_bench(mg, reps=3)}), flush=True)
+        return
     if args.workload == "serve16":
         return serve_bench(args)
     import torch

@@ -55,6 +55,44 @@ __global__ __launch_bounds__(256) void k_tsdf_grid(const float* __restrict__ dis
     for (int32_t o = tid; o < tb * 32; o += 256) dst[o] = src[o];
 }
 
+// The same with 16-byte loads: four consecutive voxels along x per thread
+// (needs nx % 4 == 0, so every row starts 16-byte aligned); the 256 threads
+// cover four rows of the run at a time.
+__global__ __launch_bounds__(256) void k_tsdf_grid4(const float* __restrict__ dist, const float* __restrict__ weight,
+                                                    uint8_t* __restrict__ bricks, MapDev m, float surface,
+                                                    float min_weight) {
+    __shared__ __align__(16) uint8_t tile[kTileBricks * 512];
+    const int32_t tb = m.nbx < kTileBricks ? m.nbx : kTileBricks;
+    const int32_t bx0 = (int32_t)blockIdx.x * tb, by = (int32_t)blockIdx.y, bz = (int32_t)blockIdx.z;
+    const int32_t tid = (int32_t)threadIdx.x;
+    const int32_t quad = tid & 63, sub = tid >> 6;          // 4 voxels along x, one of 4 rows
+    const int32_t x = bx0 * 8 + quad * 4;
+    const bool lane_in = quad < tb * 2;
+    for (int32_t r0 = 0; r0 < 64; r0 += 4) {
+        const int32_t r = r0 + sub;
+        const int32_t yy = r & 7, zz = r >> 3;
+        const int32_t y = by * 8 + yy, z = bz * 8 + zz;
+        if (lane_in) {
+            uint32_t v = kOutside * 0x01010101u;
+            if (y < m.ny && z < m.nz && x < m.nx) {           // x < nx and nx % 4 == 0: all four inside
+                const size_t i = (size_t)x + (size_t)m.nx * ((size_t)y + (size_t)m.ny * (size_t)z);
+                const float4 d = *(const float4*)(dist + i);
+                const float4 w = *(const float4*)(weight + i);
+                v = (uint32_t)tsdf_state(d.x, w.x, surface, min_weight) |
+                    ((uint32_t)tsdf_state(d.y, w.y, surface, min_weight) << 8) |
+                    ((uint32_t)tsdf_state(d.z, w.z, surface, min_weight) << 16) |
+                    ((uint32_t)tsdf_state(d.w, w.w, surface, min_weight) << 24);
+            }
+            *(uint32_t*)&tile[(quad >> 1) * 512 + (quad & 1) * 4 + (yy << 3) + (zz << 6)] = v;
+        }
+    }
+    __syncthreads();
+    const size_t base = ((size_t)bx0 + (size_t)m.nbx * ((size_t)by + (size_t)m.nby * (size_t)bz)) * 512u;
+    uint4* dst = (uint4*)(bricks + base);
+    const uint4* src = (const uint4*)tile;
+    for (int32_t o = tid; o < tb * 32; o += 256) dst[o] = src[o];
+}
+
 // A box of the grid (lo, size), its TSDF given box-local and x-fastest.
 __global__ void k_tsdf_box(const float* __restrict__ dist, const float* __restrict__ weight,
                            uint8_t* __restrict__ bricks, MapDev m, int32_t lx, int32_t ly, int32_t lz, int32_t sx,
@@ -122,7 +160,13 @@ hipError_t launch_tsdf_grid(const float* dist, const float* weight, const MapDev
     const int32_t tb = m.nbx < kTileBricks ? m.nbx : kTileBricks;
     const int32_t ux = (m.nx + 7) / 8, uy = (m.ny + 7) / 8, uz = (m.nz + 7) / 8;   // bricks holding grid voxels
     const dim3 grid((unsigned)((ux + tb - 1) / tb), (unsigned)uy, (unsigned)uz);
-    hipLaunchKernelGGL(k_tsdf_grid, grid, dim3(256), 0, s, dist, weight, (uint8_t*)m.bricks, m, surface, min_weight);
+    const bool aligned = m.nx % 4 == 0 && ((uintptr_t)dist % 16) == 0 && ((uintptr_t)weight % 16) == 0;
+    if (aligned)
+        hipLaunchKernelGGL(k_tsdf_grid4, grid, dim3(256), 0, s, dist, weight, (uint8_t*)m.bricks, m, surface,
+                           min_weight);
+    else
+        hipLaunchKernelGGL(k_tsdf_grid, grid, dim3(256), 0, s, dist, weight, (uint8_t*)m.bricks, m, surface,
+                           min_weight);
     return hipGetLastError();
 }
 
