@@ -639,3 +639,87 @@ done:
     mgref_sensor_free(&s);
     return rc;
 }
+
+/* ------------------------------------------------------------------ exact marginal with its own yaw */
+
+/* The exact marginal gain as a planner would use it (eq. 2 with the yaw
+ * choice of Sec. III-B): nodes in depth order; for node n every panorama ray
+ * is traversed and each unknown voxel it meets counts towards the bin of the
+ * ray's column unless some ancestor's set I(a) holds it (I(a) taken at a's
+ * own chosen window); the window with the largest sum wins (smallest k on
+ * ties), and I(n) is then the set of distinct unknown voxels met by that
+ * window's rays. Counts are ray incidences, as for the depth-buffer gain.
+ * mask: NULL or an ancestor-closed subset. */
+int mgref_exact_marginal(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
+                         const float origin_m[3], const float* pos_m, const int32_t* parent, int32_t n,
+                         const mgref_sensor_params* sp, const uint8_t* mask, uint32_t* gain, int32_t* k_out) {
+    mgref_sensor s;
+    if (mgref_sensor_init(sp, &s) != 0) return -1;
+    const int W = s.p.n_az, H = s.p.n_el, B = s.p.yaw_bins;
+    const float rv = sp->range_m / voxel_m;
+    const int32_t cap = 3 * (int32_t)ceilf(rv) + 16;
+    float* q = (float*)malloc(sizeof(float) * 3 * (size_t)n);
+    int32_t* depth = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    uint32_t** sets = (uint32_t**)calloc((size_t)n, sizeof(uint32_t*));
+    uint32_t* setn = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
+    uint32_t* ids = (uint32_t*)malloc(sizeof(uint32_t) * cap);
+    uint8_t* st = (uint8_t*)malloc((size_t)cap);
+    float* te = (float*)malloc(sizeof(float) * cap);
+    uint32_t* bins = (uint32_t*)malloc(sizeof(uint32_t) * B);
+    int rc = -1;
+    int32_t maxd = 0;
+    if (!q || !depth || !sets || !setn || !ids || !st || !te || !bins) goto done;
+    if (prepare_tree(nx, ny, nz, voxel_m, origin_m, pos_m, parent, n, q, depth) != 0) goto done;
+    if (mask)
+        for (int32_t i = 1; i < n; ++i)
+            if (mask[i] && !mask[parent[i]]) goto done;
+    for (int32_t i = 0; i < n; ++i) if (depth[i] > maxd) maxd = depth[i];
+    for (int32_t d = 0; d <= maxd; ++d) {
+        for (int32_t i = 0; i < n; ++i) {
+            if (depth[i] != d || (mask && !mask[i])) continue;
+            int32_t anc[65], na = 0;
+            for (int32_t a = parent[i]; a >= 0 && na < 65; a = parent[a]) anc[na++] = a;
+            memset(bins, 0, sizeof(uint32_t) * B);
+            for (int c = 0; c < W; ++c) {
+                const int b = s.bin_of_col[c];
+                for (int j = 0; j < H; ++j) {
+                    const int r = c * H + j;
+                    float h;
+                    int nv = mgref_trace_ray(states, nx, ny, nz, q + 3 * i, s.dir + 3 * r, s.inv + 3 * r, rv, cap,
+                                             ids, st, te, &h);
+                    if (nv < 0) goto done;
+                    for (int v = 0; v < nv; ++v) {
+                        if (st[v] != S_UNK) continue;
+                        int in_union = 0;
+                        for (int m = 0; m < na && !in_union; ++m)
+                            in_union = contains(sets[anc[m]], setn[anc[m]], ids[v]);
+                        if (!in_union) bins[b]++;
+                    }
+                }
+            }
+            int32_t k;
+            gain[i] = mgref_best_window(bins, B, s.win_bins, &k);
+            k_out[i] = k;
+            /* I(i) at the chosen window: at most the window's unknown incidences, which the
+             * absolute count of that window bounds; grow until the set fits */
+            int64_t capn = 4096, cnt;
+            uint32_t* buf = NULL;
+            for (;;) {
+                buf = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)capn);
+                if (!buf) goto done;
+                cnt = mgref_node_set(states, nx, ny, nz, sp, rv, q + 3 * i, k, capn, buf);
+                if (cnt >= 0) break;
+                free(buf);
+                capn *= 4;
+            }
+            sets[i] = buf;
+            setn[i] = (uint32_t)cnt;
+        }
+    }
+    rc = 0;
+done:
+    if (sets) for (int32_t i = 0; i < n; ++i) free(sets[i]);
+    free(sets); free(setn); free(q); free(depth); free(ids); free(st); free(te); free(bins);
+    mgref_sensor_free(&s);
+    return rc;
+}

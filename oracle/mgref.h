@@ -143,6 +143,15 @@ int mgref_exact(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float
                 const uint8_t* mask, uint32_t* A_set, uint32_t* X_set, uint32_t* X_ray,
                 uint32_t* G_db_set);
 
+/* Exact marginal gain with its own yaw choice (eq. 2, Sec. III-B): depth
+ * order; a node's per-bin counts are the incidences of its panorama rays whose
+ * unknown voxel lies in no ancestor's I (each taken at that ancestor's chosen
+ * window); gain/k as for the other evaluations; I(n) is then built at the
+ * chosen window. mask as above. Returns 0 or -1. */
+int mgref_exact_marginal(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
+                         const float origin_m[3], const float* pos_m, const int32_t* parent, int32_t n,
+                         const mgref_sensor_params* sp, const uint8_t* mask, uint32_t* gain, int32_t* k_out);
+
 #ifdef __cplusplus
 }
 #endif

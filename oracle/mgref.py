@@ -83,6 +83,9 @@ def lib():
         L.mgref_exact.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, C.c_int32,
                                   C.POINTER(SensorParams), P, P, P, P, P, P, P]
         L.mgref_exact.restype = C.c_int
+        L.mgref_exact_marginal.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, C.c_int32,
+                                           C.POINTER(SensorParams), P, P, P]
+        L.mgref_exact_marginal.restype = C.c_int
         _lib = L
     return _lib
 
@@ -257,3 +260,21 @@ def ancestor_closure(parent, nodes):
             mask[i] = 1
             i = int(parent[i])
     return mask
+
+
+def exact_marginal(m, tree, sensor, mask=None):
+    """Exact marginal gain with its own yaw choice: dict(g_ex, k_ex)."""
+    sp = sensor_params(sensor)
+    st = np.ascontiguousarray(m.states, dtype=np.uint8)
+    nz, ny, nx = st.shape
+    n = tree.n
+    out = dict(g_ex=np.zeros(n, np.uint32), k_ex=np.full(n, -1, np.int32))
+    origin = np.ascontiguousarray(m.origin_m, dtype=np.float32)
+    pos = np.ascontiguousarray(tree.pos_m, dtype=np.float32)
+    par = np.ascontiguousarray(tree.parent, dtype=np.int32)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().mgref_exact_marginal(_p(st), nx, ny, nz, float(m.voxel_m), _p(origin), _p(pos), _p(par), n,
+                                    C.byref(sp), _p(mk), _p(out["g_ex"]), _p(out["k_ex"]))
+    if rc != 0:
+        raise ValueError("oracle rejected the input")
+    return out

@@ -526,3 +526,28 @@ def test_range_cut_is_strict(rv):
     ids, _, _, h = mg.trace_ray(st, q, d, d, rv)
     assert len(ids) == 1 + sum(1 for k in range(1, 12) if k - 0.5 < rv)
     assert h == np.float32(rv)
+
+
+# ----------------------------------------------------------------- exact marginal with its own yaw
+
+def test_exact_marginal_argmax_and_consistency():
+    """The exact gain with its own yaw choice equals, at every node, the exact per-incidence count
+    (X_ray of the pinned exact pass) at its chosen window, and no other window of that node (the
+    rest of the tree fixed) counts more; ties go to the smallest window; the root's is its absolute
+    gain and no node exceeds its absolute gain."""
+    mg = _mg()
+    m, tree, s = W.random_micro(55, dims=(14, 12, 8), n_nodes=7, max_depth=3, range_vox=6.0, p_occ=0.06,
+                                p_free=0.45, n_az=16, n_el=4, yaw_bins=8)
+    e = mg.exact_marginal(m, tree, s)
+    o = mg.eval_tree(m, tree, s)
+    assert e["g_ex"][0] == o["g_abs"][0] and e["k_ex"][0] == o["k_abs"][0]
+    assert np.all(e["g_ex"] <= o["g_abs"])
+    x = mg.exact(m, tree, s, e["k_ex"], o["D"])
+    assert np.array_equal(x["X_ray"], e["g_ex"])
+    for nd in range(tree.n):
+        sums = []
+        for k in range(s.yaw_bins):
+            kk = e["k_ex"].copy()
+            kk[nd] = k
+            sums.append(int(mg.exact(m, tree, s, kk, o["D"])["X_ray"][nd]))
+        assert max(sums) == e["g_ex"][nd] and int(np.argmax(sums)) == e["k_ex"][nd], nd
