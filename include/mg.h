@@ -270,6 +270,18 @@ int mg_interval_tables(const mg_sensor* sensor, float voxel_m, int32_t wd, int32
 int mg_eval_exact(mg_tree tree, void* hip_stream, const int32_t* yaw_bin, uint32_t* x_ray, uint32_t* x_set,
                   uint32_t* a_set);
 
+/* Exact marginal gain with its own yaw choice (eq. 2 with the yaw choice of
+ * Sec. III-B; the paper's exact planner gain, there computed with hash maps on
+ * the CPU): nodes in depth order; node n's bin counts are the unknown
+ * incidences of its panorama rays whose voxel lies in no ancestor's set I(a)
+ * (each I(a) at a's own chosen window); the best window is chosen as for the
+ * other evaluations and I(n) is then built at it. gain DEVICE uint32[n],
+ * yaw_bin DEVICE int32[n]. Tables are sized from an absolute pass (one host
+ * synchronisation; the pool may grow, about 8 bytes per unknown incidence of
+ * each node's best absolute window); the call returns after the work. It
+ * overwrites the tree's bins and window starts. */
+int mg_eval_exact_marginal(mg_tree tree, void* hip_stream, uint32_t* gain, int32_t* yaw_bin);
+
 /* Absolute gain of every node (eq. 1 maximised over the yaw windows), no
  * conditioning and no level order: one flat launch over all nodes.
  *   gain DEVICE uint32[n], yaw_bin DEVICE int32[n]. */

@@ -101,9 +101,11 @@ struct RayOf {
     bool ok;
 };
 
-__device__ __forceinline__ RayOf window_ray(const SensorDev& S, const int32_t* yaw, int32_t tiles) {
+__device__ __forceinline__ RayOf window_ray(const SensorDev& S, const int32_t* yaw, int32_t tiles,
+                                            const int32_t* nodes) {
     RayOf o;
-    o.node = (int32_t)(blockIdx.x / (uint32_t)tiles);
+    const int32_t item = (int32_t)(blockIdx.x / (uint32_t)tiles);
+    o.node = nodes ? nodes[item] : item;
     const int32_t k = (int32_t)(blockIdx.x % (uint32_t)tiles) * kXThreads + (int32_t)threadIdx.x;
     o.ok = k < S.WB * S.H;
     const int32_t ci = k / S.H, j = k % S.H;
@@ -120,8 +122,9 @@ struct CountF {
 
 __global__ __launch_bounds__(kXThreads) void k_exact_count(MapDev M, SensorDev S, TreeDev Tr,
                                                            const int32_t* __restrict__ yaw, int32_t tiles,
+                                                           const int32_t* __restrict__ nodes,
                                                            uint32_t* __restrict__ inc) {
-    const RayOf R = window_ray(S, yaw, tiles);
+    const RayOf R = window_ray(S, yaw, tiles, nodes);
     CountF f;
     if (R.ok) walk_unknown(M, S.rv, Tr.q4[R.node], S.d4[R.r], S.iv4[R.r], f);
     if (f.n) atomicAdd(&inc[R.node], f.n);
@@ -136,8 +139,9 @@ struct InsertF {
 
 __global__ __launch_bounds__(kXThreads) void k_exact_insert(MapDev M, SensorDev S, TreeDev Tr, Tables T,
                                                             const int32_t* __restrict__ yaw, int32_t tiles,
+                                                            const int32_t* __restrict__ nodes,
                                                             uint32_t* __restrict__ a_set) {
-    const RayOf R = window_ray(S, yaw, tiles);
+    const RayOf R = window_ray(S, yaw, tiles, nodes);
     InsertF f{&T, R.node};
     if (R.ok) walk_unknown(M, S.rv, Tr.q4[R.node], S.d4[R.r], S.iv4[R.r], f);
     if (f.added && a_set) atomicAdd(&a_set[R.node], f.added);
@@ -160,11 +164,33 @@ struct MarginalF {
 
 __global__ __launch_bounds__(kXThreads) void k_exact_xray(MapDev M, SensorDev S, TreeDev Tr, Tables T,
                                                           const int32_t* __restrict__ yaw, int32_t tiles,
+                                                          const int32_t* __restrict__ nodes,
                                                           uint32_t* __restrict__ x_ray) {
-    const RayOf R = window_ray(S, yaw, tiles);
+    const RayOf R = window_ray(S, yaw, tiles, nodes);
     MarginalF f{&T, &Tr, R.node};
     if (R.ok) walk_unknown(M, S.rv, Tr.q4[R.node], S.d4[R.r], S.iv4[R.r], f);
     if (f.n) atomicAdd(&x_ray[R.node], f.n);
+}
+
+// Own-yaw exact gain, one level: work item = (level node, panorama ray); each
+// unknown incidence whose voxel is in no ancestor's set counts towards the bin
+// of the ray's column (the node's marginal bins).
+__global__ __launch_bounds__(kXThreads) void k_exact_bins(MapDev M, SensorDev S, TreeDev Tr, Tables T,
+                                                          const int32_t* __restrict__ nodes, int32_t tiles) {
+    __shared__ uint32_t s_bins[kMaxBins];
+    const int32_t node = nodes[blockIdx.x / (uint32_t)tiles];
+    const int32_t r = (int32_t)(blockIdx.x % (uint32_t)tiles) * kXThreads + (int32_t)threadIdx.x;
+    for (int32_t i = threadIdx.x; i < S.B; i += kXThreads) s_bins[i] = 0u;
+    __syncthreads();
+    if (r < S.R) {
+        MarginalF f{&T, &Tr, node};
+        walk_unknown(M, S.rv, Tr.q4[node], S.d4[r], S.iv4[r], f);
+        if (f.n) atomicAdd(&s_bins[S.bin_of_col[r / S.H]], f.n);
+    }
+    __syncthreads();
+    uint32_t* gb = Tr.bins + (size_t)node * 2 * S.B + S.B;
+    for (int32_t i = threadIdx.x; i < S.B; i += kXThreads)
+        if (s_bins[i]) atomicAdd(&gb[i], s_bins[i]);
 }
 
 // Grid: (slot blocks, nodes); every occupied slot of node n's table not in an
@@ -209,6 +235,46 @@ unsigned blocks_for(size_t n) {
 
 int fail_hip(hipError_t e, const char* what) {
     return mgb::set_error(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, what);
+}
+
+// Lays out one table per node, a power of two at least twice bound[i] slots
+// (bound[i] >= |I(i)|), grows the pool when needed, uploads the layout and
+// marks every slot empty. The host layout must outlive the enqueued copies
+// (the caller synchronises before returning).
+int setup_tables(State& st, int32_t n, const uint32_t* bound, hipStream_t s, Tables* T) {
+    hipError_t e = hipSuccess;
+    if (!st.inc) {
+        e = hipMalloc(&st.inc, sizeof(uint32_t) * n);
+        if (e == hipSuccess) e = hipMalloc(&st.off, sizeof(uint64_t) * n);
+        if (e == hipSuccess) e = hipMalloc(&st.mask, sizeof(uint32_t) * n);
+        if (e != hipSuccess) return fail_hip(e, "exact-gain state");
+        st.inc_h.resize(n);
+        st.off_h.resize(n);
+        st.mask_h.resize(n);
+    }
+    size_t total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        uint64_t cap = 64;
+        while (cap < 2ull * bound[i]) cap *= 2;
+        if (cap > (1ull << 32)) return mgb::set_error(MG_E_UNSUPPORTED, "a node's set needs more than 2^32 slots");
+        st.off_h[i] = total;
+        st.mask_h[i] = (uint32_t)(cap - 1);
+        total += cap;
+    }
+    if (total > st.pool_slots) {
+        (void)hipFree(st.pool);
+        st.pool = nullptr;
+        st.pool_slots = 0;
+        e = hipMalloc(&st.pool, sizeof(uint32_t) * total);
+        if (e != hipSuccess) return fail_hip(e, "exact-gain tables");
+        st.pool_slots = total;
+    }
+    e = hipMemcpyAsync(st.off, st.off_h.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.mask, st.mask_h.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail_hip(e, "exact-gain table layout");
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(total)), dim3(256), 0, s, st.pool, total, kEmpty);
+    *T = Tables{st.pool, st.off, st.mask};
+    return MG_OK;
 }
 
 }  // namespace mgx
@@ -265,39 +331,20 @@ extern "C" int mg_eval_exact(mg_tree t, void* hip_stream, const int32_t* yaw_bin
     }
     // 1. unknown incidences per node bound |I(n)|: size the tables
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(256), 0, s, st.inc, (size_t)n, 0u);
-    hipLaunchKernelGGL(k_exact_count, grid, dim3(kXThreads), 0, s, *v.map, S, Tr, yaw_bin, tiles, st.inc);
+    hipLaunchKernelGGL(k_exact_count, grid, dim3(kXThreads), 0, s, *v.map, S, Tr, yaw_bin, tiles, nullptr, st.inc);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(st.inc_h.data(), st.inc, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_hip(e, "exact-gain sizing");
-    size_t total = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        uint64_t cap = 64;
-        while (cap < 2ull * st.inc_h[i]) cap *= 2;
-        if (cap > (1ull << 32)) return mgb::set_error(MG_E_UNSUPPORTED, "a node's set needs more than 2^32 slots");
-        st.off_h[i] = total;
-        st.mask_h[i] = (uint32_t)(cap - 1);
-        total += cap;
-    }
-    if (total > st.pool_slots) {
-        (void)hipFree(st.pool);
-        st.pool = nullptr;
-        st.pool_slots = 0;
-        e = hipMalloc(&st.pool, sizeof(uint32_t) * total);
-        if (e != hipSuccess) return fail_hip(e, "exact-gain tables");
-        st.pool_slots = total;
-    }
-    e = hipMemcpyAsync(st.off, st.off_h.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(st.mask, st.mask_h.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return fail_hip(e, "exact-gain table layout");
-    Tables T{st.pool, st.off, st.mask};
+    Tables T{};
+    rc = setup_tables(st, n, st.inc_h.data(), s, &T);
+    if (rc != MG_OK) return rc;
     // 2. sets, 3. X_ray, 4. X_set
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(total)), dim3(256), 0, s, st.pool, total, kEmpty);
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(256), 0, s, x_ray, (size_t)n, 0u);
     if (x_set) hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(256), 0, s, x_set, (size_t)n, 0u);
     if (a_set) hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(256), 0, s, a_set, (size_t)n, 0u);
-    hipLaunchKernelGGL(k_exact_insert, grid, dim3(kXThreads), 0, s, *v.map, S, Tr, T, yaw_bin, tiles, a_set);
-    hipLaunchKernelGGL(k_exact_xray, grid, dim3(kXThreads), 0, s, *v.map, S, Tr, T, yaw_bin, tiles, x_ray);
+    hipLaunchKernelGGL(k_exact_insert, grid, dim3(kXThreads), 0, s, *v.map, S, Tr, T, yaw_bin, tiles, nullptr, a_set);
+    hipLaunchKernelGGL(k_exact_xray, grid, dim3(kXThreads), 0, s, *v.map, S, Tr, T, yaw_bin, tiles, nullptr, x_ray);
     if (x_set) {
         uint64_t maxcap = 0;
         for (int32_t i = 0; i < n; ++i) maxcap = std::max<uint64_t>(maxcap, (uint64_t)st.mask_h[i] + 1u);
@@ -310,5 +357,55 @@ extern "C" int mg_eval_exact(mg_tree t, void* hip_stream, const int32_t* yaw_bin
     // the host copies of the layout must outlive the copies enqueued above
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_hip(e, "exact-gain kernels");
+    return MG_OK;
+}
+
+extern "C" int mg_eval_exact_marginal(mg_tree t, void* hip_stream, uint32_t* gain, int32_t* yaw_bin) {
+    using namespace mgx;
+    if (!t || !gain || !yaw_bin) return mgb::set_error(MG_E_INVALID, "tree/gain/yaw_bin is NULL");
+    mgb::TreeView v;
+    int rc = mgb::tree_view(t, &v);
+    if (rc != MG_OK) return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev != v.device) return mgb::set_error(MG_E_INVALID, "the tree lives on another device");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const SensorDev& S = *v.sd;
+    const TreeDev& Tr = *v.td;
+    const int32_t n = v.n;
+    std::lock_guard<std::mutex> lk(g_mu);
+    State& st = g_state[t];
+    // 1. bound |I(n)| by the absolute gain (the largest window's unknown incidences)
+    e = launch_zero_u32(Tr.bins, (size_t)2 * S.B * n, s);
+    if (e == hipSuccess) e = launch_trace(*v.map, S, Tr, Tr.level_nodes, n, false, 0, s);
+    if (e == hipSuccess) e = launch_finish(S, Tr, Tr.level_nodes, n, false, v.scratch_gain, v.scratch_yaw, s);
+    std::vector<uint32_t> bound(n);
+    if (e == hipSuccess) e = hipMemcpyAsync(bound.data(), v.scratch_gain, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "exact-gain sizing");
+    Tables T{};
+    rc = setup_tables(st, n, bound.data(), s, &T);
+    if (rc != MG_OK) return rc;
+    // 2. level by level: new incidences per bin, window, then the node's set at that window
+    e = launch_zero_u32(Tr.bins, (size_t)2 * S.B * n, s);
+    const int32_t tiles_all = (S.R + kXThreads - 1) / kXThreads;
+    const int32_t tiles_win = (S.WB * S.H + kXThreads - 1) / kXThreads;
+    for (int32_t d = 0; d < v.levels && e == hipSuccess; ++d) {
+        const int32_t b = (*v.level_ptr)[d], cnt = (*v.level_ptr)[d + 1] - b;
+        if (cnt <= 0) continue;
+        const int32_t* nodes = Tr.level_nodes + b;
+        hipLaunchKernelGGL(k_exact_bins, dim3((unsigned)cnt * (unsigned)tiles_all), dim3(kXThreads), 0, s, *v.map, S,
+                           Tr, T, nodes, tiles_all);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = launch_finish(S, Tr, nodes, cnt, true, gain, yaw_bin, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_exact_insert, dim3((unsigned)cnt * (unsigned)tiles_win), dim3(kXThreads), 0, s,
+                               *v.map, S, Tr, T, (const int32_t*)yaw_bin, tiles_win, nodes, nullptr);
+            e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "exact marginal gain");
     return MG_OK;
 }

@@ -30,9 +30,9 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
                      "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update",
-                     "mg_map_read", "mg_eval_exact", "mg_server_map_update",
+                     "mg_map_read", "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal",
            "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read",
-           "mg_eval_exact", "mg_server_map_update")
+           "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal")
 
 
 class MGError(RuntimeError):
@@ -78,6 +78,7 @@ def lib() -> C.CDLL:
         L.mg_map_update.argtypes = [P, P, P, P, I32, P]
         L.mg_map_read.argtypes = [P, P, P]
         L.mg_eval_exact.argtypes = [P, P, P, P, P, P]
+        L.mg_eval_exact_marginal.argtypes = [P, P, P, P]
         L.mg_interval_config.argtypes = [I32]
         L.mg_interval_tables.argtypes = [C.POINTER(mg_sensor), C.c_float, I32, I32, P, P, P, P]
         L.mg_eval_marginal_levelsync.argtypes = [P, P, P, P, P, P, P]
@@ -204,6 +205,10 @@ def interval_tables(sensor, voxel_m, wd=0, hd=0):
 def mg_eval_exact(tree: int, yaw_bin, x_ray, x_set=None, a_set=None, stream=None):
     _check(lib().mg_eval_exact(C.c_void_p(tree), _stream(stream), _dev_ptr(yaw_bin), _dev_ptr(x_ray), _dev_ptr(x_set),
                                _dev_ptr(a_set)))
+
+
+def mg_eval_exact_marginal(tree: int, gain, yaw_bin, stream=None):
+    _check(lib().mg_eval_exact_marginal(C.c_void_p(tree), _stream(stream), _dev_ptr(gain), _dev_ptr(yaw_bin)))
 
 
 def mg_eval_single_parent(tree: int, gain, yaw_bin, depth=None, stream=None):
@@ -395,6 +400,12 @@ class Tree:
         a = torch.empty_like(xr)
         mg_eval_exact(self.handle, yaw_bin, xr, xs, a, stream)
         return xr, xs, a
+
+    def eval_exact_marginal(self, stream=None):
+        """Exact marginal gain with its own yaw choice (hash sets): (gain, yaw)."""
+        g, y, _ = self.outputs(False)
+        mg_eval_exact_marginal(self.handle, g, y, stream)
+        return g, y
 
     def eval_interval(self, wd=0, hd=0, depth=False, stream=None):
         """Interval mode (the paper's pinhole buffers and overlap intervals): (gain, yaw, depth or None)."""

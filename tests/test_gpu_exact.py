@@ -91,3 +91,44 @@ def test_exact_deepest_chain(mg, orc):
     chain_pos = np.clip(chain_pos, 0.05, w.map.extent_m.astype(np.float32) - 0.05).astype(np.float32)
     chain = W.Tree(pos_m=chain_pos, parent=np.arange(-1, 63, dtype=np.int32))
     _check(mg, orc, w.map, chain, w.sensor, "chain63")
+
+
+def _check_own_yaw(mg, orc, m, tree, sen, label, mask=None):
+    import torch
+    M = mg.Map(m.states, m.voxel_m, m.origin_m)
+    T = mg.Tree(M, tree.pos_m, tree.parent, sen)
+    g, y = T.eval_exact_marginal()
+    torch.cuda.synchronize()
+    ref = orc.exact_marginal(m, tree, sen, mask=mask)
+    sel = np.arange(tree.n) if mask is None else np.flatnonzero(mask)
+    log(f"[exact] own yaw {label}: n={tree.n}, compared {sel.size}")
+    assert np.array_equal(mg.as_u32(g)[sel], ref["g_ex"][sel])
+    assert np.array_equal(y.cpu().numpy()[sel], ref["k_ex"][sel])
+    T.close()
+    M.close()
+
+
+@pytest.mark.parametrize("case", ["tiny", "micro0", "micro1", "chain"])
+def test_exact_own_yaw(mg, orc, case):
+    w = W.make("tiny")
+    if case == "tiny":
+        m, tree, sen = w.map, w.trees[0], w.sensor
+    elif case == "chain":
+        p = w.trees[0].pos_m
+        cp = np.repeat(p[:4], 17, axis=0)[:64] + np.float32(0.013) * np.arange(64, dtype=np.float32)[:, None]
+        cp = np.clip(cp, 0.05, w.map.extent_m.astype(np.float32) - 0.05).astype(np.float32)
+        m, tree, sen = w.map, W.Tree(pos_m=cp, parent=np.arange(-1, 63, dtype=np.int32)), w.sensor
+    else:
+        k = int(case[-1])
+        m, tree, sen = W.random_micro(820 + k, dims=(17, 13, 9), n_nodes=12, max_depth=4, range_vox=9.0,
+                                      p_occ=0.06, p_free=0.45, n_az=[16, 100][k], n_el=[6, 7][k],
+                                      yaw_bins=[8, 36][k])
+    _check_own_yaw(mg, orc, m, tree, sen, case)
+
+
+def test_exact_own_yaw_step_sampled(mg, orc):
+    w = W.make("step")
+    t = w.trees[0]
+    dep = t.depth()
+    mask = orc.ancestor_closure(t.parent, np.flatnonzero(dep == dep.max())[:2])
+    _check_own_yaw(mg, orc, w.map, t, w.sensor, "step", mask=mask)
