@@ -589,6 +589,21 @@ def main():
         exact = {"ms_per_step": dt * 1e3, "window_rays_per_s": n_total * sen.n_el * sen.w_buf / dt,
                  "steps": args.exact_steps, "over_depth_buffer": dt * 1e3 / results["batched"]["ms_per_step"],
                  "path": "mg_eval_exact per tree (hash sets of the window rays' unknown voxels; X_ray, X_set, A_set)"}
+        # the exact planner gain with its own yaw choice (depth order, hash sets), the device
+        # counterpart of the paper's exact CPU implementation
+        ge, ye = torch.empty_like(xr), torch.empty_like(xr)
+        for T in trees:
+            mg.mg_eval_exact_marginal(T.handle, ge, ye)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.exact_steps):
+            for T in trees:
+                mg.mg_eval_exact_marginal(T.handle, ge, ye)
+        torch.cuda.synchronize()
+        dt2 = (time.perf_counter() - t0) / args.exact_steps
+        exact["own_yaw"] = {"ms_per_step": dt2 * 1e3, "rays_per_s": rays_per_step / dt2,
+                            "over_depth_buffer": dt2 * 1e3 / results["batched"]["ms_per_step"],
+                            "path": "mg_eval_exact_marginal per tree"}
         log(f"[bench] exact: {exact}")
     mapb = map_bench(mg) if args.map_bench else None
     if mapb:

@@ -4,7 +4,9 @@ For every node of a workload: the depth-buffer marginal gain (per-voxel
 test), the interval-mode gain (the paper's own test), the single-parent gain
 and the absolute gain, against the exact marginal gain counted with device
 hash sets (mg_eval_exact) at the depth-buffer windows (the interval mode
-against the exact gain at its own windows). Reports, as the CPU error report
+against the exact gain at its own windows); and how often the depth-buffer
+method picks the window the exact planner gain picks (mg_eval_exact_marginal,
+its own yaw choice on its own sets). Reports, as the CPU error report
 does, the least-squares slope through the origin, R^2 and the over/under
 estimate of each conditioned gain against the exact one, and per depth the
 mean ratios. Uses only the HIP library and the seeded workload generator.
@@ -46,7 +48,7 @@ def study(name: str, n_trees=None) -> dict:
     from paper_2609_40297_amd import mg, workloads as W
     w = W.make(name, n_trees=n_trees)
     M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
-    cols = {k: [] for k in ("dep", "g_db", "x_db", "g_iv", "x_iv", "g_sp", "g_abs")}
+    cols = {k: [] for k in ("dep", "g_db", "x_db", "g_iv", "x_iv", "g_sp", "g_abs", "k_db", "g_ex", "k_ex")}
     for t in w.trees:
         T = mg.Tree(M, t.pos_m, t.parent, w.sensor)
         g_db, k_db, _ = T.eval_marginal()
@@ -55,17 +57,23 @@ def study(name: str, n_trees=None) -> dict:
         x_iv = T.eval_exact(k_iv)[0]
         g_sp = T.eval_single_parent()[0]
         g_abs = T.eval_absolute()[0]
+        g_ex, k_ex = T.eval_exact_marginal()
         torch.cuda.synchronize()
         cols["dep"].append(t.depth())
         for k, v in (("g_db", g_db), ("x_db", x_db), ("g_iv", g_iv), ("x_iv", x_iv), ("g_sp", g_sp),
-                     ("g_abs", g_abs)):
+                     ("g_abs", g_abs), ("g_ex", g_ex)):
             cols[k].append(mg.as_u32(v))
+        cols["k_db"].append(k_db.cpu().numpy())
+        cols["k_ex"].append(k_ex.cpu().numpy())
         T.close()
     M.close()
     c = {k: np.concatenate(v) for k, v in cols.items()}
     return dict(workload=name, trees=len(w.trees), nodes=int(c["dep"].size),
                 depth_buffer=_fit(c["dep"], c["g_db"], c["x_db"]),
                 interval=_fit(c["dep"], c["g_iv"], c["x_iv"]),
+                # against the exact planner gain with its own yaw choice: same window chosen, and the gain
+                same_window=float(np.mean(c["k_db"] == c["k_ex"])),
+                depth_buffer_vs_own_yaw_exact=_fit(c["dep"], c["g_db"], c["g_ex"]),
                 per_depth=_per_depth(c["dep"], c["x_db"], db=c["g_db"], sp=c["g_sp"], abs=c["g_abs"]),
                 interval_per_depth=_per_depth(c["dep"], c["x_iv"], interval=c["g_iv"]))
 
