@@ -168,13 +168,13 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
         i = ni;
         j = nj;
         off = noff;
-        if (stepu) {
-            bu += si;
-            su = ((float)bu - uA) * iu;
-        } else {
-            bv += sj;
-            sv = ((float)bv - vA) * iv;
-        }
+        // the stepped axis moves to its next boundary (selects, not a branch: the
+        // axis that did not step keeps its value)
+        bu += stepu ? si : 0;
+        bv += stepu ? 0 : sj;
+        const float nsu = ((float)bu - uA) * iu, nsv = ((float)bv - vA) * iv;
+        su = stepu ? nsu : su;
+        sv = stepu ? sv : nsv;
         sa = e;
         wD = wN;
     }
