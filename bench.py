@@ -58,7 +58,8 @@ def score_bench(mg, trees, gain, n_total, depth_sum, reps=200):
     # (16 B) once, each ancestor id of its root path (4 B) once; per tree the branch row (65 x 4 B)
     alg = n_total * 40 + depth_sum * 4 + len(trees) * (mg.MG_BRANCH_LEN * 4 + 4)
     gbs = alg / (us * 1e-6) / 1e9
-    return {"us_per_call": us, "nodes_per_s": n_total / (us * 1e-6), "launches_per_call": 2,
+    return {"us_per_call": us, "nodes_per_s": n_total / (us * 1e-6),
+            "launches_per_call": 1 if max(t.n for t in trees) <= 8192 else 2,
             "lambda": 0.5, "algorithmic_bytes_per_call": alg,
             "roofline": {"bound": "latency", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS, "traffic": None},

@@ -632,17 +632,12 @@ hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth
 
 // ---------------------------------------------------------------- path score (eq. 3, eq. 4)
 
-// One thread per node of one tree (grid: blocks x trees). The traversal cost
-// (eq. 3) and the exponential objective (eq. 4) are summed from the root down
-// the node's ancestor list (nearest first, so walked backwards), in the order
-// the recursions take: c += |p_m - p_prev| and o += g(m) v^3 exp(-lambda c),
-// in float64 on the float32 positions in metres.
-__global__ void k_score(const BatchTree* __restrict__ trees, const uint32_t* __restrict__ gain, double lambda,
-                        double* __restrict__ cost, double* __restrict__ obj) {
-    const BatchTree& T = trees[blockIdx.y];
-    const int32_t node = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (node >= T.td.n) return;
-    const uint32_t* g = gain + T.out_off;
+// Traversal cost (eq. 3) and exponential objective (eq. 4) of one node, summed
+// from the root down its ancestor list (nearest first, so walked backwards) in
+// the order the recursions take: c += |p_m - p_prev| and
+// o += g(m) v^3 exp(-lambda c), in float64 on the float32 positions in metres.
+__device__ __forceinline__ void score_node(const BatchTree& T, const uint32_t* __restrict__ g, int32_t node,
+                                           double lambda, double* c_out, double* o_out) {
     const int32_t a0 = T.td.anc_ptr[node], a1 = T.td.anc_ptr[node + 1];
     int32_t prev = a1 > a0 ? T.td.anc_ids[a1 - 1] : node;      // the root
     double c = 0.0;
@@ -657,26 +652,29 @@ __global__ void k_score(const BatchTree* __restrict__ trees, const uint32_t* __r
         o = o + (double)g[m] * T.vox3 * exp(-lambda * c);
         prev = m;
     }
+    *c_out = c;
+    *o_out = o;
+}
+
+// One thread per node of one tree (grid: blocks x trees).
+__global__ void k_score(const BatchTree* __restrict__ trees, const uint32_t* __restrict__ gain, double lambda,
+                        double* __restrict__ cost, double* __restrict__ obj) {
+    const BatchTree& T = trees[blockIdx.y];
+    const int32_t node = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (node >= T.td.n) return;
+    double c, o;
+    score_node(T, gain + T.out_off, node, lambda, &c, &o);
     if (cost) cost[T.out_off + node] = c;
     obj[T.out_off + node] = o;
 }
 
-// One workgroup per tree: the node of largest objective, smallest id on ties,
-// and (if asked) its root path, root first, padded with -1.
-__global__ __launch_bounds__(kThreads) void k_best(const BatchTree* __restrict__ trees,
-                                                   const double* __restrict__ obj, int32_t* __restrict__ best,
-                                                   int32_t* __restrict__ branch) {
+// Whole workgroup: the node of largest objective among the threads'
+// candidates (bo, bi), smallest id on ties, written to best[tree]; and (if
+// asked) its root path, root first, padded with -1.
+__device__ __forceinline__ void best_and_branch(const BatchTree& T, double bo, int32_t bi, int32_t tree,
+                                                int32_t* __restrict__ best, int32_t* __restrict__ branch) {
     __shared__ double s_o[kThreads];
     __shared__ int32_t s_i[kThreads];
-    const BatchTree& T = trees[blockIdx.x];
-    const double* o = obj + T.out_off;
-    double bo = 0.0;
-    int32_t bi = -1;
-    for (int32_t i = threadIdx.x; i < T.td.n; i += kThreads)
-        if (bi < 0 || o[i] > bo) {           // ids ascend, so a later equal value never wins
-            bo = o[i];
-            bi = i;
-        }
     s_o[threadIdx.x] = bo;
     s_i[threadIdx.x] = bi;
     __syncthreads();
@@ -694,16 +692,61 @@ __global__ __launch_bounds__(kThreads) void k_best(const BatchTree* __restrict__
         __syncthreads();
     }
     const int32_t b = s_i[0];
-    if (threadIdx.x == 0) best[blockIdx.x] = b;
+    if (threadIdx.x == 0) best[tree] = b;
     if (branch && threadIdx.x < kMaxAnc + 1) {
         const int32_t a0 = T.td.anc_ptr[b], d = T.td.anc_ptr[b + 1] - a0;     // ancestors, nearest first
         const int32_t t = (int32_t)threadIdx.x;
-        branch[(size_t)blockIdx.x * (kMaxAnc + 1) + t] = t < d ? T.td.anc_ids[a0 + d - 1 - t] : t == d ? b : -1;
+        branch[(size_t)tree * (kMaxAnc + 1) + t] = t < d ? T.td.anc_ids[a0 + d - 1 - t] : t == d ? b : -1;
     }
 }
 
+// One workgroup per tree: argmax over the objectives k_score wrote.
+__global__ __launch_bounds__(kThreads) void k_best(const BatchTree* __restrict__ trees,
+                                                   const double* __restrict__ obj, int32_t* __restrict__ best,
+                                                   int32_t* __restrict__ branch) {
+    const BatchTree& T = trees[blockIdx.x];
+    const double* o = obj + T.out_off;
+    double bo = 0.0;
+    int32_t bi = -1;
+    for (int32_t i = threadIdx.x; i < T.td.n; i += kThreads)
+        if (bi < 0 || o[i] > bo) {           // ids ascend, so a later equal value never wins
+            bo = o[i];
+            bi = i;
+        }
+    best_and_branch(T, bo, bi, (int32_t)blockIdx.x, best, branch);
+}
+
+// Small trees: score and argmax in one launch, one workgroup per tree.
+__global__ __launch_bounds__(kThreads) void k_score_best(const BatchTree* __restrict__ trees,
+                                                         const uint32_t* __restrict__ gain, double lambda,
+                                                         double* __restrict__ cost, double* __restrict__ obj,
+                                                         int32_t* __restrict__ best, int32_t* __restrict__ branch) {
+    const BatchTree& T = trees[blockIdx.x];
+    double bo = 0.0;
+    int32_t bi = -1;
+    for (int32_t i = threadIdx.x; i < T.td.n; i += kThreads) {
+        double c, o;
+        score_node(T, gain + T.out_off, i, lambda, &c, &o);
+        if (cost) cost[T.out_off + i] = c;
+        obj[T.out_off + i] = o;
+        if (bi < 0 || o > bo) {
+            bo = o;
+            bi = i;
+        }
+    }
+    best_and_branch(T, bo, bi, (int32_t)blockIdx.x, best, branch);
+}
+
+// Trees of up to kFuseNodes nodes take the single-launch kernel.
+constexpr uint32_t kFuseNodes = 8192;
+
 hipError_t launch_score(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const uint32_t* gain,
                         double lambda, double* cost, double* obj, int32_t* best, int32_t* branch, hipStream_t s) {
+    if (max_nodes <= kFuseNodes) {
+        hipLaunchKernelGGL(k_score_best, dim3((unsigned)n_trees), dim3(kThreads), 0, s, trees, gain, lambda, cost, obj,
+                           best, branch);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_score, dim3((unsigned)grid_for(max_nodes, 256), (unsigned)n_trees), dim3(256), 0, s, trees,
                        gain, lambda, cost, obj);
     hipError_t e = hipGetLastError();

@@ -145,3 +145,33 @@ def test_score_errors(mg):
     assert br[0, 0].item() == 0 and bool((br[0, 1:] == -1).all())
     T.close()
     M.close()
+
+
+def test_score_of_a_tree_past_the_single_launch_size(mg):
+    """A 12,000-node tree (past the single-launch size, so scored by the per-node kernel and the
+    argmax kernel) and the 20-node tree in one batch, with seeded gains given to both sides."""
+    import torch
+    w = W.make("tiny")
+    rng = np.random.Generator(np.random.PCG64(31))
+    n = 12000
+    par = np.concatenate([[-1], rng.integers(0, np.minimum(np.arange(1, n), 200))]).astype(np.int32)
+    pos = rng.uniform(0.1, w.map.extent_m.astype(np.float32) - 0.1, (n, 3)).astype(np.float32)
+    big = W.Tree(pos_m=pos, parent=par)
+    assert big.depth().max() <= 64
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    trees = [mg.Tree(M, big.pos_m, big.parent, w.sensor), mg.Tree(M, w.trees[0].pos_m, w.trees[0].parent, w.sensor)]
+    mg.eval_batch(trees)                               # the plan the score call uses
+    gains = rng.integers(0, 20000, n + w.trees[0].n).astype(np.uint32)
+    g = torch.from_numpy(gains.view(np.int32)).cuda()
+    c, o, b, br = mg.score_batch(trees, g, 0.5)
+    torch.cuda.synchronize()
+    c, o, b, br = c.cpu().numpy(), o.cpu().numpy(), b.cpu().numpy(), br.cpu().numpy()
+    off = 0
+    for k, t in enumerate((big, w.trees[0])):
+        cost, obj, _ = paths.score_paths(t.pos_m, t.parent, gains[off:off + t.n], w.map.voxel_m, 0.5)
+        _check_tree(c[off:off + t.n], o[off:off + t.n], int(b[k]), cost, obj)
+        _check_branch(br[k], t.parent, int(b[k]))
+        off += t.n
+    for T in trees:
+        T.close()
+    M.close()
