@@ -128,9 +128,10 @@ hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t m
                              hipStream_t s);
 // One depth level of many trees: trace with launch shape `shape`, then window
 // selection. t0/t1 (may be null): events the trace kernel's dispatch itself
-// records at its start and end.
+// records at its start and end. `ahead`: the trace kernel keeps two voxels in
+// flight per lane (for launches too small to hide load latency with waves).
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
                               const SensorDev& sd, int32_t max_anc, hipStream_t s, int shape = 0,
-                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, bool ahead = false);
 
 }  // namespace mgk

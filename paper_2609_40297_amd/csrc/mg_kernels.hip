@@ -275,7 +275,13 @@ __device__ __forceinline__ void load_tables(const TraceLDS& L, const SensorDev& 
 // whenever the queue could overflow it is drained against the ancestors.
 // Requires the tables in LDS; ends with the tile's bins added to the node's
 // global bins.
-template <bool kMarginal, int kTh, int kQ>
+//
+// kAhead = 2 keeps two voxels in flight per lane instead of one: the walk's
+// front runs a step ahead of the voxel being examined, so a grid load has a
+// whole step of work to hide behind. Launches with few waves per SIMD (the
+// small levels near the root) are bound by that load latency rather than by
+// instruction issue; results are the same either way.
+template <bool kMarginal, int kTh, int kQ, int kAhead = 1>
 __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
                                            int32_t tile, const TraceLDS& L) {
     const int32_t tid = threadIdx.x;
@@ -337,9 +343,10 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     const gbytes_t grid = as_global(M.bricks);
     // the node lies inside the grid and t = 0 < rv, so its own voxel is
     // visited; a lane without a ray reads a padding byte and is done at once
+    int32_t qn = 0;
+    if constexpr (kAhead == 1) {
     uint32_t addr = has_ray ? voxel_addr(ix, iy, iz, M) : M.outside;   // address of the current voxel
     uint32_t st = grid[addr];
-    int32_t qn = 0;
     uint64_t alive = ballot(has_ray);
     while (alive) {
         // Straight-line step without divergent branches: the current voxel's
@@ -399,6 +406,85 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, L.lut_col, L.lut_row, Tr.dpan, L.bins + S.B, lane);
             qn = 0;
         }
+    }
+    } else {
+    static_assert(kAhead == 2, "one or two voxels in flight");
+    // Slot a and slot b hold the two voxels in flight (grid address, state,
+    // entry parameter, coordinates packed as in a queue entry); they are
+    // examined alternately, a first. `live`: the lane has not yet examined a
+    // voxel that ends its ray, so a slot filled after that voxel is ignored.
+    // The front (ix, iy, iz and the face parameters) is the newest voxel in
+    // flight; refilling a slot takes the front one DDA step further. Once the
+    // front has left the grid it takes at most one more step before the lane
+    // examines the padding voxel it left through (which ends the ray) and
+    // stops loading; coordinates -2 and n + 1 still give an address inside the
+    // bricked grid (the coordinate bits are masked), whose byte is never
+    // examined.
+    bool live = has_ray;
+    uint32_t addr_a = has_ray ? voxel_addr(ix, iy, iz, M) : M.outside;
+    uint32_t st_a = grid[addr_a];
+    float t_a = 0.f;
+    uint32_t xy_a = (uint32_t)ix | ((uint32_t)iy << 16), z_a = (uint32_t)iz;
+    uint32_t addr_b, st_b, xy_b, z_b;
+    float t_b;
+    auto advance = [&](uint32_t& addr_s, uint32_t& st_s, float& t_s, uint32_t& xy_s, uint32_t& z_s) {
+        const bool mx = (tx <= ty) & (tx <= tz);
+        const bool my = !mx & (ty <= tz);
+        const bool mz = !mx & !my;
+        const float tn = mx ? tx : (my ? ty : tz);
+        ix += mx ? sx : 0;
+        iy += my ? sy : 0;
+        iz += mz ? sz : 0;
+        const bool ok = live & (tn < S.rv);
+        addr_s = ok ? voxel_addr(ix, iy, iz, M) : M.outside;
+        st_s = grid[addr_s];
+        bx += mx ? dbx : 0.f;
+        by += my ? dby : 0.f;
+        bz += mz ? dbz : 0.f;
+        tx = (bx - p.x) * fx;
+        ty = (by - p.y) * fy;
+        tz = (bz - p.z) * fz;
+        t_s = tn;
+        xy_s = (uint32_t)ix | ((uint32_t)iy << 16);
+        z_s = (uint32_t)iz;
+    };
+    auto examine = [&](uint32_t addr_s, uint32_t st_s, float t_s, uint32_t xy_s, uint32_t z_s) {
+        const bool unk = live & (st_s == kUnknown);
+        const bool occ = live & (st_s == kOccupied);
+        h = occ ? t_s : h;
+        n_abs += unk ? 1u : 0u;
+        if (kMarginal && ballot(unk) != 0) {
+            // the same run-merging append as with one voxel in flight
+            const uint32_t key = unk ? addr_s : (0xffffffc0u | (uint32_t)lane);
+            const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int32_t)0xffffffbfu, (int32_t)key, 0x138,
+                                                                          0xf, 0xf, false);
+            const uint64_t dups = ballot(prev == key) & bin_as_prev_mask;
+            const uint64_t heads = ballot(unk) & ~dups;
+            const bool head = unk & !((prev == key) & bin_as_prev);
+            const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> lane) >> 1));
+            const int32_t below = (int32_t)lane_prefix(heads);
+            const int32_t npop = __popcll(heads);
+            const int32_t m = -(int32_t)head;
+            q[qn + ((below & m) | ((npop + lane - below) & ~m))] = make_uint2(xy_s, z_s | ebin | (extra << 24));
+            qn = __builtin_amdgcn_readfirstlane(qn + npop);
+        }
+        live = live & (st_s < kOccupied);
+    };
+    advance(addr_b, st_b, t_b, xy_b, z_b);
+    uint64_t alive = ballot(live);
+    while (alive) {
+        do {
+            examine(addr_a, st_a, t_a, xy_a, z_a);
+            advance(addr_a, st_a, t_a, xy_a, z_a);
+            examine(addr_b, st_b, t_b, xy_b, z_b);
+            advance(addr_b, st_b, t_b, xy_b, z_b);
+            alive = ballot(live);
+        } while (alive && (!kMarginal || qn + 128 <= kQ));
+        if (kMarginal) {
+            drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, L.lut_col, L.lut_row, Tr.dpan, L.bins + S.B, lane);
+            qn = 0;
+        }
+    }
     }
     if (kMarginal && has_ray) Tr.dpan[(size_t)node * S.R + r] = h;
     if (n_abs) atomicAdd(&L.bins[bin], n_abs);
@@ -495,7 +581,7 @@ __global__ void k_batch_zero(const BatchTree* __restrict__ trees, int32_t B2) {
 
 // One depth level of all trees at once: work item = (tree, node) from
 // `items` (tree << 32 | node), T workgroups per item.
-template <int kTh, int kQ>
+template <int kTh, int kQ, int kAhead>
 __global__ __launch_bounds__(kTh) void k_trace_multi(const BatchTree* __restrict__ trees,
                                                      const unsigned long long* __restrict__ items, SensorDev S) {
     extern __shared__ char smem[];
@@ -508,7 +594,7 @@ __global__ __launch_bounds__(kTh) void k_trace_multi(const BatchTree* __restrict
     St.rv2 = BT.rv2;
     const MapDev M = BT.map;     // copies: loaded once, not re-read through the descriptor
     const TreeDev Tr = BT.td;
-    trace_tile<true, kTh, kQ>(M, St, Tr, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
+    trace_tile<true, kTh, kQ, kAhead>(M, St, Tr, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
 }
 
 // Window selection for one depth level of all trees; writes each tree's
@@ -770,12 +856,12 @@ namespace {
 
 template <int kTh, int kQ>
 void launch_multi(const BatchTree* trees, const unsigned long long* items, int32_t n_items, const SensorDev& sd,
-                  int32_t max_anc, hipStream_t s, hipEvent_t t0, hipEvent_t t1, int shape) {
+                  int32_t max_anc, hipStream_t s, hipEvent_t t0, hipEvent_t t1, int shape, bool ahead) {
     SensorDev st = sd;
     st.T = tiles_per_node(sd, shape);
     const dim3 grid((unsigned)n_items * (unsigned)st.T);
     const uint32_t lds = (uint32_t)trace_lds_bytes(sd, shape, max_anc);
-    auto kern = k_trace_multi<kTh, kQ>;
+    auto kern = ahead ? k_trace_multi<kTh, kQ, 2> : k_trace_multi<kTh, kQ, 1>;
     if (t0 && t1)
         hipExtLaunchKernelGGL(kern, grid, dim3(kTh), lds, s, t0, t1, 0u, trees, items, st);
     else
@@ -784,12 +870,14 @@ void launch_multi(const BatchTree* trees, const unsigned long long* items, int32
 
 template <int I>
 void launch_multi_shape(int shape, const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                        const SensorDev& sd, int32_t max_anc, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+                        const SensorDev& sd, int32_t max_anc, hipStream_t s, hipEvent_t t0, hipEvent_t t1,
+                        bool ahead) {
     if constexpr (I < kNumShapes) {
         if (shape == I)
-            launch_multi<kShapes[I].threads, kShapes[I].queue>(trees, items, n_items, sd, max_anc, s, t0, t1, I);
+            launch_multi<kShapes[I].threads, kShapes[I].queue>(trees, items, n_items, sd, max_anc, s, t0, t1, I,
+                                                               ahead);
         else
-            launch_multi_shape<I + 1>(shape, trees, items, n_items, sd, max_anc, s, t0, t1);
+            launch_multi_shape<I + 1>(shape, trees, items, n_items, sd, max_anc, s, t0, t1, ahead);
     }
 }
 
@@ -797,11 +885,11 @@ void launch_multi_shape(int shape, const BatchTree* trees, const unsigned long l
 
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
                               const SensorDev& sd, int32_t max_anc, hipStream_t s, int shape, hipEvent_t t0,
-                              hipEvent_t t1) {
+                              hipEvent_t t1, bool ahead) {
     if (n_items <= 0) return hipSuccess;
     if (shape < 0 || shape >= kNumShapes || max_anc < 0 || max_anc > kMaxAnc) return hipErrorInvalidValue;
     if (!shape_fits(sd, shape, max_anc)) return hipErrorInvalidConfiguration;
-    launch_multi_shape<0>(shape, trees, items, n_items, sd, max_anc, s, t0, t1);
+    launch_multi_shape<0>(shape, trees, items, n_items, sd, max_anc, s, t0, t1, ahead);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finish_multi, dim3((unsigned)n_items), dim3(kThreads), 0, s, trees, items, sd);
