@@ -245,7 +245,7 @@ def next_row_oracles(w, threads):
     """The oracles of the next-row paths, each on a bounded sample, for context beside the device
     figures: the interval mode and the exact sets on the three deepest leaves of tree 0 and their
     ancestors (the exact pass at the depth-buffer windows of the same nodes), the TSDF conversion
-    on a 512x512x128 grid."""
+    on a 512x512x128 grid; and the depth-buffer oracle itself on one thread over the same nodes."""
     from oracle import ivlref, maps, mgref
     t = w.trees[0]
     dep = t.depth()
@@ -258,7 +258,11 @@ def next_row_oracles(w, threads):
     dt = time.perf_counter() - t0
     out["interval"] = {"value": nodes * w.sensor.rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
                        "sample": f"{nodes} nodes (3 deepest leaves of tree 0 and their ancestors), {dt:.2f} s"}
-    ref = mgref.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads)
+    t0 = time.perf_counter()
+    ref = mgref.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=1)
+    dt = time.perf_counter() - t0
+    out["serial"] = {"value": nodes * w.sensor.rays / dt, "unit": "rays/s", "cores": 1, "kind": "oracle",
+                     "sample": f"the same {nodes} nodes, depth-buffer marginal gain on one thread, {dt:.2f} s"}
     t0 = time.perf_counter()
     mgref.exact(w.map, t, w.sensor, ref["k_db"], ref["D"], mask=mask)
     dt = time.perf_counter() - t0
