@@ -58,11 +58,6 @@ struct Plan {
 
 // Configuration for plans built from now on (mg_batch_config).
 int g_cfg_shape = -1;                      // -1: autotune
-// Launches of fewer workgroups than this (a few waves per SIMD at most) run the
-// trace kernel with two voxels in flight per lane; measured on a 500-node tree
-// (levels of 1 to 360 nodes, 85 workgroups per node) against thresholds of 0,
-// 1024, 4096, 16384 workgroups and every launch: 1024 is fastest, by 1.2 %.
-constexpr int64_t kAheadWorkgroups = 1024;
 bool g_cfg_graph = false;                  // replaying a graph measured slower than direct launches
 // Autotuned shapes per workload shape (sensor, range, map dims, sizes).
 std::map<std::vector<int64_t>, int> g_tuned;

@@ -11,6 +11,11 @@ constexpr int kMaxAnc = 64;        // deepest supported ancestor chain
 constexpr int kMaxBins = 256;      // yaw bins
 constexpr int kMaxAz = 4096;       // panorama columns (LDS holds their boundaries)
 constexpr int kMaxEl = 2048;
+// Trace launches of fewer workgroups than this (a few waves per SIMD at most)
+// keep two voxels in flight per lane; measured on a 500-node tree (levels of 1
+// to 360 nodes, 85 workgroups per node) against thresholds of 0, 1024, 4096,
+// 16384 workgroups and every launch: 1024 is fastest, by 1.2 %.
+constexpr int64_t kAheadWorkgroups = 1024;
 
 // kOutside marks the padding around the grid: a traversal that reaches it
 // has left the grid.

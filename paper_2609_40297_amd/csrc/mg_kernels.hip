@@ -496,7 +496,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     }
 }
 
-template <bool kMarginal>
+template <bool kMarginal, int kAhead>
 __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
                                                     const int32_t* __restrict__ nodes) {
     constexpr int kTh = kShapes[0].threads, kQ = kShapes[0].queue;
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeD
     extern __shared__ char smem[];
     const TraceLDS L = carve_lds<kTh, kQ>(smem, S);
     load_tables<kTh>(L, S);
-    trace_tile<kMarginal, kTh, kQ>(M, S, Tr, nodes[blockIdx.x / S.T], blockIdx.x % S.T, L);
+    trace_tile<kMarginal, kTh, kQ, kAhead>(M, S, Tr, nodes[blockIdx.x / S.T], blockIdx.x % S.T, L);
 }
 
 // ---------------------------------------------------------------- window selection
@@ -696,10 +696,12 @@ hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td,
     dim3 grid((unsigned)n_nodes * (unsigned)sd.T);
     size_t lds = trace_lds_bytes(sd, 0, marginal ? max_anc : 0);
     if (lds > lds_limit()) return hipErrorInvalidConfiguration;
-    if (marginal)
-        hipLaunchKernelGGL(k_trace<true>, grid, dim3(kThreads), lds, s, m, sd, td, nodes);
+    if (marginal && (int64_t)grid.x < kAheadWorkgroups)
+        hipLaunchKernelGGL((k_trace<true, 2>), grid, dim3(kThreads), lds, s, m, sd, td, nodes);
+    else if (marginal)
+        hipLaunchKernelGGL((k_trace<true, 1>), grid, dim3(kThreads), lds, s, m, sd, td, nodes);
     else
-        hipLaunchKernelGGL(k_trace<false>, grid, dim3(kThreads), lds, s, m, sd, td, nodes);
+        hipLaunchKernelGGL((k_trace<false, 1>), grid, dim3(kThreads), lds, s, m, sd, td, nodes);
     return hipGetLastError();
 }
 
