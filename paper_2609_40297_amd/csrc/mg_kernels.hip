@@ -94,10 +94,11 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     // table bucket holding at most one column boundary, giving a guess gc. The
     // boundaries gc, gc + 1 and gc + 2 of the window are read at once (the LDS
     // table holds the boundaries twice over, so window boundary k is entry
-    // c0 + k); the column is gc + 1 if boundary gc + 1 lies at or left of r and
-    // gc + 2 does not, gc if boundary gc does and gc + 1 does not. Lanes where
-    // neither holds (rounding at a bucket edge) settle with the
-    // boundary-by-boundary walk.
+    // c0 + k). When boundary gc lies at or left of r and gc + 2 does not, the
+    // column is gc + 1 if boundary gc + 1 does and gc otherwise. Other lanes
+    // (rounding at a bucket edge) settle with the boundary-by-boundary walk,
+    // which also returns gc + l1 in the two patterns that break monotonicity
+    // (1-0-1 and 0-1-0).
     const float u0 = A.b0x * rx + A.b0y * ry;
     float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
     pa = u0 < 0.f ? 2.f - pa : pa;
@@ -109,7 +110,7 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
     // (and/or rather than a select, so that all three reads stay unconditional)
     int32_t col = gc + (int32_t)l1;
-    const bool c_ok = (l1 & !l2) | (!l1 & l0);
+    const bool c_ok = l0 & !l2;
     if (ballot(!c_ok)) {
         if (!c_ok) {
             for (;;) {
@@ -132,7 +133,7 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
     const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
     int32_t row = gr + (int32_t)r1;
-    const bool r_ok = (r1 & !r2) | (!r1 & r0);
+    const bool r_ok = r0 & !r2;
     if (ballot(!r_ok)) {
         if (!r_ok) {
             for (;;) {
@@ -360,10 +361,12 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             const bool unk = st == kUnknown;
             const bool occ = st == kOccupied;
             h = occ ? t : h;
-            n_abs += unk ? 1u : 0u;
-            // queueing runs only in steps where some lane of the wave is on an
+            if (!kMarginal) n_abs += unk ? 1u : 0u;
+            // queueing (and the absolute count, which adds nothing in other
+            // steps) runs only in steps where some lane of the wave is on an
             // unknown voxel (a wave-uniform branch)
             if (kMarginal && ballot(unk) != 0) {
+                n_abs += unk ? 1u : 0u;
                 // a lane whose unknown voxel and bin equal the previous lane's
                 // joins that lane's entry; the first lane of each run appends
                 // one entry carrying the run's length. Keys of other lanes are
@@ -452,8 +455,9 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
         const bool unk = live & (st_s == kUnknown);
         const bool occ = live & (st_s == kOccupied);
         h = occ ? t_s : h;
-        n_abs += unk ? 1u : 0u;
+        if (!kMarginal) n_abs += unk ? 1u : 0u;
         if (kMarginal && ballot(unk) != 0) {
+            n_abs += unk ? 1u : 0u;
             // the same run-merging append as with one voxel in flight
             const uint32_t key = unk ? addr_s : (0xffffffc0u | (uint32_t)lane);
             const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int32_t)0xffffffbfu, (int32_t)key, 0x138,
