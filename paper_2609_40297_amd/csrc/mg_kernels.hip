@@ -73,9 +73,11 @@ __device__ __forceinline__ bool left_of(float2 b, float rx, float ry) { return b
 // guesses them and the exact boundary comparisons settle them. Those
 // comparisons are monotone along the boundaries, so the settled index is the
 // exact count whatever the guess. The cheap rejections (range, band, wedge)
-// form one mask so that a wave branches once.
-__device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float cy, float cz, const SensorDev& S,
-                                              const float2* __restrict__ s_bv, const float* __restrict__ s_ts,
+// form one mask so that a wave branches once. A lane with act false (no
+// queue entry) gets true, so that its negation keeps nothing.
+__device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float cy, float cz, bool act,
+                                              const SensorDev& S, const float2* __restrict__ s_bv,
+                                              const float* __restrict__ s_ts,
                                               float ts0, float tsH, const uint16_t* __restrict__ s_lut_col,
                                               const uint16_t* __restrict__ s_lut_row,
                                               const float* __restrict__ dpan) {
@@ -87,67 +89,74 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
     const float sz = rz * fabsf(rz);
     const float w0 = A.b0x * ry - A.b0y * rx;
     const float w1 = A.b1x * ry - A.b1y * rx;
-    const bool inside = (range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH) & (w0 >= 0.f) & (w1 < 0.f);
-    if (!inside) return false;
-
-    // Column: pseudo-angle past the left boundary (monotone in the angle) picks a
-    // table bucket holding at most one column boundary, giving a guess gc. The
-    // boundaries gc, gc + 1 and gc + 2 of the window are read at once (the LDS
-    // table holds the boundaries twice over, so window boundary k is entry
-    // c0 + k). When boundary gc lies at or left of r and gc + 2 does not, the
-    // column is gc + 1 if boundary gc + 1 does and gc otherwise. Other lanes
-    // (rounding at a bucket edge) settle with the boundary-by-boundary walk,
-    // which also returns gc + l1 in the two patterns that break monotonicity
-    // (1-0-1 and 0-1-0).
-    const float u0 = A.b0x * rx + A.b0y * ry;
-    float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
-    pa = u0 < 0.f ? 2.f - pa : pa;
-    const int32_t gc = s_lut_col[(int32_t)fminf(fmaxf(pa * S.lut_col_scale, 0.f), (float)(S.n_lut_col - 1))];
-    const int32_t cb = A.c0 + gc;
-    const float2 v0 = s_bv[cb], v1 = s_bv[cb + 1], v2 = s_bv[cb + 2];
-    const bool l0 = (gc == 0) | left_of(v0, rx, ry);
-    const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
-    const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
-    // (and/or rather than a select, so that all three reads stay unconditional)
-    int32_t col = gc + (int32_t)l1;
-    const bool c_ok = l0 & !l2;
-    if (ballot(!c_ok)) {
-        if (!c_ok) {
-            for (;;) {
-                if (col + 1 >= S.WB || !left_of(s_bv[A.c0 + col + 1], rx, ry)) break;
-                ++col;
-            }
-            for (;;) {
-                if (col == 0 || left_of(s_bv[A.c0 + col], rx, ry)) break;
-                --col;
-            }
-        }
-    }
-    // Row: elevation tangent picks a bucket holding at most one row boundary;
-    // the same three-boundary decision, same fallback.
-    const float tg = rz * __builtin_amdgcn_rsqf(rho2);
-    const int32_t gr = s_lut_row[(int32_t)fminf(fmaxf((tg - S.lut_row_lo) * S.lut_row_scale, 0.f),
-                                                (float)(S.n_lut_row - 1))];
-    const float e0 = s_ts[gr], e1 = s_ts[gr + 1], e2 = s_ts[min(gr + 2, S.H)];
-    const bool r0 = (gr == 0) | (sz >= rho2 * e0);
-    const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
-    const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
-    int32_t row = gr + (int32_t)r1;
-    const bool r_ok = r0 & !r2;
-    if (ballot(!r_ok)) {
-        if (!r_ok) {
-            for (;;) {
-                if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
-                ++row;
-            }
-            for (;;) {
-                if (row == 0 || sz >= rho2 * s_ts[row]) break;
-                --row;
+    const bool inside =
+        act & (range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH) & (w0 >= 0.f) & (w1 < 0.f);
+    // The result is one comparison after the lookup (so that a ballot of it
+    // takes the comparison's mask as it stands): lanes outside the window, band
+    // or range keep a limit of -1, which no squared range meets; lanes without
+    // an entry (act false) a limit of +inf, which every one meets.
+    float lim = act ? -1.f : __builtin_inff();
+    if (inside) {
+        // Column: pseudo-angle past the left boundary (monotone in the angle) picks a
+        // table bucket holding at most one column boundary, giving a guess gc. The
+        // boundaries gc, gc + 1 and gc + 2 of the window are read at once (the LDS
+        // table holds the boundaries twice over, so window boundary k is entry
+        // c0 + k). When boundary gc lies at or left of r and gc + 2 does not, the
+        // column is gc + 1 if boundary gc + 1 does and gc otherwise. Other lanes
+        // (rounding at a bucket edge) settle with the boundary-by-boundary walk,
+        // which also returns gc + l1 in the two patterns that break monotonicity
+        // (1-0-1 and 0-1-0).
+        const float u0 = A.b0x * rx + A.b0y * ry;
+        float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
+        pa = u0 < 0.f ? 2.f - pa : pa;
+        const int32_t gc = s_lut_col[(int32_t)fminf(fmaxf(pa * S.lut_col_scale, 0.f), (float)(S.n_lut_col - 1))];
+        const int32_t cb = A.c0 + gc;
+        const float2 v0 = s_bv[cb], v1 = s_bv[cb + 1], v2 = s_bv[cb + 2];
+        const bool l0 = (gc == 0) | left_of(v0, rx, ry);
+        const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
+        const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
+        // (and/or rather than a select, so that all three reads stay unconditional)
+        int32_t col = gc + (int32_t)l1;
+        const bool c_ok = l0 & !l2;
+        if (ballot(!c_ok)) {
+            if (!c_ok) {
+                for (;;) {
+                    if (col + 1 >= S.WB || !left_of(s_bv[A.c0 + col + 1], rx, ry)) break;
+                    ++col;
+                }
+                for (;;) {
+                    if (col == 0 || left_of(s_bv[A.c0 + col], rx, ry)) break;
+                    --col;
+                }
             }
         }
+        // Row: elevation tangent picks a bucket holding at most one row boundary;
+        // the same three-boundary decision, same fallback.
+        const float tg = rz * __builtin_amdgcn_rsqf(rho2);
+        const int32_t gr = s_lut_row[(int32_t)fminf(fmaxf((tg - S.lut_row_lo) * S.lut_row_scale, 0.f),
+                                                    (float)(S.n_lut_row - 1))];
+        const float e0 = s_ts[gr], e1 = s_ts[gr + 1], e2 = s_ts[min(gr + 2, S.H)];
+        const bool r0 = (gr == 0) | (sz >= rho2 * e0);
+        const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
+        const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
+        int32_t row = gr + (int32_t)r1;
+        const bool r_ok = r0 & !r2;
+        if (ballot(!r_ok)) {
+            if (!r_ok) {
+                for (;;) {
+                    if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
+                    ++row;
+                }
+                for (;;) {
+                    if (row == 0 || sz >= rho2 * s_ts[row]) break;
+                    --row;
+                }
+            }
+        }
+        const float D = as_global(dpan)[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
+        lim = D * D;
     }
-    const float D = as_global(dpan)[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
-    return range2 <= D * D;
+    return range2 <= lim;
 }
 
 // ---------------------------------------------------------------- ray traversal
@@ -215,13 +224,12 @@ __device__ __forceinline__ void drain_queue(uint2* __restrict__ q, int32_t n, co
             const int32_t i = base + lane;
             const bool act = i < n;
             const uint2 e = act ? q[i] : make_uint2(0u, 0u);
-            bool keep = false;
-            if (act) {
-                const float cx = (float)(int32_t)(e.x & 0xffffu) + 0.5f;
-                const float cy = (float)(int32_t)(e.x >> 16) + 0.5f;
-                const float cz = (float)(int32_t)(e.y & 0xffffu) + 0.5f;
-                keep = !ancestor_sees(A, cx, cy, cz, S, s_bv, s_ts, ts0, tsH, s_lut_col, s_lut_row, dpan);
-            }
+            // (lanes without an entry run the cheap rejections on voxel 0 and
+            // are masked out)
+            const float cx = (float)(int32_t)(e.x & 0xffffu) + 0.5f;
+            const float cy = (float)(int32_t)(e.x >> 16) + 0.5f;
+            const float cz = (float)(int32_t)(e.y & 0xffffu) + 0.5f;
+            const bool keep = !ancestor_sees(A, cx, cy, cz, act, S, s_bv, s_ts, ts0, tsH, s_lut_col, s_lut_row, dpan);
             const uint64_t bal = ballot(keep);
             if (keep) q[m + (int32_t)lane_prefix(bal)] = e;
             m += __popcll(bal);
@@ -392,8 +400,12 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             ix += mx ? sx : 0;
             iy += my ? sy : 0;
             iz += mz ? sz : 0;
-            const bool stepping = st < kOccupied;      // alive and not stopped here
-            const bool next_ok = stepping & (tn < S.rv);
+            // a lane that stops here (occupied, finished or outside) compares
+            // +inf with the range: one comparison gives the mask, and the
+            // ballot below takes it as it stands
+            const float tn_go = st < kOccupied ? tn : __builtin_inff();
+            const bool next_ok = tn_go < S.rv;
+            alive = ballot(next_ok);
             addr = next_ok ? voxel_addr(ix, iy, iz, M) : M.outside;
             st = grid[addr];
             bx += mx ? dbx : 0.f;
@@ -403,7 +415,6 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             ty = (by - p.y) * fy;
             tz = (bz - p.z) * fz;
             t = tn;
-            alive = ballot(next_ok);
         } while (alive && (!kMarginal || qn + 64 <= kQ));
         if (kMarginal) {
             drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, L.lut_col, L.lut_row, Tr.dpan, L.bins + S.B, lane);
