@@ -118,16 +118,14 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
         // (and/or rather than a select, so that all three reads stay unconditional)
         int32_t col = gc + (int32_t)l1;
         const bool c_ok = l0 & !l2;
-        if (ballot(!c_ok)) {
-            if (!c_ok) {
-                for (;;) {
-                    if (col + 1 >= S.WB || !left_of(s_bv[A.c0 + col + 1], rx, ry)) break;
-                    ++col;
-                }
-                for (;;) {
-                    if (col == 0 || left_of(s_bv[A.c0 + col], rx, ry)) break;
-                    --col;
-                }
+        if (!c_ok) {      // (a divergent branch: skipped when no lane needs it)
+            for (;;) {
+                if (col + 1 >= S.WB || !left_of(s_bv[A.c0 + col + 1], rx, ry)) break;
+                ++col;
+            }
+            for (;;) {
+                if (col == 0 || left_of(s_bv[A.c0 + col], rx, ry)) break;
+                --col;
             }
         }
         // Row: elevation tangent picks a bucket holding at most one row boundary;
@@ -141,16 +139,14 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
         const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
         int32_t row = gr + (int32_t)r1;
         const bool r_ok = r0 & !r2;
-        if (ballot(!r_ok)) {
-            if (!r_ok) {
-                for (;;) {
-                    if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
-                    ++row;
-                }
-                for (;;) {
-                    if (row == 0 || sz >= rho2 * s_ts[row]) break;
-                    --row;
-                }
+        if (!r_ok) {
+            for (;;) {
+                if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
+                ++row;
+            }
+            for (;;) {
+                if (row == 0 || sz >= rho2 * s_ts[row]) break;
+                --row;
             }
         }
         const float D = as_global(dpan)[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
@@ -385,7 +381,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 const uint64_t dups = ballot(prev == key) & bin_as_prev_mask;
                 const uint64_t heads = ballot(unk) & ~dups;
                 const bool head = unk & !((prev == key) & bin_as_prev);
-                const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> lane) >> 1));
+                const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> 1) >> lane));
                 const int32_t below = (int32_t)lane_prefix(heads);
                 const int32_t npop = __popcll(heads);
                 const int32_t m = -(int32_t)head;     // all ones for a lane that appends
@@ -476,7 +472,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             const uint64_t dups = ballot(prev == key) & bin_as_prev_mask;
             const uint64_t heads = ballot(unk) & ~dups;
             const bool head = unk & !((prev == key) & bin_as_prev);
-            const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> lane) >> 1));
+            const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> 1) >> lane));
             const int32_t below = (int32_t)lane_prefix(heads);
             const int32_t npop = __popcll(heads);
             const int32_t m = -(int32_t)head;
