@@ -358,9 +358,8 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
         // byte is used first, then the next voxel is found and its byte
         // requested, so the load stays in flight until the next step uses it.
         // A lane that has finished (or left the grid) reads a padding byte,
-        // which is neither unknown nor occupied. Every lane writes a queue
-        // slot (lanes without an entry write past the new end, into slots the
-        // next step overwrites).
+        // which is neither unknown nor occupied. The first lane of each run
+        // of equal unknown voxels writes the queue entry.
         do {
             const bool unk = st == kUnknown;
             const bool occ = st == kOccupied;
@@ -374,20 +373,20 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 // a lane whose unknown voxel and bin equal the previous lane's
                 // joins that lane's entry; the first lane of each run appends
                 // one entry carrying the run's length. Keys of other lanes are
-                // distinct values above every address.
+                // distinct values above every address. (Lane 0 receives 0 from
+                // the shift; it is never a duplicate, its bin_as_prev being
+                // false.)
                 const uint32_t key = unk ? addr : (0xffffffc0u | (uint32_t)lane);
-                const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int32_t)0xffffffbfu, (int32_t)key, 0x138,
-                                                                              0xf, 0xf, false);
+                const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int32_t)key, 0x138, 0xf, 0xf, true);
                 const uint64_t dups = ballot(prev == key) & bin_as_prev_mask;
                 const uint64_t heads = ballot(unk) & ~dups;
                 const bool head = unk & !((prev == key) & bin_as_prev);
                 const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> 1) >> lane));
                 const int32_t below = (int32_t)lane_prefix(heads);
-                const int32_t npop = __popcll(heads);
-                const int32_t m = -(int32_t)head;     // all ones for a lane that appends
-                q[qn + ((below & m) | ((npop + lane - below) & ~m))] =
-                    make_uint2((uint32_t)ix | ((uint32_t)iy << 16), (uint32_t)iz | ebin | (extra << 24));
-                qn = __builtin_amdgcn_readfirstlane(qn + npop);
+                if (head)
+                    q[qn + below] =
+                        make_uint2((uint32_t)ix | ((uint32_t)iy << 16), (uint32_t)iz | ebin | (extra << 24));
+                qn = __builtin_amdgcn_readfirstlane(qn + __popcll(heads));
             }
             const bool mx = (tx <= ty) & (tx <= tz);
             const bool my = !mx & (ty <= tz);
@@ -467,17 +466,14 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             n_abs += unk ? 1u : 0u;
             // the same run-merging append as with one voxel in flight
             const uint32_t key = unk ? addr_s : (0xffffffc0u | (uint32_t)lane);
-            const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int32_t)0xffffffbfu, (int32_t)key, 0x138,
-                                                                          0xf, 0xf, false);
+            const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int32_t)key, 0x138, 0xf, 0xf, true);
             const uint64_t dups = ballot(prev == key) & bin_as_prev_mask;
             const uint64_t heads = ballot(unk) & ~dups;
             const bool head = unk & !((prev == key) & bin_as_prev);
             const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> 1) >> lane));
             const int32_t below = (int32_t)lane_prefix(heads);
-            const int32_t npop = __popcll(heads);
-            const int32_t m = -(int32_t)head;
-            q[qn + ((below & m) | ((npop + lane - below) & ~m))] = make_uint2(xy_s, z_s | ebin | (extra << 24));
-            qn = __builtin_amdgcn_readfirstlane(qn + npop);
+            if (head) q[qn + below] = make_uint2(xy_s, z_s | ebin | (extra << 24));
+            qn = __builtin_amdgcn_readfirstlane(qn + __popcll(heads));
         }
         live = live & (st_s < kOccupied);
     };
