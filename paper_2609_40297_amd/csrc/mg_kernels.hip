@@ -72,9 +72,9 @@ __device__ __forceinline__ bool left_of(float2 b, float rx, float ry) { return b
 // numbers of inner boundaries the centre lies at-or-beyond; a table lookup
 // guesses them and the exact boundary comparisons settle them. Those
 // comparisons are monotone along the boundaries, so the settled index is the
-// exact count whatever the guess. The cheap rejections (range, band, wedge)
-// form one mask so that a wave branches once. A lane with act false (no
-// queue entry) gets true, so that its negation keeps nothing.
+// exact count whatever the guess. The cheap rejections come first: the
+// wedge, then range and band as one mask. A lane with act false (no queue
+// entry) gets true, so that its negation keeps nothing.
 __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float cy, float cz, bool act,
                                               const SensorDev& S, const float2* __restrict__ s_bv,
                                               const float* __restrict__ s_ts,
@@ -83,74 +83,78 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
                                               const float* __restrict__ dpan) {
     const float rx = cx - A.qx;
     const float ry = cy - A.qy;
-    const float rz = cz - A.qz;
-    const float rho2 = rx * rx + ry * ry;
-    const float range2 = rho2 + rz * rz;
-    const float sz = rz * fabsf(rz);
     const float w0 = A.b0x * ry - A.b0y * rx;
     const float w1 = A.b1x * ry - A.b1y * rx;
-    const bool inside =
-        act & (range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH) & (w0 >= 0.f) & (w1 < 0.f);
     // The result is one comparison after the lookup (so that a ballot of it
     // takes the comparison's mask as it stands): lanes outside the window, band
-    // or range keep a limit of -1, which no squared range meets; lanes without
-    // an entry (act false) a limit of +inf, which every one meets.
+    // or range keep a limit of -1, which no squared range meets (their range2
+    // is 0 unless computed); lanes without an entry (act false) a limit of
+    // +inf, which every one meets. The wedge is tested first and alone: the
+    // voxels of a chunk often lie outside an ancestor's window together, and
+    // the wave then skips the rest.
     float lim = act ? -1.f : __builtin_inff();
-    if (inside) {
-        // Column: pseudo-angle past the left boundary (monotone in the angle) picks a
-        // table bucket holding at most one column boundary, giving a guess gc. The
-        // boundaries gc, gc + 1 and gc + 2 of the window are read at once (the LDS
-        // table holds the boundaries twice over, so window boundary k is entry
-        // c0 + k). When boundary gc lies at or left of r and gc + 2 does not, the
-        // column is gc + 1 if boundary gc + 1 does and gc otherwise. Other lanes
-        // (rounding at a bucket edge) settle with the boundary-by-boundary walk,
-        // which also returns gc + l1 in the two patterns that break monotonicity
-        // (1-0-1 and 0-1-0).
-        const float u0 = A.b0x * rx + A.b0y * ry;
-        float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
-        pa = u0 < 0.f ? 2.f - pa : pa;
-        const int32_t gc = s_lut_col[(int32_t)fminf(fmaxf(pa * S.lut_col_scale, 0.f), (float)(S.n_lut_col - 1))];
-        const int32_t cb = A.c0 + gc;
-        const float2 v0 = s_bv[cb], v1 = s_bv[cb + 1], v2 = s_bv[cb + 2];
-        const bool l0 = (gc == 0) | left_of(v0, rx, ry);
-        const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
-        const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
-        // (and/or rather than a select, so that all three reads stay unconditional)
-        int32_t col = gc + (int32_t)l1;
-        const bool c_ok = l0 & !l2;
-        if (!c_ok) {      // (a divergent branch: skipped when no lane needs it)
-            for (;;) {
-                if (col + 1 >= S.WB || !left_of(s_bv[A.c0 + col + 1], rx, ry)) break;
-                ++col;
+    float range2 = 0.f;
+    if (act & (w0 >= 0.f) & (w1 < 0.f)) {
+        const float rz = cz - A.qz;
+        const float rho2 = rx * rx + ry * ry;
+        range2 = rho2 + rz * rz;
+        const float sz = rz * fabsf(rz);
+        if ((range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH)) {
+            // Column: pseudo-angle past the left boundary (monotone in the angle) picks a
+            // table bucket holding at most one column boundary, giving a guess gc. The
+            // boundaries gc, gc + 1 and gc + 2 of the window are read at once (the LDS
+            // table holds the boundaries twice over, so window boundary k is entry
+            // c0 + k). When boundary gc lies at or left of r and gc + 2 does not, the
+            // column is gc + 1 if boundary gc + 1 does and gc otherwise. Other lanes
+            // (rounding at a bucket edge) settle with the boundary-by-boundary walk,
+            // which also returns gc + l1 in the two patterns that break monotonicity
+            // (1-0-1 and 0-1-0).
+            const float u0 = A.b0x * rx + A.b0y * ry;
+            float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
+            pa = u0 < 0.f ? 2.f - pa : pa;
+            const int32_t gc = s_lut_col[(int32_t)fminf(fmaxf(pa * S.lut_col_scale, 0.f), (float)(S.n_lut_col - 1))];
+            const int32_t cb = A.c0 + gc;
+            const float2 v0 = s_bv[cb], v1 = s_bv[cb + 1], v2 = s_bv[cb + 2];
+            const bool l0 = (gc == 0) | left_of(v0, rx, ry);
+            const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
+            const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
+            // (and/or rather than a select, so that all three reads stay unconditional)
+            int32_t col = gc + (int32_t)l1;
+            const bool c_ok = l0 & !l2;
+            if (!c_ok) {      // (a divergent branch: skipped when no lane needs it)
+                for (;;) {
+                    if (col + 1 >= S.WB || !left_of(s_bv[A.c0 + col + 1], rx, ry)) break;
+                    ++col;
+                }
+                for (;;) {
+                    if (col == 0 || left_of(s_bv[A.c0 + col], rx, ry)) break;
+                    --col;
+                }
             }
-            for (;;) {
-                if (col == 0 || left_of(s_bv[A.c0 + col], rx, ry)) break;
-                --col;
+            // Row: elevation tangent picks a bucket holding at most one row boundary;
+            // the same three-boundary decision, same fallback.
+            const float tg = rz * __builtin_amdgcn_rsqf(rho2);
+            const int32_t gr = s_lut_row[(int32_t)fminf(fmaxf((tg - S.lut_row_lo) * S.lut_row_scale, 0.f),
+                                                        (float)(S.n_lut_row - 1))];
+            const float e0 = s_ts[gr], e1 = s_ts[gr + 1], e2 = s_ts[min(gr + 2, S.H)];
+            const bool r0 = (gr == 0) | (sz >= rho2 * e0);
+            const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
+            const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
+            int32_t row = gr + (int32_t)r1;
+            const bool r_ok = r0 & !r2;
+            if (!r_ok) {
+                for (;;) {
+                    if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
+                    ++row;
+                }
+                for (;;) {
+                    if (row == 0 || sz >= rho2 * s_ts[row]) break;
+                    --row;
+                }
             }
+            const float D = as_global(dpan)[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
+            lim = D * D;
         }
-        // Row: elevation tangent picks a bucket holding at most one row boundary;
-        // the same three-boundary decision, same fallback.
-        const float tg = rz * __builtin_amdgcn_rsqf(rho2);
-        const int32_t gr = s_lut_row[(int32_t)fminf(fmaxf((tg - S.lut_row_lo) * S.lut_row_scale, 0.f),
-                                                    (float)(S.n_lut_row - 1))];
-        const float e0 = s_ts[gr], e1 = s_ts[gr + 1], e2 = s_ts[min(gr + 2, S.H)];
-        const bool r0 = (gr == 0) | (sz >= rho2 * e0);
-        const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
-        const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
-        int32_t row = gr + (int32_t)r1;
-        const bool r_ok = r0 & !r2;
-        if (!r_ok) {
-            for (;;) {
-                if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
-                ++row;
-            }
-            for (;;) {
-                if (row == 0 || sz >= rho2 * s_ts[row]) break;
-                --row;
-            }
-        }
-        const float D = as_global(dpan)[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
-        lim = D * D;
     }
     return range2 <= lim;
 }
