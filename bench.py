@@ -409,8 +409,8 @@ def serve_bench(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
-        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        print(json.dumps({"error": "this library runs on one GPU only; use --gpus 1"}))
+        log("bench.py: only --gpus 1 is supported (the library runs on one GPU)")
         sys.exit(2)
     if args.copy_probe_mib:
         return copy_probe(args.copy_probe_mib)

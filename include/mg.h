@@ -40,7 +40,7 @@ enum {
     MG_E_NOMEM = -2,        /* device or host allocation failed                 */
     MG_E_DEVICE = -3,       /* a HIP call or a kernel failed                    */
     MG_E_BUSY = -4,         /* the handle is still referenced                   */
-    MG_E_UNSUPPORTED = -5   /* valid input outside the sizes this build handles */
+    MG_E_UNSUPPORTED = -5   /* valid input outside the sizes this library handles */
 };
 
 /* Longest root path of a tree (depth <= 64): the row length of the branch

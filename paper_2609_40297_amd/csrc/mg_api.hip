@@ -92,7 +92,7 @@ int check_sensor(const mg_sensor* s, int32_t* w_out, int32_t* wb_out) {
     if (((long)s->n_az * w) % s->yaw_bins != 0)
         return fail(MG_E_INVALID, "n_az * window_bins must be a multiple of yaw_bins");
     if (s->yaw_bins > kMaxBins || s->n_az > kMaxAz || s->n_el > kMaxEl || (long)s->n_az * s->n_el > (1L << 22))
-        return fail(MG_E_UNSUPPORTED, "sensor larger than this build supports");
+        return fail(MG_E_UNSUPPORTED, "sensor larger than this library supports");
     *w_out = (int32_t)w;
     *wb_out = (int32_t)((long)s->n_az * w / s->yaw_bins);
     return MG_OK;

@@ -104,7 +104,7 @@ def test_occupied_everywhere_and_unknown_everywhere(mg, orc):
 
 
 def test_widest_panorama_or_clean_refusal(mg, orc):
-    """The widest panorama this build accepts (4096 columns): bit-exact if the device's LDS per
+    """The widest panorama the library accepts (4096 columns): bit-exact if the device's LDS per
     workgroup holds its tables, otherwise MG_E_UNSUPPORTED at upload with nothing launched."""
     w = W.make("tiny")
     sen = W.Sensor(n_az=4096, n_el=2, fov_h_deg=90, fov_v_deg=60, range_m=3.0, yaw_bins=64)
