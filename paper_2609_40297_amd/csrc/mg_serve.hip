@@ -299,7 +299,10 @@ int mg_server_s::step() {
     hipError_t e = hipMemcpyAsync(d_trees, h_trees, sizeof(BatchTree) * active.size(), hipMemcpyHostToDevice, compute);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_items, h_items, sizeof(unsigned long long) * n_items, hipMemcpyHostToDevice, compute);
-    if (e == hipSuccess) e = launch_batch_level(d_trees, d_items, (int32_t)n_items, sd, max_anc, compute);
+    // (a level of few nodes keeps two voxels in flight per lane, as in the batch path)
+    const bool ahead = (int64_t)n_items * tiles_per_node(sd, 0) < kAheadWorkgroups;
+    if (e == hipSuccess)
+        e = launch_batch_level(d_trees, d_items, (int32_t)n_items, sd, max_anc, compute, 0, nullptr, nullptr, ahead);
     size_t so = 0;
     std::vector<std::pair<Request*, size_t>> finishing;
     for (Request* r : active) {
