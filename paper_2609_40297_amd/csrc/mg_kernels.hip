@@ -112,7 +112,10 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
             const float u0 = A.b0x * rx + A.b0y * ry;
             float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
             pa = u0 < 0.f ? 2.f - pa : pa;
-            const int32_t gc = s_lut_col[(int32_t)fminf(fmaxf(pa * S.lut_col_scale, 0.f), (float)(S.n_lut_col - 1))];
+            // (pa and tg are finite here: the wedge excludes r = 0 in x and y, so
+            // one median-of-three clamps the table index)
+            const int32_t gc =
+                s_lut_col[(int32_t)__builtin_amdgcn_fmed3f(pa * S.lut_col_scale, 0.f, (float)(S.n_lut_col - 1))];
             const int32_t cb = A.c0 + gc;
             const float2 v0 = s_bv[cb], v1 = s_bv[cb + 1], v2 = s_bv[cb + 2];
             const bool l0 = (gc == 0) | left_of(v0, rx, ry);
@@ -134,8 +137,8 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
             // Row: elevation tangent picks a bucket holding at most one row boundary;
             // the same three-boundary decision, same fallback.
             const float tg = rz * __builtin_amdgcn_rsqf(rho2);
-            const int32_t gr = s_lut_row[(int32_t)fminf(fmaxf((tg - S.lut_row_lo) * S.lut_row_scale, 0.f),
-                                                        (float)(S.n_lut_row - 1))];
+            const int32_t gr = s_lut_row[(int32_t)__builtin_amdgcn_fmed3f((tg - S.lut_row_lo) * S.lut_row_scale, 0.f,
+                                                                          (float)(S.n_lut_row - 1))];
             const float e0 = s_ts[gr], e1 = s_ts[gr + 1], e2 = s_ts[min(gr + 2, S.H)];
             const bool r0 = (gr == 0) | (sz >= rho2 * e0);
             const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
@@ -152,7 +155,9 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
                     --row;
                 }
             }
-            const float D = as_global(dpan)[A.dpan_off + (uint32_t)(wrap(A.c0 + col, S.W) * S.H + row)];
+            // (column < 4096 and H <= 2048: the product fits the 24-bit multiplier)
+            const float D =
+                as_global(dpan)[A.dpan_off + __umul24((uint32_t)wrap(A.c0 + col, S.W), (uint32_t)S.H) + (uint32_t)row];
             lim = D * D;
         }
     }
