@@ -142,19 +142,19 @@ static float t_of_s(const segment* g, float s) {
     return g->tlo + lam * (g->thi - g->tlo);
 }
 
-/* Observed runs in screen parameter s: a run that starts at or before the end
- * of the open one joins it; a closed run is written out as [t(lo), t(hi)]. */
+/* One ancestor's overlap intervals in t, in the order the 2D DDA finds them:
+ * an interval that starts at or before the end of the open one is joined to
+ * it, otherwise the open one is written out and the new one opened. */
 typedef struct {
     float* out;
     int32_t cap, n;
-    float lo, hi;            /* the open run, in s */
-    const segment* g;
+    float lo, hi;            /* the open interval, in t */
 } ivl_list;
 
 static void ivl_emit(ivl_list* L) {
     if (L->n > 0 && L->n - 1 < L->cap) {
-        L->out[2 * (L->n - 1)] = t_of_s(L->g, L->lo);
-        L->out[2 * (L->n - 1) + 1] = t_of_s(L->g, L->hi);
+        L->out[2 * (L->n - 1)] = L->lo;
+        L->out[2 * (L->n - 1) + 1] = L->hi;
     }
 }
 
@@ -169,27 +169,28 @@ static void ivl_push(ivl_list* L, float lo, float hi) {
     L->n++;
 }
 
-int32_t ivlref_intervals(const ivlref_camera* cam, const float qn[3], const float d[3], float tmax,
-                         const float qa[3], int32_t ka, const float* Da, float* out, int32_t cap, uint64_t* steps) {
+int32_t ivlref_intervals(const ivlref_camera* cam, const float qn[3], const float d[3], const float qa[3],
+                         int32_t ka, const float* Da, float* out, int32_t cap, uint64_t* steps) {
     const float c = cam->cs[2 * ka], s = cam->cs[2 * ka + 1];
     const int32_t wd = cam->wd, hd = cam->hd;
     segment g;
-    ivl_list L = {out, cap, 0, 0.0f, 0.0f, &g};
+    ivl_list L = {out, cap, 0, 0.0f, 0.0f};
     if (steps) *steps = 0;
     /* the ray's origin and direction in the ancestor's camera frame */
     const float o[3] = {qn[0] - qa[0], qn[1] - qa[1], qn[2] - qa[2]};
     const float P0[3] = {s * o[0] - c * o[1], -o[2], c * o[0] + s * o[1]};
     const float Dc[3] = {s * d[0] - c * d[1], -d[2], c * d[0] + s * d[1]};
-    /* clip 0 <= t <= tmax to the valid depth range znear <= z <= Rv; z is linear in t */
+    /* the ray r(t), 0 <= t <= Rv (Sec. IV-B), clipped to the valid depth range
+     * znear <= z <= Rv; z is linear in t */
     if (Dc[2] == 0.0f) {
         if (!(P0[2] >= cam->znear && P0[2] <= cam->rv)) return 0;
         g.tlo = 0.0f;
-        g.thi = tmax;
+        g.thi = cam->rv;
     } else {
         float t1 = (cam->znear - P0[2]) / Dc[2], t2 = (cam->rv - P0[2]) / Dc[2];
         float a = t1 < t2 ? t1 : t2, b = t1 < t2 ? t2 : t1;
         g.tlo = a > 0.0f ? a : 0.0f;
-        g.thi = b < tmax ? b : tmax;
+        g.thi = b < cam->rv ? b : cam->rv;
     }
     if (!(g.tlo < g.thi)) return 0;
     float A[3], Bp[3];
@@ -203,7 +204,6 @@ int32_t ivlref_intervals(const ivlref_camera* cam, const float qn[3], const floa
     const float uB = cam->fx * Bp[0] / Bp[2] + cam->cx, vB = cam->fy * Bp[1] / Bp[2] + cam->cy;
     g.wa = 1.0f / A[2];
     g.wb = 1.0f / Bp[2];
-    const float rden = g.wb != g.wa ? 1.0f / (g.wb - g.wa) : 0.0f;
     /* Liang-Barsky: clip the screen segment to 0 <= u <= W_D, 0 <= v <= H_D */
     const float du = uB - uA, dv = vB - vA;
     const float pp[4] = {-du, du, -dv, dv};
@@ -249,11 +249,11 @@ int32_t ivlref_intervals(const ivlref_camera* cam, const float qn[3], const floa
             if (g.wb == g.wa) {
                 ok = g.wa >= wD;
             } else {
-                const float ss = (wD - g.wa) * rden;
+                const float ss = (wD - g.wa) / (g.wb - g.wa);
                 if (g.wb > g.wa) lo = sa > ss ? sa : ss;
                 else hi = e < ss ? e : ss;
             }
-            if (ok && lo <= hi) ivl_push(&L, lo, hi);
+            if (ok && lo <= hi) ivl_push(&L, t_of_s(&g, lo), t_of_s(&g, hi));
         }
         if (!(e < s1)) break;
         if (su <= sv) {
@@ -361,20 +361,15 @@ static int eval_node(ivl_job* J, int32_t n, ivl_work* W, uint32_t* ids, uint8_t*
         for (int j = 0; j < H && rc == 0; ++j) {
             const int r = c * H + j;
             const float* d = s->dir + 3 * r;
-            /* the ray ends at its first hit: only t in [0, h] can matter */
-            float h;
-            int nv = mgref_trace_ray_exit(J->states, J->nx, J->ny, J->nz, qn, d, s->inv + 3 * r, cam->rv, cap, ids,
-                                          st, te, tx, &h);
-            if (nv < 0) { rc = -1; break; }
             int32_t m = 0;
             for (int32_t k = 0; k < na && rc == 0; ++k) {
                 const int32_t a = anc[k];
                 uint64_t steps = 0;
-                int32_t ns = ivlref_intervals(cam, qn, d, h, J->q + 3 * a, J->k_db[a], J->D + (size_t)a * npx, W->S,
+                int32_t ns = ivlref_intervals(cam, qn, d, J->q + 3 * a, J->k_db[a], J->D + (size_t)a * npx, W->S,
                                               W->cap, &steps);
                 if (ns > W->cap) {
                     if (grow(W, ns) != 0) { rc = -1; break; }
-                    ns = ivlref_intervals(cam, qn, d, h, J->q + 3 * a, J->k_db[a], J->D + (size_t)a * npx, W->S,
+                    ns = ivlref_intervals(cam, qn, d, J->q + 3 * a, J->k_db[a], J->D + (size_t)a * npx, W->S,
                                           W->cap, &steps);
                 }
                 cnt->pixel_steps += steps;
@@ -385,6 +380,10 @@ static int eval_node(ivl_job* J, int32_t n, ivl_work* W, uint32_t* ids, uint8_t*
             if (rc != 0) break;
             cnt->intervals += (uint64_t)m;
             if ((uint64_t)m > cnt->max_merged) cnt->max_merged = (uint64_t)m;
+            float h;
+            int nv = mgref_trace_ray_exit(J->states, J->nx, J->ny, J->nz, qn, d, s->inv + 3 * r, cam->rv, cap, ids,
+                                          st, te, tx, &h);
+            if (nv < 0) { rc = -1; break; }
             cnt->visits += (uint64_t)nv;
             for (int v = 0; v < nv; ++v) {
                 if (st[v] != S_UNK) continue;

@@ -11,15 +11,15 @@
  *     voxel, W_D = ceil(2 d_max tan(fov_h/2) / v), H_D likewise with fov_v;
  *     a pixel holds the camera-frame z of the first occupied voxel on the ray
  *     through its centre, or of the ray's end at the range limit;
- *   - a candidate ray r(t) = q_n + t d is taken up to its own first hit
- *     (t <= h; nothing past it is counted, and h <= Rv), moved into each
- *     ancestor's camera frame, clipped to the valid depth range
- *     z_near <= z <= Rv, projected with eq. (5), clipped to the buffer with
- *     the Liang-Barsky algorithm and walked pixel by pixel with a 2D DDA;
- *     inverse depth is interpolated linearly in screen space (eq. 6), the
- *     part of each pixel's span where z <= the stored depth is observed, and
- *     each maximal observed run of screen parameter s is one overlap
- *     interval, mapped back to t (eq. 7);
+ *   - a candidate ray r(t) = q_n + t d, 0 <= t <= Rv (the maximum range in
+ *     voxel units), is moved into each ancestor's camera frame, clipped to
+ *     the valid depth range z_near <= z <= Rv, projected with eq. (5),
+ *     clipped to the buffer with the Liang-Barsky algorithm and walked pixel
+ *     by pixel with a 2D DDA; inverse depth is interpolated linearly in
+ *     screen space (eq. 6), and the part of each pixel's span where z <= the
+ *     stored depth is observed: its two ends, mapped back to t, are an
+ *     overlap interval (eq. 7), joined to the previous one of the same
+ *     ancestor when it starts at or before that one's end;
  *   - the ancestors' intervals are merged one ancestor after another, and the
  *     3D DDA counts an unknown voxel unless the midpoint of its chord lies in
  *     a merged interval.
@@ -74,13 +74,13 @@ int ivlref_render(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, con
                   const float q[3], int32_t k, float* D);
 
 /* Overlap intervals of one ancestor (position qa, window ka, buffer Da) on
- * the candidate ray from qn along the unit direction d, for 0 <= t <= tmax
- * (the ray's first-hit parameter, or Rv): up to cap intervals [lo, hi] in t
- * (voxel units), sorted, touching ones joined, written to out[2*i],
- * out[2*i+1]. Returns their number (which may exceed cap: only the first cap
- * are written). *steps (may be NULL) receives the pixels visited. */
-int32_t ivlref_intervals(const ivlref_camera* cam, const float qn[3], const float d[3], float tmax,
-                         const float qa[3], int32_t ka, const float* Da, float* out, int32_t cap, uint64_t* steps);
+ * the candidate ray from qn along the unit direction d, 0 <= t <= Rv: up to
+ * cap intervals [lo, hi] in t (voxel units), in the order found, touching
+ * ones joined, written to out[2*i], out[2*i+1]. Returns their number (which
+ * may exceed cap: only the first cap are written). *steps (may be NULL)
+ * receives the pixels visited. */
+int32_t ivlref_intervals(const ivlref_camera* cam, const float qn[3], const float d[3], const float qa[3],
+                         int32_t ka, const float* Da, float* out, int32_t cap, uint64_t* steps);
 
 /* Union of two sorted lists of disjoint intervals M [m][2] and S [ns][2] into
  * out [m + ns][2], sorted, overlapping or touching intervals joined. Returns

@@ -41,8 +41,7 @@ def lib():
         L.ivlref_camera_tables.restype = C.c_int
         L.ivlref_render.argtypes = [P, I32, I32, I32, C.POINTER(Camera), P, I32, P]
         L.ivlref_render.restype = C.c_int
-        L.ivlref_intervals.argtypes = [C.POINTER(Camera), P, P, C.c_float, P, I32, P, P, I32,
-                                       C.POINTER(C.c_uint64)]
+        L.ivlref_intervals.argtypes = [C.POINTER(Camera), P, P, P, I32, P, P, I32, C.POINTER(C.c_uint64)]
         L.ivlref_intervals.restype = I32
         L.ivlref_eval_tree.argtypes = [P, I32, I32, I32, C.c_float, P, P, P, I32, C.POINTER(SensorParams),
                                        I32, I32, P, P, P, P, P, P, P, P, C.POINTER(Counters), I32]
@@ -93,16 +92,14 @@ def render(states, cam: CameraHandle, q, k):
     return D
 
 
-def intervals(cam: CameraHandle, qn, d, qa, ka, Da, cap=4096, tmax=None):
-    """Overlap intervals [m, 2] of one ancestor on one candidate ray (0 <= t <= tmax, default Rv), and the
-    pixels visited."""
-    tmax = cam.cam.rv if tmax is None else float(np.float32(tmax))
+def intervals(cam: CameraHandle, qn, d, qa, ka, Da, cap=4096):
+    """Overlap intervals [m, 2] of one ancestor on one candidate ray (0 <= t <= Rv), and the pixels visited."""
     out = np.zeros((cap, 2), np.float32)
     steps = C.c_uint64(0)
     f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     Dd = f(Da)
-    n = lib().ivlref_intervals(C.byref(cam.cam), _p(f(qn)), _p(f(d)), tmax, _p(f(qa)), int(ka), _p(Dd), _p(out),
-                               cap, C.byref(steps))
+    n = lib().ivlref_intervals(C.byref(cam.cam), _p(f(qn)), _p(f(d)), _p(f(qa)), int(ka), _p(Dd), _p(out), cap,
+                               C.byref(steps))
     if n > cap:
         raise ValueError("interval cap too small")
     return out[:n].copy(), int(steps.value)

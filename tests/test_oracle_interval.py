@@ -240,9 +240,8 @@ def _node_counts_from_blocks(m, tree, s, o, nd):
     for r in range(s.n_az * s.n_el):
         c = r // s.n_el
         b = int(t["bins"][c])
-        _, st, te, tx, h = ivl.trace_ray_exit(m.states, q[nd], t["dir"][r], t["inv"][r], rv)
-        lists = [ivl.intervals(cam, q[nd], t["dir"][r], q[a], int(o["k_db"][a]), o["D"][a], tmax=h)[0]
-                 for a in reversed(anc)]
+        lists = [ivl.intervals(cam, q[nd], t["dir"][r], q[a], int(o["k_db"][a]), o["D"][a])[0] for a in reversed(anc)]
+        _, st, te, tx, _ = ivl.trace_ray_exit(m.states, q[nd], t["dir"][r], t["inv"][r], rv)
         for sv, a_, b_ in zip(st, te, tx):
             if sv != W.UNK:
                 continue
