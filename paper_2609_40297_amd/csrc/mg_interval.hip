@@ -5,20 +5,26 @@
 // (Sec. IV-A). A pixel holds the camera-frame z of the first occupied voxel on
 // the ray through its centre, or of the ray's end at the range limit.
 //
-// A candidate ray r(t) = q + t d (one thread per panorama ray) is taken up to
-// its own first hit h <= Rv (nothing past it is counted), moved into every
-// ancestor's camera frame, clipped to the valid depth range z_near <= z <= Rv
-// (z is linear in t), projected with eq. (5), clipped to the buffer with the
-// Liang-Barsky algorithm and walked pixel by pixel with a 2D DDA. Inverse
-// depth is linear in screen space (eq. 6), so the part of a pixel's span where
-// z <= the stored depth is found by solving one linear equation; each maximal
-// observed run of the screen parameter s is one of the ancestor's overlap
-// intervals (eq. 7), mapped back to t perspective-correctly. Intervals of all ancestors are merged
+// A candidate ray r(t) = q + t d, 0 <= t <= Rv (one thread per panorama ray),
+// is moved into every ancestor's camera frame, clipped to the valid depth
+// range z_near <= z <= Rv (z is linear in t), projected with eq. (5), clipped
+// to the buffer with the Liang-Barsky algorithm and walked pixel by pixel with
+// a 2D DDA. Inverse depth is linear in screen space (eq. 6), so the part of a
+// pixel's span where z <= the stored depth is found by solving one linear
+// equation; its two ends, mapped back to t perspective-correctly, are an
+// overlap interval of the ancestor (eq. 7), joined to the previous one when it
+// starts at or before that one's end. Intervals of all ancestors are merged
 // into one sorted list of disjoint intervals per ray. The 3D DDA then counts
 // an unknown voxel towards the absolute bin of the ray's column, and towards
 // the marginal bin unless the midpoint of its chord [t_enter, min(t_exit, Rv)]
 // lies in a merged interval. Window selection reuses the per-level finish
 // kernel; the nodes of the level then render their buffers at the chosen yaw.
+//
+// No voxel past the ray's first hit h is counted, and every counted midpoint
+// is <= h (the last chord before the hit ends at h exactly). An ancestor's
+// intervals start strictly later one after another, so once one starts past h
+// it and all later ones cover no counted midpoint: the walk of that ancestor
+// stops there, which leaves every count as it is.
 //
 // The merged list lives in registers/scratch with room for kIvlCap intervals
 // per ray, as a window of the union: it holds the union's components from t0
@@ -75,13 +81,15 @@ __device__ __forceinline__ float t_of_s(float s, float wa, float wb, float tlo, 
     return tlo + lam * (thi - tlo);
 }
 
-// Overlap intervals of ancestor A on the ray from qn along d, 0 <= t <= tmax,
-// in increasing t: observed runs of s (a run starting at or before the end of
-// the open one joins it), each mapped to [t(lo), t(hi)] when it closes and
-// given to sink(lo, hi); a sink returning true stops the walk (and this
-// function returns true).
+// Overlap intervals of ancestor A on the ray from qn along d, 0 <= t <= Rv,
+// in the order the 2D DDA finds them: each pixel's observed span [lo, hi] in s
+// is mapped to [t(lo), t(hi)]; it joins the open interval when t(lo) <= the
+// open one's end, otherwise the open one goes to sink(lo, hi) and the new one
+// is opened. The walk ends early once the open interval starts past tstop
+// (the ray's first hit) or a sink returns true (then this function returns
+// true).
 template <class Sink>
-__device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float dx, float dy, float dz, float tmax,
+__device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float dx, float dy, float dz, float tstop,
                               const Anc& A, Sink& sink) {
     const float c = A.c, s = A.s;
     const float ox = qx - A.qx, oy = qy - A.qy, oz = qz - A.qz;
@@ -91,12 +99,12 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
     if (Dz == 0.0f) {
         if (!(P0z >= C.znear && P0z <= C.rv)) return false;
         tlo = 0.0f;
-        thi = tmax;
+        thi = C.rv;
     } else {
         const float t1 = (C.znear - P0z) / Dz, t2 = (C.rv - P0z) / Dz;
         const float a = t1 < t2 ? t1 : t2, b = t1 < t2 ? t2 : t1;
         tlo = a > 0.0f ? a : 0.0f;
-        thi = b < tmax ? b : tmax;
+        thi = b < C.rv ? b : C.rv;
     }
     if (!(tlo < thi)) return false;
     const float Ax = P0x + tlo * Dx, Ay = P0y + tlo * Dy, Az = P0z + tlo * Dz;
@@ -105,7 +113,7 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
     const float uA = C.fx * Ax / Az + C.cx, vA = C.fy * Ay / Az + C.cy;
     const float uB = C.fx * Bx / Bz + C.cx, vB = C.fy * By / Bz + C.cy;
     const float wa = 1.0f / Az, wb = 1.0f / Bz;
-    const float rden = wb != wa ? 1.0f / (wb - wa) : 0.0f;
+    const float dw = wb - wa;
     // Liang-Barsky against u >= 0, u <= W_D, v >= 0, v <= H_D
     const float du = uB - uA, dv = vB - vA;
     const float pp[4] = {-du, du, -dv, dv};
@@ -136,7 +144,7 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
     float sv = sj ? ((float)bv - vA) * iv : inf;
     float sa = s0;
     const float* __restrict__ Wa = C.winv + (size_t)A.node * (size_t)C.npx;
-    float olo = 0.0f, ohi = 0.0f;
+    float olo = 0.0f, ohi = 0.0f;             // the open interval, in t
     bool open = false;
     int32_t off = j * C.wd + i;               // the pixel's offset, kept up to date by the steps
     const int32_t voff = sj * C.wd;
@@ -151,18 +159,23 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
         const int32_t noff = more ? off + (stepu ? si : voff) : off;
         const float wN = Wa[noff];
         // the part [lo, hi] of [sa, e] where w(s) >= 1/D, i.e. z(s) <= D (w is
-        // linear in s; with w constant the whole span or nothing)
-        const float ss = (wD - wa) * rden;
-        const float lo = wb > wa ? (sa > ss ? sa : ss) : sa;
-        const float hi = wb < wa ? (e < ss ? e : ss) : e;
-        const bool ok = (wD > 0.0f) & ((wb != wa) | (wa >= wD)) & (lo <= hi);
-        const bool join = ok & open & (lo <= ohi);     // continues the open run
-        ohi = join ? (hi > ohi ? hi : ohi) : ohi;
-        if (ok & !join) {                              // a new run: the open one is finished
-            if (open && sink(t_of_s(olo, wa, wb, tlo, thi), t_of_s(ohi, wa, wb, tlo, thi))) return true;
-            olo = lo;
-            ohi = hi;
-            open = true;
+        // linear in s, eq. 6; with w constant the whole span or nothing)
+        if (wD > 0.0f) {
+            const float ss = (wD - wa) / dw;
+            const float lo = wb > wa ? (sa > ss ? sa : ss) : sa;
+            const float hi = wb < wa ? (e < ss ? e : ss) : e;
+            if (((wb != wa) | (wa >= wD)) & (lo <= hi)) {
+                const float tl = t_of_s(lo, wa, wb, tlo, thi), th = t_of_s(hi, wa, wb, tlo, thi);
+                if (open & (tl <= ohi)) {
+                    ohi = th > ohi ? th : ohi;
+                } else {
+                    if (open && sink(olo, ohi)) return true;
+                    if (tl > tstop) return false;     // this and every later interval start past tstop
+                    olo = tl;
+                    ohi = th;
+                    open = true;
+                }
+            }
         }
         if (!more) break;
         i = ni;
@@ -178,7 +191,7 @@ __device__ bool anc_intervals(const Cam& C, float qx, float qy, float qz, float 
         sa = e;
         wD = wN;
     }
-    return open ? sink(t_of_s(olo, wa, wb, tlo, thi), t_of_s(ohi, wa, wb, tlo, thi)) : false;
+    return open ? sink(olo, ohi) : false;
 }
 
 // Window of the union of intervals: its components that reach t0 or later,
