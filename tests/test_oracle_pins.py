@@ -551,3 +551,85 @@ def test_exact_marginal_argmax_and_consistency():
             kk[nd] = k
             sums.append(int(mg.exact(m, tree, s, kk, o["D"])["X_ray"][nd]))
         assert max(sums) == e["g_ex"][nd] and int(np.argmax(sums)) == e["k_ex"][nd], nd
+
+
+# ----------------------------------------------------------------- exact quantities (eq. 2)
+
+def _brute_exact(m, tree, sen, mg, k_db, D):
+    """X_ray, X_set, A_set and G_db_set of every node from fp64 slab-test ray sets and fp64
+    (atan2) pixel cells, at the given windows and ancestor buffers, with Python sets. Returns the
+    four arrays and a per-node flag: some decision of the node or of its ancestors lies within
+    rounding distance of a boundary."""
+    t = mg.sensor_tables(sen)
+    st = m.states
+    flat = st.reshape(-1)
+    nz_, ny_, nx_ = st.shape
+    n = tree.n
+    H, Wp, wb = sen.n_el, sen.n_az, sen.w_buf
+    rv = float(np.float32(np.float32(sen.range_m) / np.float32(m.voxel_m)))
+    q = ((tree.pos_m - m.origin_m) / np.float32(m.voxel_m)).astype(np.float32)
+    rays, sets, amb = [], [], np.zeros(n, bool)
+    for nd in range(n):                      # I_ray(n, c, j) for the window's rays, and I(n)
+        c0 = int(t["c0"][int(k_db[nd])])
+        per_ray = []
+        for i in range(wb):
+            c = (c0 + i) % Wp
+            for j in range(H):
+                must, may, _, _, _ = brute.ray_reference(st, q[nd], t["dir"][c * H + j], rv)
+                mu = {v for v in must if flat[v] == W.UNK}
+                if mu != {v for v in may if flat[v] == W.UNK}:
+                    amb[nd] = True
+                per_ray.append(mu)
+        rays.append(per_ray)
+        sets.append(set().union(*per_ray))
+    out = {k: np.zeros(n, np.int64) for k in ("X_ray", "X_set", "A_set", "G_db_set")}
+    flag = np.zeros(n, bool)
+    for nd in range(n):
+        anc = []
+        a = int(tree.parent[nd])
+        while a >= 0:
+            anc.append(a)
+            a = int(tree.parent[a])
+        flag[nd] = amb[nd] or any(amb[a] for a in anc)
+        union = set().union(*[sets[a] for a in anc]) if anc else set()
+        out["A_set"][nd] = len(sets[nd])
+        out["X_set"][nd] = len(sets[nd] - union)
+        out["X_ray"][nd] = sum(len(r - union) for r in rays[nd])
+        g = 0
+        for vid in sets[nd]:
+            ix, iy, iz = vid % nx_, (vid // nx_) % ny_, vid // (nx_ * ny_)
+            seen = False
+            for a in anc:
+                ok, oamb = brute.observed(sen, q[a], int(t["c0"][int(k_db[a])]), D[a], ix, iy, iz)
+                flag[nd] |= oamb
+                if ok:
+                    seen = True
+                    break
+            g += 0 if seen else 1
+        out["G_db_set"][nd] = g
+    return out, flag
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_exact_quantities_bruteforce(seed):
+    """Eq. (2) at fixed windows (Sec. V-A protocol): every exact output of the oracle against Python
+    sets built from the slab-test references; once at the oracle's own windows and buffers, once at
+    seeded random windows with random buffers (so that ancestors observe part of their frustum)."""
+    mg = _mg()
+    m, tree, sen = W.random_micro(300 + seed, dims=(11, 10, 7), n_nodes=7, max_depth=4, n_az=16, n_el=4,
+                                  range_vox=6.0, yaw_bins=8, p_occ=0.05, p_free=0.35)
+    o = mg.eval_tree(m, tree, sen)
+    rng = np.random.default_rng(seed)
+    rv = np.float32(sen.range_m) / np.float32(m.voxel_m)
+    cases = [(o["k_db"], o["D"]),
+             (rng.integers(0, sen.yaw_bins, tree.n).astype(np.int32),
+              (rng.random(o["D"].shape) * rv).astype(np.float32))]
+    for k_db, D in cases:
+        e = mg.exact(m, tree, sen, k_db, D)
+        b, flag = _brute_exact(m, tree, sen, mg, k_db, D)
+        cmp = np.flatnonzero(~flag)
+        assert cmp.size >= tree.n - 2, (seed, flag)
+        for key in ("A_set", "X_set", "X_ray", "G_db_set"):
+            assert np.array_equal(e[key][cmp].astype(np.int64), b[key][cmp]), (seed, key, e[key], b[key])
+        deep = [nd for nd in cmp if tree.depth()[nd] >= 2]
+        assert deep, "the case needs nodes with two or more ancestors"
