@@ -83,7 +83,9 @@ typedef struct {
 int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int32_t nz, float voxel_m,
                   const float origin_m[3], void* hip_stream, mg_map* out);
 
-/* Frees the map. MG_E_BUSY while trees created on it still exist. */
+/* Frees the map. MG_E_BUSY while trees created on it still exist, or while
+ * server requests or map updates submitted on it (mg_server_submit,
+ * mg_server_map_update) have not finished. */
 int mg_map_destroy(mg_map map);
 
 /* Map from a truncated signed distance field (the planners' volumetric map,

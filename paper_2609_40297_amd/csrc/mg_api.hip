@@ -490,7 +490,8 @@ extern "C" int mg_map_read(mg_map map, void* hip_stream, uint8_t* states) {
 
 extern "C" int mg_map_destroy(mg_map map) {
     if (!map) return fail(MG_E_INVALID, "map is NULL");
-    if (map->trees.load() != 0) return fail(MG_E_BUSY, "%d trees still use this map", map->trees.load());
+    if (map->trees.load() != 0)
+        return fail(MG_E_BUSY, "%d trees or server requests still use this map", map->trees.load());
     (void)hipFree(map->bricks);
     delete map;
     return MG_OK;
@@ -827,5 +828,6 @@ int tree_view(mg_tree t, TreeView* v) {
 }
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 const mgk::MapDev* map_dev(mg_map m) { return &m->dev; }
+void map_ref(mg_map m, int delta) { m->trees += delta; }
 size_t map_voxel_count(mg_map m) { return (size_t)m->dev.nx * m->dev.ny * m->dev.nz; }
 }  // namespace mgb

@@ -25,6 +25,7 @@ struct TreeView {
 int tree_view(mg_tree t, TreeView* v);     // mg_api.hip
 const mgk::MapDev* map_dev(mg_map m);      // mg_api.hip
 size_t map_voxel_count(mg_map m);          // mg_api.hip
+void map_ref(mg_map m, int delta);         // mg_api.hip: holders that keep mg_map_destroy from freeing m
 int set_error(int code, const char* msg);  // mg_api.hip
 
 // Tree uploads into memory the caller provides (mg_api.hip), for the server's arena.

@@ -98,8 +98,23 @@ struct Request {
     int32_t level = 0, levels = 0;
     int rc = MG_OK;
     int state = 0;                   // 0 queued, 1 in flight, 2 done (rc tells success)
+    bool holds_map = false;          // a reference on `map` (mg_map_destroy answers MG_E_BUSY meanwhile)
+    void hold_map(mg_map m) {
+        map = m;
+        mgb::map_ref(m, 1);
+        holds_map = true;
+    }
+    // Done (rc tells success): the map is no longer used by this request.
+    void finish(int code) {
+        rc = code;
+        state = 2;
+        t_done = Clock::now();
+        if (holds_map) mgb::map_ref(map, -1);
+        holds_map = false;
+    }
     ~Request() {
         if (host) mgb::free_host_tree(host);
+        if (holds_map) mgb::map_ref(map, -1);
     }
 };
 
@@ -225,9 +240,7 @@ int mg_server_s::step() {
             std::lock_guard<std::mutex> lk(mu);
             r->upd_ids = std::vector<uint32_t>();
             r->upd_states = std::vector<uint8_t>();
-            r->rc = urc;
-            r->state = 2;
-            r->t_done = Clock::now();
+            r->finish(urc);
             cv_done.notify_all();
             if (urc != MG_OK) return urc;
             continue;
@@ -244,9 +257,7 @@ int mg_server_s::step() {
         std::lock_guard<std::mutex> lk(mu);
         if (rc != MG_OK) {
             arena.release(r->arena_off, r->bytes);
-            r->rc = rc;
-            r->state = 2;
-            r->t_done = Clock::now();
+            r->finish(rc);
             cv_done.notify_all();
             continue;
         }
@@ -331,9 +342,7 @@ int mg_server_s::step() {
     for (auto& f : finishing) {
         Request* r = f.first;
         arena.release(r->arena_off, r->bytes);
-        r->rc = MG_OK;
-        r->state = 2;
-        r->t_done = Clock::now();
+        r->finish(MG_OK);
         rays_done += (double)r->n * cfg.sensor.n_az * cfg.sensor.n_el;
         ++completed;
         inflight.erase(std::find(inflight.begin(), inflight.end(), r));
@@ -356,8 +365,8 @@ void mg_server_s::run() {
             std::lock_guard<std::mutex> lk(mu);
             fatal = rc;
             fatal_msg = mg_last_error();
-            for (Request* r : inflight) { r->rc = rc; r->state = 2; r->t_done = Clock::now(); }
-            for (Request* r : queue) { r->rc = rc; r->state = 2; r->t_done = Clock::now(); }
+            for (Request* r : inflight) r->finish(rc);
+            for (Request* r : queue) r->finish(rc);
             inflight.clear();
             queue.clear();
             cv_done.notify_all();
@@ -406,7 +415,6 @@ extern "C" int mg_server_submit(mg_server s, mg_map map, const float* pos_m, con
     r->bytes = mgb::block_bytes(*r->host);
     if (r->bytes > s->arena.size())
         return mgb::set_error(MG_E_NOMEM, "the tree needs more device memory than the server's whole arena");
-    r->map = map;
     r->n = n;
     r->out_gain = gain;
     r->out_yaw = yaw_bin;
@@ -414,6 +422,7 @@ extern "C" int mg_server_submit(mg_server s, mg_map map, const float* pos_m, con
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->fatal != MG_OK) return mgb::set_error(s->fatal, s->fatal_msg.c_str());
     if (s->stop) return mgb::set_error(MG_E_BUSY, "server is shutting down");
+    r->hold_map(map);
     r->ticket = s->next_ticket++;
     *ticket = r->ticket;
     s->queue.push_back(r.get());
@@ -422,9 +431,12 @@ extern "C" int mg_server_submit(mg_server s, mg_map map, const float* pos_m, con
     return MG_OK;
 }
 
+// Retires a finished ticket (the caller holds s->mu). MG_E_INVALID when the
+// ticket is unknown, e.g. retired meanwhile by another caller.
 static int finish_ticket(mg_server s, std::unique_lock<std::mutex>& lk, int64_t ticket, int32_t* status,
                          double* latency_us) {
     auto it = s->all.find(ticket);
+    if (it == s->all.end()) return mgb::set_error(MG_E_INVALID, "unknown ticket (retired by another caller)");
     Request* r = it->second.get();
     if (latency_us) latency_us[0] = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
     const int rc = r->rc;
@@ -445,13 +457,13 @@ extern "C" int mg_server_map_update(mg_server s, mg_map map, const uint32_t* vox
     std::unique_ptr<Request> r(new (std::nothrow) Request());
     if (!r) return mgb::set_error(MG_E_NOMEM, "host allocation failed");
     r->kind = 1;
-    r->map = map;
     r->upd_ids.assign(voxel_ids, voxel_ids + count);
     r->upd_states.assign(states, states + count);
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->fatal != MG_OK) return mgb::set_error(s->fatal, s->fatal_msg.c_str());
     if (s->stop) return mgb::set_error(MG_E_BUSY, "server is shutting down");
+    r->hold_map(map);
     r->ticket = s->next_ticket++;
     *ticket = r->ticket;
     s->queue.push_back(r.get());
@@ -469,18 +481,21 @@ extern "C" int mg_server_poll(mg_server s, int64_t ticket, int32_t* status, doub
         *status = 0;
         return MG_OK;
     }
-    finish_ticket(s, lk, ticket, status, latency_us);
-    return MG_OK;
+    const int rc = finish_ticket(s, lk, ticket, status, latency_us);
+    return rc == MG_E_INVALID ? rc : MG_OK;
 }
 
 extern "C" int mg_server_wait(mg_server s, int64_t ticket, double* latency_us) {
     if (!s) return mgb::set_error(MG_E_INVALID, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->all.find(ticket);
-    if (it == s->all.end()) return mgb::set_error(MG_E_INVALID, "unknown ticket");
-    Request* r = it->second.get();
-    s->cv_done.wait(lk, [&] { return r->state == 2; });
+    if (s->all.find(ticket) == s->all.end()) return mgb::set_error(MG_E_INVALID, "unknown ticket");
+    // the ticket is looked up again on every wake-up: another caller may retire it meanwhile
+    s->cv_done.wait(lk, [&] {
+        auto it = s->all.find(ticket);
+        return it == s->all.end() || it->second->state == 2;
+    });
     const int rc = finish_ticket(s, lk, ticket, nullptr, latency_us);
+    if (rc == MG_E_INVALID) return rc;
     if (rc != MG_OK) return mgb::set_error(rc, "request failed");
     return MG_OK;
 }

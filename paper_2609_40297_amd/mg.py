@@ -29,8 +29,6 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait", "mg_server_stats",
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
-                     "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update",
-                     "mg_map_read", "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal",
            "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read",
            "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal")
 
@@ -493,7 +491,7 @@ class Server:
         _check(lib().mg_server_poll(C.c_void_p(self.handle), C.c_int64(ticket), C.byref(st), C.byref(lat)))
         if st.value == 0:
             return None
-        g, y = self._keep.pop(ticket)
+        g, y = self._keep.pop(ticket, (None, None))
         if st.value < 0:
             raise MGError(st.value, "request failed")
         return g, y, lat.value
@@ -501,7 +499,7 @@ class Server:
     def wait(self, ticket: int):
         lat = C.c_double()
         rc = lib().mg_server_wait(C.c_void_p(self.handle), C.c_int64(ticket), C.byref(lat))
-        g, y = self._keep.pop(ticket)
+        g, y = self._keep.pop(ticket, (None, None))    # (an unknown ticket fails in _check)
         _check(rc)
         return g, y, lat.value
 

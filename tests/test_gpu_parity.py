@@ -269,3 +269,42 @@ def test_errors_from_device_api(mg):
     assert T.footprint_bytes > T.n * w.sensor.rays * 4
     T.close()
     M.close()
+
+
+def _oracle_chains(orc, jobs):
+    """Oracle on several (map, tree, sensor, mask) jobs at once: one host thread per job (the
+    library releases the interpreter lock), each job's levels evaluated serially."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads()) as ex:
+        return list(ex.map(lambda j: orc.eval_tree(j[0], j[1], j[2], mask=j[3], n_threads=1), jobs))
+
+
+def test_batch64_full_call_against_oracle(mg, orc):
+    """The 64-tree workload as it is benchmarked: all 64 trees (29 k nodes) in one
+    mg_eval_marginal_batch call (autotuned launch shape, stream groups). In every tree the ancestor
+    chain of one deepest leaf is compared with the oracle: gains, windows and depth buffers."""
+    import torch
+    w = W.make("batch64")
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    trees = [mg.Tree(M, t.pos_m, t.parent, w.sensor) for t in w.trees]
+    log(f"[parity] batch64 full: {len(trees)} trees, {sum(t.n for t in trees)} nodes in one call")
+    gb, yb, db = mg.eval_batch(trees, depth=True)
+    torch.cuda.synchronize()
+    gb, yb = mg.as_u32(gb), yb.cpu().numpy()
+    db = db.cpu().numpy().reshape(-1, w.sensor.n_el, w.sensor.w_buf)
+    jobs, offs = [], []
+    off = 0
+    for t in w.trees:
+        dep = t.depth()
+        leaf = int(np.flatnonzero(dep == dep.max())[0])
+        jobs.append((w.map, t, w.sensor, orc.ancestor_closure(t.parent, [leaf])))
+        offs.append(off)
+        off += t.n
+    log(f"[parity] batch64 full: oracle on {sum(int(j[3].sum()) for j in jobs)} chain nodes")
+    refs = _oracle_chains(orc, jobs)
+    for i, (t, ref, o) in enumerate(zip(w.trees, refs, offs)):
+        got = dict(g_db=gb[o:o + t.n], k_db=yb[o:o + t.n], D=db[o:o + t.n])
+        assert_same(got, ref, nodes=np.flatnonzero(jobs[i][3]))
+    for T in trees:
+        T.close()
+    M.close()

@@ -168,3 +168,61 @@ def test_map_updates_are_ordered_with_requests(mg):
         S.map_update(Ms, np.array([st0.size], np.uint32), np.array([1], np.uint8))
     S.close()
     Ms.close()
+
+
+def test_served_robot_maps_against_oracle(mg):
+    """The serving workload's own requests (robot maps at 0.05, 0.1 and 0.2 m, trees of 167-1751
+    nodes, depth 3-10) submitted together to a 16-slot server; in each request the ancestor chains of
+    two deepest leaves are compared with the oracle (gains and windows)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import mgref
+    from tests.gpu_util import threads
+    reqs = W.serve_requests(64)
+    pick = [0, 1, 2, 3, 5, 6]                  # voxel sizes 0.1, 0.05, 0.05, 0.1, 0.2, 0.2
+    robots = sorted({reqs[i][1] for i in pick})
+    maps = {r: W.make_robot(r) for r in robots}
+    assert {maps[reqs[i][1]][0].voxel_m for i in pick} == {0.05, 0.1, 0.2}
+    sen = W.Sensor(**W.SENSOR_STEP)
+    trees = [W.make_rrt(reqs[i][2], maps[reqs[i][1]][0], maps[reqs[i][1]][1][-1], reqs[i][3], reqs[i][4])
+             for i in pick]
+    dev = {r: mg.Map(maps[r][0].states, maps[r][0].voxel_m, maps[r][0].origin_m) for r in robots}
+    log(f"[serve] oracle parity: {len(pick)} requests, nodes {[t.n for t in trees]}")
+    S = mg.Server(sen, max_inflight=16, arena_bytes=16 << 30)
+    tickets = [S.submit(dev[reqs[i][1]], t.pos_m, t.parent) for i, t in zip(pick, trees)]
+    got = [S.wait(tk)[:2] for tk in tickets]
+    S.close()
+    jobs = []
+    for i, t in zip(pick, trees):
+        dep = t.depth()
+        leaves = np.flatnonzero(dep == dep.max())[:2]
+        jobs.append((maps[reqs[i][1]][0], t, mgref.ancestor_closure(t.parent, leaves)))
+    with ThreadPoolExecutor(max_workers=threads()) as ex:
+        refs = list(ex.map(lambda j: mgref.eval_tree(j[0], j[1], sen, mask=j[2], n_threads=1), jobs))
+    for (g, y), ref, (_, _, mask) in zip(got, refs, jobs):
+        sel = np.flatnonzero(mask)
+        assert np.array_equal(g[sel].astype(np.int64), ref["g_db"][sel].astype(np.int64))
+        assert np.array_equal(y[sel], ref["k_db"][sel])
+    for M in dev.values():
+        M.close()
+
+
+def test_map_held_by_pending_requests(mg):
+    """A map with queued or in-flight server work refuses to be destroyed (MG_E_BUSY) until that work
+    has finished; a ticket retired by one caller is unknown to the next."""
+    w = W.make("tiny")
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    S = mg.Server(w.sensor, max_inflight=2, arena_bytes=1 << 30)
+    t = w.trees[0]
+    tickets = [S.submit(M, t.pos_m, t.parent) for _ in range(3)]
+    upd = S.map_update(M, np.array([0], np.uint32), np.array([w.map.states.reshape(-1)[0]], np.uint8))
+    with pytest.raises(mg.MGError) as e:
+        M.close()
+    assert e.value.code == mg.MG_E_BUSY
+    for tk in tickets:
+        S.wait(tk)
+    S.wait(upd)
+    with pytest.raises(mg.MGError) as e:
+        S.wait(tickets[0])
+    assert e.value.code == mg.MG_E_INVALID
+    S.close()
+    M.close()
