@@ -2,20 +2,28 @@
 """Benchmark: marginal-gain rays/s and replan p50/p99 latency, batched vs plain, one MI355X.
 
 One step = one replanning request: every node of the workload's tree(s) is
-evaluated (absolute and depth-buffer marginal gain, yaw window, depth buffer)
-and the gains and yaw windows are copied back to host memory. Inputs (map and
-trees) are resident on the GPU before the timed region starts.
+evaluated (depth-buffer marginal gain, yaw window, depth buffer) and the gains
+and yaw windows are copied back to host memory. Inputs (map and trees) are
+resident on the GPU before the timed region starts.
+
+Workloads (seeded, synthetic): `large` (default, the headline: 8 trees of 3000
+nodes on a 512x512x128 grid at 0.05 m, 720x120 rays, 15 m), `step`, `batch64`,
+`tiny`, and `serve16` (its own serving line). With the default headline the
+line also carries `step` and `batch64` as extra keys, and the next-row paths
+(single-parent gain, interval mode, exact hash sets, path score, map
+conversion) timed on `step`.
 
 Modes
-  plain    paper-style (Sec. IV-C): one launch pair per depth level, stream
-           synchronised and gains/yaws copied to the host after every level.
+  plain    paper-style (Sec. IV-C): tree after tree, one launch group per depth
+           level, stream synchronised and gains/yaws copied to the host after
+           every level.
   batched  the whole request in one call (mg_eval_marginal_batch), one copy
            of the results at the end.
 `value` is the batched mode's rays/s; the plain mode is reported beside it.
 
 Prints ONE JSON line (rank 0, N = 1). Extra fields: latency percentiles,
-the roofline of the dominant kernel and the oracle's CPU rate on a bounded
-sample (the oracle is used only in that leg).
+the roofline of the marginal-gain kernels (trace and path-mask builder) and
+the oracle's CPU rate on a bounded sample (the oracle is used only in that leg).
 """
 from __future__ import annotations
 
@@ -125,9 +133,12 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="step", choices=["tiny", "step", "batch64", "large", "serve16"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large", choices=["tiny", "step", "batch64", "large", "serve16"])
+    ap.add_argument("--extras", default=None,
+                    help="comma-separated extra workloads timed in the same line (default: step,batch64 with "
+                         "the large headline, none otherwise; 'none' skips them)")
     ap.add_argument("--requests", type=int, default=64, help="serve16: number of replanning requests")
     ap.add_argument("--trees", type=int, default=None, help="keep only the first trees of a multi-tree workload")
     ap.add_argument("--modes", default="plain,batched")
@@ -139,7 +150,8 @@ def parse():
                     help="only run the map conversion / update timing (3 calls each) and exit")
     ap.add_argument("--no-map-bench", dest="map_bench", action="store_false",
                     help="skip the map conversion / update timing")
-    ap.add_argument("--cpu-sample-rays", type=float, default=1.5e6, help="oracle sample, rays per host thread")
+    ap.add_argument("--cpu-sample-rays", type=float, default=None,
+                    help="oracle sample, rays per host thread (default: 1.5e6, 0.5e6 on large)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -216,6 +228,20 @@ def cpu_threads():
     return max(1, min(16, n))
 
 
+def cpu_model():
+    """The host CPU's model name and logical CPU count (as the OS reports them)."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    name = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count() or 1
+
+
 def cpu_baseline(w, target_rays_per_thread):
     """The oracle as it stands, with its threaded driver (nodes of a level in parallel), on an
     ancestor-closed set of deepest leaves of tree 0 (the whole tree if the target exceeds it)."""
@@ -237,8 +263,10 @@ def cpu_baseline(w, target_rays_per_thread):
     dt = time.perf_counter() - t0
     rays = int(mask.sum()) * w.sensor.rays
     what = "all nodes of tree 0" if mask.all() else f"{len(leaves)} deepest leaves of tree 0 and their ancestors"
+    model, nproc = cpu_model()
     return {"value": rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{int(mask.sum())} nodes ({what}), {rays} rays, {dt:.1f} s on {threads} threads"}
+            "sample": f"{int(mask.sum())} nodes ({what}), {rays} rays, {dt:.1f} s on {threads} threads",
+            "cpu_model": model, "nproc": nproc}
 
 
 def next_row_oracles(w, threads):
@@ -406,35 +434,40 @@ def serve_bench(args):
         m.close()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this library runs on one GPU only; use --gpus 1"}))
-        log("bench.py: only --gpus 1 is supported (the library runs on one GPU)")
-        sys.exit(2)
-    if args.copy_probe_mib:
-        return copy_probe(args.copy_probe_mib)
-    if args.map_bench_only:
-        import torch
-        from paper_2609_40297_amd import mg
-        torch.cuda.set_device(0)
-        print(json.dumps({"maps": map_bench(mg, reps=3)}), flush=True)
-        return
-    if args.workload == "serve16":
-        return serve_bench(args)
-    import torch
-    from paper_2609_40297_amd import mg, workloads as W
+def roofline_of(wc, trace, steps, n_total, yaw_bins, ms_per_step, sources_ok):
+    """Roofline of the marginal-gain kernels (trace + path-mask builder) from the oracle's work counts
+    and the live launch intervals, or None when either is missing."""
+    if wc is None or not trace or not trace["launches"]:
+        return None
+    # algorithmic bytes of the path, per step: 1 B per voxel visit (grid gather), 4 B per ancestor depth
+    # read (ancestor tests, parent first, to the first that observes), 4 B per ray (first-hit write),
+    # 2 x B x 4 B of bin counts per node
+    alg_step = wc["visits"] * 1 + wc["anc_tests"] * 4 + wc["rays"] * 4 + n_total * 2 * yaw_bins * 4
+    busy = trace["busy_ms"] / steps                 # union of the trace and builder launch intervals
+    summed = trace["total_ms"] / steps              # their summed durations (groups overlap on two streams)
+    achieved = alg_step / (busy * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": sources_ok,
+            "kernels": ["k_trace_multi", "k_mask_build_multi"],
+            "algorithmic_bytes_per_step": alg_step,
+            "busy_ms_per_step": busy, "summed_launch_ms_per_step": summed,
+            "launches_per_step": trace["launches"] / steps,
+            "achieved_over_summed_launches": alg_step / (summed * 1e-3) / 1e9,
+            "achieved_over_whole_step": alg_step / (ms_per_step * 1e-3) / 1e9,
+            "timing": "HIP events recorded by each trace and mask-builder dispatch over the timed steps; "
+                      "achieved = algorithmic bytes per step / union of those launch intervals per step"}
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    mg.lib()
-    log(f"[bench] generating workload {args.workload}")
-    w = W.make(args.workload, n_trees=args.trees)
+
+def measure(mg, W, name, steps, warmup, modes, n_trees=None):
+    """Times one workload: plain (tree after tree, per-level sync) and batched (one call) steps.
+    Returns a dict with the results and the objects the next-row legs reuse."""
+    import torch
+    log(f"[bench] generating workload {name}")
+    w = W.make(name, n_trees=n_trees)
     sen = w.sensor
     n_total = sum(t.n for t in w.trees)
     rays_per_step = n_total * sen.rays
-    log(f"[bench] {len(w.trees)} trees, {n_total} nodes, {rays_per_step} rays per step")
-
+    log(f"[bench] {name}: {len(w.trees)} trees, {n_total} nodes, {rays_per_step} rays per step")
     stream = torch.cuda.current_stream()
     M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
     trees = [mg.Tree(M, t.pos_m, t.parent, sen) for t in w.trees]
@@ -465,19 +498,19 @@ def main():
 
     results = {}
     trace = None
-    for mode in args.modes.split(","):
+    for mode in modes:
         fn = {"plain": step_plain, "batched": step_batched}[mode]
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         kernel_ms.clear()
         lat = []
-        if mode == "batched":     # trace-kernel launches timed by events their own dispatches record
+        if mode == "batched":     # trace and builder launches timed by events their own dispatches record
             mg.mg_timing_read()
             mg.mg_timing_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             s0 = time.perf_counter()
             fn()
             lat.append((time.perf_counter() - s0) * 1e3)
@@ -487,11 +520,10 @@ def main():
             t_ms, t_busy, t_n, t_wg = mg.mg_timing_read()
             mg.mg_timing_enable(False)
             trace = dict(total_ms=t_ms, busy_ms=t_busy, launches=t_n, workgroups=t_wg)
-        results[mode] = dict(rays_per_s=rays_per_step * args.steps / total, ms_per_step=total * 1e3 / args.steps,
+        results[mode] = dict(rays_per_s=rays_per_step * steps / total, ms_per_step=total * 1e3 / steps,
                              p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                              kernel_ms=float(np.mean(kernel_ms)) if kernel_ms else None)
-        log(f"[bench] {mode}: {results[mode]}")
-
+        log(f"[bench] {name} {mode}: {results[mode]}")
     # parity of the two modes on this workload (identical results required)
     if "plain" in results and "batched" in results:
         off = 0
@@ -499,35 +531,31 @@ def main():
             assert np.array_equal(hg, host_g.numpy()[off:off + t.n].view(np.uint32)), "plain and batched differ"
             assert np.array_equal(hy, host_y.numpy()[off:off + t.n]), "plain and batched differ"
             off += t.n
-
+    main_mode = "batched" if "batched" in results else "plain"
     shape_idx, graphed = mg.mg_batch_plan_info(handles) if "batched" in results else (0, False)
     shape = mg.mg_trace_shapes()[shape_idx]
-    main_mode = "batched" if "batched" in results else "plain"
-    R = results[main_mode]
-    roof = None
-    wc = work_counts(args.workload if args.trees is None else f"{args.workload}:{args.trees}")
-    if wc is not None and trace and trace["launches"]:
-        # algorithmic bytes of the trace kernel: 1 B per voxel visit (grid gather), 4 B per ancestor
-        # depth read, 4 B per ray (first-hit write), 2 x B x 4 B of bin counts per node
-        alg_step = wc["visits"] * 1 + wc["anc_tests"] * 4 + wc["rays"] * 4 + n_total * 2 * sen.yaw_bins * 4
-        launches_per_step = trace["launches"] / args.steps
-        avg_ms = trace["total_ms"] / trace["launches"]
-        alg_launch = alg_step / launches_per_step
-        # The plan's groups run on two streams, so trace launches overlap: the
-        # achieved rate divides by the time during which at least one ran
-        # (union of the launch intervals), i.e. per launch by busy / launches.
-        busy_per_launch_ms = trace["busy_ms"] / trace["launches"]
-        achieved = alg_launch / (busy_per_launch_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
-                "kernel": "k_trace_multi", "launches_per_step": launches_per_step,
-                "algorithmic_bytes_per_launch": alg_launch,
-                "avg_launch_ms": avg_ms, "busy_ms_per_step": trace["busy_ms"] / args.steps,
-                "kernel_share_of_step": trace["busy_ms"] / args.steps / R["ms_per_step"],
-                "timing": "HIP events recorded by each trace dispatch over the timed steps; achieved = "
-                          "algorithmic bytes / union of the launch intervals (launches of the two groups "
-                          "overlap); avg_launch_ms = mean single-launch duration"}
-    sp = None
+    wc = work_counts(name if n_trees is None else f"{name}:{n_trees}")
+    roof = roofline_of(wc, trace, steps, n_total, sen.yaw_bins, results[main_mode]["ms_per_step"],
+                       measured_traffic(name))
+    return dict(w=w, M=M, trees=trees, g_all=g_all, y_all=y_all, n_total=n_total, rays_per_step=rays_per_step,
+                results=results, main_mode=main_mode, roof=roof, trace=trace,
+                launch_shape={"rays_per_workgroup": shape[0], "mask_bricks_per_workgroup": shape[1],
+                              "chosen_by": "autotune", "graph": graphed})
+
+
+def close(m):
+    for T in m["trees"]:
+        T.close()
+    m["M"].close()
+
+
+def next_rows(mg, m, args):
+    """The next-row paths on one measured workload: single-parent gain, interval mode, exact hash sets."""
+    import torch
+    w, trees, n_total, rays_per_step = m["w"], m["trees"], m["n_total"], m["rays_per_step"]
+    sen = w.sensor
+    dev = m["g_all"].device
+    out = {}
     if args.sp_steps > 0:
         # single-parent gain g_sp (the comparison gain of Fig. 4) on the same trees, per-tree path
         g_sp = torch.empty(max(t.n for t in trees), dtype=torch.int32, device=dev)
@@ -541,10 +569,9 @@ def main():
                 mg.mg_eval_single_parent(T.handle, g_sp, y_sp)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.sp_steps
-        sp = {"rays_per_s": rays_per_step / dt, "ms_per_step": dt * 1e3, "steps": args.sp_steps,
-              "path": "mg_eval_single_parent, tree after tree"}
-        log(f"[bench] single parent: {sp}")
-    ivl = None
+        out["single_parent"] = {"rays_per_s": rays_per_step / dt, "ms_per_step": dt * 1e3, "steps": args.sp_steps,
+                                "path": "mg_eval_single_parent, tree after tree"}
+        log(f"[bench] single parent: {out['single_parent']}")
     if args.ivl_steps > 0:
         # interval mode (the paper's pinhole buffers and overlap intervals), per-tree level path
         wd, hd, _, _, _ = mg.interval_tables(sen, w.map.voxel_m)
@@ -561,7 +588,7 @@ def main():
         dt = (time.perf_counter() - t0) / args.ivl_steps
         ivl = {"rays_per_s": rays_per_step / dt, "ms_per_step": dt * 1e3, "steps": args.ivl_steps,
                "buffer": f"{wd}x{hd}", "path": "mg_eval_interval, tree after tree"}
-        wci = work_counts((args.workload if args.trees is None else f"{args.workload}:{args.trees}") + "/interval")
+        wci = work_counts(w.name + "/interval")
         if wci is not None:
             # algorithmic bytes: 1 B per voxel visit, 4 B per pixel walked in an ancestor buffer, 4 B per
             # rendered pixel, 2 x B x 4 B of bins per node; divided by the whole call's time
@@ -570,11 +597,13 @@ def main():
             ivl["algorithmic_bytes_per_step"] = alg
             ivl["achieved_GBps_whole_call"] = alg / dt / 1e9
             ivl["pixel_steps_per_ray"] = wci["pixel_steps"] / wci["rays"]
+        out["interval"] = ivl
         log(f"[bench] interval: {ivl}")
-    exact = None
-    if args.exact_steps > 0 and "batched" in results:
+    if args.exact_steps > 0 and "batched" in m["results"]:
         # exact marginal gain with device hash sets at the depth-buffer windows just computed
         # (the exact comparison of Sec. V-A), per tree: X_ray, X_set, A_set
+        y_all = m["y_all"]
+        batched_ms = m["results"]["batched"]["ms_per_step"]
         xr = torch.empty(max(t.n for t in trees), dtype=torch.int32, device=dev)
         xs, xa = torch.empty_like(xr), torch.empty_like(xr)
         ys = []
@@ -592,7 +621,7 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.exact_steps
         exact = {"ms_per_step": dt * 1e3, "window_rays_per_s": n_total * sen.n_el * sen.w_buf / dt,
-                 "steps": args.exact_steps, "over_depth_buffer": dt * 1e3 / results["batched"]["ms_per_step"],
+                 "steps": args.exact_steps, "over_depth_buffer": dt * 1e3 / batched_ms,
                  "path": "mg_eval_exact per tree (hash sets of the window rays' unknown voxels; X_ray, X_set, A_set)"}
         # the exact planner gain with its own yaw choice (depth order, hash sets), the device
         # counterpart of the paper's exact CPU implementation
@@ -607,24 +636,92 @@ def main():
         torch.cuda.synchronize()
         dt2 = (time.perf_counter() - t0) / args.exact_steps
         exact["own_yaw"] = {"ms_per_step": dt2 * 1e3, "rays_per_s": rays_per_step / dt2,
-                            "over_depth_buffer": dt2 * 1e3 / results["batched"]["ms_per_step"],
+                            "over_depth_buffer": dt2 * 1e3 / batched_ms,
                             "path": "mg_eval_exact_marginal per tree"}
+        out["exact"] = exact
         log(f"[bench] exact: {exact}")
-    mapb = map_bench(mg) if args.map_bench else None
-    if mapb:
-        log(f"[bench] maps: {mapb}")
-    score = None
-    if "batched" in results:
-        score = score_bench(mg, trees, g_all, n_total, int(sum(t.depth().sum() for t in w.trees)))
-        log(f"[bench] path score: {score}")
+    if "batched" in m["results"]:
+        # the path score runs on the evaluated batch (it needs its plan), after the exact leg
+        # rewrote nothing it reads (gains are passed in)
+        out["path_score"] = score_bench(mg, trees, m["g_all"], n_total,
+                                        int(sum(t.depth().sum() for t in w.trees)))
+        log(f"[bench] path score: {out['path_score']}")
+    return out
+
+
+def summary_of(m):
+    """The compact record of an extra workload."""
+    r = {"workload": f"{m['w'].name}: {W_DESC(m['w'].name)}", "trees": len(m["trees"]), "nodes": m["n_total"],
+         "rays_per_step": m["rays_per_step"], "modes": m["results"], "roofline": m["roof"],
+         "launch_shape": m["launch_shape"]}
+    if "batched" in m["results"]:
+        r["rays_per_s"] = m["results"]["batched"]["rays_per_s"]
+        r["ms_per_step"] = m["results"]["batched"]["ms_per_step"]
+    return r
+
+
+def W_DESC(name):
+    from paper_2609_40297_amd import workloads as W
+    return W.WORKLOADS[name]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this library runs on one GPU only; use --gpus 1"}))
+        log("bench.py: only --gpus 1 is supported (the library runs on one GPU)")
+        sys.exit(2)
+    if args.copy_probe_mib:
+        return copy_probe(args.copy_probe_mib)
+    if args.map_bench_only:
+        import torch
+        from paper_2609_40297_amd import mg
+        torch.cuda.set_device(0)
+        print(json.dumps({"maps": map_bench(mg, reps=3)}), flush=True)
+        return
+    if args.workload == "serve16":
+        return serve_bench(args)
+    import torch
+    from paper_2609_40297_amd import mg, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    mg.lib()
+    modes = args.modes.split(",")
+    extras = args.extras
+    if extras is None:
+        extras = "step,batch64" if args.workload == "large" and args.trees is None else "none"
+    extras = [] if extras == "none" else [e for e in extras.split(",") if e and e != args.workload]
+
+    head = measure(mg, W, args.workload, args.steps, args.warmup, modes, n_trees=args.trees)
+    R = head["results"][head["main_mode"]]
+    rows = {}
+    if not extras:
+        rows = next_rows(mg, head, args)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on the host threads, bounded sample)")
-        cpu = cpu_baseline(w, args.cpu_sample_rays)
-        if score is not None:
-            cpu["path_score"] = score_oracle(w)
-            cpu.update(next_row_oracles(w, cpu_threads()))
+        per_thread = args.cpu_sample_rays or (0.5e6 if args.workload == "large" else 1.5e6)
+        cpu = cpu_baseline(head["w"], per_thread)
         log(f"[bench] cpu: {cpu}")
+    line_extras = {}
+    head_summary = {"workload": f"{args.workload}: {W.WORKLOADS[args.workload]}", "trees": len(head["trees"]),
+                    "nodes": head["n_total"], "rays_per_step": head["rays_per_step"], "mode": head["main_mode"],
+                    "launch_shape": head["launch_shape"]}
+    close(head)
+    for name in extras:
+        ex = measure(mg, W, name, max(3, args.steps) if name != "step" else 20, max(1, args.warmup), modes)
+        line_extras[name] = summary_of(ex)
+        if name == "step":
+            rows = next_rows(mg, ex, args)
+            if cpu is not None:
+                rows_cpu = {"path_score": score_oracle(ex["w"])}
+                rows_cpu.update(next_row_oracles(ex["w"], cpu_threads()))
+                line_extras[name]["cpu_baseline_next_rows"] = rows_cpu
+        close(ex)
+    mapb = map_bench(mg) if args.map_bench else None
+    if mapb:
+        log(f"[bench] maps: {mapb}")
 
     line = {
         "metric": "marginal-gain rays/s + replan p50/p99 ms, batched vs plain, 1xMI355X",
@@ -639,25 +736,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {W.WORKLOADS[args.workload]}", "trees": len(w.trees),
-                   "nodes": n_total, "rays_per_step": rays_per_step, "mode": main_mode,
-                   "launch_shape": {"rays_per_workgroup": shape[0], "queue_per_wave": shape[1],
-                                    "chosen_by": "autotune", "graph": graphed}},
+        "config": head_summary,
         "p50_ms": R["p50_ms"],
         "p99_ms": R["p99_ms"],
-        "modes": results,
-        "roofline": roof,
+        "modes": head["results"],
+        "roofline": head["roof"],
         "cpu_baseline": cpu,
-        "path_score": score,
-        "single_parent": sp,
-        "interval": ivl,
+        "extras": line_extras,
+        "next_rows_on": "step" if "step" in line_extras else args.workload,
+        "single_parent": rows.get("single_parent"),
+        "interval": rows.get("interval"),
+        "exact": rows.get("exact"),
+        "path_score": rows.get("path_score"),
         "maps": mapb,
-        "exact": exact,
     }
     print(json.dumps(line), flush=True)
-    for T in trees:
-        T.close()
-    M.close()
 
 
 if __name__ == "__main__":

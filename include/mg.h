@@ -126,7 +126,8 @@ int mg_map_read(mg_map map, void* hip_stream, uint8_t* states);
  *   pos_m: HOST array [n][3] in metres; parent: HOST array [n] with
  *   parent[0] = -1 and 0 <= parent[i] < i. Depth <= 64, every node inside the
  *   map, n >= 1; otherwise MG_E_INVALID. Both arrays are copied. Device
- *   buffers for all later evaluations (depth buffers, bins, ancestor lists)
+ *   buffers for all later evaluations (depth buffers, bins, ancestor lists,
+ *   and one path mask of one bit per map voxel for every node with children)
  *   are allocated here, so evaluation calls allocate nothing. */
 int mg_tree_upload(mg_map map, const float* pos_m, const int32_t* parent, int32_t n,
                    const mg_sensor* sensor, void* hip_stream, mg_tree* out);
@@ -142,8 +143,10 @@ int32_t mg_tree_buffer_pixels(mg_tree tree);
 int64_t mg_tree_footprint_bytes(mg_tree tree);
 
 /* Path-dependent marginal gain of every node (eq. 2 with depth buffers,
- * Sec. IV-B), nodes in depth order (Sec. IV-C), one launch pair per depth
- * level (trace + window selection).
+ * Sec. IV-B), nodes in depth order (Sec. IV-C). Per depth level: one trace
+ * launch, one window selection, then one launch that records, for every node
+ * of the level with children, which voxels the node or an ancestor observes
+ * (its path mask, what conditions its children).
  *   gain    DEVICE uint32[n]: marginal gain at the chosen window (incidences).
  *   yaw_bin DEVICE int32[n]: chosen window k (bins k..k+w-1); the yaw angle
  *           of the window centre is az_offset + k*360/B + fov_h/2.
@@ -194,19 +197,20 @@ int mg_score_branches(const mg_tree* trees, int32_t n_trees, void* hip_stream, c
  *   shape: -1 (default) = autotune: the first call with a tree list whose
  *          workload shape (sensor, range, map dims, tree count, depth, node
  *          count to a power of two) has not been seen times every compiled
- *          launch shape of the trace kernel on that call's own trees, twice
- *          each, keeps the fastest for that workload shape, and blocks until
- *          done; 0 .. count-1 = that shape (mg_trace_shapes).
+ *          launch shape (trace and mask-builder workgroup sizes) on that
+ *          call's own trees, twice each, keeps the fastest for that workload
+ *          shape, and blocks until done; 0 .. count-1 = that shape
+ *          (mg_trace_shapes).
  *   graph: 1 = the plan's launches are recorded once into a HIP graph and
  *          each call replays it (on a library stream joined to hip_stream by
  *          events before and after); 0 (default) = launched one by one.
  * Results do not depend on either setting. MG_E_INVALID for other values. */
 int mg_batch_config(int32_t shape, int32_t graph);
 
-/* The compiled launch shapes of the trace kernel: *count, and for the first
- * `capacity` shapes the rays per workgroup and the per-wave queue capacity
- * (queued unknown voxels). Host only. */
-int mg_trace_shapes(int32_t* count, int32_t* threads, int32_t* queue, int32_t capacity);
+/* The compiled launch shapes: *count, and for the first `capacity` shapes the
+ * rays per workgroup of the trace kernel and the 8x8x8-voxel bricks per
+ * workgroup of the path-mask builder. Host only. */
+int mg_trace_shapes(int32_t* count, int32_t* threads, int32_t* bricks, int32_t capacity);
 
 /* Launch shape index and whether a graph is replayed (1) for the cached plan
  * of this tree list. MG_E_INVALID when the list has no plan yet. */
@@ -346,19 +350,21 @@ int mg_server_stats(mg_server server, int64_t* steps, int64_t* completed, double
 int mg_server_destroy(mg_server server);
 
 /* ---------------------------------------------------------------- timing
- * Measurement of the dominant kernel (the trace kernel of
- * mg_eval_marginal_batch). While enabled (on != 0), every trace launch that
- * mg_eval_marginal_batch makes on the current device carries a pair of HIP
- * events recorded by the kernel dispatch itself, so the interval is the
- * kernel's own execution (while enabled, batch plans are launched one by one
- * instead of replaying their graph). Enabling binds the timer to the current device;
- * MG_E_BUSY if unread launches of another device remain. Process-wide. */
+ * Measurement of the dominant kernels (the trace kernel and the path-mask
+ * builder of mg_eval_marginal_batch). While enabled (on != 0), every trace
+ * and builder launch that mg_eval_marginal_batch makes on the current device
+ * carries a pair of HIP events recorded by the kernel dispatch itself, so the
+ * interval is the kernel's own execution (while enabled, batch plans are
+ * launched one by one instead of replaying their graph). Enabling binds the
+ * timer to the current device; MG_E_BUSY if unread launches of another device
+ * remain. Process-wide. */
 int mg_timing_enable(int32_t on);
 
 /* Waits for the timed launches since the last read, returns the sum of their
  * durations (ms), the union of their intervals (ms during which at least one
  * ran: launches of different groups of a batch plan overlap), their number
- * and the workgroups they ran (any pointer may be NULL), and resets the sums.
+ * and the workgroups the trace launches ran (any pointer may be NULL), and
+ * resets the sums.
  * At most 65536 launches may be timed between two reads (MG_E_BUSY from the
  * launch call beyond that). */
 int mg_timing_read(double* total_ms, double* busy_ms, int64_t* launches, int64_t* workgroups);

@@ -382,6 +382,10 @@ int map_alloc(int32_t nx, int32_t ny, int32_t nz, float voxel_m, const float ori
     m->dev.shy = 6u + log2i(nbx);
     m->dev.shz = 6u + log2i(nbx) + log2i(nby);
     m->dev.outside = voxel_addr(8 * nbx - 1, 0, 0, m->dev);
+    m->dev.mbx = (uint32_t)(nx + 7) / 8u;
+    m->dev.mby = (uint32_t)(ny + 7) / 8u;
+    m->dev.mbz = (uint32_t)(nz + 7) / 8u;
+    m->dev.mask_words = 16u * m->dev.mbx * m->dev.mby * m->dev.mbz;    // < 2^32 / 32 (voxels < 2^32)
     m->voxel_m = voxel_m;
     for (int a = 0; a < 3; ++a) m->origin[a] = origin_m[a];
     m->bytes = padded;
@@ -507,6 +511,8 @@ struct mg_tree_s {
     int32_t levels = 0;
     std::vector<int32_t> level_ptr;       // host copy [levels+1]
     std::vector<int32_t> level_nodes_h;   // host copy [n]
+    std::vector<int32_t> mask_level_ptr;  // host copy [levels+1]: nodes with children, by level
+    std::vector<int32_t> mask_nodes_h;    // host copy
     std::vector<int32_t> parent_h;
     std::vector<int32_t> depth_h;
     // device
@@ -524,12 +530,14 @@ namespace mgb {
 
 // Host side of a tree upload: validation and every array the device needs.
 struct HostTree {
-    int32_t n = 0, maxd = 0;
+    int32_t n = 0, maxd = 0, n_masks = 0;
     std::vector<float4> q4, pm;
     std::vector<int32_t> depth, level_ptr, level_nodes, anc_ptr, anc_ids, child_ptr, child_ids, parent;
+    // path masks: slot per node (-1 for leaves), nodes with children by level
+    std::vector<int32_t> mask_slot, mask_level_ptr, mask_nodes;
     // device block layout
     size_t o_q4 = 0, o_pm = 0, o_ap = 0, o_ai = 0, o_ln = 0, o_cp = 0, o_ci = 0, o_c0 = 0, o_g = 0, o_y = 0, o_bins = 0,
-           o_dpan = 0, total = 0;
+           o_dpan = 0, o_ms = 0, o_mn = 0, o_masks = 0, total = 0;
 };
 
 }  // namespace mgb
@@ -598,9 +606,25 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
         std::vector<int32_t> fill(H->child_ptr.begin(), H->child_ptr.end() - 1);
         for (int32_t i = 1; i < n; ++i) H->child_ids[fill[parent[i]]++] = i;
     }
+    // path masks for the nodes with children, slots in level order
+    H->mask_slot.assign(n, -1);
+    H->mask_level_ptr.assign(H->maxd + 2, 0);
+    H->mask_nodes.clear();
+    for (int32_t d = 0; d <= H->maxd; ++d) {
+        for (int32_t k = H->level_ptr[d]; k < H->level_ptr[d + 1]; ++k) {
+            const int32_t v = H->level_nodes[k];
+            if (H->child_ptr[v + 1] > H->child_ptr[v]) {
+                H->mask_slot[v] = (int32_t)H->mask_nodes.size();
+                H->mask_nodes.push_back(v);
+            }
+        }
+        H->mask_level_ptr[d + 1] = (int32_t)H->mask_nodes.size();
+    }
+    H->n_masks = (int32_t)H->mask_nodes.size();
     const size_t R = (size_t)sensor->n_az * sensor->n_el;
     if (R * (size_t)n >= (1ull << 32)) return fail(MG_E_UNSUPPORTED, "nodes x rays = %zu exceeds 2^32 per tree", R * (size_t)n);
-    // one device block: q4 | anc_ptr | anc_ids | level_nodes | child_ptr | child_ids | c0 | gain | yaw | bins | dpan
+    // one device block: q4 | pm | anc_ptr | anc_ids | level_nodes | child_ptr | child_ids | c0 | gain | yaw | bins |
+    // dpan | mask_slot | mask_nodes | masks
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     H->o_q4 = take(sizeof(float4) * n);
@@ -615,6 +639,9 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
     H->o_y = take(sizeof(int32_t) * n);
     H->o_bins = take(sizeof(uint32_t) * 2 * sensor->yaw_bins * (size_t)n);
     H->o_dpan = take(sizeof(float) * R * (size_t)n);
+    H->o_ms = take(sizeof(int32_t) * n);
+    H->o_mn = take(sizeof(int32_t) * std::max<size_t>(H->mask_nodes.size(), 1));
+    H->o_masks = take(sizeof(uint32_t) * (size_t)map->dev.mask_words * (size_t)H->n_masks);
     H->total = off;
     return MG_OK;
 }
@@ -642,6 +669,8 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     if (e == hipSuccess) e = up(H.o_cp, H.child_ptr.data(), sizeof(int32_t) * (n + 1));
     if (e == hipSuccess) e = up(H.o_ci, H.child_ids.data(), sizeof(int32_t) * n);
     if (e == hipSuccess) e = up(H.o_c0, zeros_c0.data(), sizeof(int32_t) * n);
+    if (e == hipSuccess) e = up(H.o_ms, H.mask_slot.data(), sizeof(int32_t) * n);
+    if (e == hipSuccess) e = up(H.o_mn, H.mask_nodes.data(), sizeof(int32_t) * H.mask_nodes.size());
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         release_sensor(t->sensor);
@@ -657,15 +686,18 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     t->dev.c0 = (int32_t*)(base + H.o_c0);
     t->dev.bins = (uint32_t*)(base + H.o_bins);
     t->dev.dpan = (float*)(base + H.o_dpan);
+    t->dev.mask_slot = (const int32_t*)(base + H.o_ms);
+    t->dev.mask_nodes = (const int32_t*)(base + H.o_mn);
+    t->dev.masks = (uint32_t*)(base + H.o_masks);
     t->dev.n = n;
     t->dev.anc_cap = kMaxAnc;
     t->scratch_gain = (uint32_t*)(base + H.o_g);
     t->scratch_yaw = (int32_t*)(base + H.o_y);
     t->sd = sensor_dev(t->sensor, sensor->range_m / map->voxel_m);
-    if (!shape_fits(t->sd, 0, std::min<int32_t>(H.maxd, kMaxAnc))) {
+    if (build_lds_bytes(t->sd) + 256 > lds_limit()) {
         release_sensor(t->sensor);
-        return fail(MG_E_UNSUPPORTED, "sensor tables and queues need %zu bytes of LDS per workgroup, the device has %zu",
-                    trace_lds_bytes(t->sd, 0, std::min<int32_t>(H.maxd, kMaxAnc)), lds_limit());
+        return fail(MG_E_UNSUPPORTED, "sensor tables need %zu bytes of LDS per workgroup, the device has %zu",
+                    build_lds_bytes(t->sd), lds_limit());
     }
     t->map = map;
     t->params = *sensor;
@@ -673,6 +705,8 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     t->levels = H.maxd + 1;
     t->level_ptr = H.level_ptr;
     t->level_nodes_h = H.level_nodes;
+    t->mask_level_ptr = H.mask_level_ptr;
+    t->mask_nodes_h = H.mask_nodes;
     t->parent_h = H.parent;
     t->depth_h = H.depth;
     t->block = block;
@@ -742,8 +776,9 @@ int check_device(mg_tree t) {
     return MG_OK;
 }
 
-// Depth-ordered evaluation: for each level, trace all its nodes' rays, then
-// select their windows; level d+1 reads the buffers and windows of levels <= d.
+// Depth-ordered evaluation: for each level, trace all its nodes' rays, select
+// their windows, then build the path masks of those with children; level d+1
+// reads the masks of level d.
 int eval_levels(mg_tree t, hipStream_t s, uint32_t* gain, int32_t* yaw, float* depth, uint32_t* host_gain,
                 int32_t* host_yaw, int32_t anc_cap = kMaxAnc) {
     TreeDev td = t->dev;
@@ -752,8 +787,10 @@ int eval_levels(mg_tree t, hipStream_t s, uint32_t* gain, int32_t* yaw, float* d
     for (int32_t d = 0; d < t->levels; ++d) {
         const int32_t b = t->level_ptr[d], cnt = t->level_ptr[d + 1] - b;
         const int32_t* nodes = td.level_nodes + b;
-        HIP_TRY(launch_trace(t->map->dev, t->sd, td, nodes, cnt, true, std::min(d, anc_cap), s));
+        HIP_TRY(launch_trace(t->map->dev, t->sd, td, nodes, cnt, true, s));
         HIP_TRY(launch_finish(t->sd, td, nodes, cnt, true, gain, yaw, s));
+        const int32_t mb = t->mask_level_ptr[d], mcnt = t->mask_level_ptr[d + 1] - mb;
+        HIP_TRY(launch_mask_build(t->map->dev, t->sd, td, td.mask_nodes + mb, mcnt, s));
         if (host_gain) {
             // results of this level back to the host before the next level (Sec. IV-C)
             HIP_TRY(hipMemcpyAsync(host_gain, gain, sizeof(uint32_t) * t->n, hipMemcpyDeviceToHost, s));
@@ -801,7 +838,7 @@ extern "C" int mg_eval_absolute(mg_tree t, void* hip_stream, uint32_t* gain, int
     if (rc != MG_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_TRY(launch_zero_u32(t->dev.bins, (size_t)2 * t->sd.B * t->n, s));
-    HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, t->dev.level_nodes, t->n, false, 0, s));
+    HIP_TRY(launch_trace(t->map->dev, t->sd, t->dev, t->dev.level_nodes, t->n, false, s));
     HIP_TRY(launch_finish(t->sd, t->dev, t->dev.level_nodes, t->n, false, gain, yaw_bin, s));
     return MG_OK;
 }
@@ -815,6 +852,8 @@ int tree_view(mg_tree t, TreeView* v) {
     v->td = &t->dev;
     v->level_ptr = &t->level_ptr;
     v->level_nodes = &t->level_nodes_h;
+    v->mask_level_ptr = &t->mask_level_ptr;
+    v->mask_nodes = &t->mask_nodes_h;
     v->parent = &t->parent_h;
     v->depth = &t->depth_h;
     v->scratch_gain = t->scratch_gain;

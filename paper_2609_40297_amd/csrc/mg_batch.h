@@ -13,6 +13,8 @@ struct TreeView {
     const mgk::TreeDev* td;
     const std::vector<int32_t>* level_ptr;     // host copy, [levels + 1]
     const std::vector<int32_t>* level_nodes;   // host copy, [n]
+    const std::vector<int32_t>* mask_level_ptr;// host copy, [levels + 1]: nodes with children by level
+    const std::vector<int32_t>* mask_nodes;    // host copy
     const std::vector<int32_t>* parent;        // host copy, [n]
     const std::vector<int32_t>* depth;         // host copy, [n]
     uint32_t* scratch_gain;                    // device outputs inside the tree's block

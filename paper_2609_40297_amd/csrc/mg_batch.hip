@@ -32,13 +32,16 @@ struct Plan {
     uint32_t* gain = nullptr;             // output buffers the descriptors point into
     int32_t* yaw = nullptr;
     float* depth = nullptr;
-    void* block = nullptr;                 // BatchTree[n_trees] | items[total]
+    void* block = nullptr;                 // BatchTree[n_trees] | items[total] | mitems (nodes with children)
     const BatchTree* dtrees = nullptr;
     const unsigned long long* ditems = nullptr;
+    const unsigned long long* dmitems = nullptr;
+    uint32_t mask_bricks = 0;              // bricks of the largest path mask among the trees
     // Launch records in host order: stream 0 is the caller's (the shared
-    // prefix of levels), stream g + 1 runs group g.
+    // prefix of levels), stream g + 1 runs group g. [mbegin, mbegin + mcount)
+    // are the launch's nodes with children (their path masks are built).
     struct Launch {
-        int32_t stream, begin, count, depth;
+        int32_t stream, begin, count, mbegin, mcount, depth;
     };
     std::vector<Launch> launches;
     int32_t groups = 0;
@@ -116,6 +119,7 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
             return mgb::set_error(MG_E_UNSUPPORTED, "batch has 2^31 nodes or more");
         P->total += (uint32_t)v.n;
         P->max_nodes = std::max(P->max_nodes, (uint32_t)v.n);
+        P->mask_bricks = std::max(P->mask_bricks, v.map->mask_words >> 4);
         levels = std::max(levels, v.levels);
     }
     P->sd = *v0.sd;
@@ -182,41 +186,44 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
     }
     P->groups = G;
     // items: the prefix level by level (trees in order), then every group's
-    // levels; one launch record per non-empty (stream, level)
-    std::vector<unsigned long long> items;
+    // levels; one launch record per non-empty (stream, level); mitems: the
+    // same launches' nodes with children
+    std::vector<unsigned long long> items, mitems;
     items.reserve(P->total);
-    auto add_launch = [&](int32_t stream, int32_t begin, int32_t d) -> int {
+    auto add_launch = [&](int32_t stream, int32_t begin, int32_t mbegin, int32_t d) -> int {
         const int32_t count = (int32_t)items.size() - begin;
         if (count == 0) return MG_OK;
         if ((uint64_t)count * (uint64_t)max_tiles >= (1ull << 31))
             return mgb::set_error(MG_E_UNSUPPORTED, "a depth level of the batch has 2^31 workgroups or more");
-        P->launches.push_back({stream, begin, count, d});
+        P->launches.push_back({stream, begin, count, mbegin, (int32_t)mitems.size() - mbegin, d});
         return MG_OK;
     };
-    for (int32_t d = 0; d < split; ++d) {
-        const int32_t begin = (int32_t)items.size();
+    auto add_level = [&](int32_t d, int32_t g) {    // g < 0: every node of the level
         for (int32_t i = 0; i < nt; ++i) {
             const std::vector<int32_t>& lp = *views[i].level_ptr;
             const std::vector<int32_t>& ln = *views[i].level_nodes;
+            const std::vector<int32_t>& mp = *views[i].mask_level_ptr;
+            const std::vector<int32_t>& mn = *views[i].mask_nodes;
             if (d + 1 >= (int32_t)lp.size()) continue;
             for (int32_t k = lp[d]; k < lp[d + 1]; ++k)
-                items.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)ln[k]);
+                if (g < 0 || group_of_unit[unit_of[i][ln[k]]] == g)
+                    items.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)ln[k]);
+            for (int32_t k = mp[d]; k < mp[d + 1]; ++k)
+                if (g < 0 || group_of_unit[unit_of[i][mn[k]]] == g)
+                    mitems.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)mn[k]);
         }
-        int rc = add_launch(0, begin, d);
+    };
+    for (int32_t d = 0; d < split; ++d) {
+        const int32_t begin = (int32_t)items.size(), mbegin = (int32_t)mitems.size();
+        add_level(d, -1);
+        int rc = add_launch(0, begin, mbegin, d);
         if (rc != MG_OK) return rc;
     }
     for (int32_t d = split; d < levels; ++d) {
         for (int32_t g = 0; g < G; ++g) {
-            const int32_t begin = (int32_t)items.size();
-            for (int32_t i = 0; i < nt; ++i) {
-                const std::vector<int32_t>& lp = *views[i].level_ptr;
-                const std::vector<int32_t>& ln = *views[i].level_nodes;
-                if (d + 1 >= (int32_t)lp.size()) continue;
-                for (int32_t k = lp[d]; k < lp[d + 1]; ++k)
-                    if (group_of_unit[unit_of[i][ln[k]]] == g)
-                        items.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)ln[k]);
-            }
-            int rc = add_launch(g + 1, begin, d);
+            const int32_t begin = (int32_t)items.size(), mbegin = (int32_t)mitems.size();
+            add_level(d, g);
+            int rc = add_launch(g + 1, begin, mbegin, d);
             if (rc != MG_OK) return rc;
         }
     }
@@ -225,12 +232,16 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     const size_t o_trees = take(sizeof(BatchTree) * nt);
     const size_t o_items = take(sizeof(unsigned long long) * items.size());
+    const size_t o_mitems = take(sizeof(unsigned long long) * std::max<size_t>(mitems.size(), 1));
     hipError_t e = hipMalloc(&P->block, off);
     if (e != hipSuccess) return hip_fail(e, "batch plan allocation");
     char* base = (char*)P->block;
     e = hipMemcpyAsync(base + o_trees, bt.data(), sizeof(BatchTree) * nt, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(base + o_items, items.data(), sizeof(unsigned long long) * items.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !mitems.empty())
+        e = hipMemcpyAsync(base + o_mitems, mitems.data(), sizeof(unsigned long long) * mitems.size(),
                            hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "batch plan upload");
@@ -239,6 +250,7 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
     P->yaw = yaw;
     P->depth = depth;
     P->ditems = (const unsigned long long*)(base + o_items);
+    P->dmitems = (const unsigned long long*)(base + o_mitems);
     *out = std::move(P);
     return MG_OK;
 }
@@ -336,14 +348,15 @@ int run_plan(const Plan& P, hipStream_t s, bool timed) {
             if (e != hipSuccess) return hip_fail(e, "group fork");
             forked = true;
         }
-        hipEvent_t t0 = nullptr, t1 = nullptr;
+        hipEvent_t t0 = nullptr, t1 = nullptr, b0 = nullptr, b1 = nullptr;
         if (timed) {
             int rc = next_events(P.device, &t0, &t1);
+            if (rc == MG_OK && L.mcount > 0) rc = next_events(P.device, &b0, &b1);
             if (rc != MG_OK) return rc;
         }
         hipStream_t ls = L.stream == 0 ? s : GS->stream[L.stream - 1];
-        const bool ahead = (int64_t)L.count * tiles_per_node(P.sd, P.shape) < kAheadWorkgroups;
-        e = launch_batch_level(P.dtrees, P.ditems + L.begin, L.count, P.sd, L.depth, ls, P.shape, t0, t1, ahead);
+        e = launch_batch_level(P.dtrees, P.ditems + L.begin, L.count, P.dmitems + L.mbegin, L.mcount, P.mask_bricks,
+                               P.sd, ls, P.shape, t0, t1, b0, b1);
         if (e != hipSuccess) return hip_fail(e, "batch level");
         if (t0) {
             std::lock_guard<std::mutex> lk(g_timing.mu);
@@ -380,9 +393,7 @@ int autotune(Plan& P, hipStream_t s) {
     int best = 0;
     float best_ms = 0.f;
     bool any = false;
-    const int32_t deepest = P.levels - 1;                     // most ancestors of any node
     for (int k = 0; k < shape_count() && e == hipSuccess; ++k) {
-        if (!shape_fits(P.sd, k, deepest)) continue;         // needs more LDS than the device has
         P.shape = k;
         float ms = 0.f;
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
@@ -575,15 +586,15 @@ extern "C" int mg_batch_config(int32_t shape, int32_t graph) {
     return MG_OK;
 }
 
-extern "C" int mg_trace_shapes(int32_t* count, int32_t* threads, int32_t* queue, int32_t capacity) {
-    if (!count || capacity < 0 || (capacity > 0 && (!threads || !queue)))
+extern "C" int mg_trace_shapes(int32_t* count, int32_t* threads, int32_t* bricks, int32_t capacity) {
+    if (!count || capacity < 0 || (capacity > 0 && (!threads || !bricks)))
         return mgb::set_error(MG_E_INVALID, "bad shape query");
     *count = shape_count();
     for (int k = 0; k < shape_count() && k < capacity; ++k) {
-        int th = 0, q = 0;
-        shape_of(k, &th, &q);
+        int th = 0, b = 0;
+        shape_of(k, &th, &b);
         threads[k] = th;
-        queue[k] = q;
+        bricks[k] = b;
     }
     return MG_OK;
 }

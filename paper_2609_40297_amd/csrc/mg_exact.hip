@@ -378,7 +378,7 @@ extern "C" int mg_eval_exact_marginal(mg_tree t, void* hip_stream, uint32_t* gai
     State& st = g_state[t];
     // 1. bound |I(n)| by the absolute gain (the largest window's unknown incidences)
     e = launch_zero_u32(Tr.bins, (size_t)2 * S.B * n, s);
-    if (e == hipSuccess) e = launch_trace(*v.map, S, Tr, Tr.level_nodes, n, false, 0, s);
+    if (e == hipSuccess) e = launch_trace(*v.map, S, Tr, Tr.level_nodes, n, false, s);
     if (e == hipSuccess) e = launch_finish(S, Tr, Tr.level_nodes, n, false, v.scratch_gain, v.scratch_yaw, s);
     std::vector<uint32_t> bound(n);
     if (e == hipSuccess) e = hipMemcpyAsync(bound.data(), v.scratch_gain, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s);

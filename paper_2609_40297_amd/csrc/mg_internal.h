@@ -11,12 +11,6 @@ constexpr int kMaxAnc = 64;        // deepest supported ancestor chain
 constexpr int kMaxBins = 256;      // yaw bins
 constexpr int kMaxAz = 4096;       // panorama columns (LDS holds their boundaries)
 constexpr int kMaxEl = 2048;
-// Trace launches of fewer workgroups than this (a few waves per SIMD at most)
-// keep two voxels in flight per lane; measured on a 500-node tree (levels of 1
-// to 360 nodes, 85 workgroups per node) against thresholds of 0, 512, 1024,
-// 2048, 4096, 16384 workgroups and every launch: 1024 is 1.2 % faster than 0,
-// and 512 to 2048 are within 0.4 % of each other.
-constexpr int64_t kAheadWorkgroups = 1024;
 
 // kOutside marks the padding around the grid: a traversal that reaches it
 // has left the grid.
@@ -35,6 +29,10 @@ struct MapDev {
     uint32_t xm, ym, zm;    // brick-index bits of a coordinate: (8 * nb - 1) & ~7
     uint32_t shy, shz;      // left shifts placing (y & ym) and (z & zm) in the address
     uint32_t outside;       // address of a padding byte (kOutside)
+    // Path masks (one bit per voxel, see mask_word): bricks per axis holding
+    // the grid, ceil(n / 8), and 32-bit words per mask (16 per brick).
+    uint32_t mbx, mby, mbz;
+    uint32_t mask_words;
 };
 
 // Byte address of voxel (x, y, z) in the bricked grid, for -1 <= x <= nx
@@ -45,6 +43,17 @@ __host__ __device__ inline uint32_t voxel_addr(int32_t x, int32_t y, int32_t z, 
     return (ux & 7u) | ((uy & 7u) << 3) | ((uz & 7u) << 6) | ((ux & M.xm) << 6) | ((uy & M.ym) << M.shy) |
            ((uz & M.zm) << M.shz);
 }
+
+// Path masks: one bit per voxel of the grid, in 8x8x8 bricks of 512 bits (16
+// words), bricks x fastest with tight counts mbx = ceil(nx / 8) etc. Voxel
+// (x, y, z) is bit (x & 7) | (y & 3) << 3 of word (z & 7) << 1 | (y & 7) >> 2
+// of its brick, i.e. bit (x & 7) | (y & 7) << 3 | (z & 7) << 6 of the brick's
+// 512 bits: a z-slice of a brick is 64 consecutive bits, two words.
+__device__ __forceinline__ uint32_t mask_word(int32_t x, int32_t y, int32_t z, const MapDev& M) {
+    const uint32_t b = (uint32_t)(x >> 3) + __umul24(M.mbx, (uint32_t)(y >> 3) + __umul24(M.mby, (uint32_t)(z >> 3)));
+    return (b << 4) | ((uint32_t)(z & 7) << 1) | ((uint32_t)(y & 4) >> 2);
+}
+__device__ __forceinline__ uint32_t mask_bit(int32_t x, int32_t y) { return (uint32_t)(x & 7) | ((uint32_t)(y & 3) << 3); }
 
 // Panorama ray tables and yaw-window geometry (built on the host, see mg_api).
 struct SensorDev {
@@ -70,7 +79,10 @@ struct SensorDev {
 
 // One tree's device state. Depth buffers are kept as full panoramas: the
 // first-hit parameter of every ray of node n lives at dpan[n*R + r] and the
-// node's buffer is the window slice starting at column c0[n].
+// node's buffer is the window slice starting at column c0[n]. Every node with
+// children has a path mask (mask_slot[n] >= 0): the set of voxels that n or
+// one of its ancestors observes (with anc_cap = 1: that n observes), which is
+// what conditions n's children.
 struct TreeDev {
     const float4* q4;          // [n] position in voxel units
     const float4* pm;          // [n] position in metres, as given
@@ -82,8 +94,11 @@ struct TreeDev {
     uint32_t* bins;            // [n][2][B]: absolute, then marginal
     float* dpan;               // [n][R]
     int32_t* c0;               // [n]
+    uint32_t* masks;           // [nodes with children][mask_words]
+    const int32_t* mask_slot;  // [n] index into masks, -1 for a leaf
+    const int32_t* mask_nodes; // nodes with children, by depth level
     int32_t n;
-    int32_t anc_cap;           // nearest ancestors that condition a node (kMaxAnc: all; 1: parent only)
+    int32_t anc_cap;           // ancestors that condition a node: kMaxAnc (all) or 1 (the parent only)
 };
 
 // One tree of a multi-tree launch: its map and node data, its range in voxel
@@ -112,32 +127,34 @@ hipError_t launch_map_scatter(const uint32_t* ids, const uint8_t* states, uint32
                               uint32_t* rejected, hipStream_t s);
 hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s);
 hipError_t launch_fill_outside(const MapDev& m, hipStream_t s);
-// max_anc: the most ancestors any node of the launch has (the LDS holds that
-// many); every node of depth level d has exactly d.
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
-                        int32_t n_nodes, bool marginal, int32_t max_anc, hipStream_t s);
+                        int32_t n_nodes, bool marginal, hipStream_t s);
+// Path masks of the listed nodes (all with children), after their windows are chosen.
+hipError_t launch_mask_build(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
+                             int32_t n_nodes, hipStream_t s);
 hipError_t launch_finish(const SensorDev& sd, const TreeDev& td, const int32_t* nodes, int32_t n_nodes,
                          bool marginal, uint32_t* gain, int32_t* yaw, hipStream_t s);
 hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth, hipStream_t s);
-// Launch shapes of the multi-tree trace kernel (shape 0 = default): rays per
-// workgroup and queue capacity per wave; LDS bytes and workgroups per node.
+// Launch shapes (shape 0 = default): rays per workgroup of the trace kernel
+// and bricks per workgroup of the mask builder.
 int shape_count();
-void shape_of(int shape, int* threads, int* queue);
-size_t trace_lds_bytes(const SensorDev& sd, int shape, int32_t max_anc);
+void shape_of(int shape, int* threads, int* bricks);
 int32_t tiles_per_node(const SensorDev& sd, int shape);
 size_t lds_limit();                        // LDS bytes one workgroup may use on the current device
-bool shape_fits(const SensorDev& sd, int shape, int32_t max_anc);
+size_t build_lds_bytes(const SensorDev& sd);   // LDS of the mask builder (sensor tables)
 // Path score of every node of the trees (eq. 3, eq. 4) and each tree's best node.
 hipError_t launch_score(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const uint32_t* gain,
                         double lambda, double* cost, double* obj, int32_t* best, int32_t* branch, hipStream_t s);
 hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const SensorDev& sd,
                              hipStream_t s);
-// One depth level of many trees: trace with launch shape `shape`, then window
-// selection. t0/t1 (may be null): events the trace kernel's dispatch itself
-// records at its start and end. `ahead`: the trace kernel keeps two voxels in
-// flight per lane (for launches too small to hide load latency with waves).
+// One depth level of many trees: trace with launch shape `shape`, window
+// selection, then the path masks of the level's nodes with children
+// (`mitems`, a subset of `items`). t0/t1 and b0/b1 (may be null): events the
+// trace and the builder dispatches themselves record at their start and end.
+// mask_bricks: bricks of the largest path mask among the launch's trees.
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                              const SensorDev& sd, int32_t max_anc, hipStream_t s, int shape = 0,
-                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, bool ahead = false);
+                              const unsigned long long* mitems, int32_t n_mitems, uint32_t mask_bricks,
+                              const SensorDev& sd, hipStream_t s, int shape = 0, hipEvent_t t0 = nullptr,
+                              hipEvent_t t1 = nullptr, hipEvent_t b0 = nullptr, hipEvent_t b1 = nullptr);
 
 }  // namespace mgk

@@ -18,8 +18,20 @@ namespace mgk {
 // memory: the compiler then issues global (not flat) loads for them.
 typedef const __attribute__((address_space(1))) uint8_t* gbytes_t;
 typedef const __attribute__((address_space(1))) float* gfloats_t;
+typedef const __attribute__((address_space(1))) uint32_t* gwords_t;
 __device__ __forceinline__ gbytes_t as_global(const uint8_t* p) { return (gbytes_t)p; }
 __device__ __forceinline__ gfloats_t as_global(const float* p) { return (gfloats_t)p; }
+__device__ __forceinline__ gwords_t as_global(const uint32_t* p) { return (gwords_t)p; }
+
+// A workgroup-uniform pointer moved to scalar registers (loads through it then
+// take a scalar base and a 32-bit vector offset).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
 
 // Wave ballot of a boolean (no widening of the predicate to an integer).
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -65,39 +77,40 @@ __device__ __forceinline__ int32_t wrap(int32_t c, int32_t W) { return c >= W ? 
 // r lies at or to the left (counter-clockwise side) of boundary direction b.
 __device__ __forceinline__ bool left_of(float2 b, float rx, float ry) { return b.x * ry - b.y * rx >= 0.f; }
 
-// Does ancestor A see the voxel centre (cx, cy, cz)? The centre must fall in a
-// pixel cell of A's window (azimuth between two column boundaries, elevation
-// between two row boundaries; cells half-open) and its squared range from A
-// must be <= the squared depth stored for that pixel. Row and column are the
-// numbers of inner boundaries the centre lies at-or-beyond; a table lookup
-// guesses them and the exact boundary comparisons settle them. Those
-// comparisons are monotone along the boundaries, so the settled index is the
-// exact count whatever the guess. The cheap rejections come first: the
-// wedge, then range and band as one mask. A lane with act false (no queue
-// entry) gets true, so that its negation keeps nothing.
-__device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float cy, float cz, bool act,
-                                              const SensorDev& S, const float2* __restrict__ s_bv,
-                                              const float* __restrict__ s_ts,
-                                              float ts0, float tsH, const uint16_t* __restrict__ s_lut_col,
-                                              const uint16_t* __restrict__ s_lut_row,
-                                              const float* __restrict__ dpan) {
+// The pixel of ancestor A's buffer that would decide whether A sees the voxel
+// centre (cx, cy, cz), and the centre's squared range from A. A sees the
+// centre when it falls in a pixel cell of A's window (azimuth between two
+// column boundaries, elevation between two row boundaries; cells half-open)
+// and its squared range is <= the squared depth stored for that pixel
+// (see_depth). Row and column are the numbers of inner boundaries the centre
+// lies at-or-beyond; a table lookup guesses them and the exact boundary
+// comparisons settle them. Those comparisons are monotone along the
+// boundaries, so the settled index is the exact count whatever the guess. The
+// cheap rejections come first: the wedge, then range and band as one mask.
+// idx = kNoPixel for a centre outside the window, band or range, and for a
+// lane with act false.
+constexpr uint32_t kNoPixel = 0xffffffffu;
+struct Pixel {
+    uint32_t idx;        // element of the panorama array holding the pixel's depth, or kNoPixel
+    float range2;
+};
+
+__device__ __forceinline__ Pixel pixel_of(const AncLDS& A, float cx, float cy, float cz, bool act,
+                                          const SensorDev& S, const float2* __restrict__ s_bv,
+                                          const float* __restrict__ s_ts, float ts0, float tsH,
+                                          const uint16_t* __restrict__ s_lut_col,
+                                          const uint16_t* __restrict__ s_lut_row) {
     const float rx = cx - A.qx;
     const float ry = cy - A.qy;
     const float w0 = A.b0x * ry - A.b0y * rx;
     const float w1 = A.b1x * ry - A.b1y * rx;
-    // The result is one comparison after the lookup (so that a ballot of it
-    // takes the comparison's mask as it stands): lanes outside the window, band
-    // or range keep a limit of -1, which no squared range meets (their range2
-    // is 0 unless computed); lanes without an entry (act false) a limit of
-    // +inf, which every one meets. The wedge is tested first and alone: the
-    // voxels of a chunk often lie outside an ancestor's window together, and
-    // the wave then skips the rest.
-    float lim = act ? -1.f : __builtin_inff();
-    float range2 = 0.f;
+    Pixel P{kNoPixel, 0.f};
+    // The wedge is tested first and alone: the voxels of a brick slice often
+    // lie outside the window together, and the wave then skips the rest.
     if (act & (w0 >= 0.f) & (w1 < 0.f)) {
         const float rz = cz - A.qz;
         const float rho2 = rx * rx + ry * ry;
-        range2 = rho2 + rz * rz;
+        const float range2 = rho2 + rz * rz;
         const float sz = rz * fabsf(rz);
         if ((range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH)) {
             // Column: pseudo-angle past the left boundary (monotone in the angle) picks a
@@ -156,181 +169,254 @@ __device__ __forceinline__ bool ancestor_sees(const AncLDS& A, float cx, float c
                 }
             }
             // (column < 4096 and H <= 2048: the product fits the 24-bit multiplier)
-            const float D =
-                as_global(dpan)[A.dpan_off + __umul24((uint32_t)wrap(A.c0 + col, S.W), (uint32_t)S.H) + (uint32_t)row];
-            lim = D * D;
+            P.idx = A.dpan_off + __umul24((uint32_t)wrap(A.c0 + col, S.W), (uint32_t)S.H) + (uint32_t)row;
+            P.range2 = range2;
         }
     }
-    return range2 <= lim;
+    return P;
 }
 
-// ---------------------------------------------------------------- ray traversal
+// A sees the centre: it lies in a pixel cell of A's window whose stored depth D
+// has range2 <= D * D (Sec. IV-B counts equality as observed).
+__device__ __forceinline__ bool see_depth(const Pixel& P, float D) { return (P.idx != kNoPixel) & (P.range2 <= D * D); }
 
-// Launch shapes of the trace kernel (rays per workgroup, queued unknown
-// voxels per wave), all compiled; shape 0 is the default.
+// ---------------------------------------------------------------- path masks
+
+// Mask builder launch shapes (rays per workgroup of the trace kernel, bricks
+// per workgroup of the builder), all compiled; shape 0 is the default.
 struct Shape {
-    int threads, queue;
+    int threads, bricks;
 };
-constexpr Shape kShapes[] = {{256, 512}, {256, 384}, {256, 256}, {128, 512}, {128, 256}, {512, 256}};
+constexpr Shape kShapes[] = {{256, 64}, {128, 64}, {512, 64}, {256, 128}, {256, 32}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr int kMaxBuildBricks = 128;
+constexpr int kBuildThreads = 256;
 
-
-__device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Queue entry: .x = x | y << 16, .y = z | bin << 16 | (m - 1) << 24, where m
-// (1..64) is the number of ray incidences the entry stands for: neighbouring
-// lanes that reach the same unknown voxel in the same step, with the same bin,
-// share one entry (the ancestor test depends on the voxel alone).
-__device__ __forceinline__ uint32_t entry_bin(uint32_t ey) { return (ey >> 16) & 0xffu; }
-
-// Adds the incidences of the queued entries to their bins: per distinct bin,
-// the sum of the entries' multiplicities is assembled from ballots bit by bit.
-__device__ __forceinline__ void count_by_bin(const uint2* __restrict__ q, int32_t n, uint32_t* __restrict__ bins,
-                                             int32_t lane) {
-    for (int32_t base = 0; base < n; base += 64) {
-        const int32_t i = base + lane;
-        bool pending = i < n;
-        const uint32_t ey = pending ? q[i].y : 0u;
-        const uint32_t bin = entry_bin(ey);
-        const uint32_t extra = ey >> 24;      // multiplicity - 1, 6 bits
-        uint64_t left = ballot(pending);
-        while (left) {
-            const int32_t leader = __builtin_ctzll(left);
-            const uint32_t b = __shfl(bin, leader, 64);
-            const bool mine = pending && bin == b;
-            const uint64_t same = ballot(mine);
-            uint32_t sum = (uint32_t)__popcll(same);
-#pragma unroll
-            for (int32_t k = 0; k < 6; ++k) sum += (uint32_t)__popcll(ballot(mine && ((extra >> k) & 1u))) << k;
-            if (lane == leader) atomicAdd(&bins[b], sum);
-            pending = pending && bin != b;
-            left &= ~same;
-        }
-    }
-}
-
-// Tests the n queued voxels against the ancestors, nearest first. Each pass
-// tests every voxel still unobserved against one ancestor and compacts the
-// survivors in place (a lane writes its survivor only after the whole chunk
-// has been read, and survivors never overtake the read position). What is left
-// after the last ancestor is new to the path and counts into the marginal bins.
-__device__ __forceinline__ void drain_queue(uint2* __restrict__ q, int32_t n, const AncLDS* __restrict__ s_anc,
-                                            int32_t na, const SensorDev& S, const float2* __restrict__ s_bv,
-                                            const float* __restrict__ s_ts, const uint16_t* __restrict__ s_lut_col,
-                                            const uint16_t* __restrict__ s_lut_row, const float* __restrict__ dpan,
-                                            uint32_t* __restrict__ marg_bins, int32_t lane) {
-    const float ts0 = s_ts[0], tsH = s_ts[S.H];
-    for (int32_t k = 0; k < na && n > 0; ++k) {
-        const AncLDS A = s_anc[k];
-        int32_t m = 0;
-        for (int32_t base = 0; base < n; base += 64) {
-            const int32_t i = base + lane;
-            const bool act = i < n;
-            const uint2 e = act ? q[i] : make_uint2(0u, 0u);
-            // (lanes without an entry run the cheap rejections on voxel 0 and
-            // are masked out)
-            const float cx = (float)(int32_t)(e.x & 0xffffu) + 0.5f;
-            const float cy = (float)(int32_t)(e.x >> 16) + 0.5f;
-            const float cz = (float)(int32_t)(e.y & 0xffffu) + 0.5f;
-            const bool keep = !ancestor_sees(A, cx, cy, cz, act, S, s_bv, s_ts, ts0, tsH, s_lut_col, s_lut_row, dpan);
-            const uint64_t bal = ballot(keep);
-            if (keep) q[m + (int32_t)lane_prefix(bal)] = e;
-            m += __popcll(bal);
-        }
-        n = m;
-    }
-    count_by_bin(q, n, marg_bins, lane);
-}
-
-struct TraceLDS {
+struct TableLDS {
     float2* bv;
     float* ts;
-    uint32_t* bins;
-    AncLDS* anc;
-    uint2* queue;
     uint16_t* lut_col;
     uint16_t* lut_row;
 };
 
-// LDS carve-up: boundary table (twice over) | row table | bins [2B] | guess tables |
-// per-wave queues | ancestors (as many as the launch provides for).
-template <int kTh, int kQ>
-__device__ __forceinline__ TraceLDS carve_lds(char* smem, const SensorDev& S) {
-    TraceLDS L;
+// LDS carve-up of the builder: boundary table (twice over) | row table | guess tables.
+__device__ __forceinline__ TableLDS carve_tables(char* smem, const SensorDev& S) {
+    TableLDS L;
     L.bv = reinterpret_cast<float2*>(smem);                 // column boundaries twice over: [2W + 1]
     L.ts = reinterpret_cast<float*>(L.bv + 2 * S.W + 1);
-    L.bins = reinterpret_cast<uint32_t*>(L.ts + S.H + 1);
-    L.lut_col = reinterpret_cast<uint16_t*>(L.bins + 2 * S.B);
+    L.lut_col = reinterpret_cast<uint16_t*>(L.ts + S.H + 1);
     L.lut_row = L.lut_col + S.n_lut_col;
-    char* tail = smem + ((reinterpret_cast<char*>(L.lut_row + S.n_lut_row) - smem + 15) & ~static_cast<ptrdiff_t>(15));
-    L.queue = reinterpret_cast<uint2*>(tail);
-    L.anc = reinterpret_cast<AncLDS*>(L.queue + kQ * (kTh / 64));
     return L;
 }
 
-template <int kTh>
-__device__ __forceinline__ void load_tables(const TraceLDS& L, const SensorDev& S) {
-    for (int32_t i = threadIdx.x; i <= 2 * S.W; i += kTh) L.bv[i] = S.bv[i < S.W ? i : (i < 2 * S.W ? i - S.W : 0)];
-    for (int32_t i = threadIdx.x; i <= S.H; i += kTh) L.ts[i] = S.ts[i];
-    for (int32_t i = threadIdx.x; i < S.n_lut_col; i += kTh) L.lut_col[i] = S.lut_col[i];
-    for (int32_t i = threadIdx.x; i < S.n_lut_row; i += kTh) L.lut_row[i] = S.lut_row[i];
+__device__ __forceinline__ void load_tables(const TableLDS& L, const SensorDev& S) {
+    for (int32_t i = threadIdx.x; i <= 2 * S.W; i += blockDim.x)
+        L.bv[i] = S.bv[i < S.W ? i : (i < 2 * S.W ? i - S.W : 0)];
+    for (int32_t i = threadIdx.x; i <= S.H; i += blockDim.x) L.ts[i] = S.ts[i];
+    for (int32_t i = threadIdx.x; i < S.n_lut_col; i += blockDim.x) L.lut_col[i] = S.lut_col[i];
+    for (int32_t i = threadIdx.x; i < S.n_lut_row; i += blockDim.x) L.lut_row[i] = S.lut_row[i];
 }
 
-// One workgroup = kTh consecutive rays (tile `tile`) of one node; each
-// wave owns a queue in LDS. A lane walks its ray with the Amanatides-Woo 3D
-// DDA (face-crossing parameters recomputed as (boundary - q) * (1/d); ties
-// step x, then y, then z; a voxel is visited while its entry parameter is
-// below the range and it is inside the grid). The grid byte of the next voxel
-// is loaded one step ahead. An occupied voxel ends the ray and its entry
-// parameter (or the range) is the ray's first hit; unknown voxels count into
-// the absolute bin of the ray's column and, in marginal mode, are queued;
-// whenever the queue could overflow it is drained against the ancestors.
-// Requires the tables in LDS; ends with the tile's bins added to the node's
-// global bins.
-//
-// kAhead = 2 keeps two voxels in flight per lane instead of one: the walk's
-// front runs a step ahead of the voxel being examined, so a grid load has a
-// whole step of work to hide behind. Launches with few waves per SIMD (the
-// small levels near the root) are bound by that load latency rather than by
-// instruction issue; results are the same either way.
-template <bool kMarginal, int kTh, int kQ, int kAhead = 1>
-__device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
-                                           int32_t tile, const TraceLDS& L) {
+// Path mask of node `node` over bricks [chunk * bricks, ...) of the mask grid:
+// the parent's path mask (none at the root, and none with anc_cap = 1) ORed
+// with the unknown voxels the node itself observes, decided voxel by voxel with
+// pixel_of and see_depth on the node's own window and buffer, i.e. the test its
+// descendants would make against it. A brick is left to the parent's bits
+// without testing when it lies beyond the range, or wholly outside the node's
+// azimuth wedge, by a margin that covers the brick's voxel centres (within
+// 3.5 * sqrt(3) of its centre, 3.5 * sqrt(2) across in x and y) and rounding.
+// The sensor tables are loaded into LDS only when some brick of the chunk is
+// tested. One wave tests one brick slice of 64 voxels at a time (64
+// consecutive grid bytes, two mask words). Whole workgroup; chunks past the
+// map's last brick do nothing (a batch launch covers its largest map).
+__device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
+                                            int32_t chunk, int32_t bricks, char* smem, uint8_t* s_live,
+                                            int32_t* s_any) {
     const int32_t tid = threadIdx.x;
+    const int32_t slot = Tr.mask_slot[node];
+    const uint32_t nb = M.mask_words >> 4;
+    const uint32_t lo = (uint32_t)chunk * (uint32_t)bricks;
+    if (slot < 0 || lo >= nb) return;                        // a leaf (nothing reads its mask), or past the map
+    uint32_t* out = Tr.masks + (size_t)slot * M.mask_words;
+    const int32_t a0 = Tr.anc_ptr[node];
+    const uint32_t* par = nullptr;
+    if (Tr.anc_cap > 1 && Tr.anc_ptr[node + 1] > a0)
+        par = Tr.masks + (size_t)Tr.mask_slot[Tr.anc_ids[a0]] * M.mask_words;
+    const float4 q = Tr.q4[node];
+    const int32_t c0 = Tr.c0[node];
+    int32_t c1 = c0 + S.WB;
+    c1 = c1 >= S.W ? c1 - S.W : c1;
+    AncLDS A;
+    A.qx = q.x; A.qy = q.y; A.qz = q.z; A.c0 = c0;
+    const float2 b0 = S.bv[c0], b1 = S.bv[c1];
+    A.b0x = b0.x; A.b0y = b0.y; A.b1x = b1.x; A.b1y = b1.y;
+    A.dpan_off = (uint32_t)node * (uint32_t)S.R;
+    A.pad[0] = A.pad[1] = A.pad[2] = 0u;
+    const int32_t cnt = (int32_t)min((uint32_t)bricks, nb - lo);
+    if (tid == 0) *s_any = 0;
+    __syncthreads();
+    if (tid < cnt) {
+        const uint32_t b = lo + (uint32_t)tid;
+        const uint32_t bx = b % M.mbx, by = (b / M.mbx) % M.mby, bz = b / (M.mbx * M.mby);
+        const float rx = (float)(bx * 8u) + 4.0f - q.x, ry = (float)(by * 8u) + 4.0f - q.y,
+                    rz = (float)(bz * 8u) + 4.0f - q.z;
+        const float reach = S.rv + 6.6f;                     // 3.5 sqrt(3) = 6.06, plus rounding
+        const bool near = rx * rx + ry * ry + rz * rz <= reach * reach;
+        const float w0 = A.b0x * ry - A.b0y * rx, w1 = A.b1x * ry - A.b1y * rx;
+        const bool wedge = (w0 >= -5.5f) & (w1 < 5.5f);      // 3.5 sqrt(2) = 4.95, plus rounding
+        const bool live = near & wedge;
+        s_live[tid] = (uint8_t)live;
+        if (live) *s_any = 1;
+    }
+    __syncthreads();
+    // bricks that cannot hold an observed voxel keep the parent's bits
+    for (int32_t w = tid; w < cnt * 16; w += blockDim.x)
+        if (!s_live[w >> 4]) out[lo * 16u + (uint32_t)w] = par ? par[lo * 16u + (uint32_t)w] : 0u;
+    if (!*s_any) return;
+    const TableLDS L = carve_tables(smem, S);
+    load_tables(L, S);
+    __syncthreads();
     const int32_t lane = tid & 63;
-    int32_t na = 0;
+    const float ts0 = L.ts[0], tsH = L.ts[S.H];
+    const gbytes_t grid = as_global(M.bricks);
+    const gfloats_t dpan = as_global(Tr.dpan);
+    for (int32_t i = tid >> 6; i < cnt; i += (int32_t)(blockDim.x >> 6)) {
+        if (!s_live[i]) continue;
+        const uint32_t b = lo + (uint32_t)i;
+        const int32_t bx = (int32_t)(b % M.mbx), by = (int32_t)((b / M.mbx) % M.mby), bz = (int32_t)(b / (M.mbx * M.mby));
+        const int32_t x = bx * 8 + (lane & 7), y = by * 8 + (lane >> 3);
+        const float cx = (float)x + 0.5f, cy = (float)y + 0.5f;
+        const uint32_t wbase = b << 4;
+        uint32_t pw = 0u;
+        if (par && lane < 16) pw = par[wbase + (uint32_t)lane];
+        // The lane's column of the brick: its 8 grid bytes (slice pz is 64 bytes
+        // further; (x, y, z) < 8 * mb <= 8 * nb is inside the bricked grid, and
+        // voxels past the true extent read the padding state, not unknown), the
+        // azimuth column of its pixels (the same for the 8 voxels, which share x
+        // and y), the row of each voxel, then the 8 depths, the loads of each
+        // batch issued together. The arithmetic is pixel_of's.
+        const uint32_t g0 = voxel_addr(x, y, bz * 8, M);
+        uint32_t st[8];
+#pragma unroll
+        for (int32_t pz = 0; pz < 8; ++pz) st[pz] = grid[g0 + (uint32_t)(pz * 64)];
+        const float rx = cx - A.qx, ry = cy - A.qy;
+        const float w0 = A.b0x * ry - A.b0y * rx;
+        const float w1 = A.b1x * ry - A.b1y * rx;
+        const bool wedge = (w0 >= 0.f) & (w1 < 0.f);
+        const float rho2 = rx * rx + ry * ry;
+        // column (computed for every lane; only lanes in the wedge use it, and the
+        // clamps keep every table index inside its table)
+        const float u0 = A.b0x * rx + A.b0y * ry;
+        float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
+        pa = u0 < 0.f ? 2.f - pa : pa;
+        const int32_t gc =
+            L.lut_col[(int32_t)__builtin_amdgcn_fmed3f(pa * S.lut_col_scale, 0.f, (float)(S.n_lut_col - 1))];
+        const int32_t cb = A.c0 + gc;
+        const float2 v0 = L.bv[cb], v1 = L.bv[cb + 1], v2 = L.bv[cb + 2];
+        const bool l0 = (gc == 0) | left_of(v0, rx, ry);
+        const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
+        const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
+        int32_t col = gc + (int32_t)l1;
+        if (wedge & !(l0 & !l2)) {      // (rare: a guess at a bucket edge)
+            for (;;) {
+                if (col + 1 >= S.WB || !left_of(L.bv[A.c0 + col + 1], rx, ry)) break;
+                ++col;
+            }
+            for (;;) {
+                if (col == 0 || left_of(L.bv[A.c0 + col], rx, ry)) break;
+                --col;
+            }
+        }
+        // (column < 4096 and H <= 2048: the product fits the 24-bit multiplier)
+        const uint32_t colbase = A.dpan_off + __umul24((uint32_t)wrap(A.c0 + col, S.W), (uint32_t)S.H);
+        const float irho = __builtin_amdgcn_rsqf(rho2);
+        uint32_t idx[8];
+        float r2[8];
+        bool ok[8];
+#pragma unroll
+        for (int32_t pz = 0; pz < 8; ++pz) {
+            const float rz = ((float)(bz * 8 + pz) + 0.5f) - A.qz;
+            const float range2 = rho2 + rz * rz;
+            const float sz = rz * fabsf(rz);
+            ok[pz] = (st[pz] == kUnknown) & wedge & (range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH);
+            const float tg = rz * irho;
+            const int32_t gr = L.lut_row[(int32_t)__builtin_amdgcn_fmed3f((tg - S.lut_row_lo) * S.lut_row_scale, 0.f,
+                                                                         (float)(S.n_lut_row - 1))];
+            const float e0 = L.ts[gr], e1 = L.ts[gr + 1], e2 = L.ts[min(gr + 2, S.H)];
+            const bool q0 = (gr == 0) | (sz >= rho2 * e0);
+            const bool q1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
+            const bool q2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
+            int32_t row = gr + (int32_t)q1;
+            if (ok[pz] & !(q0 & !q2)) {  // (rare: a guess at a bucket edge)
+                for (;;) {
+                    if (row + 1 >= S.H || !(sz >= rho2 * L.ts[row + 1])) break;
+                    ++row;
+                }
+                for (;;) {
+                    if (row == 0 || sz >= rho2 * L.ts[row]) break;
+                    --row;
+                }
+            }
+            idx[pz] = colbase + (uint32_t)row;
+            r2[pz] = range2;
+        }
+        float D[8];
+#pragma unroll
+        for (int32_t pz = 0; pz < 8; ++pz) D[pz] = dpan[ok[pz] ? idx[pz] : A.dpan_off];
+        // observed: the centre's squared range is at most its pixel's squared depth;
+        // lane l < 16 collects mask word l of the brick (slice l / 2) and stores it
+        uint32_t word = 0u;
+#pragma unroll
+        for (int32_t pz = 0; pz < 8; ++pz) {
+            const uint64_t bal = ballot(ok[pz] & (r2[pz] <= D[pz] * D[pz]));
+            word = lane == 2 * pz ? (uint32_t)bal : word;
+            word = lane == 2 * pz + 1 ? (uint32_t)(bal >> 32) : word;
+        }
+        if (lane < 16) out[wbase + (uint32_t)lane] = pw | word;
+    }
+}
+
+__global__ __launch_bounds__(kBuildThreads) void k_mask_build(MapDev M, SensorDev S, TreeDev Tr,
+                                                              const int32_t* __restrict__ nodes, int32_t chunks,
+                                                              int32_t bricks) {
+    extern __shared__ char smem[];
+    __shared__ uint8_t s_live[kMaxBuildBricks];
+    __shared__ int32_t s_any;
+    build_chunk(M, S, Tr, nodes[blockIdx.x / chunks], (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, &s_any);
+}
+
+// ---------------------------------------------------------------- ray traversal
+
+// One workgroup = kTh consecutive rays (tile `tile`) of one node. A lane walks
+// its ray with the Amanatides-Woo 3D DDA (face-crossing parameters recomputed
+// as (boundary - q) * (1/d); ties step x, then y, then z; a voxel is visited
+// while its entry parameter is below the range and it is inside the grid). An
+// occupied voxel ends the ray and its entry parameter (or the range) is the
+// ray's first hit. Unknown voxels count into the absolute bin of the ray's
+// column and, in marginal mode, into the marginal bin unless the parent's
+// path mask holds them (some ancestor observes them); the root has no
+// ancestor, so all its unknown voxels count. The grid byte of the next voxel is
+// requested before the step ends, and a mask word is used one step after it
+// was requested, so both loads have a step of work to hide behind. Ends with
+// the tile's bins added to the node's global bins.
+template <bool kMarginal, int kTh>
+__device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
+                                           int32_t tile, uint32_t* __restrict__ s_bins) {
+    const int32_t tid = threadIdx.x;
+    const uint32_t* pmask = nullptr;     // the parent's path mask
     if (kMarginal) {
         const int32_t a0 = Tr.anc_ptr[node];
-        na = min(Tr.anc_ptr[node + 1] - a0, Tr.anc_cap);     // the list is nearest first
-        for (int32_t k = tid; k < na; k += kTh) {
-            const int32_t a = Tr.anc_ids[a0 + k];
-            const float4 qa = Tr.q4[a];
-            const int32_t c0 = Tr.c0[a];
-            int32_t c1 = c0 + S.WB;
-            c1 = c1 >= S.W ? c1 - S.W : c1;
-            const float2 b0 = S.bv[c0], b1 = S.bv[c1];   // global copy: LDS tables are not yet synchronised
-            AncLDS A;
-            A.qx = qa.x; A.qy = qa.y; A.qz = qa.z; A.c0 = c0;
-            A.b0x = b0.x; A.b0y = b0.y; A.b1x = b1.x; A.b1y = b1.y;
-            A.dpan_off = (uint32_t)a * (uint32_t)S.R;
-            A.pad[0] = A.pad[1] = A.pad[2] = 0u;
-            L.anc[k] = A;
-        }
+        if (Tr.anc_cap > 0 && Tr.anc_ptr[node + 1] > a0)
+            pmask = Tr.masks + (size_t)Tr.mask_slot[Tr.anc_ids[a0]] * M.mask_words;
     }
-    for (int32_t i = tid; i < 2 * S.B; i += kTh) L.bins[i] = 0u;
+    const gwords_t pm = as_global(uniform_ptr(pmask));
+    for (int32_t i = tid; i < 2 * S.B; i += kTh) s_bins[i] = 0u;
     __syncthreads();
 
-    uint2* q = L.queue + (tid >> 6) * kQ;
     const int32_t r = tile * kTh + tid;
     const bool has_ray = r < S.R;
     const int32_t rr = has_ray ? r : 0;
     const int32_t bin = S.bin_of_col[rr / S.H];
-    // lanes whose previous lane has the same bin (DPP wave shift right by one;
-    // lane 0 receives -1)
-    const bool bin_as_prev = __builtin_amdgcn_update_dpp(-1, bin, 0x138, 0xf, 0xf, false) == bin;
-    const uint64_t bin_as_prev_mask = ballot(bin_as_prev);
     const float4 p = Tr.q4[node];
     const float4 d = S.d4[rr];
     const float4 iv = S.iv4[rr];
@@ -352,50 +438,39 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     float ty = (by - p.y) * fy;
     float tz = (bz - p.z) * fz;
     float t = 0.f, h = S.rv;
-    uint32_t n_abs = 0;
-    const uint32_t ebin = (uint32_t)bin << 16;
+    uint32_t n_abs = 0, n_new = 0;
     const gbytes_t grid = as_global(M.bricks);
     // the node lies inside the grid and t = 0 < rv, so its own voxel is
     // visited; a lane without a ray reads a padding byte and is done at once
-    int32_t qn = 0;
-    if constexpr (kAhead == 1) {
     uint32_t addr = has_ray ? voxel_addr(ix, iy, iz, M) : M.outside;   // address of the current voxel
-    uint32_t st = grid[addr];
-    uint64_t alive = ballot(has_ray);
-    while (alive) {
-        // Straight-line step without divergent branches: the current voxel's
-        // byte is used first, then the next voxel is found and its byte
-        // requested, so the load stays in flight until the next step uses it.
-        // A lane that has finished (or left the grid) reads a padding byte,
-        // which is neither unknown nor occupied. The first lane of each run
-        // of equal unknown voxels writes the queue entry.
+    // (this first byte is read through the generic pointer and the loop's through
+    // the global one, so the compiler keeps the loop's load at the end of the
+    // step instead of merging the two into one load at the top of the loop)
+    uint32_t st = M.bricks[addr];
+    uint32_t mw = 0u, mb = 0u;          // mask word of the last unknown voxel, and its bit
+    bool pend = false;                  // (a word requested in the previous step)
+    if (ballot(has_ray)) {
+        uint64_t alive;
         do {
+            // Straight-line step: the mask word requested in the previous step
+            // and the current voxel's byte are used first, then the next voxel is
+            // found and its byte requested. A lane that has finished (or left the
+            // grid) reads a padding byte, which is neither unknown nor occupied.
+            if (kMarginal) {
+                n_new += (pend & !((mw >> mb) & 1u)) ? 1u : 0u;
+                pend = false;
+            }
             const bool unk = st == kUnknown;
             const bool occ = st == kOccupied;
             h = occ ? t : h;
-            if (!kMarginal) n_abs += unk ? 1u : 0u;
-            // queueing (and the absolute count, which adds nothing in other
-            // steps) runs only in steps where some lane of the wave is on an
-            // unknown voxel (a wave-uniform branch)
-            if (kMarginal && ballot(unk) != 0) {
-                n_abs += unk ? 1u : 0u;
-                // a lane whose unknown voxel and bin equal the previous lane's
-                // joins that lane's entry; the first lane of each run appends
-                // one entry carrying the run's length. Keys of other lanes are
-                // distinct values above every address. (Lane 0 receives 0 from
-                // the shift; it is never a duplicate, its bin_as_prev being
-                // false.)
-                const uint32_t key = unk ? addr : (0xffffffc0u | (uint32_t)lane);
-                const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int32_t)key, 0x138, 0xf, 0xf, true);
-                const uint64_t dups = ballot(prev == key) & bin_as_prev_mask;
-                const uint64_t heads = ballot(unk) & ~dups;
-                const bool head = unk & !((prev == key) & bin_as_prev);
-                const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> 1) >> lane));
-                const int32_t below = (int32_t)lane_prefix(heads);
-                if (head)
-                    q[qn + below] =
-                        make_uint2((uint32_t)ix | ((uint32_t)iy << 16), (uint32_t)iz | ebin | (extra << 24));
-                qn = __builtin_amdgcn_readfirstlane(qn + __popcll(heads));
+            n_abs += unk ? 1u : 0u;
+            if (kMarginal && pm != nullptr) {
+                // every lane loads (a lane off unknown voxels reads word 0), so the
+                // word lands in the register the next step reads
+                const uint32_t off = (unk ? mask_word(ix, iy, iz, M) : 0u) << 2;   // < 2^29 bytes
+                mw = *(gwords_t)((gbytes_t)pm + off);
+                mb = mask_bit(ix, iy);
+                pend = unk;
             }
             const bool mx = (tx <= ty) & (tx <= tz);
             const bool my = !mx & (ty <= tz);
@@ -404,10 +479,9 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             ix += mx ? sx : 0;
             iy += my ? sy : 0;
             iz += mz ? sz : 0;
-            // a lane that stops here (occupied, finished or outside) compares
-            // +inf with the range: one comparison gives the mask, and the
-            // ballot below takes it as it stands
-            const float tn_go = st < kOccupied ? tn : __builtin_inff();
+            // a lane that stops here (occupied, finished or outside) compares +inf
+            // with the range: one comparison gives the mask the ballot takes
+            const float tn_go = st < kOccupied ? tn : inf;
             const bool next_ok = tn_go < S.rv;
             alive = ballot(next_ok);
             addr = next_ok ? voxel_addr(ix, iy, iz, M) : M.outside;
@@ -419,108 +493,31 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             ty = (by - p.y) * fy;
             tz = (bz - p.z) * fz;
             t = tn;
-        } while (alive && (!kMarginal || qn + 64 <= kQ));
-        if (kMarginal) {
-            drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, L.lut_col, L.lut_row, Tr.dpan, L.bins + S.B, lane);
-            qn = 0;
-        }
+        } while (alive);
     }
-    } else {
-    static_assert(kAhead == 2, "one or two voxels in flight");
-    // Slot a and slot b hold the two voxels in flight (grid address, state,
-    // entry parameter, coordinates packed as in a queue entry); they are
-    // examined alternately, a first. `live`: the lane has not yet examined a
-    // voxel that ends its ray, so a slot filled after that voxel is ignored.
-    // The front (ix, iy, iz and the face parameters) is the newest voxel in
-    // flight; refilling a slot takes the front one DDA step further. Once the
-    // front has left the grid it takes at most one more step before the lane
-    // examines the padding voxel it left through (which ends the ray) and
-    // stops loading; coordinates -2 and n + 1 still give an address inside the
-    // bricked grid (the coordinate bits are masked), whose byte is never
-    // examined.
-    bool live = has_ray;
-    uint32_t addr_a = has_ray ? voxel_addr(ix, iy, iz, M) : M.outside;
-    uint32_t st_a = grid[addr_a];
-    float t_a = 0.f;
-    uint32_t xy_a = (uint32_t)ix | ((uint32_t)iy << 16), z_a = (uint32_t)iz;
-    uint32_t addr_b, st_b, xy_b, z_b;
-    float t_b;
-    auto advance = [&](uint32_t& addr_s, uint32_t& st_s, float& t_s, uint32_t& xy_s, uint32_t& z_s) {
-        const bool mx = (tx <= ty) & (tx <= tz);
-        const bool my = !mx & (ty <= tz);
-        const bool mz = !mx & !my;
-        const float tn = mx ? tx : (my ? ty : tz);
-        ix += mx ? sx : 0;
-        iy += my ? sy : 0;
-        iz += mz ? sz : 0;
-        const bool ok = live & (tn < S.rv);
-        addr_s = ok ? voxel_addr(ix, iy, iz, M) : M.outside;
-        st_s = grid[addr_s];
-        bx += mx ? dbx : 0.f;
-        by += my ? dby : 0.f;
-        bz += mz ? dbz : 0.f;
-        tx = (bx - p.x) * fx;
-        ty = (by - p.y) * fy;
-        tz = (bz - p.z) * fz;
-        t_s = tn;
-        xy_s = (uint32_t)ix | ((uint32_t)iy << 16);
-        z_s = (uint32_t)iz;
-    };
-    auto examine = [&](uint32_t addr_s, uint32_t st_s, float t_s, uint32_t xy_s, uint32_t z_s) {
-        const bool unk = live & (st_s == kUnknown);
-        const bool occ = live & (st_s == kOccupied);
-        h = occ ? t_s : h;
-        if (!kMarginal) n_abs += unk ? 1u : 0u;
-        if (kMarginal && ballot(unk) != 0) {
-            n_abs += unk ? 1u : 0u;
-            // the same run-merging append as with one voxel in flight
-            const uint32_t key = unk ? addr_s : (0xffffffc0u | (uint32_t)lane);
-            const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int32_t)key, 0x138, 0xf, 0xf, true);
-            const uint64_t dups = ballot(prev == key) & bin_as_prev_mask;
-            const uint64_t heads = ballot(unk) & ~dups;
-            const bool head = unk & !((prev == key) & bin_as_prev);
-            const uint32_t extra = (uint32_t)__builtin_ctzll(~((dups >> 1) >> lane));
-            const int32_t below = (int32_t)lane_prefix(heads);
-            if (head) q[qn + below] = make_uint2(xy_s, z_s | ebin | (extra << 24));
-            qn = __builtin_amdgcn_readfirstlane(qn + __popcll(heads));
-        }
-        live = live & (st_s < kOccupied);
-    };
-    advance(addr_b, st_b, t_b, xy_b, z_b);
-    uint64_t alive = ballot(live);
-    while (alive) {
-        do {
-            examine(addr_a, st_a, t_a, xy_a, z_a);
-            advance(addr_a, st_a, t_a, xy_a, z_a);
-            examine(addr_b, st_b, t_b, xy_b, z_b);
-            advance(addr_b, st_b, t_b, xy_b, z_b);
-            alive = ballot(live);
-        } while (alive && (!kMarginal || qn + 128 <= kQ));
-        if (kMarginal) {
-            drain_queue(q, qn, L.anc, na, S, L.bv, L.ts, L.lut_col, L.lut_row, Tr.dpan, L.bins + S.B, lane);
-            qn = 0;
-        }
+    if (kMarginal) {
+        n_new += (pend & !((mw >> mb) & 1u)) ? 1u : 0u;
+        if (pm == nullptr) n_new = n_abs;                   // the root: nothing is observed yet
+        if (has_ray) Tr.dpan[(size_t)node * S.R + r] = h;
+        if (n_new) atomicAdd(&s_bins[S.B + bin], n_new);
     }
-    }
-    if (kMarginal && has_ray) Tr.dpan[(size_t)node * S.R + r] = h;
-    if (n_abs) atomicAdd(&L.bins[bin], n_abs);
+    if (n_abs) atomicAdd(&s_bins[bin], n_abs);
     __syncthreads();
     uint32_t* gb = Tr.bins + (size_t)node * 2 * S.B;
     for (int32_t i = tid; i < 2 * S.B; i += kTh) {
-        const uint32_t v = L.bins[i];
+        const uint32_t v = s_bins[i];
         if (v) atomicAdd(&gb[i], v);
     }
 }
 
-template <bool kMarginal, int kAhead>
+template <bool kMarginal>
 __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
                                                     const int32_t* __restrict__ nodes) {
-    constexpr int kTh = kShapes[0].threads, kQ = kShapes[0].queue;
-    static_assert(kTh == kThreads, "the per-tree path tiles rays by kThreads");
-    extern __shared__ char smem[];
-    const TraceLDS L = carve_lds<kTh, kQ>(smem, S);
-    load_tables<kTh>(L, S);
-    trace_tile<kMarginal, kTh, kQ, kAhead>(M, S, Tr, nodes[blockIdx.x / S.T], blockIdx.x % S.T, L);
+    __shared__ uint32_t s_bins[2 * kMaxBins];
+    // (workgroup-uniform values kept in scalar registers)
+    const int32_t item = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)S.T));
+    const int32_t tile = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x - item * S.T);
+    trace_tile<kMarginal, kThreads>(M, S, Tr, nodes[item], tile, s_bins);
 }
 
 // ---------------------------------------------------------------- window selection
@@ -597,20 +594,39 @@ __global__ void k_batch_zero(const BatchTree* __restrict__ trees, int32_t B2) {
 
 // One depth level of all trees at once: work item = (tree, node) from
 // `items` (tree << 32 | node), T workgroups per item.
-template <int kTh, int kQ, int kAhead>
+template <int kTh>
 __global__ __launch_bounds__(kTh) void k_trace_multi(const BatchTree* __restrict__ trees,
                                                      const unsigned long long* __restrict__ items, SensorDev S) {
-    extern __shared__ char smem[];
-    const TraceLDS L = carve_lds<kTh, kQ>(smem, S);
-    load_tables<kTh>(L, S);
-    const unsigned long long it = items[blockIdx.x / S.T];
+    __shared__ uint32_t s_bins[2 * kMaxBins];
+    // (workgroup-uniform values kept in scalar registers)
+    const int32_t item = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)S.T));
+    const int32_t tile = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x - item * S.T);
+    const unsigned long long it = items[item];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
     SensorDev St = S;
     St.rv = BT.rv;
     St.rv2 = BT.rv2;
     const MapDev M = BT.map;     // copies: loaded once, not re-read through the descriptor
     const TreeDev Tr = BT.td;
-    trace_tile<true, kTh, kQ, kAhead>(M, St, Tr, (int32_t)(uint32_t)it, blockIdx.x % S.T, L);
+    trace_tile<true, kTh>(M, St, Tr, (int32_t)(uint32_t)it, tile, s_bins);
+}
+
+// Path masks of one depth level's nodes with children, all trees at once:
+// `chunks` workgroups per item, `bricks` bricks each.
+__global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchTree* __restrict__ trees,
+                                                                    const unsigned long long* __restrict__ items,
+                                                                    SensorDev S, int32_t chunks, int32_t bricks) {
+    extern __shared__ char smem[];
+    __shared__ uint8_t s_live[kMaxBuildBricks];
+    __shared__ int32_t s_any;
+    const unsigned long long it = items[blockIdx.x / chunks];
+    const BatchTree& BT = trees[(uint32_t)(it >> 32)];
+    SensorDev St = S;
+    St.rv = BT.rv;
+    St.rv2 = BT.rv2;
+    const MapDev M = BT.map;
+    const TreeDev Tr = BT.td;
+    build_chunk(M, St, Tr, (int32_t)(uint32_t)it, (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, &s_any);
 }
 
 // Window selection for one depth level of all trees; writes each tree's
@@ -678,16 +694,14 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
 
 int shape_count() { return kNumShapes; }
 
-void shape_of(int shape, int* threads, int* queue) {
+void shape_of(int shape, int* threads, int* bricks) {
     *threads = kShapes[shape].threads;
-    *queue = kShapes[shape].queue;
+    *bricks = kShapes[shape].bricks;
 }
 
-size_t trace_lds_bytes(const SensorDev& sd, int shape, int32_t max_anc) {
-    const size_t tables = sizeof(float2) * (2 * sd.W + 1) + sizeof(float) * (sd.H + 1) + sizeof(uint32_t) * 2 * sd.B +
-                          sizeof(uint16_t) * (sd.n_lut_col + sd.n_lut_row);
-    return ((tables + 15) & ~(size_t)15) + sizeof(uint2) * kShapes[shape].queue * (kShapes[shape].threads / 64) +
-           sizeof(AncLDS) * (size_t)max_anc;
+size_t build_lds_bytes(const SensorDev& sd) {
+    return sizeof(float2) * (2 * sd.W + 1) + sizeof(float) * (sd.H + 1) +
+           sizeof(uint16_t) * (sd.n_lut_col + sd.n_lut_row);
 }
 
 size_t lds_limit() {
@@ -698,26 +712,33 @@ size_t lds_limit() {
     return (size_t)v;
 }
 
-bool shape_fits(const SensorDev& sd, int shape, int32_t max_anc) {
-    return trace_lds_bytes(sd, shape, max_anc) <= lds_limit();
-}
-
 int32_t tiles_per_node(const SensorDev& sd, int shape) {
     return (sd.R + kShapes[shape].threads - 1) / kShapes[shape].threads;
 }
 
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
-                        int32_t n_nodes, bool marginal, int32_t max_anc, hipStream_t s) {
+                        int32_t n_nodes, bool marginal, hipStream_t s) {
     if (n_nodes <= 0) return hipSuccess;
     dim3 grid((unsigned)n_nodes * (unsigned)sd.T);
-    size_t lds = trace_lds_bytes(sd, 0, marginal ? max_anc : 0);
-    if (lds > lds_limit()) return hipErrorInvalidConfiguration;
-    if (marginal && (int64_t)grid.x < kAheadWorkgroups)
-        hipLaunchKernelGGL((k_trace<true, 2>), grid, dim3(kThreads), lds, s, m, sd, td, nodes);
-    else if (marginal)
-        hipLaunchKernelGGL((k_trace<true, 1>), grid, dim3(kThreads), lds, s, m, sd, td, nodes);
+    if (marginal)
+        hipLaunchKernelGGL((k_trace<true>), grid, dim3(kThreads), 0, s, m, sd, td, nodes);
     else
-        hipLaunchKernelGGL((k_trace<false, 1>), grid, dim3(kThreads), lds, s, m, sd, td, nodes);
+        hipLaunchKernelGGL((k_trace<false>), grid, dim3(kThreads), 0, s, m, sd, td, nodes);
+    return hipGetLastError();
+}
+
+static int32_t build_chunks(const MapDev& m, int32_t bricks) {
+    return (int32_t)(((m.mask_words >> 4) + (uint32_t)bricks - 1) / (uint32_t)bricks);
+}
+
+hipError_t launch_mask_build(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
+                             int32_t n_nodes, hipStream_t s) {
+    if (n_nodes <= 0) return hipSuccess;
+    const int32_t bricks = kShapes[0].bricks, chunks = build_chunks(m, bricks);
+    const size_t lds = build_lds_bytes(sd);
+    if (lds + kMaxBuildBricks > lds_limit()) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_mask_build, dim3((unsigned)n_nodes * (unsigned)chunks), dim3(kBuildThreads), lds, s, m, sd,
+                       td, nodes, chunks, bricks);
     return hipGetLastError();
 }
 
@@ -872,45 +893,54 @@ hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t m
 
 namespace {
 
-template <int kTh, int kQ>
+template <int kTh>
 void launch_multi(const BatchTree* trees, const unsigned long long* items, int32_t n_items, const SensorDev& sd,
-                  int32_t max_anc, hipStream_t s, hipEvent_t t0, hipEvent_t t1, int shape, bool ahead) {
+                  hipStream_t s, hipEvent_t t0, hipEvent_t t1, int shape) {
     SensorDev st = sd;
     st.T = tiles_per_node(sd, shape);
     const dim3 grid((unsigned)n_items * (unsigned)st.T);
-    const uint32_t lds = (uint32_t)trace_lds_bytes(sd, shape, max_anc);
-    auto kern = ahead ? k_trace_multi<kTh, kQ, 2> : k_trace_multi<kTh, kQ, 1>;
     if (t0 && t1)
-        hipExtLaunchKernelGGL(kern, grid, dim3(kTh), lds, s, t0, t1, 0u, trees, items, st);
+        hipExtLaunchKernelGGL(k_trace_multi<kTh>, grid, dim3(kTh), 0, s, t0, t1, 0u, trees, items, st);
     else
-        hipLaunchKernelGGL(kern, grid, dim3(kTh), lds, s, trees, items, st);
+        hipLaunchKernelGGL(k_trace_multi<kTh>, grid, dim3(kTh), 0, s, trees, items, st);
 }
 
 template <int I>
 void launch_multi_shape(int shape, const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                        const SensorDev& sd, int32_t max_anc, hipStream_t s, hipEvent_t t0, hipEvent_t t1,
-                        bool ahead) {
+                        const SensorDev& sd, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     if constexpr (I < kNumShapes) {
         if (shape == I)
-            launch_multi<kShapes[I].threads, kShapes[I].queue>(trees, items, n_items, sd, max_anc, s, t0, t1, I,
-                                                               ahead);
+            launch_multi<kShapes[I].threads>(trees, items, n_items, sd, s, t0, t1, I);
         else
-            launch_multi_shape<I + 1>(shape, trees, items, n_items, sd, max_anc, s, t0, t1, ahead);
+            launch_multi_shape<I + 1>(shape, trees, items, n_items, sd, s, t0, t1);
     }
 }
 
 }  // namespace
 
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
-                              const SensorDev& sd, int32_t max_anc, hipStream_t s, int shape, hipEvent_t t0,
-                              hipEvent_t t1, bool ahead) {
+                              const unsigned long long* mitems, int32_t n_mitems, uint32_t mask_bricks,
+                              const SensorDev& sd, hipStream_t s, int shape, hipEvent_t t0, hipEvent_t t1,
+                              hipEvent_t b0, hipEvent_t b1) {
     if (n_items <= 0) return hipSuccess;
-    if (shape < 0 || shape >= kNumShapes || max_anc < 0 || max_anc > kMaxAnc) return hipErrorInvalidValue;
-    if (!shape_fits(sd, shape, max_anc)) return hipErrorInvalidConfiguration;
-    launch_multi_shape<0>(shape, trees, items, n_items, sd, max_anc, s, t0, t1, ahead);
+    if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
+    const size_t lds = build_lds_bytes(sd);
+    if (lds + kMaxBuildBricks > lds_limit()) return hipErrorInvalidConfiguration;
+    launch_multi_shape<0>(shape, trees, items, n_items, sd, s, t0, t1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finish_multi, dim3((unsigned)n_items), dim3(kThreads), 0, s, trees, items, sd);
+    e = hipGetLastError();
+    if (e != hipSuccess || n_mitems <= 0) return e;
+    const int32_t bricks = kShapes[shape].bricks;
+    const int32_t chunks = (int32_t)((mask_bricks + (uint32_t)bricks - 1) / (uint32_t)bricks);
+    if ((uint64_t)n_mitems * (uint64_t)chunks >= (1ull << 32)) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)n_mitems * (unsigned)chunks);
+    if (b0 && b1)
+        hipExtLaunchKernelGGL(k_mask_build_multi, grid, dim3(kBuildThreads), lds, s, b0, b1, 0u, trees, mitems, sd,
+                              chunks, bricks);
+    else
+        hipLaunchKernelGGL(k_mask_build_multi, grid, dim3(kBuildThreads), lds, s, trees, mitems, sd, chunks, bricks);
     return hipGetLastError();
 }
 

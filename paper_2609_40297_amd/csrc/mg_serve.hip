@@ -95,6 +95,8 @@ struct Request {
     mg_tree tree = nullptr;
     const std::vector<int32_t>* level_ptr = nullptr;
     const std::vector<int32_t>* level_nodes = nullptr;
+    const std::vector<int32_t>* mask_level_ptr = nullptr;   // nodes with children, by level
+    const std::vector<int32_t>* mask_nodes = nullptr;
     int32_t level = 0, levels = 0;
     int rc = MG_OK;
     int state = 0;                   // 0 queued, 1 in flight, 2 done (rc tells success)
@@ -265,6 +267,8 @@ int mg_server_s::step() {
         mgb::tree_view(r->tree, &v);
         r->level_ptr = v.level_ptr;
         r->level_nodes = v.level_nodes;
+        r->mask_level_ptr = v.mask_level_ptr;
+        r->mask_nodes = v.mask_nodes;
         r->level = 0;
         r->levels = v.levels;
         r->state = 1;
@@ -279,18 +283,20 @@ int mg_server_s::step() {
     }
     if (active.empty()) return MG_OK;
 
-    // descriptors and the work list of this step
-    size_t n_items = 0, stage = 0;
-    int32_t max_anc = 0;     // a node of depth level d has d ancestors
+    // descriptors and the work lists of this step: every node of the current
+    // levels, and those of them with children (their path masks are built)
+    size_t n_items = 0, n_mitems = 0, stage = 0;
+    uint32_t mask_bricks = 0;
     for (Request* r : active) {
-        max_anc = std::max(max_anc, r->level);
         n_items += (size_t)((*r->level_ptr)[r->level + 1] - (*r->level_ptr)[r->level]);
+        n_mitems += (size_t)((*r->mask_level_ptr)[r->level + 1] - (*r->mask_level_ptr)[r->level]);
+        mask_bricks = std::max(mask_bricks, mgb::map_dev(r->map)->mask_words >> 4);
         if (r->level + 1 == r->levels) stage += 2 * (size_t)r->n;
     }
-    int rc = grow(active.size(), n_items, stage);
+    int rc = grow(active.size(), n_items + n_mitems, stage);
     if (rc != MG_OK) return rc;
     SensorDev sd{};
-    size_t k = 0;
+    size_t k = 0, km = n_items;
     for (size_t i = 0; i < active.size(); ++i) {
         Request* r = active[i];
         mgb::TreeView v;
@@ -306,14 +312,16 @@ int mg_server_s::step() {
         bt.depth = nullptr;
         for (int32_t j = (*r->level_ptr)[r->level]; j < (*r->level_ptr)[r->level + 1]; ++j)
             h_items[k++] = ((unsigned long long)i << 32) | (uint32_t)(*r->level_nodes)[j];
+        for (int32_t j = (*r->mask_level_ptr)[r->level]; j < (*r->mask_level_ptr)[r->level + 1]; ++j)
+            h_items[km++] = ((unsigned long long)i << 32) | (uint32_t)(*r->mask_nodes)[j];
     }
     hipError_t e = hipMemcpyAsync(d_trees, h_trees, sizeof(BatchTree) * active.size(), hipMemcpyHostToDevice, compute);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(d_items, h_items, sizeof(unsigned long long) * n_items, hipMemcpyHostToDevice, compute);
-    // (a level of few nodes keeps two voxels in flight per lane, as in the batch path)
-    const bool ahead = (int64_t)n_items * tiles_per_node(sd, 0) < kAheadWorkgroups;
+        e = hipMemcpyAsync(d_items, h_items, sizeof(unsigned long long) * (n_items + n_mitems), hipMemcpyHostToDevice,
+                           compute);
     if (e == hipSuccess)
-        e = launch_batch_level(d_trees, d_items, (int32_t)n_items, sd, max_anc, compute, 0, nullptr, nullptr, ahead);
+        e = launch_batch_level(d_trees, d_items, (int32_t)n_items, d_items + n_items, (int32_t)n_mitems, mask_bricks, sd,
+                               compute, 0);
     size_t so = 0;
     std::vector<std::pair<Request*, size_t>> finishing;
     for (Request* r : active) {

@@ -119,8 +119,8 @@ def test_launch_shape_table_and_config_validation():
     from paper_2609_40297_amd import mg
     shapes = mg.mg_trace_shapes()
     assert len(shapes) >= 2
-    for th, q in shapes:
-        assert th % 64 == 0 and 64 <= th <= 1024 and q % 64 == 0 and q >= 128
+    for th, bricks in shapes:      # rays per trace workgroup, bricks per mask-builder workgroup
+        assert th % 64 == 0 and 64 <= th <= 1024 and 16 <= bricks <= 128
     for bad in [(-2, 0), (len(shapes), 0), (0, 2)]:
         with pytest.raises(mg.MGError) as e:
             mg._check(mg.lib().mg_batch_config(*bad))

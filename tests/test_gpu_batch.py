@@ -128,7 +128,8 @@ def test_batch_rejects_mixed_geometry(mg):
 
 
 def test_kernel_timing_counts_trace_launches_and_keeps_results(mg):
-    """Timed launches (events carried by the dispatch) give the same results and one interval per level."""
+    """Timed launches (events carried by the dispatch) give the same results and intervals for every trace
+    and mask-builder launch."""
     import torch
     w = W.make("tiny")
     M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
@@ -147,7 +148,9 @@ def test_kernel_timing_counts_trace_launches_and_keeps_results(mg):
     shape, _ = mg.mg_batch_plan_info([T.handle])
     threads = mg.mg_trace_shapes()[shape][0]
     tiles = -(-sen.n_az * sen.n_el // threads)
-    assert n % 2 == 0 and n // 2 >= levels      # at least one launch per level (groups may split levels)
+    # per call: at least one trace launch per level (groups may split levels), and a mask-builder
+    # launch for every trace launch whose nodes include one with children (not the deepest level)
+    assert n % 2 == 0 and n // 2 >= 2 * levels - 1
     assert wg == 2 * T.n * tiles                # every node traced exactly once per call
     assert ms > 0.0 and 0.0 < busy <= ms * 1.001
     assert mg.mg_timing_read() == (0.0, 0.0, 0, 0)
@@ -171,10 +174,10 @@ def test_every_launch_shape_gives_identical_results(mg):
     shapes = mg.mg_trace_shapes()
     log(f"[shapes] {shapes}")
     try:
-        for k, (th, q) in enumerate(shapes):
+        for k, (th, bricks) in enumerate(shapes):
             for graph in (False, True):
                 mg.mg_batch_config(k, graph)
-                log(f"[shapes] shape {k} ({th} rays/WG, queue {q}) graph={graph}")
+                log(f"[shapes] shape {k} ({th} rays/WG, {bricks} mask bricks/WG) graph={graph}")
                 _check_batch(mg, trees, ref)
                 assert mg.mg_batch_plan_info([t.handle for t in trees]) == (k, graph)
     finally:

@@ -71,10 +71,12 @@ def test_alone_and_mixed_are_identical(mg, scene):
 def test_small_arena_and_single_slot(mg, scene):
     sen, reqs, ref, _ = scene
     # room for roughly the largest tree only: admission must wait for memory
-    import math
-    biggest = max(len(p) for _, _, p in reqs)
-    per_node = sen.n_az * sen.n_el * 4 + 2 * sen.yaw_bins * 4 + 64
-    S = mg.Server(sen, max_inflight=8, arena_bytes=int(biggest * per_node * 1.3) + (1 << 20))
+    biggest = 0
+    for M, pos, par in reqs:
+        T = mg.Tree(M, pos, par, sen)
+        biggest = max(biggest, T.footprint_bytes)
+        T.close()
+    S = mg.Server(sen, max_inflight=8, arena_bytes=int(biggest * 1.3) + (1 << 20))
     tickets = [S.submit(M, pos, par) for M, pos, par in reqs]
     _check([S.wait(t)[:2] for t in tickets], ref)
     S.close()
