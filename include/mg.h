@@ -175,6 +175,22 @@ int mg_eval_marginal_levelsync(mg_tree tree, void* hip_stream, uint32_t* gain, i
 int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
                            int32_t* yaw_bin, float* depth);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture
+ * planning, tight serving loops, harnesses that forbid hipMalloc): the
+ * evaluation of mg_eval_marginal_batch with the same outputs and results, but
+ * no allocation of any kind. The launch descriptors and per-level work lists
+ * (8 bytes per node and per node with children, plus about 0.3 KB per tree)
+ * go into a fixed 16 MiB device array that the library holds on every device
+ * it runs on until the process ends, written from a fixed host array on
+ * hip_stream. Every depth level runs on hip_stream (no stream groups, launch
+ * shape 0, no graph). The call waits until the previous call's copies have
+ * left the host array. Calls that overlap on one device (other streams or
+ * threads) share the array and race: serialise them. MG_E_UNSUPPORTED for more
+ * than 4096 trees or descriptors and lists above 16 MiB; other errors as
+ * mg_eval_marginal_batch. */
+int mg_eval_marginal_batch_noalloc(const mg_tree* trees, int32_t n_trees, void* hip_stream, uint32_t* gain,
+                                   int32_t* yaw_bin, float* depth);
+
 /* Path score of every node of a batch (Sec. III-C): traversal cost
  * c(n) = c(Pa(n)) + |p_n - p_Pa(n)| in metres (eq. 3) and exponential
  * objective o(n) = o(Pa(n)) + g(n) exp(-lambda c(n)) (eq. 4), with g(n) the

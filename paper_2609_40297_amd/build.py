@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = ["mg_api.hip", "mg_kernels.hip", "mg_batch.hip", "mg_serve.hip", "mg_interval.hip", "mg_map.hip", "mg_exact.hip"]
+SOURCES = ["mg_api.hip", "mg_kernels.hip", "mg_batch.hip", "mg_serve.hip", "mg_interval.hip", "mg_map.hip", "mg_exact.hip",
+           "mg_noalloc.hip"]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

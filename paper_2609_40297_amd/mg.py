@@ -30,7 +30,7 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
            "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read",
-           "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal")
+           "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal", "mg_eval_marginal_batch_noalloc")
 
 
 class MGError(RuntimeError):
@@ -81,6 +81,8 @@ def lib() -> C.CDLL:
         L.mg_interval_tables.argtypes = [C.POINTER(mg_sensor), C.c_float, I32, I32, P, P, P, P]
         L.mg_eval_marginal_levelsync.argtypes = [P, P, P, P, P, P, P]
         L.mg_eval_marginal_batch.argtypes = [P, I32, P, P, P, P]
+        L.mg_eval_marginal_batch_noalloc.argtypes = [P, I32, P, P, P, P]
+        L.mg_eval_marginal_batch_noalloc.restype = C.c_int
         L.mg_eval_absolute.argtypes = [P, P, P, P]
         L.mg_sensor_tables.argtypes = [C.POINTER(mg_sensor), P, P, P, P, P, P]
         L.mg_server_create.argtypes = [C.POINTER(mg_server_config), C.POINTER(P)]
@@ -226,6 +228,12 @@ def mg_eval_marginal_batch(trees: Sequence[int], gain, yaw_bin, depth=None, stre
     arr = (C.c_void_p * len(trees))(*trees)
     _check(lib().mg_eval_marginal_batch(C.cast(arr, C.c_void_p), len(trees), _stream(stream), _dev_ptr(gain),
                                         _dev_ptr(yaw_bin), _dev_ptr(depth)))
+
+
+def mg_eval_marginal_batch_noalloc(trees: Sequence[int], gain, yaw_bin, depth=None, stream=None):
+    arr = (C.c_void_p * len(trees))(*trees)
+    _check(lib().mg_eval_marginal_batch_noalloc(C.cast(arr, C.c_void_p), len(trees), _stream(stream),
+                                                _dev_ptr(gain), _dev_ptr(yaw_bin), _dev_ptr(depth)))
 
 
 def mg_eval_absolute(tree: int, gain, yaw_bin, stream=None):
