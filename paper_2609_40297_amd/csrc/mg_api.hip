@@ -369,7 +369,8 @@ int map_alloc(int32_t nx, int32_t ny, int32_t nz, float voxel_m, const float ori
     std::unique_ptr<mg_map_s> m(new (std::nothrow) mg_map_s());
     if (!m) return fail(MG_E_NOMEM, "host allocation failed");
     HIP_TRY(hipGetDevice(&m->device));
-    hipError_t e = hipMalloc(&m->bricks, padded);
+    const size_t n_mbricks = (size_t)((nx + 7) / 8) * ((ny + 7) / 8) * ((nz + 7) / 8);
+    hipError_t e = hipMalloc(&m->bricks, padded + n_mbricks);      // the grid, then the brick flags
     if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? MG_E_NOMEM : MG_E_DEVICE, "map allocation: %s", hipGetErrorString(e));
     m->dev.bricks = m->bricks;
@@ -386,9 +387,10 @@ int map_alloc(int32_t nx, int32_t ny, int32_t nz, float voxel_m, const float ori
     m->dev.mby = (uint32_t)(ny + 7) / 8u;
     m->dev.mbz = (uint32_t)(nz + 7) / 8u;
     m->dev.mask_words = 16u * m->dev.mbx * m->dev.mby * m->dev.mbz;    // < 2^32 / 32 (voxels < 2^32)
+    m->dev.brick_unk = m->bricks + padded;
     m->voxel_m = voxel_m;
     for (int a = 0; a < 3; ++a) m->origin[a] = origin_m[a];
-    m->bytes = padded;
+    m->bytes = padded + n_mbricks;
     *out = std::move(m);
     return MG_OK;
 }
@@ -413,6 +415,7 @@ extern "C" int mg_map_create(const uint8_t* states, int32_t nx, int32_t ny, int3
     hipError_t e = hipMalloc(&dense, nvox);
     if (e == hipSuccess) e = hipMemcpyAsync(dense, states, nvox, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_brick(dense, m->bricks, m->dev, s);
+    if (e == hipSuccess) e = launch_brick_flags(m->dev, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dense);
     if (e != hipSuccess) {
@@ -439,6 +442,7 @@ extern "C" int mg_map_create_tsdf(const float* distance, const float* weight, in
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = launch_fill_outside(m->dev, s);
     if (e == hipSuccess) e = launch_tsdf_grid(distance, weight, m->dev, surface_m, min_weight, s);
+    if (e == hipSuccess) e = launch_brick_flags(m->dev, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(m->bricks);
@@ -468,6 +472,7 @@ extern "C" int mg_map_update_tsdf(mg_map map, void* hip_stream, const float* dis
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_TRY(whole ? launch_tsdf_grid(distance, weight, map->dev, surface_m, min_weight, s)
                   : launch_tsdf_box(distance, weight, map->dev, lo, size, surface_m, min_weight, s));
+    HIP_TRY(launch_brick_flags(map->dev, s));
     return MG_OK;
 }
 
@@ -480,6 +485,7 @@ extern "C" int mg_map_update(mg_map map, void* hip_stream, const uint32_t* voxel
     hipStream_t s = (hipStream_t)hip_stream;
     if (rejected) HIP_TRY(launch_zero_u32(rejected, 1, s));
     HIP_TRY(launch_map_scatter(voxel_ids, states, (uint32_t)count, map->dev, rejected, s));
+    HIP_TRY(launch_brick_flags(map->dev, s));
     return MG_OK;
 }
 

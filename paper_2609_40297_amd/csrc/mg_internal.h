@@ -33,6 +33,9 @@ struct MapDev {
     // the grid, ceil(n / 8), and 32-bit words per mask (16 per brick).
     uint32_t mbx, mby, mbz;
     uint32_t mask_words;
+    // [mbx * mby * mbz] per mask brick: 1 when it holds an unknown voxel (kept
+    // current by every write of the map's states)
+    uint8_t* brick_unk;
 };
 
 // Byte address of voxel (x, y, z) in the bricked grid, for -1 <= x <= nx
@@ -127,6 +130,8 @@ hipError_t launch_map_scatter(const uint32_t* ids, const uint8_t* states, uint32
                               uint32_t* rejected, hipStream_t s);
 hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s);
 hipError_t launch_fill_outside(const MapDev& m, hipStream_t s);
+// Recomputes brick_unk from the states (after any write of the states).
+hipError_t launch_brick_flags(const MapDev& m, hipStream_t s);
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
                         int32_t n_nodes, bool marginal, hipStream_t s);
 // Path masks of the listed nodes (all with children), after their windows are chosen.

@@ -56,6 +56,24 @@ __global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__
     }
 }
 
+// brick_unk[b] = 1 when mask brick b holds an unknown voxel: one wave per
+// brick, each lane reading 8 of its 512 bytes (padding voxels past the grid
+// hold kOutside).
+__global__ void k_brick_flags(MapDev m) {
+    const uint32_t nb = m.mask_words >> 4;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < nb; b += (gridDim.x * blockDim.x) >> 6) {
+        const uint32_t bx = b % m.mbx, by = (b / m.mbx) % m.mby, bz = b / (m.mbx * m.mby);
+        const uint32_t base = voxel_addr((int32_t)(bx * 8u), (int32_t)(by * 8u), (int32_t)(bz * 8u), m);
+        const uint64_t v = *reinterpret_cast<const uint64_t*>(m.bricks + base + lane * 8u);
+        bool unk = false;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) unk |= ((v >> (8 * k)) & 0xffu) == kUnknown;
+        const uint64_t any = ballot(unk);
+        if (lane == 0) m.brick_unk[b] = any != 0 ? 1 : 0;
+    }
+}
+
 __global__ void k_zero_u32(uint32_t* __restrict__ p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0u;
@@ -219,7 +237,7 @@ __device__ __forceinline__ void load_tables(const TableLDS& L, const SensorDev& 
 
 // Path mask of node `node` over bricks [chunk * bricks, ...) of the mask grid:
 // the parent's path mask (none at the root, and none with anc_cap = 1) ORed
-// with the unknown voxels the node itself observes, decided voxel by voxel with
+// with the voxels the node itself observes, decided voxel by voxel with
 // pixel_of and see_depth on the node's own window and buffer, i.e. the test its
 // descendants would make against it. A brick is left to the parent's bits
 // without testing when it lies beyond the range, or wholly outside the node's
@@ -264,7 +282,8 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         const bool near = rx * rx + ry * ry + rz * rz <= reach * reach;
         const float w0 = A.b0x * ry - A.b0y * rx, w1 = A.b1x * ry - A.b1y * rx;
         const bool wedge = (w0 >= -5.5f) & (w1 < 5.5f);      // 3.5 sqrt(2) = 4.95, plus rounding
-        const bool live = near & wedge;
+        // (a brick without unknown voxels needs no bits: only unknown voxels' bits are read)
+        const bool live = near & wedge & (M.brick_unk[b] != 0);
         s_live[tid] = (uint8_t)live;
         if (live) *s_any = 1;
     }
@@ -278,9 +297,10 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     __syncthreads();
     const int32_t lane = tid & 63;
     const float ts0 = L.ts[0], tsH = L.ts[S.H];
-    const gbytes_t grid = as_global(M.bricks);
-    const gfloats_t dpan = as_global(Tr.dpan);
-    for (int32_t i = tid >> 6; i < cnt; i += (int32_t)(blockDim.x >> 6)) {
+    const gfloats_t dnode = as_global(uniform_ptr(Tr.dpan + (size_t)node * S.R));   // the node's panorama
+    // (the wave's brick is wave-uniform: its index arithmetic stays scalar)
+    const int32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int32_t i = wave; i < cnt; i += (int32_t)(blockDim.x >> 6)) {
         if (!s_live[i]) continue;
         const uint32_t b = lo + (uint32_t)i;
         const int32_t bx = (int32_t)(b % M.mbx), by = (int32_t)((b / M.mbx) % M.mby), bz = (int32_t)(b / (M.mbx * M.mby));
@@ -289,16 +309,11 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         const uint32_t wbase = b << 4;
         uint32_t pw = 0u;
         if (par && lane < 16) pw = par[wbase + (uint32_t)lane];
-        // The lane's column of the brick: its 8 grid bytes (slice pz is 64 bytes
-        // further; (x, y, z) < 8 * mb <= 8 * nb is inside the bricked grid, and
-        // voxels past the true extent read the padding state, not unknown), the
-        // azimuth column of its pixels (the same for the 8 voxels, which share x
-        // and y), the row of each voxel, then the 8 depths, the loads of each
-        // batch issued together. The arithmetic is pixel_of's.
-        const uint32_t g0 = voxel_addr(x, y, bz * 8, M);
-        uint32_t st[8];
-#pragma unroll
-        for (int32_t pz = 0; pz < 8; ++pz) st[pz] = grid[g0 + (uint32_t)(pz * 64)];
+        // The lane's column of the brick: the azimuth column of its pixels (the
+        // same for the 8 voxels, which share x and y), the row of each voxel,
+        // then the 8 depths, loaded together. The arithmetic is pixel_of's. The
+        // voxels' states are not read: only unknown voxels' bits are ever looked
+        // up, so bits of known voxels (and of voxels past the grid) do not matter.
         const float rx = cx - A.qx, ry = cy - A.qy;
         const float w0 = A.b0x * ry - A.b0y * rx;
         const float w1 = A.b1x * ry - A.b1y * rx;
@@ -327,42 +342,65 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
                 --col;
             }
         }
-        // (column < 4096 and H <= 2048: the product fits the 24-bit multiplier)
-        const uint32_t colbase = A.dpan_off + __umul24((uint32_t)wrap(A.c0 + col, S.W), (uint32_t)S.H);
+        // (column < 4096 and H <= 2048: the product fits the 24-bit multiplier; the
+        // index is into the node's own panorama, R < 2^22 entries)
+        const uint32_t colbase = __umul24((uint32_t)wrap(A.c0 + col, S.W), (uint32_t)S.H);
         const float irho = __builtin_amdgcn_rsqf(rho2);
+        // Rows: the row of a voxel is the number of inner row boundaries j in
+        // 1..H-1 with sz >= rho2 * ts[j] (ts and hence rho2 * ts[j] grow with j,
+        // so they form a prefix). Within the lane's column sz grows with z, so
+        // the count never falls from one slice to the next: slice 0 takes the
+        // guess table and its settle (exact for any sz: the table's clamped ends
+        // give 0 and H - 1 outside the band), each later slice checks the next
+        // two boundaries and walks on only when both are passed (steep voxels
+        // near the node). Lanes outside the wedge never use their rows.
         uint32_t idx[8];
         float r2[8];
         bool ok[8];
+        int32_t row = 0;
 #pragma unroll
         for (int32_t pz = 0; pz < 8; ++pz) {
             const float rz = ((float)(bz * 8 + pz) + 0.5f) - A.qz;
             const float range2 = rho2 + rz * rz;
             const float sz = rz * fabsf(rz);
-            ok[pz] = (st[pz] == kUnknown) & wedge & (range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH);
-            const float tg = rz * irho;
-            const int32_t gr = L.lut_row[(int32_t)__builtin_amdgcn_fmed3f((tg - S.lut_row_lo) * S.lut_row_scale, 0.f,
-                                                                         (float)(S.n_lut_row - 1))];
-            const float e0 = L.ts[gr], e1 = L.ts[gr + 1], e2 = L.ts[min(gr + 2, S.H)];
-            const bool q0 = (gr == 0) | (sz >= rho2 * e0);
-            const bool q1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
-            const bool q2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
-            int32_t row = gr + (int32_t)q1;
-            if (ok[pz] & !(q0 & !q2)) {  // (rare: a guess at a bucket edge)
-                for (;;) {
-                    if (row + 1 >= S.H || !(sz >= rho2 * L.ts[row + 1])) break;
-                    ++row;
+            ok[pz] = wedge & (range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH);
+            r2[pz] = range2;
+            if (pz == 0) {
+                const float tg = rz * irho;
+                const int32_t gr = L.lut_row[(int32_t)__builtin_amdgcn_fmed3f((tg - S.lut_row_lo) * S.lut_row_scale,
+                                                                             0.f, (float)(S.n_lut_row - 1))];
+                const float e0 = L.ts[gr], e1 = L.ts[gr + 1], e2 = L.ts[min(gr + 2, S.H)];
+                const bool q0 = (gr == 0) | (sz >= rho2 * e0);
+                const bool q1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
+                const bool q2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
+                row = gr + (int32_t)q1;
+                if (wedge & !(q0 & !q2)) {   // (rare: a guess at a bucket edge)
+                    for (;;) {
+                        if (row + 1 >= S.H || !(sz >= rho2 * L.ts[row + 1])) break;
+                        ++row;
+                    }
+                    for (;;) {
+                        if (row == 0 || sz >= rho2 * L.ts[row]) break;
+                        --row;
+                    }
                 }
-                for (;;) {
-                    if (row == 0 || sz >= rho2 * L.ts[row]) break;
-                    --row;
+            } else {
+                const float e1 = L.ts[min(row + 1, S.H)], e2 = L.ts[min(row + 2, S.H)];
+                const bool a1 = (row + 1 < S.H) & (sz >= rho2 * e1);
+                const bool a2 = (row + 2 < S.H) & (sz >= rho2 * e2);
+                row += (int32_t)a1;
+                if (wedge & a2) {            // (two or more boundaries between neighbouring voxels)
+                    for (;;) {
+                        if (row + 1 >= S.H || !(sz >= rho2 * L.ts[row + 1])) break;
+                        ++row;
+                    }
                 }
             }
-            idx[pz] = colbase + (uint32_t)row;
-            r2[pz] = range2;
+            idx[pz] = ok[pz] ? colbase + (uint32_t)row : 0u;
         }
         float D[8];
 #pragma unroll
-        for (int32_t pz = 0; pz < 8; ++pz) D[pz] = dpan[ok[pz] ? idx[pz] : A.dpan_off];
+        for (int32_t pz = 0; pz < 8; ++pz) D[pz] = *(gfloats_t)((gbytes_t)dnode + (idx[pz] << 2));
         // observed: the centre's squared range is at most its pixel's squared depth;
         // lane l < 16 collects mask word l of the brick (slice l / 2) and stores it
         uint32_t word = 0u;
@@ -683,6 +721,12 @@ static int grid_for(size_t n, int threads) {
 hipError_t launch_brick(const uint8_t* dense, uint8_t* bricks, const MapDev& m, hipStream_t s) {
     size_t total = (size_t)m.nbx * m.nby * m.nbz * 512u;
     hipLaunchKernelGGL(k_brick, dim3(grid_for(total, 256)), dim3(256), 0, s, dense, bricks, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_brick_flags(const MapDev& m, hipStream_t s) {
+    const size_t threads = (size_t)(m.mask_words >> 4) * 64u;
+    hipLaunchKernelGGL(k_brick_flags, dim3(grid_for(threads, 256)), dim3(256), 0, s, m);
     return hipGetLastError();
 }
 

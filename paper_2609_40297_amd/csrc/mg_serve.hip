@@ -182,6 +182,7 @@ int mg_server_s::apply_update(Request* r) {
     e = hipMemcpyAsync(d_upd, r->upd_ids.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, compute);
     if (e == hipSuccess) e = hipMemcpyAsync(d_states, r->upd_states.data(), n, hipMemcpyHostToDevice, compute);
     if (e == hipSuccess) e = launch_map_scatter(d_upd, d_states, (uint32_t)n, *mgb::map_dev(r->map), nullptr, compute);
+    if (e == hipSuccess) e = launch_brick_flags(*mgb::map_dev(r->map), compute);
     if (e == hipSuccess) e = hipStreamSynchronize(compute);
     if (e != hipSuccess) return hip_fail(e, "server map update");
     return MG_OK;
