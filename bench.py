@@ -157,13 +157,26 @@ def parse():
     return ap.parse_args()
 
 
-def work_counts(name):
-    """Per-workload oracle work counts (visits V, unknown visits U, ancestor tests T)."""
+def work_counts(name, rays_total=None):
+    """Per-workload oracle work counts (visits V, unknown visits U, ancestor tests T). An entry that
+    counted only the first trees of a multi-tree workload (trees_counted < trees) is scaled to
+    `rays_total` by its per-ray rates and says so in "counted"."""
     p = os.path.join(ROOT, "tests", "golden", "work_counts.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
-        return json.load(f).get(name)
+        wc = json.load(f).get(name)
+    if wc is None or not wc.get("rays"):
+        return None
+    done, trees = wc.get("trees_counted"), wc.get("trees")
+    if done is None or done == trees or rays_total is None:
+        return dict(wc, counted="all trees, exact")
+    f = rays_total / wc["rays"]
+    out = {k: (wc[k] * f if k in ("visits", "unk_visits", "anc_tests") else wc[k]) for k in wc}
+    out["rays"] = rays_total
+    out["counted"] = (f"first {done} of {trees} trees exactly ({wc['rays']} rays); the rest at their per-ray "
+                      f"rates")
+    return out
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_multi_step_traffic.md")
@@ -243,29 +256,37 @@ def cpu_model():
 
 
 def cpu_baseline(w, target_rays_per_thread):
-    """The oracle as it stands, with its threaded driver (nodes of a level in parallel), on an
-    ancestor-closed set of deepest leaves of tree 0 (the whole tree if the target exceeds it)."""
+    """The oracle as it stands, with its threaded driver (the nodes of one depth level in parallel), on
+    a seeded uniform sample of nodes of tree 0 and their ancestors (the whole tree if the target
+    exceeds it). The driver starts min(threads, level width) threads per level: `cores` is the most it
+    started and `threads_mean` the node-weighted mean over the sample's levels."""
     from oracle import mgref
     threads = cpu_threads()
     target_rays = target_rays_per_thread * threads
     t = w.trees[0]
     dep = t.depth()
-    order = np.argsort(-dep, kind="stable")
-    leaves = []
+    order = np.random.Generator(np.random.PCG64(12345)).permutation(t.n)
+    picked = []
     mask = np.zeros(t.n, np.uint8)
     for nd in order:
-        leaves.append(int(nd))
-        mask = mgref.ancestor_closure(t.parent, leaves)
+        picked.append(int(nd))
+        mask = mgref.ancestor_closure(t.parent, picked)
         if mask.sum() * w.sensor.rays >= target_rays:
             break
     t0 = time.perf_counter()
     mgref.eval_tree(w.map, t, w.sensor, mask=mask, n_threads=threads)
     dt = time.perf_counter() - t0
-    rays = int(mask.sum()) * w.sensor.rays
-    what = "all nodes of tree 0" if mask.all() else f"{len(leaves)} deepest leaves of tree 0 and their ancestors"
+    nodes = int(mask.sum())
+    rays = nodes * w.sensor.rays
+    widths = np.bincount(dep[mask.astype(bool)])
+    widths = widths[widths > 0]
+    used = np.minimum(widths, threads)
+    what = "all nodes of tree 0" if mask.all() else f"{len(picked)} uniformly drawn nodes of tree 0 and their ancestors"
     model, nproc = cpu_model()
-    return {"value": rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{int(mask.sum())} nodes ({what}), {rays} rays, {dt:.1f} s on {threads} threads",
+    return {"value": rays / dt, "unit": "rays/s", "cores": int(used.max()), "kind": "oracle",
+            "threads_mean": float((used * widths).sum() / widths.sum()),
+            "sample": f"{nodes} nodes ({what}; level widths {widths.tolist()}), {rays} rays, {dt:.1f} s, "
+                      f"up to {threads} threads",
             "cpu_model": model, "nproc": nproc}
 
 
@@ -449,7 +470,7 @@ def roofline_of(wc, trace, steps, n_total, yaw_bins, ms_per_step, sources_ok):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": sources_ok,
             "kernels": ["k_trace_multi", "k_mask_build_multi"],
-            "algorithmic_bytes_per_step": alg_step,
+            "algorithmic_bytes_per_step": alg_step, "work_counts": wc.get("counted"),
             "busy_ms_per_step": busy, "summed_launch_ms_per_step": summed,
             "launches_per_step": trace["launches"] / steps,
             "achieved_over_summed_launches": alg_step / (summed * 1e-3) / 1e9,
@@ -534,7 +555,7 @@ def measure(mg, W, name, steps, warmup, modes, n_trees=None):
     main_mode = "batched" if "batched" in results else "plain"
     shape_idx, graphed = mg.mg_batch_plan_info(handles) if "batched" in results else (0, False)
     shape = mg.mg_trace_shapes()[shape_idx]
-    wc = work_counts(name if n_trees is None else f"{name}:{n_trees}")
+    wc = work_counts(name if n_trees is None else f"{name}:{n_trees}", rays_per_step)
     roof = roofline_of(wc, trace, steps, n_total, sen.yaw_bins, results[main_mode]["ms_per_step"],
                        measured_traffic(name))
     return dict(w=w, M=M, trees=trees, g_all=g_all, y_all=y_all, n_total=n_total, rays_per_step=rays_per_step,
@@ -701,7 +722,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on the host threads, bounded sample)")
-        per_thread = args.cpu_sample_rays or (0.5e6 if args.workload == "large" else 1.5e6)
+        per_thread = args.cpu_sample_rays or (0.3e6 if args.workload == "large" else 1.5e6)
         cpu = cpu_baseline(head["w"], per_thread)
         log(f"[bench] cpu: {cpu}")
     line_extras = {}

@@ -292,7 +292,9 @@ SensorDev sensor_dev(const SensorRes* r, float rv) {
     sd.d4 = r->d4; sd.iv4 = r->iv4; sd.bin_of_col = r->bins; sd.bv = r->bv; sd.ts = r->ts; sd.c0_of_win = r->c0;
     sd.W = T.W; sd.H = T.H; sd.B = T.B; sd.w = T.w; sd.WB = T.WB;
     sd.R = T.W * T.H;
-    sd.T = (sd.R + kThreads - 1) / kThreads;
+    sd.nrb = (T.H + kRayBlockRows - 1) / kRayBlockRows;
+    sd.n_blocks = (T.W + kRayBlockCols - 1) / kRayBlockCols * sd.nrb;
+    sd.T = (sd.n_blocks * 64 + kThreads - 1) / kThreads;
     sd.rv = rv;
     sd.rv2 = rv * rv;
     sd.lut_col = r->luts;

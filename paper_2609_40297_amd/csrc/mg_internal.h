@@ -11,6 +11,8 @@ constexpr int kMaxAnc = 64;        // deepest supported ancestor chain
 constexpr int kMaxBins = 256;      // yaw bins
 constexpr int kMaxAz = 4096;       // panorama columns (LDS holds their boundaries)
 constexpr int kMaxEl = 2048;
+constexpr int kRayBlockCols = 16;  // pixel block of one wave of the trace kernels: 16 columns
+constexpr int kRayBlockRows = 4;   // by 4 rows
 
 // kOutside marks the padding around the grid: a traversal that reaches it
 // has left the grid.
@@ -67,6 +69,11 @@ struct SensorDev {
     const float* ts;           // [H+1] tan(e)|tan(e)| at the row boundaries
     const int32_t* c0_of_win;  // [B] first column of window k
     int32_t W, H, B, w, WB, R, T;   // R = W*H rays, T = workgroups per node
+    // The trace kernels give each wave a block of kRayBlockCols x kRayBlockRows
+    // pixels (rays of one block have similar lengths, so a wave's lanes finish
+    // at similar steps); blocks are numbered row block fastest.
+    int32_t nrb;               // row blocks, ceil(H / kRayBlockRows)
+    int32_t n_blocks;          // ceil(W / kRayBlockCols) * nrb
     float rv;                  // range in voxel units
     float rv2;                 // rv*rv (no depth can exceed it)
     // Guess tables for the pixel lookup (a guess only picks where the exact

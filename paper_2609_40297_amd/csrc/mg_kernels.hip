@@ -425,7 +425,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build(MapDev M, SensorDe
 
 // ---------------------------------------------------------------- ray traversal
 
-// One workgroup = kTh consecutive rays (tile `tile`) of one node. A lane walks
+// One workgroup = kTh / 64 pixel blocks (tile `tile`) of one node, one block of
+// kRayBlockCols x kRayBlockRows rays per wave: neighbouring pixels have rays of
+// similar length, so a wave's lanes run for similar numbers of steps. A lane walks
 // its ray with the Amanatides-Woo 3D DDA (face-crossing parameters recomputed
 // as (boundary - q) * (1/d); ties step x, then y, then z; a voxel is visited
 // while its entry parameter is below the range and it is inside the grid). An
@@ -451,10 +453,15 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     for (int32_t i = tid; i < 2 * S.B; i += kTh) s_bins[i] = 0u;
     __syncthreads();
 
-    const int32_t r = tile * kTh + tid;
-    const bool has_ray = r < S.R;
+    // this wave's pixel block and this lane's pixel in it (column c, row j)
+    const int32_t blk = __builtin_amdgcn_readfirstlane(tile * (kTh / 64) + (tid >> 6));
+    const int32_t cb = __builtin_amdgcn_readfirstlane(blk / S.nrb);
+    const int32_t c = cb * kRayBlockCols + (tid & (kRayBlockCols - 1));
+    const int32_t j = (blk - cb * S.nrb) * kRayBlockRows + ((tid & 63) / kRayBlockCols);
+    const bool has_ray = (blk < S.n_blocks) & (c < S.W) & (j < S.H);
+    const int32_t r = c * S.H + j;
     const int32_t rr = has_ray ? r : 0;
-    const int32_t bin = S.bin_of_col[rr / S.H];
+    const int32_t bin = S.bin_of_col[has_ray ? c : 0];
     const float4 p = Tr.q4[node];
     const float4 d = S.d4[rr];
     const float4 iv = S.iv4[rr];
@@ -757,7 +764,7 @@ size_t lds_limit() {
 }
 
 int32_t tiles_per_node(const SensorDev& sd, int shape) {
-    return (sd.R + kShapes[shape].threads - 1) / kShapes[shape].threads;
+    return (sd.n_blocks * 64 + kShapes[shape].threads - 1) / kShapes[shape].threads;
 }
 
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,

@@ -40,3 +40,33 @@ def test_traffic_summary_applies_only_to_its_sources(tmp_path):
     assert bench.summary_traffic(str(summary), [str(src)]) is None
     assert bench.summary_traffic(str(tmp_path / "missing.md"), [str(src)]) is None
 
+
+
+def test_roofline_uses_the_union_of_launch_intervals():
+    wc = {"visits": 1000, "anc_tests": 100, "rays": 10, "counted": "all trees, exact"}
+    trace = {"launches": 6, "busy_ms": 2.0, "total_ms": 3.0}
+    r = bench.roofline_of(wc, trace, steps=2, n_total=2, yaw_bins=4, ms_per_step=5.0, sources_ok=None)
+    alg = 1000 + 4 * 100 + 4 * 10 + 2 * 2 * 4 * 4
+    assert r["algorithmic_bytes_per_step"] == alg
+    assert r["busy_ms_per_step"] == 1.0 and r["summed_launch_ms_per_step"] == 1.5
+    assert r["achieved"] == pytest.approx(alg / 1e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    assert r["achieved_over_whole_step"] == pytest.approx(alg / 5e-3 / 1e9)
+    assert bench.roofline_of(None, trace, 2, 2, 4, 5.0, None) is None
+
+
+def test_partial_work_counts_are_scaled_by_rays(tmp_path, monkeypatch):
+    d = tmp_path / "tests" / "golden"
+    d.mkdir(parents=True)
+    (d / "work_counts.json").write_text(json.dumps({
+        "w": {"visits": 300, "unk_visits": 30, "anc_tests": 60, "rays": 100, "nodes": 2, "trees": 4,
+              "trees_counted": 1},
+        "v": {"visits": 7, "unk_visits": 1, "anc_tests": 2, "rays": 5, "nodes": 1, "trees": 1,
+              "trees_counted": 1}}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    w = bench.work_counts("w", 400)
+    assert (w["visits"], w["unk_visits"], w["anc_tests"], w["rays"]) == (1200, 120, 240, 400)
+    assert "first 1 of 4 trees" in w["counted"]
+    v = bench.work_counts("v", 5)
+    assert v["visits"] == 7 and v["counted"] == "all trees, exact"
+    assert bench.work_counts("missing", 5) is None
