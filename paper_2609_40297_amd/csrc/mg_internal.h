@@ -15,8 +15,10 @@ constexpr int kRayBlockCols = 16;  // pixel block of one wave of the trace kerne
 constexpr int kRayBlockRows = 4;   // by 4 rows
 
 // kOutside marks the padding around the grid: a traversal that reaches it
-// has left the grid.
-enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3 };
+// has left the grid. kFreeBrick is a free voxel whose whole 8x8x8 brick is
+// free (the traversal crosses such a brick in one step); states bit 1 set
+// (kOccupied, kOutside) end a traversal.
+enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3, kFreeBrick = 5 };
 
 // Occupancy grid in 8x8x8-voxel bricks (512 B each, x fastest inside a
 // brick, bricks x fastest): a ray stays inside one brick for several steps,
@@ -36,7 +38,7 @@ struct MapDev {
     uint32_t mbx, mby, mbz;
     uint32_t mask_words;
     // [mbx * mby * mbz] per mask brick: 1 when it holds an unknown voxel (kept
-    // current by every write of the map's states)
+    // current, with the kFreeBrick marks, by every write of the map's states)
     uint8_t* brick_unk;
 };
 

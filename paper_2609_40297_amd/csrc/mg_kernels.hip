@@ -56,21 +56,39 @@ __global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__
     }
 }
 
-// brick_unk[b] = 1 when mask brick b holds an unknown voxel: one wave per
-// brick, each lane reading 8 of its 512 bytes (padding voxels past the grid
-// hold kOutside).
+// Per-brick summaries, after any write of the states: brick_unk[b] = 1 when
+// brick b holds an unknown voxel, and the free voxels of a brick whose 512
+// voxels are all free are marked kFreeBrick (kFree in any other brick). One
+// wave per brick, each lane reading 8 of its 512 bytes and writing them back
+// only if a mark changes (padding voxels past the grid hold kOutside, so a
+// brick that reaches past the grid is never all free).
 __global__ void k_brick_flags(MapDev m) {
     const uint32_t nb = m.mask_words >> 4;
     const uint32_t lane = threadIdx.x & 63u;
+    uint8_t* grid = const_cast<uint8_t*>(m.bricks);
     for (uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < nb; b += (gridDim.x * blockDim.x) >> 6) {
         const uint32_t bx = b % m.mbx, by = (b / m.mbx) % m.mby, bz = b / (m.mbx * m.mby);
         const uint32_t base = voxel_addr((int32_t)(bx * 8u), (int32_t)(by * 8u), (int32_t)(bz * 8u), m);
-        const uint64_t v = *reinterpret_cast<const uint64_t*>(m.bricks + base + lane * 8u);
-        bool unk = false;
+        uint64_t* p = reinterpret_cast<uint64_t*>(grid + base + lane * 8u);
+        const uint64_t v = *p;
+        bool unk = false, not_free = false;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) unk |= ((v >> (8 * k)) & 0xffu) == kUnknown;
-        const uint64_t any = ballot(unk);
-        if (lane == 0) m.brick_unk[b] = any != 0 ? 1 : 0;
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t x = (uint32_t)(v >> (8 * k)) & 0xffu;
+            unk |= x == kUnknown;
+            not_free |= x != kFree && x != kFreeBrick;
+        }
+        const bool any_unk = ballot(unk) != 0;
+        const bool all_free = ballot(not_free) == 0;
+        if (lane == 0) m.brick_unk[b] = any_unk ? 1 : 0;
+        uint64_t w = v;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t x = (uint32_t)(v >> (8 * k)) & 0xffu;
+            if (x == kFree || x == kFreeBrick)
+                w = (w & ~(0xffull << (8 * k))) | ((uint64_t)(all_free ? kFreeBrick : kFree) << (8 * k));
+        }
+        if (w != v) *p = w;
     }
 }
 
@@ -425,6 +443,30 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build(MapDev M, SensorDe
 
 // ---------------------------------------------------------------- ray traversal
 
+// Boundaries still ahead inside the voxel's brick along an axis, before the
+// brick's own exit boundary (0 for an axis the ray does not move along).
+__device__ __forceinline__ int32_t inner_left(int32_t i, int32_t s) {
+    return s > 0 ? 7 - (i & 7) : (s < 0 ? (i & 7) : 0);
+}
+
+// How many of one axis's boundaries b0, b0 + db, b0 + 2 db, ... (at most `lim`,
+// lim <= 7) the DDA crosses before the crossing at parameter T: a boundary with
+// parameter t = (b - q) * f comes first when t < T, or when t == T and the axis
+// precedes the other one in the tie order (`first`). Parameters grow along the
+// axis, so these boundaries are a prefix and three probes find its length.
+__device__ __forceinline__ int32_t crossings_before(float b0, float db, float q, float f, int32_t lim, float T,
+                                                    bool first) {
+    int32_t k = 0;
+#pragma unroll
+    for (int32_t step = 4; step >= 1; step >>= 1) {
+        const int32_t m = k + step - 1;
+        const float tb = ((b0 + (float)m * db) - q) * f;
+        const bool before = (tb < T) | ((tb == T) & first);
+        k += ((m < lim) & before) ? step : 0;
+    }
+    return k;
+}
+
 // One workgroup = kTh / 64 pixel blocks (tile `tile`) of one node, one block of
 // kRayBlockCols x kRayBlockRows rays per wave: neighbouring pixels have rays of
 // similar length, so a wave's lanes run for similar numbers of steps. A lane walks
@@ -517,23 +559,51 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 mb = mask_bit(ix, iy);
                 pend = unk;
             }
-            const bool mx = (tx <= ty) & (tx <= tz);
-            const bool my = !mx & (ty <= tz);
-            const bool mz = !mx & !my;
-            const float tn = mx ? tx : (my ? ty : tz);
-            ix += mx ? sx : 0;
-            iy += my ? sy : 0;
-            iz += mz ? sz : 0;
+            float tn;                       // entry parameter of the next voxel
+            if (st == kFreeBrick) {
+                // Every voxel of this brick is free: all the steps to the first
+                // voxel past the brick at once. The brick is left through the
+                // face whose boundary parameter comes first (ties x, y, z), and
+                // every other axis has crossed the boundaries that come before
+                // that crossing in the same order.
+                const float ex = sx > 0 ? (float)((ix | 7) + 1) : (float)(ix & ~7);
+                const float ey = sy > 0 ? (float)((iy | 7) + 1) : (float)(iy & ~7);
+                const float ez = sz > 0 ? (float)((iz | 7) + 1) : (float)(iz & ~7);
+                const float Tx = sx ? (ex - p.x) * fx : inf;
+                const float Ty = sy ? (ey - p.y) * fy : inf;
+                const float Tz = sz ? (ez - p.z) * fz : inf;
+                const bool fx_ = (Tx <= Ty) & (Tx <= Tz);
+                const bool fy_ = !fx_ & (Ty <= Tz);
+                const bool fz_ = !fx_ & !fy_;
+                tn = fx_ ? Tx : (fy_ ? Ty : Tz);
+                const int32_t kx = crossings_before(bx, dbx, p.x, fx, inner_left(ix, sx), tn, !fx_) + (int32_t)fx_;
+                const int32_t ky = crossings_before(by, dby, p.y, fy, inner_left(iy, sy), tn, fz_) + (int32_t)fy_;
+                const int32_t kz = crossings_before(bz, dbz, p.z, fz, inner_left(iz, sz), tn, false) + (int32_t)fz_;
+                ix += __mul24(kx, sx);
+                iy += __mul24(ky, sy);
+                iz += __mul24(kz, sz);
+                bx += (float)kx * dbx;
+                by += (float)ky * dby;
+                bz += (float)kz * dbz;
+            } else {
+                const bool mx = (tx <= ty) & (tx <= tz);
+                const bool my = !mx & (ty <= tz);
+                const bool mz = !mx & !my;
+                tn = mx ? tx : (my ? ty : tz);
+                ix += mx ? sx : 0;
+                iy += my ? sy : 0;
+                iz += mz ? sz : 0;
+                bx += mx ? dbx : 0.f;
+                by += my ? dby : 0.f;
+                bz += mz ? dbz : 0.f;
+            }
             // a lane that stops here (occupied, finished or outside) compares +inf
             // with the range: one comparison gives the mask the ballot takes
-            const float tn_go = st < kOccupied ? tn : inf;
+            const float tn_go = (st & 2u) == 0u ? tn : inf;
             const bool next_ok = tn_go < S.rv;
             alive = ballot(next_ok);
             addr = next_ok ? voxel_addr(ix, iy, iz, M) : M.outside;
             st = grid[addr];
-            bx += mx ? dbx : 0.f;
-            by += my ? dby : 0.f;
-            bz += mz ? dbz : 0.f;
             tx = (bx - p.x) * fx;
             ty = (by - p.y) * fy;
             tz = (bz - p.z) * fz;

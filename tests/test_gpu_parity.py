@@ -90,6 +90,42 @@ def test_boundary_positions(mg, orc):
     _full_parity(mg, orc, m, tree, sen, "boundary")
 
 
+def _free_brick_map(seed, dims):
+    """A mostly free map: about half of its 8x8x8 bricks wholly free, the others holding unknown
+    voxels, some also occupied ones, so that rays cross many wholly free bricks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = dims
+    st = np.full((nz, ny, nx), W.FREE, np.uint8)
+    for bz in range(0, nz, 8):
+        for by in range(0, ny, 8):
+            for bx in range(0, nx, 8):
+                sl = st[bz:bz + 8, by:by + 8, bx:bx + 8]
+                u = rng.uniform()
+                if u < 0.5:
+                    continue
+                sl[rng.uniform(size=sl.shape) < (0.5 if u < 0.8 else 0.3)] = W.UNK
+                if u >= 0.8:
+                    sl[rng.uniform(size=sl.shape) < 0.03] = W.OCC
+    return W.Map(states=st, voxel_m=1.0, origin_m=np.zeros(3, dtype=np.float32))
+
+
+@pytest.mark.parametrize("dims", [(40, 32, 24), (37, 29, 21)])
+def test_free_bricks_crossed_at_once(mg, orc, dims):
+    """Rays through wholly free bricks (crossed in one step by the device traversal) against the
+    oracle's voxel-by-voxel DDA: nodes on brick corners, edges and faces, 45-degree rays whose
+    boundary parameters tie, horizontal rows (no z motion), and a dense panorama; grids whose
+    size is a multiple of the brick and grids whose last bricks reach past the grid."""
+    m = _free_brick_map(900 + dims[0], dims)
+    pos = np.array([[8.0, 8.0, 8.0], [16.0, 16.0, 8.0], [8.0, 12.5, 12.0], [24.0, 8.0, 16.0], [12.5, 12.5, 12.5],
+                    [16.0, 8.0, 4.5], [9.5, 17.0, 8.0], [31.0, 23.0, 15.0], [4.25, 20.75, 19.5], [20.0, 20.0, 10.0]],
+                   np.float32)
+    tree = W.Tree(pos_m=pos, parent=np.array([-1, 0, 0, 1, 1, 2, 3, 4, 6, 8], np.int32))
+    for sen in (W.Sensor(n_az=8, n_el=3, fov_h_deg=90, fov_v_deg=90, range_m=30.0, yaw_bins=8, az_offset_deg=-22.5),
+                W.Sensor(n_az=100, n_el=17, fov_h_deg=90, fov_v_deg=80, range_m=25.0, yaw_bins=20)):
+        got, ref = _full_parity(mg, orc, m, tree, sen, f"free bricks {dims} {sen.n_az}x{sen.n_el}")
+        assert int(ref["g_abs"].sum()) > 0
+
+
 def test_occupied_everywhere_and_unknown_everywhere(mg, orc):
     sen = W.Sensor(n_az=64, n_el=12, fov_h_deg=90, fov_v_deg=60, range_m=6.0, yaw_bins=16)
     pos = np.array([[4.3, 4.6, 3.2], [5.1, 4.2, 3.7], [3.2, 5.5, 2.9]], np.float32)
