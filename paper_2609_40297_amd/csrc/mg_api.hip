@@ -64,6 +64,7 @@ struct SensorKey {
 
 struct HostTables {
     int32_t W = 0, H = 0, B = 0, w = 0, WB = 0;
+    double az0 = 0.0, fov_v = 0.0;         // radians: column 0's left boundary, vertical field of view
     std::vector<float> dir, inv, bv, ts;   // dir/inv [R*3], bv [W*2], ts [H+1]
     std::vector<int32_t> bins, c0;
     // pixel-guess tables (see SensorDev)
@@ -110,6 +111,8 @@ void build_tables(const mg_sensor* s, int32_t w, int32_t wb, HostTables* T) {
     T->bins.assign(W, 0);
     T->c0.assign(B, 0);
     const double rad = M_PI / 180.0;
+    T->az0 = (double)s->az_offset_deg * rad;
+    T->fov_v = (double)s->fov_v_deg * rad;
     const double step_az = 360.0 / (double)W;
     const double step_el = (double)s->fov_v_deg / (double)H;
     for (int c = 0; c < W; ++c) {
@@ -295,6 +298,13 @@ SensorDev sensor_dev(const SensorRes* r, float rv) {
     sd.nrb = (T.H + kRayBlockRows - 1) / kRayBlockRows;
     sd.n_blocks = (T.W + kRayBlockCols - 1) / kRayBlockCols * sd.nrb;
     sd.T = (sd.n_blocks * 64 + kThreads - 1) / kThreads;
+    sd.tcols = (T.WB + kTileCols - 1) / kTileCols;
+    sd.trows = (T.H + kTileRows - 1) / kTileRows;
+    sd.n_tiles = sd.tcols * sd.trows;
+    sd.az0 = (float)T.az0;
+    sd.daz_inv = (float)((double)T.W / (2.0 * M_PI));
+    sd.el0 = (float)(-T.fov_v / 2.0);
+    sd.del_inv = (float)((double)T.H / T.fov_v);
     sd.rv = rv;
     sd.rv2 = rv * rv;
     sd.lut_col = r->luts;
@@ -545,7 +555,7 @@ struct HostTree {
     std::vector<int32_t> mask_slot, mask_level_ptr, mask_nodes;
     // device block layout
     size_t o_q4 = 0, o_pm = 0, o_ap = 0, o_ai = 0, o_ln = 0, o_cp = 0, o_ci = 0, o_c0 = 0, o_g = 0, o_y = 0, o_bins = 0,
-           o_dpan = 0, o_ms = 0, o_mn = 0, o_masks = 0, total = 0;
+           o_dpan = 0, o_ms = 0, o_mn = 0, o_masks = 0, o_tm = 0, total = 0;
 };
 
 }  // namespace mgb
@@ -632,7 +642,7 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
     const size_t R = (size_t)sensor->n_az * sensor->n_el;
     if (R * (size_t)n >= (1ull << 32)) return fail(MG_E_UNSUPPORTED, "nodes x rays = %zu exceeds 2^32 per tree", R * (size_t)n);
     // one device block: q4 | pm | anc_ptr | anc_ids | level_nodes | child_ptr | child_ids | c0 | gain | yaw | bins |
-    // dpan | mask_slot | mask_nodes | masks
+    // dpan | mask_slot | mask_nodes | masks | tile maxima
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     H->o_q4 = take(sizeof(float4) * n);
@@ -650,6 +660,8 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
     H->o_ms = take(sizeof(int32_t) * n);
     H->o_mn = take(sizeof(int32_t) * std::max<size_t>(H->mask_nodes.size(), 1));
     H->o_masks = take(sizeof(uint32_t) * (size_t)map->dev.mask_words * (size_t)H->n_masks);
+    const size_t n_tiles = (size_t)((wb + kTileCols - 1) / kTileCols) * (size_t)((sensor->n_el + kTileRows - 1) / kTileRows);
+    H->o_tm = take(sizeof(float) * n_tiles * (size_t)std::max(H->n_masks, 1));
     H->total = off;
     return MG_OK;
 }
@@ -697,6 +709,7 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     t->dev.mask_slot = (const int32_t*)(base + H.o_ms);
     t->dev.mask_nodes = (const int32_t*)(base + H.o_mn);
     t->dev.masks = (uint32_t*)(base + H.o_masks);
+    t->dev.tmax = (float*)(base + H.o_tm);
     t->dev.n = n;
     t->dev.anc_cap = kMaxAnc;
     t->scratch_gain = (uint32_t*)(base + H.o_g);

@@ -13,6 +13,8 @@ constexpr int kMaxAz = 4096;       // panorama columns (LDS holds their boundari
 constexpr int kMaxEl = 2048;
 constexpr int kRayBlockCols = 16;  // pixel block of one wave of the trace kernels: 16 columns
 constexpr int kRayBlockRows = 4;   // by 4 rows
+constexpr int kTileCols = 4;       // depth-cull tiles of a node's window: 4 columns
+constexpr int kTileRows = 4;       // by 4 rows
 
 // kOutside marks the padding around the grid: a traversal that reaches it
 // has left the grid. kFreeBrick is a free voxel whose whole 8x8x8 brick is
@@ -76,6 +78,13 @@ struct SensorDev {
     // at similar steps); blocks are numbered row block fastest.
     int32_t nrb;               // row blocks, ceil(H / kRayBlockRows)
     int32_t n_blocks;          // ceil(W / kRayBlockCols) * nrb
+    // Depth cull of the path-mask builder: a window's pixels in tiles of
+    // kTileCols x kTileRows (tcols x trows tiles, column-major), and float
+    // angles that place a direction's pixel to within a pixel: azimuth of
+    // column 0's left boundary and columns per radian, elevation of row 0's
+    // lower boundary and rows per radian.
+    int32_t tcols, trows, n_tiles;
+    float az0, daz_inv, el0, del_inv;
     float rv;                  // range in voxel units
     float rv2;                 // rv*rv (no depth can exceed it)
     // Guess tables for the pixel lookup (a guess only picks where the exact
@@ -109,6 +118,7 @@ struct TreeDev {
     uint32_t* masks;           // [nodes with children][mask_words]
     const int32_t* mask_slot;  // [n] index into masks, -1 for a leaf
     const int32_t* mask_nodes; // nodes with children, by depth level
+    float* tmax;               // [nodes with children][n_tiles]: largest first hit of each tile of the window
     int32_t n;
     int32_t anc_cap;           // ancestors that condition a node: kMaxAnc (all) or 1 (the parent only)
 };

@@ -265,6 +265,55 @@ __device__ __forceinline__ void load_tables(const TableLDS& L, const SensorDev& 
 // tested. One wave tests one brick slice of 64 voxels at a time (64
 // consecutive grid bytes, two mask words). Whole workgroup; chunks past the
 // map's last brick do nothing (a batch launch covers its largest map).
+// Whether the node may observe a voxel of brick (bx, by, bz), from below: the
+// pixels that the brick's voxel centres can fall in lie inside a rectangle of
+// the window (azimuth from the corners of the centres' box seen from outside,
+// elevation from its nearest and farthest horizontal distance; both widened by
+// a pixel, so float angles cannot drop a pixel), and no voxel centre is nearer
+// than the box; if the largest first hit over the tiles that cover the
+// rectangle is below that distance, no voxel of the brick is observed. Returns
+// true (no cull) when the node is within a voxel of the box horizontally or the
+// rectangle covers more than 64 tiles.
+__device__ bool may_see_brick(const SensorDev& S, const float* __restrict__ tm, float4 q, int32_t c0, uint32_t bx,
+                              uint32_t by, uint32_t bz) {
+    const float x0 = (float)(bx * 8u) + 0.5f - q.x, x1 = x0 + 7.f;
+    const float y0 = (float)(by * 8u) + 0.5f - q.y, y1 = y0 + 7.f;
+    const float z0 = (float)(bz * 8u) + 0.5f - q.z, z1 = z0 + 7.f;
+    if (x0 <= 1.f && x1 >= -1.f && y0 <= 1.f && y1 >= -1.f) return true;
+    // window columns of the four corners, unwrapped around the window
+    const float W = (float)S.W, sh = 0.5f * (float)(S.W - S.WB);
+    float lo = 1e30f, hi = -1e30f;
+    const float cx[4] = {x0, x1, x0, x1}, cy[4] = {y0, y0, y1, y1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float v = (atan2f(cy[k], cx[k]) - S.az0) * S.daz_inv - (float)c0;
+        v -= W * floorf((v + sh) / W);
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+    }
+    if (hi - lo > 0.5f * W) return true;
+    if (hi + 1.f < 0.f || lo - 1.f >= (float)S.WB) return false;
+    const int32_t c_lo = (int32_t)fmaxf(floorf(lo) - 1.f, 0.f);
+    const int32_t c_hi = (int32_t)fminf(floorf(hi) + 1.f, (float)(S.WB - 1));
+    const float dx = x0 > 0.f ? x0 : (x1 < 0.f ? -x1 : 0.f);
+    const float dy = y0 > 0.f ? y0 : (y1 < 0.f ? -y1 : 0.f);
+    const float dz = z0 > 0.f ? z0 : (z1 < 0.f ? -z1 : 0.f);
+    const float rmin = sqrtf(dx * dx + dy * dy);
+    const float rmax = sqrtf(fmaxf(x0 * x0, x1 * x1) + fmaxf(y0 * y0, y1 * y1));
+    const float e_hi = atan2f(z1, z1 >= 0.f ? rmin : rmax);
+    const float e_lo = atan2f(z0, z0 >= 0.f ? rmax : rmin);
+    const float r_lo = floorf((e_lo - S.el0) * S.del_inv) - 1.f, r_hi = floorf((e_hi - S.el0) * S.del_inv) + 1.f;
+    if (r_hi < 0.f || r_lo > (float)(S.H - 1)) return false;
+    const int32_t j_lo = (int32_t)fmaxf(r_lo, 0.f), j_hi = (int32_t)fminf(r_hi, (float)(S.H - 1));
+    const int32_t tc0 = c_lo / kTileCols, tc1 = c_hi / kTileCols, tr0 = j_lo / kTileRows, tr1 = j_hi / kTileRows;
+    if ((tc1 - tc0 + 1) * (tr1 - tr0 + 1) > 64) return true;
+    float m = 0.f;
+    for (int32_t tc = tc0; tc <= tc1; ++tc)
+        for (int32_t tr = tr0; tr <= tr1; ++tr) m = fmaxf(m, tm[tc * S.trows + tr]);
+    const float dmin2 = dx * dx + dy * dy + dz * dz;
+    return m * m * 1.0001f + 0.01f >= dmin2;
+}
+
 __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
                                             int32_t chunk, int32_t bricks, char* smem, uint8_t* s_live,
                                             int32_t* s_any) {
@@ -301,7 +350,8 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         const float w0 = A.b0x * ry - A.b0y * rx, w1 = A.b1x * ry - A.b1y * rx;
         const bool wedge = (w0 >= -5.5f) & (w1 < 5.5f);      // 3.5 sqrt(2) = 4.95, plus rounding
         // (a brick without unknown voxels needs no bits: only unknown voxels' bits are read)
-        const bool live = near & wedge & (M.brick_unk[b] != 0);
+        const bool live = near && wedge && M.brick_unk[b] != 0 &&
+                          may_see_brick(S, Tr.tmax + (size_t)slot * S.n_tiles, q, c0, bx, by, bz);
         s_live[tid] = (uint8_t)live;
         if (live) *s_any = 1;
     }
@@ -642,6 +692,28 @@ __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeD
 // with the smallest k. Whole workgroup; returns (sum << 32) | (B - 1 - k) to
 // every thread. Bins are read with atomic loads (they were accumulated with
 // device-scope atomics, possibly by other workgroups).
+// The largest first hit of each tile of a node's window (kTileCols x kTileRows
+// pixels, partial at the window's edges), for the mask builder's depth cull of
+// the node's bricks; only nodes with children have a path mask to build.
+// Consecutive threads take consecutive tiles of a tile column, so their reads
+// of the column-major panorama are contiguous.
+__device__ __forceinline__ void tile_max(const SensorDev& S, const TreeDev& Tr, int32_t node, int32_t c0) {
+    const int32_t slot = Tr.mask_slot[node];
+    if (slot < 0) return;
+    const float* src = Tr.dpan + (size_t)node * S.R;
+    float* dst = Tr.tmax + (size_t)slot * S.n_tiles;
+    for (int32_t t = threadIdx.x; t < S.n_tiles; t += blockDim.x) {
+        const int32_t tc = t / S.trows, tr = t - tc * S.trows;
+        const int32_t j0 = tr * kTileRows, j1 = min(j0 + kTileRows, S.H);
+        float m = 0.f;
+        for (int32_t i = tc * kTileCols; i < min((tc + 1) * kTileCols, S.WB); ++i) {
+            const float* col = src + (size_t)wrap(c0 + i, S.W) * S.H;
+            for (int32_t j = j0; j < j1; ++j) m = fmaxf(m, col[j]);
+        }
+        dst[t] = m;
+    }
+}
+
 __device__ __forceinline__ unsigned long long select_window(const uint32_t* bins, const SensorDev& S,
                                                             uint32_t* s_p, unsigned long long* s_best) {
     const int32_t tid = threadIdx.x;
@@ -689,12 +761,13 @@ __global__ __launch_bounds__(kThreads) void k_finish(SensorDev S, TreeDev Tr, co
     const int32_t node = nodes[blockIdx.x];
     const unsigned long long best =
         select_window(Tr.bins + (size_t)node * 2 * S.B + (marginal ? S.B : 0), S, s_p, s_best);
+    const int32_t k = S.B - 1 - (int32_t)(uint32_t)(best & 0xffffffffull);
     if (threadIdx.x == 0) {
-        const int32_t k = S.B - 1 - (int32_t)(uint32_t)(best & 0xffffffffull);
         gain[node] = (uint32_t)(best >> 32);
         yaw[node] = k;
         if (marginal) Tr.c0[node] = S.c0_of_win[k];
     }
+    if (marginal) tile_max(S, Tr, node, S.c0_of_win[k]);
 }
 
 // ---------------------------------------------------------------- multi-tree, level by level
@@ -761,6 +834,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_multi(const BatchTree* __re
         BT.yaw[node] = k;
         BT.td.c0[node] = c0;
     }
+    tile_max(S, BT.td, node, c0);
     if (BT.depth) {
         const int32_t per = S.H * S.WB;
         const float* src = BT.td.dpan + (size_t)node * S.R;
