@@ -555,7 +555,7 @@ struct HostTree {
     std::vector<int32_t> mask_slot, mask_level_ptr, mask_nodes;
     // device block layout
     size_t o_q4 = 0, o_pm = 0, o_ap = 0, o_ai = 0, o_ln = 0, o_cp = 0, o_ci = 0, o_c0 = 0, o_g = 0, o_y = 0, o_bins = 0,
-           o_dpan = 0, o_ms = 0, o_mn = 0, o_masks = 0, o_tm = 0, total = 0;
+           o_dpan = 0, o_ms = 0, o_mn = 0, o_masks = 0, o_tm = 0, o_mc = 0, total = 0;
 };
 
 }  // namespace mgb
@@ -642,7 +642,7 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
     const size_t R = (size_t)sensor->n_az * sensor->n_el;
     if (R * (size_t)n >= (1ull << 32)) return fail(MG_E_UNSUPPORTED, "nodes x rays = %zu exceeds 2^32 per tree", R * (size_t)n);
     // one device block: q4 | pm | anc_ptr | anc_ids | level_nodes | child_ptr | child_ids | c0 | gain | yaw | bins |
-    // dpan | mask_slot | mask_nodes | masks | tile maxima
+    // dpan | mask_slot | mask_nodes | masks | tile maxima | mask brick codes
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     H->o_q4 = take(sizeof(float4) * n);
@@ -662,6 +662,7 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
     H->o_masks = take(sizeof(uint32_t) * (size_t)map->dev.mask_words * (size_t)H->n_masks);
     const size_t n_tiles = (size_t)((wb + kTileCols - 1) / kTileCols) * (size_t)((sensor->n_el + kTileRows - 1) / kTileRows);
     H->o_tm = take(sizeof(float) * n_tiles * (size_t)std::max(H->n_masks, 1));
+    H->o_mc = take((size_t)(map->dev.mask_words >> 4) * (size_t)std::max(H->n_masks, 1));
     H->total = off;
     return MG_OK;
 }
@@ -710,6 +711,7 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     t->dev.mask_nodes = (const int32_t*)(base + H.o_mn);
     t->dev.masks = (uint32_t*)(base + H.o_masks);
     t->dev.tmax = (float*)(base + H.o_tm);
+    t->dev.mcode = (uint8_t*)(base + H.o_mc);
     t->dev.n = n;
     t->dev.anc_cap = kMaxAnc;
     t->scratch_gain = (uint32_t*)(base + H.o_g);

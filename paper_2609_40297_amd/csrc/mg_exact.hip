@@ -85,7 +85,7 @@ __device__ void walk_unknown(const MapDev& M, float rv, float4 p, float4 d, floa
         if (!(t < rv)) break;
         const uint8_t s = M.bricks[voxel_addr(i[0], i[1], i[2], M)];
         if (s == kOccupied) break;
-        if (s == kUnknown) f((uint32_t)i[0] + (uint32_t)n[0] * ((uint32_t)i[1] + (uint32_t)n[1] * (uint32_t)i[2]));
+        if (is_unknown(s)) f((uint32_t)i[0] + (uint32_t)n[0] * ((uint32_t)i[1] + (uint32_t)n[1] * (uint32_t)i[2]));
         const int ax = (tn[0] <= tn[1] && tn[0] <= tn[2]) ? 0 : (tn[1] <= tn[2] ? 1 : 2);
         t = tn[ax];
         i[ax] += st[ax];

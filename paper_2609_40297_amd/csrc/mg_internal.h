@@ -17,10 +17,16 @@ constexpr int kTileCols = 4;       // depth-cull tiles of a node's window: 4 col
 constexpr int kTileRows = 4;       // by 4 rows
 
 // kOutside marks the padding around the grid: a traversal that reaches it
-// has left the grid. kFreeBrick is a free voxel whose whole 8x8x8 brick is
-// free (the traversal crosses such a brick in one step); states bit 1 set
-// (kOccupied, kOutside) end a traversal.
-enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3, kFreeBrick = 5 };
+// has left the grid. kUnknownBrick and kFreeBrick are an unknown and a free
+// voxel whose whole 8x8x8 brick holds that state (the traversal may cross
+// such a brick in one step): the low two bits of a byte are the state, and
+// bit 1 set (kOccupied, kOutside) ends a traversal.
+enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3, kUnknownBrick = 4, kFreeBrick = 5 };
+__host__ __device__ inline bool is_unknown(uint32_t s) { return (s & 3u) == 0u; }
+
+// Per brick of a path mask (one byte): its 512 bits are mixed, all clear (no
+// voxel of the brick observed) or all set.
+enum : uint8_t { kMaskMixed = 0, kMaskNone = 1, kMaskAll = 2 };
 
 // Occupancy grid in 8x8x8-voxel bricks (512 B each, x fastest inside a
 // brick, bricks x fastest): a ray stays inside one brick for several steps,
@@ -63,6 +69,9 @@ __device__ __forceinline__ uint32_t mask_word(int32_t x, int32_t y, int32_t z, c
     return (b << 4) | ((uint32_t)(z & 7) << 1) | ((uint32_t)(y & 4) >> 2);
 }
 __device__ __forceinline__ uint32_t mask_bit(int32_t x, int32_t y) { return (uint32_t)(x & 7) | ((uint32_t)(y & 3) << 3); }
+__device__ __forceinline__ uint32_t mask_brick(int32_t x, int32_t y, int32_t z, const MapDev& M) {
+    return (uint32_t)(x >> 3) + __umul24(M.mbx, (uint32_t)(y >> 3) + __umul24(M.mby, (uint32_t)(z >> 3)));
+}
 
 // Panorama ray tables and yaw-window geometry (built on the host, see mg_api).
 struct SensorDev {
@@ -119,6 +128,7 @@ struct TreeDev {
     const int32_t* mask_slot;  // [n] index into masks, -1 for a leaf
     const int32_t* mask_nodes; // nodes with children, by depth level
     float* tmax;               // [nodes with children][n_tiles]: largest first hit of each tile of the window
+    uint8_t* mcode;            // [nodes with children][mask bricks]: kMaskMixed / kMaskNone / kMaskAll
     int32_t n;
     int32_t anc_cap;           // ancestors that condition a node: kMaxAnc (all) or 1 (the parent only)
 };

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_trace(MapDev M, SensorDev S
             if (st == kOccupied) break;
             const int ax = (tx <= ty && tx <= tz) ? 0 : (ty <= tz ? 1 : 2);
             const float tn = ax == 0 ? tx : (ax == 1 ? ty : tz);
-            if (st == kUnknown) {
+            if (is_unknown(st)) {
                 ++n_abs;
                 const float tex = tn < S.rv ? tn : S.rv;
                 const float tm = 0.5f * (t + tex);

@@ -57,11 +57,12 @@ __global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__
 }
 
 // Per-brick summaries, after any write of the states: brick_unk[b] = 1 when
-// brick b holds an unknown voxel, and the free voxels of a brick whose 512
-// voxels are all free are marked kFreeBrick (kFree in any other brick). One
-// wave per brick, each lane reading 8 of its 512 bytes and writing them back
-// only if a mark changes (padding voxels past the grid hold kOutside, so a
-// brick that reaches past the grid is never all free).
+// brick b holds an unknown voxel, and a brick whose 512 voxels are all unknown
+// (all free) has them marked kUnknownBrick (kFreeBrick); unknown and free
+// voxels of any other brick are plain kUnknown and kFree. One wave per brick,
+// each lane reading 8 of its 512 bytes and writing them back only if a mark
+// changes (padding voxels past the grid hold kOutside, so a brick that reaches
+// past the grid is never marked).
 __global__ void k_brick_flags(MapDev m) {
     const uint32_t nb = m.mask_words >> 4;
     const uint32_t lane = threadIdx.x & 63u;
@@ -71,22 +72,26 @@ __global__ void k_brick_flags(MapDev m) {
         const uint32_t base = voxel_addr((int32_t)(bx * 8u), (int32_t)(by * 8u), (int32_t)(bz * 8u), m);
         uint64_t* p = reinterpret_cast<uint64_t*>(grid + base + lane * 8u);
         const uint64_t v = *p;
-        bool unk = false, not_free = false;
+        bool unk = false, not_unk = false, not_free = false;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint32_t x = (uint32_t)(v >> (8 * k)) & 0xffu;
-            unk |= x == kUnknown;
+            unk |= x == kUnknown || x == kUnknownBrick;
+            not_unk |= x != kUnknown && x != kUnknownBrick;
             not_free |= x != kFree && x != kFreeBrick;
         }
         const bool any_unk = ballot(unk) != 0;
+        const bool all_unk = ballot(not_unk) == 0;
         const bool all_free = ballot(not_free) == 0;
         if (lane == 0) m.brick_unk[b] = any_unk ? 1 : 0;
         uint64_t w = v;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint32_t x = (uint32_t)(v >> (8 * k)) & 0xffu;
-            if (x == kFree || x == kFreeBrick)
-                w = (w & ~(0xffull << (8 * k))) | ((uint64_t)(all_free ? kFreeBrick : kFree) << (8 * k));
+            uint32_t y = x;
+            if (x == kFree || x == kFreeBrick) y = all_free ? kFreeBrick : kFree;
+            if (x == kUnknown || x == kUnknownBrick) y = all_unk ? kUnknownBrick : kUnknown;
+            w = (w & ~(0xffull << (8 * k))) | ((uint64_t)y << (8 * k));
         }
         if (w != v) *p = w;
     }
@@ -325,8 +330,12 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     uint32_t* out = Tr.masks + (size_t)slot * M.mask_words;
     const int32_t a0 = Tr.anc_ptr[node];
     const uint32_t* par = nullptr;
-    if (Tr.anc_cap > 1 && Tr.anc_ptr[node + 1] > a0)
-        par = Tr.masks + (size_t)Tr.mask_slot[Tr.anc_ids[a0]] * M.mask_words;
+    const uint8_t* pcode = nullptr;
+    if (Tr.anc_cap > 1 && Tr.anc_ptr[node + 1] > a0) {
+        const int32_t ps = Tr.mask_slot[Tr.anc_ids[a0]];
+        par = Tr.masks + (size_t)ps * M.mask_words;
+        pcode = Tr.mcode + (size_t)ps * nb;
+    }
     const float4 q = Tr.q4[node];
     const int32_t c0 = Tr.c0[node];
     int32_t c1 = c0 + S.WB;
@@ -356,9 +365,11 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         if (live) *s_any = 1;
     }
     __syncthreads();
-    // bricks that cannot hold an observed voxel keep the parent's bits
+    // bricks that cannot hold an observed voxel keep the parent's bits (and code)
     for (int32_t w = tid; w < cnt * 16; w += blockDim.x)
         if (!s_live[w >> 4]) out[lo * 16u + (uint32_t)w] = par ? par[lo * 16u + (uint32_t)w] : 0u;
+    uint8_t* code = Tr.mcode + (size_t)slot * nb;
+    if (tid < cnt && !s_live[tid]) code[lo + (uint32_t)tid] = par ? pcode[lo + (uint32_t)tid] : (uint8_t)kMaskNone;
     if (!*s_any) return;
     const TableLDS L = carve_tables(smem, S);
     load_tables(L, S);
@@ -478,7 +489,12 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
             word = lane == 2 * pz ? (uint32_t)bal : word;
             word = lane == 2 * pz + 1 ? (uint32_t)(bal >> 32) : word;
         }
-        if (lane < 16) out[wbase + (uint32_t)lane] = pw | word;
+        word |= pw;
+        if (lane < 16) out[wbase + (uint32_t)lane] = word;
+        // the brick's code: all 512 bits clear, all set, or mixed
+        const bool none = ballot((lane < 16) & (word != 0u)) == 0;
+        const bool all = ballot((lane < 16) & (word != ~0u)) == 0;
+        if (lane == 0) code[b] = none ? (uint8_t)kMaskNone : (all ? (uint8_t)kMaskAll : (uint8_t)kMaskMixed);
     }
 }
 
@@ -536,12 +552,17 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                                            int32_t tile, uint32_t* __restrict__ s_bins) {
     const int32_t tid = threadIdx.x;
     const uint32_t* pmask = nullptr;     // the parent's path mask
+    const uint8_t* pcode = nullptr;      // and its brick codes
     if (kMarginal) {
         const int32_t a0 = Tr.anc_ptr[node];
-        if (Tr.anc_cap > 0 && Tr.anc_ptr[node + 1] > a0)
-            pmask = Tr.masks + (size_t)Tr.mask_slot[Tr.anc_ids[a0]] * M.mask_words;
+        if (Tr.anc_cap > 0 && Tr.anc_ptr[node + 1] > a0) {
+            const int32_t ps = Tr.mask_slot[Tr.anc_ids[a0]];
+            pmask = Tr.masks + (size_t)ps * M.mask_words;
+            pcode = Tr.mcode + (size_t)ps * (M.mask_words >> 4);
+        }
     }
     const gwords_t pm = as_global(uniform_ptr(pmask));
+    const gbytes_t pc = as_global(uniform_ptr(pcode));
     for (int32_t i = tid; i < 2 * S.B; i += kTh) s_bins[i] = 0u;
     __syncthreads();
 
@@ -586,6 +607,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     uint32_t st = M.bricks[addr];
     uint32_t mw = 0u, mb = 0u;          // mask word of the last unknown voxel, and its bit
     bool pend = false;                  // (a word requested in the previous step)
+    uint32_t mixed_b = ~0u;             // last unknown brick found mixed in the parent's mask
     if (ballot(has_ray)) {
         uint64_t alive;
         do {
@@ -597,25 +619,29 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 n_new += (pend & !((mw >> mb) & 1u)) ? 1u : 0u;
                 pend = false;
             }
-            const bool unk = st == kUnknown;
-            const bool occ = st == kOccupied;
-            h = occ ? t : h;
-            n_abs += unk ? 1u : 0u;
-            if (kMarginal && pm != nullptr) {
-                // every lane loads (a lane off unknown voxels reads word 0), so the
-                // word lands in the register the next step reads
-                const uint32_t off = (unk ? mask_word(ix, iy, iz, M) : 0u) << 2;   // < 2^29 bytes
-                mw = *(gwords_t)((gbytes_t)pm + off);
-                mb = mask_bit(ix, iy);
-                pend = unk;
+            h = st == kOccupied ? t : h;
+            // A brick whose voxels are all free, or all unknown with the parent's
+            // mask uniform over it (every bit clear or every bit set), is crossed
+            // in one step: it is left through the face whose boundary parameter
+            // comes first (ties x, y, z) and every other axis has crossed the
+            // boundaries that come before that crossing in the same order. The
+            // voxels crossed are one per crossing; crossing an unknown brick
+            // counts them all as absolute, and as marginal when no ancestor
+            // observes any of them. An unknown brick is crossed this way only if
+            // it is left before the range ends.
+            float tn;                           // entry parameter of the next voxel
+            bool whole = false;
+            bool cand = st == kFreeBrick;
+            uint32_t code = kMaskNone;          // (the absolute pass, and the root, see nothing observed)
+            if (st == kUnknownBrick) {
+                if (kMarginal && pc != nullptr) {
+                    const uint32_t b = mask_brick(ix, iy, iz, M);
+                    code = b == mixed_b ? (uint32_t)kMaskMixed : (uint32_t)pc[b];
+                    mixed_b = code == kMaskMixed ? b : mixed_b;
+                }
+                cand = code != kMaskMixed;
             }
-            float tn;                       // entry parameter of the next voxel
-            if (st == kFreeBrick) {
-                // Every voxel of this brick is free: all the steps to the first
-                // voxel past the brick at once. The brick is left through the
-                // face whose boundary parameter comes first (ties x, y, z), and
-                // every other axis has crossed the boundaries that come before
-                // that crossing in the same order.
+            if (cand) {
                 const float ex = sx > 0 ? (float)((ix | 7) + 1) : (float)(ix & ~7);
                 const float ey = sy > 0 ? (float)((iy | 7) + 1) : (float)(iy & ~7);
                 const float ez = sz > 0 ? (float)((iz | 7) + 1) : (float)(iz & ~7);
@@ -625,17 +651,37 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 const bool fx_ = (Tx <= Ty) & (Tx <= Tz);
                 const bool fy_ = !fx_ & (Ty <= Tz);
                 const bool fz_ = !fx_ & !fy_;
-                tn = fx_ ? Tx : (fy_ ? Ty : Tz);
-                const int32_t kx = crossings_before(bx, dbx, p.x, fx, inner_left(ix, sx), tn, !fx_) + (int32_t)fx_;
-                const int32_t ky = crossings_before(by, dby, p.y, fy, inner_left(iy, sy), tn, fz_) + (int32_t)fy_;
-                const int32_t kz = crossings_before(bz, dbz, p.z, fz, inner_left(iz, sz), tn, false) + (int32_t)fz_;
-                ix += __mul24(kx, sx);
-                iy += __mul24(ky, sy);
-                iz += __mul24(kz, sz);
-                bx += (float)kx * dbx;
-                by += (float)ky * dby;
-                bz += (float)kz * dbz;
-            } else {
+                const float T = fx_ ? Tx : (fy_ ? Ty : Tz);
+                whole = (st == kFreeBrick) | (T < S.rv);
+                if (whole) {
+                    const int32_t kx = crossings_before(bx, dbx, p.x, fx, inner_left(ix, sx), T, !fx_) + (int32_t)fx_;
+                    const int32_t ky = crossings_before(by, dby, p.y, fy, inner_left(iy, sy), T, fz_) + (int32_t)fy_;
+                    const int32_t kz = crossings_before(bz, dbz, p.z, fz, inner_left(iz, sz), T, false) + (int32_t)fz_;
+                    ix += __mul24(kx, sx);
+                    iy += __mul24(ky, sy);
+                    iz += __mul24(kz, sz);
+                    bx += (float)kx * dbx;
+                    by += (float)ky * dby;
+                    bz += (float)kz * dbz;
+                    tn = T;
+                    if (st == kUnknownBrick) {
+                        const uint32_t v = (uint32_t)(kx + ky + kz);
+                        n_abs += v;
+                        if (kMarginal) n_new += code == kMaskNone ? v : 0u;
+                    }
+                }
+            }
+            if (!whole) {
+                const bool unk = is_unknown(st);
+                n_abs += unk ? 1u : 0u;
+                if (kMarginal && pm != nullptr) {
+                    // every lane loads (a lane off unknown voxels reads word 0), so the
+                    // word lands in the register the next step reads
+                    const uint32_t off = (unk ? mask_word(ix, iy, iz, M) : 0u) << 2;   // < 2^29 bytes
+                    mw = *(gwords_t)((gbytes_t)pm + off);
+                    mb = mask_bit(ix, iy);
+                    pend = unk;
+                }
                 const bool mx = (tx <= ty) & (tx <= tz);
                 const bool my = !mx & (ty <= tz);
                 const bool mz = !mx & !my;

@@ -131,8 +131,7 @@ __global__ void k_unbrick(const uint8_t* __restrict__ bricks, MapDev m, uint8_t*
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox; i += (size_t)gridDim.x * blockDim.x) {
         const int32_t x = (int32_t)(i % (size_t)m.nx), y = (int32_t)((i / (size_t)m.nx) % (size_t)m.ny);
         const int32_t z = (int32_t)(i / nxy);
-        const uint8_t v = bricks[voxel_addr(x, y, z, m)];
-        dense[i] = v == kFreeBrick ? (uint8_t)kFree : v;
+        dense[i] = bricks[voxel_addr(x, y, z, m)] & 3u;     // (without the whole-brick marks)
     }
 }
 

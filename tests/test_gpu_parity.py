@@ -91,8 +91,9 @@ def test_boundary_positions(mg, orc):
 
 
 def _free_brick_map(seed, dims):
-    """A mostly free map: about half of its 8x8x8 bricks wholly free, the others holding unknown
-    voxels, some also occupied ones, so that rays cross many wholly free bricks."""
+    """A map of whole bricks: about 35 % of its 8x8x8 bricks wholly free, 30 % wholly unknown, the
+    others mixing free and unknown voxels, some also occupied ones, so that rays cross many bricks
+    that hold one state only."""
     rng = np.random.Generator(np.random.PCG64(seed))
     nx, ny, nz = dims
     st = np.full((nz, ny, nx), W.FREE, np.uint8)
@@ -101,18 +102,22 @@ def _free_brick_map(seed, dims):
             for bx in range(0, nx, 8):
                 sl = st[bz:bz + 8, by:by + 8, bx:bx + 8]
                 u = rng.uniform()
-                if u < 0.5:
+                if u < 0.35:
                     continue
-                sl[rng.uniform(size=sl.shape) < (0.5 if u < 0.8 else 0.3)] = W.UNK
-                if u >= 0.8:
+                if u < 0.65:
+                    sl[...] = W.UNK
+                    continue
+                sl[rng.uniform(size=sl.shape) < (0.5 if u < 0.85 else 0.3)] = W.UNK
+                if u >= 0.85:
                     sl[rng.uniform(size=sl.shape) < 0.03] = W.OCC
     return W.Map(states=st, voxel_m=1.0, origin_m=np.zeros(3, dtype=np.float32))
 
 
 @pytest.mark.parametrize("dims", [(40, 32, 24), (37, 29, 21)])
 def test_free_bricks_crossed_at_once(mg, orc, dims):
-    """Rays through wholly free bricks (crossed in one step by the device traversal) against the
-    oracle's voxel-by-voxel DDA: nodes on brick corners, edges and faces, 45-degree rays whose
+    """Rays through wholly free and wholly unknown bricks (the device traversal crosses a free
+    brick, and an unknown one over which the parent's path mask is uniform, in one step) against
+    the oracle's voxel-by-voxel DDA: nodes on brick corners, edges and faces, 45-degree rays whose
     boundary parameters tie, horizontal rows (no z motion), and a dense panorama; grids whose
     size is a multiple of the brick and grids whose last bricks reach past the grid."""
     m = _free_brick_map(900 + dims[0], dims)
