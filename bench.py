@@ -152,6 +152,9 @@ def parse():
                     help="skip the map conversion / update timing")
     ap.add_argument("--cpu-sample-rays", type=float, default=None,
                     help="oracle sample, rays per host thread (default: 1.5e6, 0.5e6 on large)")
+    ap.add_argument("--profile-summary", default=None, metavar="CSV",
+                    help="print per-step figures of the last --steps batched calls from a rocprofv3 "
+                         "kernel-trace or counter-collection CSV of a bench run, and exit (no GPU)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -218,6 +221,88 @@ def measured_traffic(workload):
 
 TSDF_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tsdf_grid_512x512x128_traffic.md")
 TSDF_SOURCES = [os.path.join(ROOT, "paper_2609_40297_amd", "csrc", "mg_map.hip")]
+
+
+PATH_KERNELS = ("k_trace_multi", "k_mask_build_multi", "k_finish_multi")
+
+
+def _short(name):
+    return next((k for k in PATH_KERNELS + ("k_batch_zero",) if k in name), name.split("(")[0])
+
+
+def _union_ns(iv):
+    tot, end = 0, None
+    for a, b in sorted(iv):
+        if end is None or a > end:
+            tot += b - a
+            end = b
+        elif b > end:
+            tot += b - end
+            end = b
+    return tot
+
+
+def profile_summary(path, steps):
+    """Per-step figures of the last `steps` mg_eval_marginal_batch calls in a rocprofv3 CSV (kernel
+    trace, or counter collection): each call starts with its k_batch_zero dispatch. For a trace:
+    dispatches, summed and average durations per path kernel, the union of the trace and mask-builder
+    intervals (what bench.py's roofline divides by) and the call's span. For counters: each
+    counter summed over each path kernel's dispatches, per call."""
+    import csv
+    with open(path) as f:
+        rows = list(csv.DictReader(f))
+    counters = "Counter_Name" in rows[0]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    starts = [i for i, r in enumerate(rows) if "k_batch_zero" in r["Kernel_Name"]]
+    if len(starts) < steps:
+        raise SystemExit(f"{path}: {len(starts)} batched calls, fewer than {steps}")
+    first = starts[len(starts) - steps:]
+    calls = [rows[a:b] for a, b in zip(first, first[1:] + [len(rows)])]
+    out = [f"Last {steps} batched calls of `{os.path.basename(path)}` (each starts at its k_batch_zero)", ""]
+    if counters:
+        names = sorted({r["Counter_Name"] for r in rows})
+        tot = {}
+        for c in calls:
+            for r in c:
+                k = (_short(r["Kernel_Name"]), r["Counter_Name"])
+                tot[k] = tot.get(k, 0.0) + float(r["Counter_Value"])
+        out += ["| kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
+        for kn in PATH_KERNELS:
+            out.append(f"| {kn} | " + " | ".join(f"{tot.get((kn, n), 0.0) / steps:.6g}" for n in names) + " |")
+        out += ["", "(per call: counter values summed over the kernel's dispatches, averaged over the calls)"]
+        return "\n".join(out)
+    out += ["| call | dispatches | " + " | ".join(f"{k} ms (n)" for k in PATH_KERNELS) +
+            " | union trace+builder ms | span ms |", "|---" * (len(PATH_KERNELS) + 4) + "|"]
+    agg = {k: [0, 0] for k in PATH_KERNELS}
+    un_sum = span_sum = 0
+    for i, c in enumerate(calls):
+        per = {k: [0, 0] for k in PATH_KERNELS}
+        iv = []
+        for r in c:
+            k = _short(r["Kernel_Name"])
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            if k in per:
+                per[k][0] += b - a
+                per[k][1] += 1
+            if k in ("k_trace_multi", "k_mask_build_multi"):
+                iv.append((a, b))
+        un = _union_ns(iv)
+        span = max(int(r["End_Timestamp"]) for r in c) - min(int(r["Start_Timestamp"]) for r in c)
+        un_sum += un
+        span_sum += span
+        for k in PATH_KERNELS:
+            agg[k][0] += per[k][0]
+            agg[k][1] += per[k][1]
+        out.append(f"| {i} | {len(c)} | " + " | ".join(f"{per[k][0] / 1e6:.3f} ({per[k][1]})" for k in PATH_KERNELS)
+                   + f" | {un / 1e6:.3f} | {span / 1e6:.3f} |")
+    out += ["", "Per call (mean over the calls):", ""]
+    for k in PATH_KERNELS:
+        n = agg[k][1]
+        out.append(f"- {k}: {n / steps:.1f} dispatches, {agg[k][0] / steps / 1e6:.3f} ms summed, "
+                   f"{(agg[k][0] / n / 1e3) if n else 0:.1f} us average")
+    out.append(f"- union of k_trace_multi and k_mask_build_multi intervals: {un_sum / steps / 1e6:.3f} ms")
+    out.append(f"- call span (first dispatch start to last dispatch end): {span_sum / steps / 1e6:.3f} ms")
+    return "\n".join(out)
 
 
 def copy_probe(mib):
@@ -692,6 +777,9 @@ def main():
         print(json.dumps({"error": "this library runs on one GPU only; use --gpus 1"}))
         log("bench.py: only --gpus 1 is supported (the library runs on one GPU)")
         sys.exit(2)
+    if args.profile_summary:
+        print(profile_summary(args.profile_summary, args.steps))
+        return
     if args.copy_probe_mib:
         return copy_probe(args.copy_probe_mib)
     if args.map_bench_only:

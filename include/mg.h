@@ -40,7 +40,8 @@ enum {
     MG_E_NOMEM = -2,        /* device or host allocation failed                 */
     MG_E_DEVICE = -3,       /* a HIP call or a kernel failed                    */
     MG_E_BUSY = -4,         /* the handle is still referenced                   */
-    MG_E_UNSUPPORTED = -5   /* valid input outside the sizes this library handles */
+    MG_E_UNSUPPORTED = -5,  /* valid input outside the sizes this library handles */
+    MG_E_CANCELLED = -6     /* a server request was cancelled (mg_server_cancel) */
 };
 
 /* Longest root path of a tree (depth <= 64): the row length of the branch
@@ -318,7 +319,11 @@ int mg_eval_absolute(mg_tree tree, void* hip_stream, uint32_t* gain, int32_t* ya
  * Requests are admitted between steps, first come first served, when fewer
  * than max_inflight are in flight and their tree fits in the server's device
  * arena (admission by device-memory footprint, mg_tree_footprint_bytes).
- * Results equal mg_eval_marginal on the same tree, alone or in any mix. */
+ * Results equal mg_eval_marginal on the same tree, alone or in any mix.
+ * Each in-flight request has a device status word that its kernels check
+ * first: a request marked failed (mg_server_fail_request) is skipped by them and
+ * retired with its status at the end of the step, and a cancelled one
+ * (mg_server_cancel) is dropped, while the other requests complete unchanged. */
 typedef struct mg_server_s* mg_server;
 
 typedef struct {
@@ -357,6 +362,30 @@ int mg_server_poll(mg_server server, int64_t ticket, int32_t* status, double* la
 
 /* Blocks until the request is done; returns its status and retires the ticket. */
 int mg_server_wait(mg_server server, int64_t ticket, double* latency_us);
+
+/* Cancels a request or a queued map update. A queued one is dropped at once;
+ * an in-flight request at the next step boundary (the device work done for it
+ * is discarded and its arena block released). It then reports
+ * MG_E_CANCELLED through mg_server_poll / mg_server_wait and its output arrays
+ * are not written. MG_E_INVALID for an unknown ticket, MG_E_BUSY when the
+ * request has already finished or the update is being applied. Thread-safe. */
+int mg_server_cancel(mg_server server, int64_t ticket);
+
+/* Marks a request failed with `code` (a negative MG_E_* value) through its
+ * device status word, as a kernel that detects an error in that request's
+ * data does: the request's remaining kernels skip it, and at the end of the
+ * step that reads the word the request is retired with `code` (its outputs not
+ * written) while every other request continues and completes unchanged. A
+ * queued request is marked when it is admitted. For callers and tests that
+ * need a request to fail in isolation. MG_E_INVALID for an unknown ticket, a
+ * map update or code >= 0; MG_E_BUSY when the request has already finished.
+ * Thread-safe. */
+int mg_server_fail_request(mg_server server, int64_t ticket, int32_t code);
+
+/* paused = 1: no step runs after the current one; requests are still admitted
+ * into flight (up to max_inflight and the arena), map updates wait. paused = 0
+ * resumes. MG_E_INVALID for another value. Thread-safe. */
+int mg_server_pause(mg_server server, int32_t paused);
 
 /* Counters: steps run, requests completed, rays evaluated, requests in flight and queued. */
 int mg_server_stats(mg_server server, int64_t* steps, int64_t* completed, double* rays, int32_t* in_flight,

@@ -15,18 +15,22 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(HERE, "mgref.c"), os.path.join(HERE, "ivlref.c")]
-LIB = os.path.join(HERE, "libmgref.so")
+# MGREF_LIB selects another build of the same sources (the sanitizer build of the tests)
+LIB = os.environ.get("MGREF_LIB") or os.path.join(HERE, "libmgref.so")
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
           "-fno-unsafe-math-optimizations", "-pthread", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+# host-only AddressSanitizer + UndefinedBehaviorSanitizer build (any report aborts the process)
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 
 
-def build(force: bool = True) -> str:
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, *SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+def build(force: bool = True, out: Optional[str] = None, sanitize: bool = False) -> str:
+    out = out or LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, *(SANITIZE if sanitize else []), *SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class SensorParams(C.Structure):

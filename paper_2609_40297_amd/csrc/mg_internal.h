@@ -144,6 +144,9 @@ struct BatchTree {
     uint32_t* gain;            // [n]
     int32_t* yaw;              // [n]
     float* depth;              // [n][H][WB] or NULL
+    // Device status word of the tree's request, or NULL: nonzero marks the
+    // request failed, and every later kernel of it returns at once.
+    const int32_t* status;
 };
 
 // Launchers (mg_kernels.hip).

@@ -837,6 +837,7 @@ __global__ __launch_bounds__(kTh) void k_trace_multi(const BatchTree* __restrict
     const int32_t tile = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x - item * S.T);
     const unsigned long long it = items[item];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
+    if (BT.status != nullptr && *BT.status != 0) return;      // (the request has failed)
     SensorDev St = S;
     St.rv = BT.rv;
     St.rv2 = BT.rv2;
@@ -855,6 +856,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchT
     __shared__ int32_t s_any;
     const unsigned long long it = items[blockIdx.x / chunks];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
+    if (BT.status != nullptr && *BT.status != 0) return;      // (the request has failed)
     SensorDev St = S;
     St.rv = BT.rv;
     St.rv2 = BT.rv2;
@@ -871,6 +873,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_multi(const BatchTree* __re
     __shared__ unsigned long long s_best[kThreads / 64];
     const unsigned long long it = items[blockIdx.x];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
+    if (BT.status != nullptr && *BT.status != 0) return;      // (the request has failed)
     const int32_t node = (int32_t)(uint32_t)it;
     const unsigned long long best = select_window(BT.td.bins + (size_t)node * 2 * S.B + S.B, S, s_p, s_best);
     const int32_t k = S.B - 1 - (int32_t)(uint32_t)(best & 0xffffffffull);

@@ -13,6 +13,14 @@
 // applied when it reaches the head of the queue and no in-flight request
 // uses its map: requests submitted before it see the old map, requests
 // submitted after it the new one.
+//
+// Failure isolation: every in-flight request has a device status word that its
+// kernels check first; a nonzero word (set by mg_server_fail_request, as a
+// kernel that finds an error in the request's data would) makes them skip the
+// request, and the step that reads it back retires the request with that
+// status while the others continue. A cancelled request is dropped from the
+// queue at once, or at the next step boundary when it is in flight. While
+// paused, requests are still admitted but no step runs.
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 
@@ -100,6 +108,10 @@ struct Request {
     int32_t level = 0, levels = 0;
     int rc = MG_OK;
     int state = 0;                   // 0 queued, 1 in flight, 2 done (rc tells success)
+    int32_t slot = -1;               // in flight: index of the request's device status word
+    int32_t inject = 0;              // status set by mg_server_fail_request (0: none)
+    bool inject_sent = false;        // ... and written to the device
+    bool cancel = false;             // cancelled while in flight (dropped at the next step boundary)
     bool holds_map = false;          // a reference on `map` (mg_map_destroy answers MG_E_BUSY meanwhile)
     void hold_map(mg_map m) {
         map = m;
@@ -138,6 +150,8 @@ struct mg_server_s {
     std::unordered_map<int64_t, std::unique_ptr<Request>> all;
     int64_t next_ticket = 1;
     bool stop = false;
+    bool paused = false;
+    uint64_t wake_seq = 0;              // bumped by every call that may give a paused worker work
     int fatal = MG_OK;
     std::string fatal_msg;
     hipStream_t compute = nullptr, upload = nullptr;
@@ -153,12 +167,17 @@ struct mg_server_s {
     size_t cap_stage = 0;
     uint32_t* d_upd = nullptr;          // map updates: ids, then states (device), grown on demand
     size_t cap_upd = 0;
+    int32_t* d_status = nullptr;        // [max_inflight] device status word per in-flight slot
+    int32_t* h_status = nullptr;        // pinned [2 * max_inflight]: read-back, then injection staging
+    std::vector<int32_t> free_slots;
     // statistics
     int64_t steps = 0, completed = 0;
     double rays_done = 0.0;
 
     int grow(size_t trees, size_t items, size_t stage_words);
     int apply_update(Request* r);
+    int send_status(Request* r);
+    void retire(Request* r, int code);
     void run();
     int step();
 };
@@ -186,6 +205,31 @@ int mg_server_s::apply_update(Request* r) {
     if (e == hipSuccess) e = hipStreamSynchronize(compute);
     if (e != hipSuccess) return hip_fail(e, "server map update");
     return MG_OK;
+}
+
+// Writes a request's injected status to its device status word (compute
+// stream; the pinned staging word is not reused before the step's end).
+int mg_server_s::send_status(Request* r) {
+    const int32_t m = cfg.max_inflight;
+    h_status[m + r->slot] = r->inject;
+    const hipError_t e =
+        hipMemcpyAsync(d_status + r->slot, h_status + m + r->slot, sizeof(int32_t), hipMemcpyHostToDevice, compute);
+    if (e != hipSuccess) return hip_fail(e, "server status word");
+    r->inject_sent = true;
+    return MG_OK;
+}
+
+// Ends an in-flight request that will not complete (failed or cancelled):
+// its tree, arena block and status slot are released. The caller holds mu and
+// no work of the request is pending on the compute stream.
+void mg_server_s::retire(Request* r, int code) {
+    if (r->tree) mg_tree_destroy(r->tree);
+    r->tree = nullptr;
+    arena.release(r->arena_off, r->bytes);
+    free_slots.push_back(r->slot);
+    r->slot = -1;
+    r->finish(code);
+    inflight.erase(std::find(inflight.begin(), inflight.end(), r));
 }
 
 int mg_server_s::grow(size_t trees, size_t items, size_t stage_words) {
@@ -233,7 +277,8 @@ int mg_server_s::step() {
             if (queue.empty()) break;
             r = queue.front();
             if (r->kind == 1) {
-                // a map update waits for the in-flight requests on its map
+                // a map update waits for the in-flight requests on its map (and for a resume)
+                if (paused) break;
                 if (std::any_of(inflight.begin(), inflight.end(), [&](Request* q) { return q->map == r->map; })) break;
                 queue.pop_front();
             }
@@ -254,12 +299,16 @@ int mg_server_s::step() {
             size_t off = 0;
             if (!arena.alloc(r->bytes, &off)) break;
             r->arena_off = off;
+            r->slot = free_slots.back();
+            free_slots.pop_back();
             queue.pop_front();
         }
         int rc = mgb::upload_into(r->map, *r->host, &cfg.sensor, upload, (char*)arena_mem + r->arena_off, &r->tree);
         std::lock_guard<std::mutex> lk(mu);
         if (rc != MG_OK) {
             arena.release(r->arena_off, r->bytes);
+            free_slots.push_back(r->slot);
+            r->slot = -1;
             r->finish(rc);
             cv_done.notify_all();
             continue;
@@ -274,12 +323,31 @@ int mg_server_s::step() {
         r->levels = v.levels;
         r->state = 1;
         hipError_t e = launch_zero_u32(v.td->bins, (size_t)2 * v.sd->B * v.n, compute);
+        if (e == hipSuccess) e = launch_zero_u32((uint32_t*)(d_status + r->slot), 1, compute);
         if (e != hipSuccess) return hip_fail(e, "server bins");
+        if (r->inject != 0) {            // failed (mg_server_fail_request) while queued
+            rc = send_status(r);
+            if (rc != MG_OK) return rc;
+        }
         inflight.push_back(r);
     }
     std::vector<Request*> active;
     {
+        // cancelled requests leave (the previous step has drained the stream);
+        // statuses injected since the last step go to the device
         std::lock_guard<std::mutex> lk(mu);
+        std::vector<Request*> gone;
+        for (Request* r : inflight) {
+            if (r->cancel) {
+                gone.push_back(r);
+            } else if (r->inject != 0 && !r->inject_sent) {
+                const int rc = send_status(r);
+                if (rc != MG_OK) return rc;
+            }
+        }
+        for (Request* r : gone) retire(r, MG_E_CANCELLED);
+        if (!gone.empty()) cv_done.notify_all();
+        if (paused) return MG_OK;
         active = inflight;
     }
     if (active.empty()) return MG_OK;
@@ -311,6 +379,7 @@ int mg_server_s::step() {
         bt.gain = v.scratch_gain;
         bt.yaw = v.scratch_yaw;
         bt.depth = nullptr;
+        bt.status = d_status + r->slot;
         for (int32_t j = (*r->level_ptr)[r->level]; j < (*r->level_ptr)[r->level + 1]; ++j)
             h_items[k++] = ((unsigned long long)i << 32) | (uint32_t)(*r->level_nodes)[j];
         for (int32_t j = (*r->mask_level_ptr)[r->level]; j < (*r->mask_level_ptr)[r->level + 1]; ++j)
@@ -336,37 +405,48 @@ int mg_server_s::step() {
         finishing.emplace_back(r, so);
         so += 2 * (size_t)r->n;
     }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h_status, d_status, sizeof(int32_t) * cfg.max_inflight, hipMemcpyDeviceToHost, compute);
     if (e == hipSuccess) e = hipStreamSynchronize(compute);
     if (e != hipSuccess) return hip_fail(e, "server step");
     ++steps;
+    std::lock_guard<std::mutex> lk(mu);
+    bool any = false;
+    for (Request* r : active) {
+        r->level++;
+        const int32_t st = h_status[r->slot];
+        if (st != 0) {              // failed on the device: its results are not copied
+            retire(r, st < 0 ? st : (int)MG_E_DEVICE);
+            any = true;
+        }
+    }
     for (auto& f : finishing) {
         Request* r = f.first;
+        if (r->state == 2) continue;
         std::memcpy(r->out_gain, h_stage + f.second, sizeof(uint32_t) * r->n);
         std::memcpy(r->out_yaw, h_stage + f.second + r->n, sizeof(int32_t) * r->n);
-        mg_tree_destroy(r->tree);
-        r->tree = nullptr;
-    }
-    std::lock_guard<std::mutex> lk(mu);
-    for (Request* r : active) r->level++;
-    for (auto& f : finishing) {
-        Request* r = f.first;
-        arena.release(r->arena_off, r->bytes);
-        r->finish(MG_OK);
         rays_done += (double)r->n * cfg.sensor.n_az * cfg.sensor.n_el;
         ++completed;
-        inflight.erase(std::find(inflight.begin(), inflight.end(), r));
+        retire(r, MG_OK);
+        any = true;
     }
-    if (!finishing.empty()) cv_done.notify_all();
+    if (any) cv_done.notify_all();
     return MG_OK;
 }
 
 void mg_server_s::run() {
     (void)hipSetDevice(device);
+    uint64_t seen = ~0ull;
     for (;;) {
         {
+            // running: work while anything is queued or in flight; paused: one
+            // admission pass per call that may have changed something
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return stop || !queue.empty() || !inflight.empty(); });
+            cv_work.wait(lk, [&] {
+                return stop || (paused ? wake_seq != seen : (!queue.empty() || !inflight.empty()));
+            });
             if (stop && queue.empty() && inflight.empty()) return;
+            seen = wake_seq;
         }
         const int rc = step();
         if (rc != MG_OK) {
@@ -400,11 +480,17 @@ extern "C" int mg_server_create(const mg_server_config* cfg, mg_server* out) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->compute, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&S->arena_mem, (size_t)cfg->arena_bytes);
+    if (e == hipSuccess) e = hipMalloc(&S->d_status, sizeof(int32_t) * (size_t)cfg->max_inflight);
+    if (e == hipSuccess)
+        e = hipHostMalloc(&S->h_status, sizeof(int32_t) * 2 * (size_t)cfg->max_inflight, hipHostMallocDefault);
     if (e != hipSuccess) {
+        (void)hipFree(S->arena_mem);
+        (void)hipFree(S->d_status);
         if (S->compute) (void)hipStreamDestroy(S->compute);
         if (S->upload) (void)hipStreamDestroy(S->upload);
         return hip_fail(e, "server setup");
     }
+    for (int32_t i = cfg->max_inflight - 1; i >= 0; --i) S->free_slots.push_back(i);
     S->arena.reset((size_t)cfg->arena_bytes);
     mg_server_s* raw = S.get();
     S->worker = std::thread([raw] { raw->run(); });
@@ -436,6 +522,7 @@ extern "C" int mg_server_submit(mg_server s, mg_map map, const float* pos_m, con
     *ticket = r->ticket;
     s->queue.push_back(r.get());
     s->all.emplace(r->ticket, std::move(r));
+    s->wake_seq++;
     s->cv_work.notify_one();
     return MG_OK;
 }
@@ -477,6 +564,7 @@ extern "C" int mg_server_map_update(mg_server s, mg_map map, const uint32_t* vox
     *ticket = r->ticket;
     s->queue.push_back(r.get());
     s->all.emplace(r->ticket, std::move(r));
+    s->wake_seq++;
     s->cv_work.notify_one();
     return MG_OK;
 }
@@ -509,6 +597,49 @@ extern "C" int mg_server_wait(mg_server s, int64_t ticket, double* latency_us) {
     return MG_OK;
 }
 
+extern "C" int mg_server_cancel(mg_server s, int64_t ticket) {
+    if (!s) return mgb::set_error(MG_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return mgb::set_error(MG_E_INVALID, "unknown ticket");
+    Request* r = it->second.get();
+    if (r->state == 2) return mgb::set_error(MG_E_BUSY, "the request has already finished");
+    if (r->state == 0) {
+        s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+        r->finish(MG_E_CANCELLED);
+        s->cv_done.notify_all();
+    } else {
+        r->cancel = true;            // the worker drops it at the next step boundary
+    }
+    s->wake_seq++;
+    s->cv_work.notify_one();
+    return MG_OK;
+}
+
+extern "C" int mg_server_fail_request(mg_server s, int64_t ticket, int32_t code) {
+    if (!s) return mgb::set_error(MG_E_INVALID, "server is NULL");
+    if (code >= 0) return mgb::set_error(MG_E_INVALID, "the status must be a negative error code");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return mgb::set_error(MG_E_INVALID, "unknown ticket");
+    Request* r = it->second.get();
+    if (r->kind != 0) return mgb::set_error(MG_E_INVALID, "a map update has no device status word");
+    if (r->state == 2) return mgb::set_error(MG_E_BUSY, "the request has already finished");
+    if (r->inject == 0) r->inject = code;
+    s->wake_seq++;
+    s->cv_work.notify_one();
+    return MG_OK;
+}
+
+extern "C" int mg_server_pause(mg_server s, int32_t paused) {
+    if (!s || (paused != 0 && paused != 1)) return mgb::set_error(MG_E_INVALID, "server is NULL or paused is not 0/1");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->paused = paused != 0;
+    s->wake_seq++;
+    s->cv_work.notify_one();
+    return MG_OK;
+}
+
 extern "C" int mg_server_stats(mg_server s, int64_t* steps, int64_t* completed, double* rays, int32_t* in_flight,
                                int32_t* queued) {
     if (!s) return mgb::set_error(MG_E_INVALID, "server is NULL");
@@ -526,6 +657,7 @@ extern "C" int mg_server_destroy(mg_server s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
+        s->paused = false;
         s->cv_work.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
@@ -538,6 +670,8 @@ extern "C" int mg_server_destroy(mg_server s) {
     (void)hipHostFree(s->h_items);
     (void)hipHostFree(s->h_stage);
     (void)hipFree(s->d_upd);
+    (void)hipFree(s->d_status);
+    (void)hipHostFree(s->h_status);
     (void)hipFree(s->arena_mem);
     (void)hipStreamDestroy(s->compute);
     (void)hipStreamDestroy(s->upload);

@@ -20,7 +20,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmg.so")
 
 MG_OK, MG_E_INVALID, MG_E_NOMEM, MG_E_DEVICE, MG_E_BUSY, MG_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-_NAMES = {-1: "MG_E_INVALID", -2: "MG_E_NOMEM", -3: "MG_E_DEVICE", -4: "MG_E_BUSY", -5: "MG_E_UNSUPPORTED"}
+_NAMES = {-1: "MG_E_INVALID", -2: "MG_E_NOMEM", -3: "MG_E_DEVICE", -4: "MG_E_BUSY", -5: "MG_E_UNSUPPORTED",
+          -6: "MG_E_CANCELLED"}
+MG_E_INVALID, MG_E_NOMEM, MG_E_DEVICE, MG_E_BUSY, MG_E_UNSUPPORTED, MG_E_CANCELLED = -1, -2, -3, -4, -5, -6
 
 # Every entry point declared in include/mg.h.
 EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy", "mg_tree_nodes",
@@ -30,7 +32,8 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_server_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_config", "mg_trace_shapes",
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
            "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read",
-           "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal", "mg_eval_marginal_batch_noalloc")
+           "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal", "mg_eval_marginal_batch_noalloc",
+           "mg_server_cancel", "mg_server_fail_request", "mg_server_pause")
 
 
 class MGError(RuntimeError):
@@ -90,6 +93,9 @@ def lib() -> C.CDLL:
         L.mg_server_map_update.argtypes = [P, P, P, P, I32, C.POINTER(I64)]
         L.mg_server_poll.argtypes = [P, I64, C.POINTER(I32), C.POINTER(C.c_double)]
         L.mg_server_wait.argtypes = [P, I64, C.POINTER(C.c_double)]
+        L.mg_server_cancel.argtypes = [P, I64]
+        L.mg_server_fail_request.argtypes = [P, I64, I32]
+        L.mg_server_pause.argtypes = [P, I32]
         L.mg_server_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(I32),
                                       C.POINTER(I32)]
         L.mg_server_destroy.argtypes = [P]
@@ -107,7 +113,7 @@ def lib() -> C.CDLL:
                      "mg_sensor_tables", "mg_server_create", "mg_server_submit", "mg_server_poll",
                      "mg_server_wait", "mg_server_stats", "mg_server_destroy", "mg_timing_enable",
                      "mg_timing_read", "mg_batch_config", "mg_trace_shapes", "mg_batch_plan_info",
-                     "mg_score_branches"):
+                     "mg_score_branches", "mg_server_cancel", "mg_server_fail_request", "mg_server_pause"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -510,6 +516,18 @@ class Server:
         g, y = self._keep.pop(ticket, (None, None))    # (an unknown ticket fails in _check)
         _check(rc)
         return g, y, lat.value
+
+    def cancel(self, ticket: int):
+        """Cancels a queued or in-flight request (it then reports MG_E_CANCELLED)."""
+        _check(lib().mg_server_cancel(C.c_void_p(self.handle), C.c_int64(ticket)))
+
+    def fail_request(self, ticket: int, code: int = MG_E_DEVICE):
+        """Marks a request failed with `code` through its device status word."""
+        _check(lib().mg_server_fail_request(C.c_void_p(self.handle), C.c_int64(ticket), int(code)))
+
+    def pause(self, paused: bool):
+        """Stops (True) or resumes (False) the steps; requests are still admitted while paused."""
+        _check(lib().mg_server_pause(C.c_void_p(self.handle), 1 if paused else 0))
 
     def stats(self):
         steps, done, q, f = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()

@@ -2,7 +2,9 @@
 change any result. Each request's gains and yaw windows are compared with a
 plain mg_eval_marginal of the same tree, alone and in a mix, under a small
 arena (admission waits for memory), with one request in flight at a time, and
-with invalid requests rejected without disturbing the others."""
+with invalid requests rejected without disturbing the others. Requests failed
+through their device status word, and cancelled ones, queued or in flight,
+end with their own status while the others complete bit-identically."""
 import numpy as np
 import pytest
 
@@ -228,3 +230,55 @@ def test_map_held_by_pending_requests(mg):
     assert e.value.code == mg.MG_E_INVALID
     S.close()
     M.close()
+
+
+def _status(mg, S, t):
+    """The request's final status code (0 on success)."""
+    try:
+        S.wait(t)
+        return 0
+    except mg.MGError as e:
+        return e.code
+
+
+def test_failed_and_cancelled_requests_leave_the_others_intact(mg, scene):
+    """Six requests with two slots, the server paused so that the first two are admitted and
+    the rest stay queued: an in-flight request marked failed through its device status word,
+    an in-flight one cancelled, a queued one cancelled, a queued one marked failed (marked when
+    it is admitted) and two untouched ones. After resuming, the failed and cancelled requests
+    report their status with outputs unwritten, and the untouched ones equal the plain path."""
+    sen, reqs, ref, _ = scene
+    S = mg.Server(sen, max_inflight=2, arena_bytes=4 << 30)
+    S.pause(True)
+    order = [0, 1, 2, 3, 4, 5]
+    tickets = [S.submit(*reqs[i]) for i in order]
+    for _ in range(2000):                       # admission runs while paused
+        st = S.stats()
+        if st["in_flight"] == 2:
+            break
+        __import__("time").sleep(0.005)
+    assert st["in_flight"] == 2 and st["queued"] == 4 and st["steps"] == 0, st
+    outs = {t: S._keep[t] for t in tickets}
+    S.fail_request(tickets[0], mg.MG_E_DEVICE)  # in flight: device status word
+    S.cancel(tickets[1])                        # in flight: dropped at the next step boundary
+    S.cancel(tickets[3])                        # queued: dropped at once
+    S.fail_request(tickets[4], mg.MG_E_UNSUPPORTED)   # queued: marked when admitted
+    log("[serve] failed/cancelled: resuming")
+    S.pause(False)
+    codes = [_status(mg, S, t) for t in tickets]
+    assert codes == [mg.MG_E_DEVICE, mg.MG_E_CANCELLED, 0, mg.MG_E_CANCELLED, mg.MG_E_UNSUPPORTED, 0], codes
+    for k in (0, 1, 3, 4):                      # outputs of failed or cancelled requests are not written
+        g, y = outs[tickets[k]]
+        assert not g.any() and not y.any(), k
+    for k in (2, 5):
+        g, y = outs[tickets[k]]
+        assert np.array_equal(g, ref[order[k]][0]) and np.array_equal(y, ref[order[k]][1]), k
+    with pytest.raises(mg.MGError) as ei:       # retired tickets are unknown
+        S.cancel(tickets[2])
+    assert ei.value.code == mg.MG_E_INVALID
+    # the server keeps serving: the same requests again, untouched, are identical
+    again = [S.submit(*reqs[i]) for i in order]
+    _check([S.wait(t)[:2] for t in again], [ref[i] for i in order])
+    st = S.stats()
+    assert st["completed"] == 8 and st["in_flight"] == 0 and st["queued"] == 0
+    S.close()
