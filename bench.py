@@ -18,8 +18,11 @@ Modes
            level, stream synchronised and gains/yaws copied to the host after
            every level.
   batched  the whole request in one call (mg_eval_marginal_batch), one copy
-           of the results at the end.
-`value` is the batched mode's rays/s; the plain mode is reported beside it.
+           of the results at the end; per depth level a trace, a window and a
+           mask-builder launch on two stream groups.
+  persistent  the same call configured as one cooperative launch per step
+           (co-resident workgroups, grid barriers between the phases).
+`value` is the batched mode's rays/s; the other modes are reported beside it.
 
 Prints ONE JSON line (rank 0, N = 1). Extra fields: latency percentiles,
 the roofline of the marginal-gain kernels (trace and path-mask builder) and
@@ -141,7 +144,8 @@ def parse():
                          "the large headline, none otherwise; 'none' skips them)")
     ap.add_argument("--requests", type=int, default=64, help="serve16: number of replanning requests")
     ap.add_argument("--trees", type=int, default=None, help="keep only the first trees of a multi-tree workload")
-    ap.add_argument("--modes", default="plain,batched")
+    ap.add_argument("--modes", default="plain,batched,persistent",
+                    help="plain, batched (per-level launches), persistent (one cooperative launch per step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sp-steps", type=int, default=5, help="timed single-parent (g_sp) passes; 0 skips")
     ap.add_argument("--ivl-steps", type=int, default=3, help="timed interval-mode passes; 0 skips")
@@ -604,8 +608,13 @@ def measure(mg, W, name, steps, warmup, modes, n_trees=None):
 
     results = {}
     trace = None
+    saved = None
     for mode in modes:
-        fn = {"plain": step_plain, "batched": step_batched}[mode]
+        fn = {"plain": step_plain, "batched": step_batched, "persistent": step_batched}[mode]
+        if mode == "persistent":            # the same call, its plan one cooperative launch
+            if "batched" in results:
+                saved = (host_g.numpy().copy(), host_y.numpy().copy())
+            mg.mg_batch_config(-1, 2)
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -630,6 +639,13 @@ def measure(mg, W, name, steps, warmup, modes, n_trees=None):
                              p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                              kernel_ms=float(np.mean(kernel_ms)) if kernel_ms else None)
         log(f"[bench] {name} {mode}: {results[mode]}")
+        if mode == "persistent":
+            if saved is not None:
+                assert np.array_equal(saved[0], host_g.numpy()), "batched and persistent differ"
+                assert np.array_equal(saved[1], host_y.numpy()), "batched and persistent differ"
+            mg.mg_batch_config(-1, 0)
+            if "batched" in results:
+                step_batched()              # the default plan again (its shape is cached)
     # parity of the two modes on this workload (identical results required)
     if "plain" in results and "batched" in results:
         off = 0

@@ -218,19 +218,33 @@ int mg_score_branches(const mg_tree* trees, int32_t n_trees, void* hip_stream, c
  *          call's own trees, twice each, keeps the fastest for that workload
  *          shape, and blocks until done; 0 .. count-1 = that shape
  *          (mg_trace_shapes).
- *   graph: 1 = the plan's launches are recorded once into a HIP graph and
- *          each call replays it (on a library stream joined to hip_stream by
- *          events before and after); 0 (default) = launched one by one.
+ *   launch: 0 (default) = per depth level a trace, a window and a mask-builder
+ *          launch, on two stream groups; 1 = those launches recorded once
+ *          into a HIP graph that each call replays (on a library stream joined
+ *          to hip_stream by events before and after); 2 = one persistent
+ *          cooperative launch per call (Sec. IV-C's level order over all trees:
+ *          as many workgroups as the device holds at once, each phase of each
+ *          level dealt out to them, grid barriers between the phases; shape 0;
+ *          the call waits for it and returns MG_E_DEVICE if a barrier wait gave
+ *          up, see mg_batch_barrier_polls; MG_E_UNSUPPORTED at the first call
+ *          when the device has no cooperative launch).
  * Results do not depend on either setting. MG_E_INVALID for other values. */
-int mg_batch_config(int32_t shape, int32_t graph);
+int mg_batch_config(int32_t shape, int32_t launch);
+
+/* Polls (each about 0.2 us) of one grid-barrier wait of the persistent batch
+ * launch before it gives up and every workgroup leaves (default 2^25, several
+ * seconds, far beyond any phase); 0 .. 2^31 - 1, else MG_E_INVALID. For
+ * callers that bound how long a stalled launch may hold the device. */
+int mg_batch_barrier_polls(int64_t polls);
 
 /* The compiled launch shapes: *count, and for the first `capacity` shapes the
  * rays per workgroup of the trace kernel and the 8x8x8-voxel bricks per
  * workgroup of the path-mask builder. Host only. */
 int mg_trace_shapes(int32_t* count, int32_t* threads, int32_t* bricks, int32_t capacity);
 
-/* Launch shape index and whether a graph is replayed (1) for the cached plan
- * of this tree list. MG_E_INVALID when the list has no plan yet. */
+/* Launch shape index and launch form (0 one by one, 1 graph replay, 2
+ * persistent) of the cached plan of this tree list. MG_E_INVALID when the list
+ * has no plan yet. */
 int mg_batch_plan_info(const mg_tree* trees, int32_t n_trees, int32_t* shape, int32_t* graphed);
 
 /* Single-parent gain g_sp (the comparison gain of Sec. V-A, Fig. 4): as

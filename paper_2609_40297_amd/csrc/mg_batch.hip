@@ -9,7 +9,9 @@
 // plan gets its trace launch shape from the autotuner (every compiled shape
 // timed on the plan itself, the result kept per workload shape) and, when
 // configured, its launches are captured once into a HIP graph that later
-// calls replay.
+// calls replay. Configured persistent, a plan is instead one cooperative
+// launch of co-resident workgroups that walks every level of every tree with
+// grid barriers between the phases (the same kernels' device code).
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 
@@ -52,16 +54,29 @@ struct Plan {
     int shape = 0;                         // launch shape of the trace kernel
     hipGraph_t graph = nullptr;            // the plan's launches, captured once
     hipGraphExec_t exec = nullptr;
+    // The persistent form: items and nodes with children of all trees by
+    // level (level_ptr / mlevel_ptr: levels + 1 offsets each), the barrier
+    // words, and a pinned word the barrier's give-up flag is read into.
+    bool persistent = false;
+    const unsigned long long* pitems = nullptr;
+    const unsigned long long* pmitems = nullptr;
+    const int32_t* plevel = nullptr;
+    const int32_t* pmlevel = nullptr;
+    uint32_t* psync = nullptr;
+    uint32_t* h_abort = nullptr;
     ~Plan() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (block) (void)hipFree(block);
+        if (h_abort) (void)hipHostFree(h_abort);
     }
 };
 
 // Configuration for plans built from now on (mg_batch_config).
 int g_cfg_shape = -1;                      // -1: autotune
 bool g_cfg_graph = false;                  // replaying a graph measured slower than direct launches
+bool g_cfg_persistent = false;             // one persistent cooperative launch per call
+uint32_t g_barrier_polls = 1u << 25;       // polls of a grid-barrier wait before it gives up (seconds)
 // Autotuned shapes per workload shape (sensor, range, map dims, sizes).
 std::map<std::vector<int64_t>, int> g_tuned;
 
@@ -228,11 +243,35 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
         }
     }
     P->levels = levels;
+    // the persistent form's lists: every tree's level d, for d = 0, 1, ...
+    std::vector<unsigned long long> pitems, pmitems;
+    std::vector<int32_t> plevel(1, 0), pmlevel(1, 0);
+    pitems.reserve(P->total);
+    for (int32_t d = 0; d < levels; ++d) {
+        for (int32_t i = 0; i < nt; ++i) {
+            const std::vector<int32_t>& lp = *views[i].level_ptr;
+            const std::vector<int32_t>& ln = *views[i].level_nodes;
+            const std::vector<int32_t>& mp = *views[i].mask_level_ptr;
+            const std::vector<int32_t>& mn = *views[i].mask_nodes;
+            if (d + 1 >= (int32_t)lp.size()) continue;
+            for (int32_t k = lp[d]; k < lp[d + 1]; ++k) pitems.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)ln[k]);
+            for (int32_t k = mp[d]; k < mp[d + 1]; ++k) pmitems.push_back(((unsigned long long)(uint32_t)i << 32) | (uint32_t)mn[k]);
+        }
+        if ((uint64_t)(pitems.size() - plevel.back()) * (uint64_t)max_tiles >= (1ull << 31))
+            return mgb::set_error(MG_E_UNSUPPORTED, "a depth level of the batch has 2^31 workgroups or more");
+        plevel.push_back((int32_t)pitems.size());
+        pmlevel.push_back((int32_t)pmitems.size());
+    }
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     const size_t o_trees = take(sizeof(BatchTree) * nt);
     const size_t o_items = take(sizeof(unsigned long long) * items.size());
     const size_t o_mitems = take(sizeof(unsigned long long) * std::max<size_t>(mitems.size(), 1));
+    const size_t o_pitems = take(sizeof(unsigned long long) * pitems.size());
+    const size_t o_pmitems = take(sizeof(unsigned long long) * std::max<size_t>(pmitems.size(), 1));
+    const size_t o_plevel = take(sizeof(int32_t) * plevel.size());
+    const size_t o_pmlevel = take(sizeof(int32_t) * pmlevel.size());
+    const size_t o_psync = take(sizeof(uint32_t) * 2);
     hipError_t e = hipMalloc(&P->block, off);
     if (e != hipSuccess) return hip_fail(e, "batch plan allocation");
     char* base = (char*)P->block;
@@ -243,6 +282,17 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
     if (e == hipSuccess && !mitems.empty())
         e = hipMemcpyAsync(base + o_mitems, mitems.data(), sizeof(unsigned long long) * mitems.size(),
                            hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + o_pitems, pitems.data(), sizeof(unsigned long long) * pitems.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !pmitems.empty())
+        e = hipMemcpyAsync(base + o_pmitems, pmitems.data(), sizeof(unsigned long long) * pmitems.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + o_plevel, plevel.data(), sizeof(int32_t) * plevel.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + o_pmlevel, pmlevel.data(), sizeof(int32_t) * pmlevel.size(), hipMemcpyHostToDevice,
+                           stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "batch plan upload");
     P->dtrees = (const BatchTree*)(base + o_trees);
@@ -251,6 +301,11 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
     P->depth = depth;
     P->ditems = (const unsigned long long*)(base + o_items);
     P->dmitems = (const unsigned long long*)(base + o_mitems);
+    P->pitems = (const unsigned long long*)(base + o_pitems);
+    P->pmitems = (const unsigned long long*)(base + o_pmitems);
+    P->plevel = (const int32_t*)(base + o_plevel);
+    P->pmlevel = (const int32_t*)(base + o_pmlevel);
+    P->psync = (uint32_t*)(base + o_psync);
     *out = std::move(P);
     return MG_OK;
 }
@@ -373,6 +428,32 @@ int run_plan(const Plan& P, hipStream_t s, bool timed) {
     return MG_OK;
 }
 
+// The persistent form: bins cleared, one cooperative launch, then the barrier's
+// give-up flag read back. Blocks on s (the flag decides the return code).
+int run_persistent(const Plan& P, hipStream_t s, bool timed) {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (timed) {
+        int rc = next_events(P.device, &t0, &t1);
+        if (rc != MG_OK) return rc;
+    }
+    hipError_t e = launch_batch_zero(P.dtrees, (int32_t)P.trees.size(), P.max_nodes, P.sd, s);
+    if (e == hipSuccess && t0) e = hipEventRecord(t0, s);
+    if (e == hipSuccess)
+        e = launch_batch_persistent(P.dtrees, P.pitems, P.plevel, P.pmitems, P.pmlevel, P.levels, P.mask_bricks, P.sd,
+                                    P.psync, g_barrier_polls, s);
+    if (e == hipSuccess && t1) e = hipEventRecord(t1, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.h_abort, P.psync + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "persistent batch");
+    if (t0) {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        g_timing.units += (int64_t)P.total * tiles_per_node(P.sd, 0);
+    }
+    if (*P.h_abort != 0)
+        return mgb::set_error(MG_E_DEVICE, "persistent batch: a grid barrier wait gave up (its poll limit ran out)");
+    return MG_OK;
+}
+
 std::vector<int64_t> tune_key(const Plan& P) {
     mgb::TreeView v;
     mgb::tree_view(P.trees[0], &v);
@@ -472,6 +553,16 @@ int replay(const Plan& P, hipStream_t s) {
 
 // Launch shape (configured, cached or tuned now) and graph of a new plan.
 int configure(Plan& P, hipStream_t s) {
+    if (g_cfg_persistent) {
+        int32_t grid = 0;
+        hipError_t e = persistent_grid(P.sd, &grid);
+        if (e == hipErrorNotSupported) return mgb::set_error(MG_E_UNSUPPORTED, "the device has no cooperative launch");
+        if (e == hipSuccess) e = hipHostMalloc(&P.h_abort, sizeof(uint32_t), hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "persistent batch set-up");
+        P.persistent = true;
+        P.shape = 0;
+        return MG_OK;
+    }
     if (g_cfg_shape >= 0) {
         P.shape = g_cfg_shape;
     } else {
@@ -547,6 +638,7 @@ extern "C" int mg_eval_marginal_batch(const mg_tree* trees, int32_t n_trees, voi
     }
     const Plan& P = *it->second;
     if (P.device != dev) return mgb::set_error(MG_E_INVALID, "batch trees live on another device");
+    if (P.persistent) return run_persistent(P, s, timing_on());
     // the kernel timer needs the launches made one by one
     if (!P.exec || timing_on()) return run_plan(P, s, true);
     return replay(P, s);
@@ -573,16 +665,24 @@ extern "C" int mg_score_branches(const mg_tree* trees, int32_t n_trees, void* hi
     return MG_OK;
 }
 
-extern "C" int mg_batch_config(int32_t shape, int32_t graph) {
-    if (shape < -1 || shape >= shape_count() || (graph != 0 && graph != 1))
-        return mgb::set_error(MG_E_INVALID, "shape must be -1 or a shape index, graph 0 or 1");
+extern "C" int mg_batch_config(int32_t shape, int32_t launch) {
+    if (shape < -1 || shape >= shape_count() || launch < 0 || launch > 2)
+        return mgb::set_error(MG_E_INVALID, "shape must be -1 or a shape index, launch 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_plans.empty()) {
         (void)hipDeviceSynchronize();          // launches of cached plans may still be queued
         g_plans.clear();
     }
     g_cfg_shape = shape;
-    g_cfg_graph = graph != 0;
+    g_cfg_graph = launch == 1;
+    g_cfg_persistent = launch == 2;
+    return MG_OK;
+}
+
+extern "C" int mg_batch_barrier_polls(int64_t polls) {
+    if (polls < 0 || polls > (int64_t)INT32_MAX) return mgb::set_error(MG_E_INVALID, "polls must be in [0, 2^31)");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_barrier_polls = (uint32_t)polls;
     return MG_OK;
 }
 
@@ -606,7 +706,7 @@ extern "C" int mg_batch_plan_info(const mg_tree* trees, int32_t n_trees, int32_t
     auto it = g_plans.find(key);
     if (it == g_plans.end()) return mgb::set_error(MG_E_INVALID, "no plan for this tree list (evaluate it first)");
     if (shape) *shape = it->second->shape;
-    if (graphed) *graphed = it->second->exec ? 1 : 0;
+    if (graphed) *graphed = it->second->persistent ? 2 : (it->second->exec ? 1 : 0);
     return MG_OK;
 }
 

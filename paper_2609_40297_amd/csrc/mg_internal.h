@@ -193,5 +193,16 @@ hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* 
                               const unsigned long long* mitems, int32_t n_mitems, uint32_t mask_bricks,
                               const SensorDev& sd, hipStream_t s, int shape = 0, hipEvent_t t0 = nullptr,
                               hipEvent_t t1 = nullptr, hipEvent_t b0 = nullptr, hipEvent_t b1 = nullptr);
+// The whole batch in one cooperative launch of co-resident workgroups: for each
+// depth level d, the trace of items[level_ptr[d] .. level_ptr[d + 1]), their
+// windows, then the path masks of mitems[mlevel_ptr[d] .. mlevel_ptr[d + 1]),
+// with grid barriers between the phases. sync: 2 device words (zeroed here);
+// sync[1] != 0 afterwards when a barrier wait gave up after spin_limit polls.
+hipError_t launch_batch_persistent(const BatchTree* trees, const unsigned long long* items, const int32_t* level_ptr,
+                                   const unsigned long long* mitems, const int32_t* mlevel_ptr, int32_t levels,
+                                   uint32_t mask_bricks, const SensorDev& sd, uint32_t* sync, uint32_t spin_limit,
+                                   hipStream_t s);
+// Workgroups of the persistent launch: the co-resident capacity of the device.
+hipError_t persistent_grid(const SensorDev& sd, int32_t* grid);
 
 }  // namespace mgk

@@ -865,13 +865,11 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchT
     build_chunk(M, St, Tr, (int32_t)(uint32_t)it, (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, &s_any);
 }
 
-// Window selection for one depth level of all trees; writes each tree's
-// outputs and, when asked, the node's depth buffer.
-__global__ __launch_bounds__(kThreads) void k_finish_multi(const BatchTree* __restrict__ trees,
-                                                           const unsigned long long* __restrict__ items, SensorDev S) {
-    __shared__ uint32_t s_p[2 * kMaxBins + 1];
-    __shared__ unsigned long long s_best[kThreads / 64];
-    const unsigned long long it = items[blockIdx.x];
+// Window selection of one (tree, node) item of a batch: gain, window, the
+// window's first column, the depth-cull tile maxima and, when asked for, the
+// node's depth buffer. One workgroup of kThreads.
+__device__ __forceinline__ void finish_item(const BatchTree* __restrict__ trees, unsigned long long it,
+                                            const SensorDev& S, uint32_t* s_p, unsigned long long* s_best) {
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
     if (BT.status != nullptr && *BT.status != 0) return;      // (the request has failed)
     const int32_t node = (int32_t)(uint32_t)it;
@@ -894,6 +892,115 @@ __global__ __launch_bounds__(kThreads) void k_finish_multi(const BatchTree* __re
             c = c >= S.W ? c - S.W : c;
             dst[o] = src[c * S.H + j];
         }
+    }
+}
+
+// Window selection for one depth level of all trees: one workgroup per item.
+__global__ __launch_bounds__(kThreads) void k_finish_multi(const BatchTree* __restrict__ trees,
+                                                           const unsigned long long* __restrict__ items, SensorDev S) {
+    __shared__ uint32_t s_p[2 * kMaxBins + 1];
+    __shared__ unsigned long long s_best[kThreads / 64];
+    finish_item(trees, items[blockIdx.x], S, s_p, s_best);
+}
+
+// ---------------------------------------------------------------- persistent batch
+
+// Barrier over the whole grid of the persistent batch kernel, whose workgroups
+// are all resident at once (the cooperative launch refuses a grid that cannot
+// be). sync[0] counts arrivals and only grows: after k barriers it reaches
+// k * gridDim.x, which each workgroup tracks in *target. A wait that polls
+// `spin_limit` times without every workgroup arriving sets sync[1], and every
+// workgroup then leaves at its next barrier, so the kernel always ends; the
+// host reads sync[1] afterwards. An agent-scope release fence before the
+// arrival and an acquire fence after the wait make each phase's writes visible
+// to the next phase on every XCD; the polls themselves are relaxed loads, which
+// leave the caches of the workgroups still working alone. Returns false once a
+// wait has given up.
+__device__ bool grid_barrier(uint32_t* sync, uint32_t* target, uint32_t spin_limit, int32_t* s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *target += gridDim.x;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t ok = 1;
+        for (uint32_t polls = 0;; ++polls) {
+            const uint32_t a = __hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int32_t)(a - *target) >= 0) break;
+            if (__hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || polls >= spin_limit) {
+                __hip_atomic_store(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// The whole batch in one launch (Sec. IV-C's depth order across all trees):
+// for each depth level, every (node, ray tile) is traced, then every node's
+// window is chosen, then the path masks of the level's nodes with children
+// are built, with a grid barrier after each phase. Work units of a phase are
+// dealt to the workgroups in turn (unit = blockIdx.x + k * gridDim.x); every
+// workgroup passes every barrier, whether it had units or not.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_batch_persistent(
+    const BatchTree* __restrict__ trees, const unsigned long long* __restrict__ items,
+    const int32_t* __restrict__ level_ptr, const unsigned long long* __restrict__ mitems,
+    const int32_t* __restrict__ mlevel_ptr, int32_t levels, SensorDev S, int32_t chunks, int32_t bricks,
+    uint32_t* sync, uint32_t spin_limit) {
+    extern __shared__ char smem[];
+    __shared__ uint32_t s_bins[2 * kMaxBins];
+    __shared__ uint32_t s_p[2 * kMaxBins + 1];
+    __shared__ unsigned long long s_best[kThreads / 64];
+    __shared__ uint8_t s_live[kMaxBuildBricks];
+    __shared__ int32_t s_any, s_ok;
+    uint32_t target = 0;
+    const uint32_t G = gridDim.x;
+    for (int32_t d = 0; d < levels; ++d) {
+        const int32_t i0 = level_ptr[d], n = level_ptr[d + 1] - i0;
+        const uint32_t units = (uint32_t)n * (uint32_t)S.T;
+        for (uint32_t u = blockIdx.x; u < units; u += G) {
+            const int32_t item = __builtin_amdgcn_readfirstlane((int32_t)(u / (uint32_t)S.T));
+            const int32_t tile = __builtin_amdgcn_readfirstlane((int32_t)u - item * S.T);
+            const unsigned long long it = items[i0 + item];
+            const BatchTree& BT = trees[(uint32_t)(it >> 32)];
+            if (BT.status == nullptr || *BT.status == 0) {
+                SensorDev St = S;
+                St.rv = BT.rv;
+                St.rv2 = BT.rv2;
+                const MapDev M = BT.map;
+                const TreeDev Tr = BT.td;
+                trace_tile<true, kThreads>(M, St, Tr, (int32_t)(uint32_t)it, tile, s_bins);
+            }
+            __syncthreads();
+        }
+        if (!grid_barrier(sync, &target, spin_limit, &s_ok)) return;
+        for (uint32_t u = blockIdx.x; u < (uint32_t)n; u += G) {
+            finish_item(trees, items[i0 + (int32_t)u], S, s_p, s_best);
+            __syncthreads();
+        }
+        if (!grid_barrier(sync, &target, spin_limit, &s_ok)) return;
+        const int32_t m0 = mlevel_ptr[d];
+        const uint32_t bunits = (uint32_t)(mlevel_ptr[d + 1] - m0) * (uint32_t)chunks;
+        for (uint32_t u = blockIdx.x; u < bunits; u += G) {
+            const int32_t item = __builtin_amdgcn_readfirstlane((int32_t)(u / (uint32_t)chunks));
+            const int32_t chunk = __builtin_amdgcn_readfirstlane((int32_t)u - item * chunks);
+            const unsigned long long it = mitems[m0 + item];
+            const BatchTree& BT = trees[(uint32_t)(it >> 32)];
+            if (BT.status == nullptr || *BT.status == 0) {
+                SensorDev St = S;
+                St.rv = BT.rv;
+                St.rv2 = BT.rv2;
+                const MapDev M = BT.map;
+                const TreeDev Tr = BT.td;
+                build_chunk(M, St, Tr, (int32_t)(uint32_t)it, chunk, bricks, smem, s_live, &s_any);
+            }
+            __syncthreads();
+        }
+        if (d + 1 < levels && !grid_barrier(sync, &target, spin_limit, &s_ok)) return;
     }
 }
 
@@ -1185,6 +1292,43 @@ hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* 
                               chunks, bricks);
     else
         hipLaunchKernelGGL(k_mask_build_multi, grid, dim3(kBuildThreads), lds, s, trees, mitems, sd, chunks, bricks);
+    return hipGetLastError();
+}
+
+hipError_t persistent_grid(const SensorDev& sd, int32_t* grid) {
+    int dev = 0, cus = 0, coop = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (e != hipSuccess) return e;
+    if (!coop) return hipErrorNotSupported;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent, kThreads, build_lds_bytes(sd));
+    if (e != hipSuccess) return e;
+    if (per_cu < 1 || cus < 1) return hipErrorInvalidConfiguration;
+    *grid = per_cu * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_batch_persistent(const BatchTree* trees, const unsigned long long* items, const int32_t* level_ptr,
+                                   const unsigned long long* mitems, const int32_t* mlevel_ptr, int32_t levels,
+                                   uint32_t mask_bricks, const SensorDev& sd, uint32_t* sync, uint32_t spin_limit,
+                                   hipStream_t s) {
+    if (levels <= 0) return hipSuccess;
+    const size_t lds = build_lds_bytes(sd);
+    if (lds + kMaxBuildBricks > lds_limit()) return hipErrorInvalidConfiguration;
+    int32_t grid = 0;
+    hipError_t e = persistent_grid(sd, &grid);
+    if (e != hipSuccess) return e;
+    SensorDev st = sd;
+    st.T = tiles_per_node(sd, 0);
+    int32_t bricks = kShapes[0].bricks;
+    int32_t chunks = (int32_t)((mask_bricks + (uint32_t)bricks - 1) / (uint32_t)bricks);
+    e = launch_zero_u32(sync, 2, s);
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&trees, (void*)&items, (void*)&level_ptr, (void*)&mitems, (void*)&mlevel_ptr,
+                    (void*)&levels, (void*)&st, (void*)&chunks, (void*)&bricks, (void*)&sync, (void*)&spin_limit};
+    e = hipLaunchCooperativeKernel((const void*)k_batch_persistent, dim3((unsigned)grid), dim3(kThreads), args, lds, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

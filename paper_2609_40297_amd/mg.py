@@ -33,7 +33,7 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
            "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read",
            "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal", "mg_eval_marginal_batch_noalloc",
-           "mg_server_cancel", "mg_server_fail_request", "mg_server_pause")
+           "mg_server_cancel", "mg_server_fail_request", "mg_server_pause", "mg_batch_barrier_polls")
 
 
 class MGError(RuntimeError):
@@ -96,6 +96,7 @@ def lib() -> C.CDLL:
         L.mg_server_cancel.argtypes = [P, I64]
         L.mg_server_fail_request.argtypes = [P, I64, I32]
         L.mg_server_pause.argtypes = [P, I32]
+        L.mg_batch_barrier_polls.argtypes = [I64]
         L.mg_server_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(I32),
                                       C.POINTER(I32)]
         L.mg_server_destroy.argtypes = [P]
@@ -113,7 +114,7 @@ def lib() -> C.CDLL:
                      "mg_sensor_tables", "mg_server_create", "mg_server_submit", "mg_server_poll",
                      "mg_server_wait", "mg_server_stats", "mg_server_destroy", "mg_timing_enable",
                      "mg_timing_read", "mg_batch_config", "mg_trace_shapes", "mg_batch_plan_info",
-                     "mg_score_branches", "mg_server_cancel", "mg_server_fail_request", "mg_server_pause"):
+                     "mg_score_branches", "mg_server_cancel", "mg_server_fail_request", "mg_server_pause", "mg_batch_barrier_polls"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -268,12 +269,18 @@ def score_batch(trees, gain, lam=0.5, stream=None):
     return cost, obj, best, branch
 
 
-def mg_batch_config(shape: int = -1, graph: bool = False):
-    _check(lib().mg_batch_config(int(shape), 1 if graph else 0))
+def mg_batch_config(shape: int = -1, launch: int = 0):
+    """launch: 0 launches one by one on stream groups, 1 graph replay, 2 one persistent cooperative launch."""
+    _check(lib().mg_batch_config(int(shape), int(launch)))
+
+
+def mg_batch_barrier_polls(polls: int):
+    """Polls of one grid-barrier wait of the persistent launch before it gives up."""
+    _check(lib().mg_batch_barrier_polls(int(polls)))
 
 
 def mg_trace_shapes():
-    """[(rays per workgroup, queue capacity per wave), ...] of the compiled launch shapes."""
+    """[(rays per trace workgroup, bricks per mask-builder workgroup), ...] of the compiled launch shapes."""
     n = C.c_int32()
     _check(lib().mg_trace_shapes(C.byref(n), None, None, 0))
     th = np.zeros(n.value, np.int32)
@@ -283,11 +290,11 @@ def mg_trace_shapes():
 
 
 def mg_batch_plan_info(trees: Sequence[int]):
-    """(shape index, graphed) of the cached plan of this tree list."""
+    """(shape index, launch form: 0 one by one, 1 graph, 2 persistent) of the cached plan of this tree list."""
     arr = (C.c_void_p * len(trees))(*trees)
     sh, gr = C.c_int32(), C.c_int32()
     _check(lib().mg_batch_plan_info(C.cast(arr, C.c_void_p), len(trees), C.byref(sh), C.byref(gr)))
-    return sh.value, bool(gr.value)
+    return sh.value, int(gr.value)
 
 
 def mg_timing_enable(on: bool):

@@ -121,7 +121,11 @@ def test_launch_shape_table_and_config_validation():
     assert len(shapes) >= 2
     for th, bricks in shapes:      # rays per trace workgroup, bricks per mask-builder workgroup
         assert th % 64 == 0 and 64 <= th <= 1024 and 16 <= bricks <= 128
-    for bad in [(-2, 0), (len(shapes), 0), (0, 2)]:
+    for bad in [(-2, 0), (len(shapes), 0), (0, 3), (0, -1)]:
         with pytest.raises(mg.MGError) as e:
             mg._check(mg.lib().mg_batch_config(*bad))
+        assert e.value.code == mg.MG_E_INVALID
+    for bad in (-1, 1 << 31):
+        with pytest.raises(mg.MGError) as e:
+            mg.mg_batch_barrier_polls(bad)
         assert e.value.code == mg.MG_E_INVALID

@@ -238,3 +238,68 @@ def test_autotune_chooses_a_shape_and_keeps_results(mg):
     for T in trees:
         T.close()
     M.close()
+
+
+def test_persistent_launch_equals_per_level_launches(mg):
+    """One persistent cooperative launch per call (co-resident workgroups, grid barriers between
+    the trace, window and mask phases of every level) gives the per-level launches' gains, windows
+    and depth buffers bit for bit: one tree (`step`), and six trees of `batch64` in one call, twice
+    in a row; the plan reports the persistent form."""
+    import torch
+    cases = [("step", None), ("batch64", 6)]
+    try:
+        mg.mg_batch_barrier_polls(1 << 22)          # each wait ends within about a second
+        for name, nt in cases:
+            w = W.make(name, n_trees=nt)
+            M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+            trees = [mg.Tree(M, t.pos_m, t.parent, w.sensor) for t in w.trees]
+            mg.mg_batch_config(-1, 0)
+            g0, y0, d0 = mg.eval_batch(trees, depth=True)
+            torch.cuda.synchronize()
+            ref = (mg.as_u32(g0), y0.cpu().numpy(), d0.cpu().numpy())
+            mg.mg_batch_config(-1, 2)
+            for rep in range(2):
+                log(f"[persistent] {name}: {len(trees)} trees, call {rep}")
+                g, y, d = mg.eval_batch(trees, depth=True)
+                torch.cuda.synchronize()
+                assert np.array_equal(mg.as_u32(g), ref[0]), name
+                assert np.array_equal(y.cpu().numpy(), ref[1]), name
+                assert np.array_equal(d.cpu().numpy().view(np.uint32), ref[2].view(np.uint32)), name
+            assert mg.mg_batch_plan_info([t.handle for t in trees])[1] == 2
+            mg.mg_batch_config(-1, 0)
+            for T in trees:
+                T.close()
+            M.close()
+    finally:
+        mg.mg_batch_barrier_polls(1 << 25)
+        mg.mg_batch_config(-1, 0)
+
+
+def test_persistent_barrier_gives_up_when_its_poll_limit_runs_out(mg):
+    """With a barrier poll limit of 0 set from the host, the first grid-barrier wait that is not
+    already satisfied gives up: every workgroup leaves at its next barrier, the launch ends and
+    the call reports MG_E_DEVICE; with the limit restored the next call is correct."""
+    import torch
+    w = W.make("tiny")
+    M = mg.Map(w.map.states, w.map.voxel_m, w.map.origin_m)
+    T = mg.Tree(M, w.trees[0].pos_m, w.trees[0].parent, w.sensor)
+    try:
+        mg.mg_batch_config(-1, 0)
+        g0, y0, _ = mg.eval_batch([T])
+        torch.cuda.synchronize()
+        ref = (mg.as_u32(g0), y0.cpu().numpy())
+        mg.mg_batch_config(-1, 2)
+        mg.mg_batch_barrier_polls(0)
+        log("[persistent] barrier poll limit 0")
+        with pytest.raises(mg.MGError) as e:
+            mg.eval_batch([T])
+        assert e.value.code == mg.MG_E_DEVICE
+        mg.mg_batch_barrier_polls(1 << 22)
+        g, y, _ = mg.eval_batch([T])
+        torch.cuda.synchronize()
+        assert np.array_equal(mg.as_u32(g), ref[0]) and np.array_equal(y.cpu().numpy(), ref[1])
+    finally:
+        mg.mg_batch_barrier_polls(1 << 25)
+        mg.mg_batch_config(-1, 0)
+        T.close()
+        M.close()
