@@ -102,124 +102,21 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, size_t n) {
         p[i] = 0u;
 }
 
-// ---------------------------------------------------------------- ancestor test
+// ---------------------------------------------------------------- window geometry
 
-struct AncLDS {
+// A node's position (voxel units) and its window: first column and the unit
+// vectors of its left and right boundaries.
+struct WindowGeom {
     float qx, qy, qz;
     int32_t c0;
     float b0x, b0y;       // left boundary of the window
     float b1x, b1y;       // right boundary (left boundary of column c0 + w_buf)
-    uint32_t dpan_off;    // element offset of the ancestor's panorama of first hits
-    uint32_t pad[3];
 };
 
 __device__ __forceinline__ int32_t wrap(int32_t c, int32_t W) { return c >= W ? c - W : c; }
 
 // r lies at or to the left (counter-clockwise side) of boundary direction b.
 __device__ __forceinline__ bool left_of(float2 b, float rx, float ry) { return b.x * ry - b.y * rx >= 0.f; }
-
-// The pixel of ancestor A's buffer that would decide whether A sees the voxel
-// centre (cx, cy, cz), and the centre's squared range from A. A sees the
-// centre when it falls in a pixel cell of A's window (azimuth between two
-// column boundaries, elevation between two row boundaries; cells half-open)
-// and its squared range is <= the squared depth stored for that pixel
-// (see_depth). Row and column are the numbers of inner boundaries the centre
-// lies at-or-beyond; a table lookup guesses them and the exact boundary
-// comparisons settle them. Those comparisons are monotone along the
-// boundaries, so the settled index is the exact count whatever the guess. The
-// cheap rejections come first: the wedge, then range and band as one mask.
-// idx = kNoPixel for a centre outside the window, band or range, and for a
-// lane with act false.
-constexpr uint32_t kNoPixel = 0xffffffffu;
-struct Pixel {
-    uint32_t idx;        // element of the panorama array holding the pixel's depth, or kNoPixel
-    float range2;
-};
-
-__device__ __forceinline__ Pixel pixel_of(const AncLDS& A, float cx, float cy, float cz, bool act,
-                                          const SensorDev& S, const float2* __restrict__ s_bv,
-                                          const float* __restrict__ s_ts, float ts0, float tsH,
-                                          const uint16_t* __restrict__ s_lut_col,
-                                          const uint16_t* __restrict__ s_lut_row) {
-    const float rx = cx - A.qx;
-    const float ry = cy - A.qy;
-    const float w0 = A.b0x * ry - A.b0y * rx;
-    const float w1 = A.b1x * ry - A.b1y * rx;
-    Pixel P{kNoPixel, 0.f};
-    // The wedge is tested first and alone: the voxels of a brick slice often
-    // lie outside the window together, and the wave then skips the rest.
-    if (act & (w0 >= 0.f) & (w1 < 0.f)) {
-        const float rz = cz - A.qz;
-        const float rho2 = rx * rx + ry * ry;
-        const float range2 = rho2 + rz * rz;
-        const float sz = rz * fabsf(rz);
-        if ((range2 <= S.rv2) & (sz >= rho2 * ts0) & (sz < rho2 * tsH)) {
-            // Column: pseudo-angle past the left boundary (monotone in the angle) picks a
-            // table bucket holding at most one column boundary, giving a guess gc. The
-            // boundaries gc, gc + 1 and gc + 2 of the window are read at once (the LDS
-            // table holds the boundaries twice over, so window boundary k is entry
-            // c0 + k). When boundary gc lies at or left of r and gc + 2 does not, the
-            // column is gc + 1 if boundary gc + 1 does and gc otherwise. Other lanes
-            // (rounding at a bucket edge) settle with the boundary-by-boundary walk,
-            // which also returns gc + l1 in the two patterns that break monotonicity
-            // (1-0-1 and 0-1-0).
-            const float u0 = A.b0x * rx + A.b0y * ry;
-            float pa = w0 * __builtin_amdgcn_rcpf(fabsf(u0) + w0);
-            pa = u0 < 0.f ? 2.f - pa : pa;
-            // (pa and tg are finite here: the wedge excludes r = 0 in x and y, so
-            // one median-of-three clamps the table index)
-            const int32_t gc =
-                s_lut_col[(int32_t)__builtin_amdgcn_fmed3f(pa * S.lut_col_scale, 0.f, (float)(S.n_lut_col - 1))];
-            const int32_t cb = A.c0 + gc;
-            const float2 v0 = s_bv[cb], v1 = s_bv[cb + 1], v2 = s_bv[cb + 2];
-            const bool l0 = (gc == 0) | left_of(v0, rx, ry);
-            const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
-            const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
-            // (and/or rather than a select, so that all three reads stay unconditional)
-            int32_t col = gc + (int32_t)l1;
-            const bool c_ok = l0 & !l2;
-            if (!c_ok) {      // (a divergent branch: skipped when no lane needs it)
-                for (;;) {
-                    if (col + 1 >= S.WB || !left_of(s_bv[A.c0 + col + 1], rx, ry)) break;
-                    ++col;
-                }
-                for (;;) {
-                    if (col == 0 || left_of(s_bv[A.c0 + col], rx, ry)) break;
-                    --col;
-                }
-            }
-            // Row: elevation tangent picks a bucket holding at most one row boundary;
-            // the same three-boundary decision, same fallback.
-            const float tg = rz * __builtin_amdgcn_rsqf(rho2);
-            const int32_t gr = s_lut_row[(int32_t)__builtin_amdgcn_fmed3f((tg - S.lut_row_lo) * S.lut_row_scale, 0.f,
-                                                                          (float)(S.n_lut_row - 1))];
-            const float e0 = s_ts[gr], e1 = s_ts[gr + 1], e2 = s_ts[min(gr + 2, S.H)];
-            const bool r0 = (gr == 0) | (sz >= rho2 * e0);
-            const bool r1 = (gr + 1 < S.H) & (sz >= rho2 * e1);
-            const bool r2 = (gr + 2 < S.H) & (sz >= rho2 * e2);
-            int32_t row = gr + (int32_t)r1;
-            const bool r_ok = r0 & !r2;
-            if (!r_ok) {
-                for (;;) {
-                    if (row + 1 >= S.H || !(sz >= rho2 * s_ts[row + 1])) break;
-                    ++row;
-                }
-                for (;;) {
-                    if (row == 0 || sz >= rho2 * s_ts[row]) break;
-                    --row;
-                }
-            }
-            // (column < 4096 and H <= 2048: the product fits the 24-bit multiplier)
-            P.idx = A.dpan_off + __umul24((uint32_t)wrap(A.c0 + col, S.W), (uint32_t)S.H) + (uint32_t)row;
-            P.range2 = range2;
-        }
-    }
-    return P;
-}
-
-// A sees the centre: it lies in a pixel cell of A's window whose stored depth D
-// has range2 <= D * D (Sec. IV-B counts equality as observed).
-__device__ __forceinline__ bool see_depth(const Pixel& P, float D) { return (P.idx != kNoPixel) & (P.range2 <= D * D); }
 
 // ---------------------------------------------------------------- path masks
 
@@ -240,36 +137,30 @@ struct TableLDS {
     uint16_t* lut_row;
 };
 
-// LDS carve-up of the builder: boundary table (twice over) | row table | guess tables.
+// LDS carve-up of the builder, for one node: the column boundaries of its
+// window (boundary k of the window = column c0 + k, k = 0 .. W_buf + 1) | row
+// table | guess tables.
 __device__ __forceinline__ TableLDS carve_tables(char* smem, const SensorDev& S) {
     TableLDS L;
-    L.bv = reinterpret_cast<float2*>(smem);                 // column boundaries twice over: [2W + 1]
-    L.ts = reinterpret_cast<float*>(L.bv + 2 * S.W + 1);
+    L.bv = reinterpret_cast<float2*>(smem);                 // [W_buf + 2]
+    L.ts = reinterpret_cast<float*>(L.bv + S.WB + 2);
     L.lut_col = reinterpret_cast<uint16_t*>(L.ts + S.H + 1);
     L.lut_row = L.lut_col + S.n_lut_col;
     return L;
 }
 
-__device__ __forceinline__ void load_tables(const TableLDS& L, const SensorDev& S) {
-    for (int32_t i = threadIdx.x; i <= 2 * S.W; i += blockDim.x)
-        L.bv[i] = S.bv[i < S.W ? i : (i < 2 * S.W ? i - S.W : 0)];
+__device__ __forceinline__ void load_tables(const TableLDS& L, const SensorDev& S, int32_t c0) {
+    for (int32_t i = threadIdx.x; i < S.WB + 2; i += blockDim.x) {
+        int32_t c = c0 + i;
+        c = c >= S.W ? c - S.W : c;
+        c = c >= S.W ? c - S.W : c;
+        L.bv[i] = S.bv[c];
+    }
     for (int32_t i = threadIdx.x; i <= S.H; i += blockDim.x) L.ts[i] = S.ts[i];
     for (int32_t i = threadIdx.x; i < S.n_lut_col; i += blockDim.x) L.lut_col[i] = S.lut_col[i];
     for (int32_t i = threadIdx.x; i < S.n_lut_row; i += blockDim.x) L.lut_row[i] = S.lut_row[i];
 }
 
-// Path mask of node `node` over bricks [chunk * bricks, ...) of the mask grid:
-// the parent's path mask (none at the root, and none with anc_cap = 1) ORed
-// with the voxels the node itself observes, decided voxel by voxel with
-// pixel_of and see_depth on the node's own window and buffer, i.e. the test its
-// descendants would make against it. A brick is left to the parent's bits
-// without testing when it lies beyond the range, or wholly outside the node's
-// azimuth wedge, by a margin that covers the brick's voxel centres (within
-// 3.5 * sqrt(3) of its centre, 3.5 * sqrt(2) across in x and y) and rounding.
-// The sensor tables are loaded into LDS only when some brick of the chunk is
-// tested. One wave tests one brick slice of 64 voxels at a time (64
-// consecutive grid bytes, two mask words). Whole workgroup; chunks past the
-// map's last brick do nothing (a batch launch covers its largest map).
 // Whether the node may observe a voxel of brick (bx, by, bz), from below: the
 // pixels that the brick's voxel centres can fall in lie inside a rectangle of
 // the window (azimuth from the corners of the centres' box seen from outside,
@@ -319,6 +210,22 @@ __device__ bool may_see_brick(const SensorDev& S, const float* __restrict__ tm, 
     return m * m * 1.0001f + 0.01f >= dmin2;
 }
 
+// Path mask of node `node` over bricks [chunk * bricks, ...) of the mask grid:
+// the parent's path mask (none at the root, and none with anc_cap = 1) ORed
+// with the voxels the node itself observes. A voxel is observed when its
+// centre lies in a pixel cell of the node's window (azimuth between two column
+// boundaries by exact left-of tests, elevation between two row boundaries by
+// r_z|r_z| against rho^2 times the tabulated t|t| of the boundary; cells
+// half-open) and its squared range is at most the squared first hit stored for
+// that pixel: the test its descendants would make against it. A brick keeps
+// the parent's bits (and code) without testing when it lies beyond the range,
+// wholly outside the node's azimuth wedge (margins cover the brick's voxel
+// centres, within 3.5 sqrt(3) of its centre and 3.5 sqrt(2) across in x and
+// y, and rounding), holds no unknown voxel, or fails the depth cull
+// (may_see_brick). The window's tables are loaded into LDS only when some
+// brick of the chunk is tested. One wave tests one brick: each lane one (x, y)
+// column of 8 voxels. Whole workgroup; chunks past the map's last brick do
+// nothing (a batch launch covers its largest map).
 __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
                                             int32_t chunk, int32_t bricks, char* smem, uint8_t* s_live,
                                             int32_t* s_any) {
@@ -340,12 +247,10 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     const int32_t c0 = Tr.c0[node];
     int32_t c1 = c0 + S.WB;
     c1 = c1 >= S.W ? c1 - S.W : c1;
-    AncLDS A;
+    WindowGeom A;
     A.qx = q.x; A.qy = q.y; A.qz = q.z; A.c0 = c0;
     const float2 b0 = S.bv[c0], b1 = S.bv[c1];
     A.b0x = b0.x; A.b0y = b0.y; A.b1x = b1.x; A.b1y = b1.y;
-    A.dpan_off = (uint32_t)node * (uint32_t)S.R;
-    A.pad[0] = A.pad[1] = A.pad[2] = 0u;
     const int32_t cnt = (int32_t)min((uint32_t)bricks, nb - lo);
     if (tid == 0) *s_any = 0;
     __syncthreads();
@@ -372,7 +277,7 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     if (tid < cnt && !s_live[tid]) code[lo + (uint32_t)tid] = par ? pcode[lo + (uint32_t)tid] : (uint8_t)kMaskNone;
     if (!*s_any) return;
     const TableLDS L = carve_tables(smem, S);
-    load_tables(L, S);
+    load_tables(L, S, c0);
     __syncthreads();
     const int32_t lane = tid & 63;
     const float ts0 = L.ts[0], tsH = L.ts[S.H];
@@ -390,8 +295,7 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         if (par && lane < 16) pw = par[wbase + (uint32_t)lane];
         // The lane's column of the brick: the azimuth column of its pixels (the
         // same for the 8 voxels, which share x and y), the row of each voxel,
-        // then the 8 depths, loaded together. The arithmetic is pixel_of's. The
-        // voxels' states are not read: only unknown voxels' bits are ever looked
+        // then the 8 depths, loaded together. The voxels' states are not read: only unknown voxels' bits are ever looked
         // up, so bits of known voxels (and of voxels past the grid) do not matter.
         const float rx = cx - A.qx, ry = cy - A.qy;
         const float w0 = A.b0x * ry - A.b0y * rx;
@@ -405,19 +309,18 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         pa = u0 < 0.f ? 2.f - pa : pa;
         const int32_t gc =
             L.lut_col[(int32_t)__builtin_amdgcn_fmed3f(pa * S.lut_col_scale, 0.f, (float)(S.n_lut_col - 1))];
-        const int32_t cb = A.c0 + gc;
-        const float2 v0 = L.bv[cb], v1 = L.bv[cb + 1], v2 = L.bv[cb + 2];
+        const float2 v0 = L.bv[gc], v1 = L.bv[gc + 1], v2 = L.bv[gc + 2];
         const bool l0 = (gc == 0) | left_of(v0, rx, ry);
         const bool l1 = (gc + 1 < S.WB) & left_of(v1, rx, ry);
         const bool l2 = (gc + 2 < S.WB) & left_of(v2, rx, ry);
         int32_t col = gc + (int32_t)l1;
         if (wedge & !(l0 & !l2)) {      // (rare: a guess at a bucket edge)
             for (;;) {
-                if (col + 1 >= S.WB || !left_of(L.bv[A.c0 + col + 1], rx, ry)) break;
+                if (col + 1 >= S.WB || !left_of(L.bv[col + 1], rx, ry)) break;
                 ++col;
             }
             for (;;) {
-                if (col == 0 || left_of(L.bv[A.c0 + col], rx, ry)) break;
+                if (col == 0 || left_of(L.bv[col], rx, ry)) break;
                 --col;
             }
         }
@@ -1051,7 +954,7 @@ void shape_of(int shape, int* threads, int* bricks) {
 }
 
 size_t build_lds_bytes(const SensorDev& sd) {
-    return sizeof(float2) * (2 * sd.W + 1) + sizeof(float) * (sd.H + 1) +
+    return sizeof(float2) * (sd.WB + 2) + sizeof(float) * (sd.H + 1) +
            sizeof(uint16_t) * (sd.n_lut_col + sd.n_lut_row);
 }
 
