@@ -186,9 +186,10 @@ def work_counts(name, rays_total=None):
     return out
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_multi_step_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_multi_large_traffic.md")
 # the trace kernel and the scheduler that decides how its launches are cut
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_40297_amd", "csrc", f) for f in ("mg_kernels.hip", "mg_batch.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_40297_amd", "csrc", f)
+                  for f in ("mg_kernels.hip", "mg_batch.hip", "mg_internal.h")]
 
 
 def kernel_source_hash(sources=None):
@@ -200,7 +201,7 @@ def kernel_source_hash(sources=None):
     return h.hexdigest()
 
 
-def summary_traffic(path, sources):
+def summary_traffic(path, sources, key="hbm_bytes_per_launch"):
     """HBM bytes per launch from a committed counter summary, or None.
 
     The summary records the SHA-256 of the sources it was taken with; when they
@@ -213,14 +214,15 @@ def summary_traffic(path, sources):
             if ln.startswith("- ") and ":" in ln:
                 k, v = ln[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != kernel_source_hash(sources) or "hbm_bytes_per_launch" not in vals:
+    if vals.get("kernel_source_sha256") != kernel_source_hash(sources) or key not in vals:
         return None
-    return float(vals["hbm_bytes_per_launch"])
+    return float(vals[key])
 
 
 def measured_traffic(workload):
-    """HBM bytes per trace launch of the step workload (committed counter summary), or None."""
-    return summary_traffic(TRAFFIC_SUMMARY, KERNEL_SOURCES) if workload == "step" else None
+    """HBM bytes per step of the trace and mask-builder dispatches of the large workload (committed counter
+    summary), or None."""
+    return summary_traffic(TRAFFIC_SUMMARY, KERNEL_SOURCES, "hbm_bytes_per_step") if workload == "large" else None
 
 
 TSDF_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tsdf_grid_512x512x128_traffic.md")
@@ -544,7 +546,7 @@ def serve_bench(args):
         m.close()
 
 
-def roofline_of(wc, trace, steps, n_total, yaw_bins, ms_per_step, sources_ok):
+def roofline_of(wc, trace, steps, n_total, yaw_bins, ms_per_step, traffic):
     """Roofline of the marginal-gain kernels (trace + path-mask builder) from the oracle's work counts
     and the live launch intervals, or None when either is missing."""
     if wc is None or not trace or not trace["launches"]:
@@ -557,7 +559,9 @@ def roofline_of(wc, trace, steps, n_total, yaw_bins, ms_per_step, sources_ok):
     summed = trace["total_ms"] / steps              # their summed durations (groups overlap on two streams)
     achieved = alg_step / (busy * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": sources_ok,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per step of the trace and mask-builder dispatches (rocprofv3 FETCH_SIZE + "
+                            "WRITE_SIZE, each scaled by what it reads for a plain device copy)",
             "kernels": ["k_trace_multi", "k_mask_build_multi"],
             "algorithmic_bytes_per_step": alg_step, "work_counts": wc.get("counted"),
             "busy_ms_per_step": busy, "summed_launch_ms_per_step": summed,

@@ -453,8 +453,8 @@ extern "C" int mg_map_create_tsdf(const float* distance, const float* weight, in
     if (rc != MG_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = launch_fill_outside(m->dev, s);
+    // (the whole-grid conversion takes the bricks' summaries itself)
     if (e == hipSuccess) e = launch_tsdf_grid(distance, weight, m->dev, surface_m, min_weight, s);
-    if (e == hipSuccess) e = launch_brick_flags(m->dev, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(m->bricks);
@@ -482,9 +482,13 @@ extern "C" int mg_map_update_tsdf(mg_map map, void* hip_stream, const float* dis
     HIP_TRY(hipGetDevice(&dev));
     if (dev != map->device) return fail(MG_E_INVALID, "the map lives on another device");
     hipStream_t s = (hipStream_t)hip_stream;
-    HIP_TRY(whole ? launch_tsdf_grid(distance, weight, map->dev, surface_m, min_weight, s)
-                  : launch_tsdf_box(distance, weight, map->dev, lo, size, surface_m, min_weight, s));
-    HIP_TRY(launch_brick_flags(map->dev, s));
+    // (the whole-grid conversion takes the bricks' summaries itself; a box needs the pass)
+    if (whole) {
+        HIP_TRY(launch_tsdf_grid(distance, weight, map->dev, surface_m, min_weight, s));
+    } else {
+        HIP_TRY(launch_tsdf_box(distance, weight, map->dev, lo, size, surface_m, min_weight, s));
+        HIP_TRY(launch_brick_flags(map->dev, s));
+    }
     return MG_OK;
 }
 

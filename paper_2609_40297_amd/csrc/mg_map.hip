@@ -19,12 +19,46 @@ __device__ __forceinline__ uint8_t tsdf_state(float d, float w, float surface, f
     return !(w >= min_weight) ? (uint8_t)kUnknown : (d <= surface ? (uint8_t)kOccupied : (uint8_t)kFree);
 }
 
+// The summaries of the run's bricks assembled in LDS (the work of
+// k_brick_flags, done here so that a whole-grid conversion needs no second
+// pass): one wave per brick, each lane 8 of its 512 bytes; the unknown and free
+// voxels of a brick that holds only that state get its mark, and brick_unk
+// records whether it holds an unknown voxel (bricks wholly in the padding have
+// no entry). Whole workgroup of 256.
+__device__ __forceinline__ void mark_run(uint8_t* tile, int32_t tb, int32_t bx0, int32_t by, int32_t bz,
+                                         const MapDev& m) {
+    const int32_t lane = (int32_t)threadIdx.x & 63, wave = (int32_t)threadIdx.x >> 6;
+    for (int32_t k = wave; k < tb; k += 4) {
+        uint64_t* p = reinterpret_cast<uint64_t*>(tile + k * 512) + lane;
+        const uint64_t v = *p;
+        bool unk = false, not_unk = false, not_free = false;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t x = (uint32_t)(v >> (8 * q)) & 0xffu;
+            unk |= x == kUnknown;
+            not_unk |= x != kUnknown;
+            not_free |= x != kFree;
+        }
+        const bool any_unk = __builtin_amdgcn_ballot_w64(unk) != 0;
+        const bool all_unk = __builtin_amdgcn_ballot_w64(not_unk) == 0;
+        const bool all_free = __builtin_amdgcn_ballot_w64(not_free) == 0;
+        if (all_unk | all_free) {
+            const uint64_t add = (all_unk ? (uint64_t)kUnknownBrick : (uint64_t)(kFreeBrick - kFree)) * 0x0101010101010101ull;
+            *p = v + add;
+        }
+        const int32_t bx = bx0 + k;
+        if (lane == 0 && (uint32_t)bx < m.mbx && (uint32_t)by < m.mby && (uint32_t)bz < m.mbz)
+            m.brick_unk[(uint32_t)bx + m.mbx * ((uint32_t)by + m.mby * (uint32_t)bz)] = any_unk ? 1 : 0;
+    }
+}
+
 // Whole grid: one workgroup per run of up to 32 bricks along x at one (by, bz),
 // over the bricks that hold grid voxels (bricks wholly in the padding keep
 // kOutside from the map's creation). Each of the 64 (y, z) rows of the run is
-// read coalesced along x, the states are assembled in LDS in brick order, and
-// the run's bricks (contiguous in memory) are written out in 16-byte stores.
-// Padding voxels inside these bricks get kOutside.
+// read coalesced along x, the states are assembled in LDS in brick order, the
+// bricks' summaries are taken (mark_run), and the run's bricks (contiguous in
+// memory) are written out in 16-byte stores. Padding voxels inside these
+// bricks get kOutside.
 constexpr int kTileBricks = 32;
 
 __global__ __launch_bounds__(256) void k_tsdf_grid(const float* __restrict__ dist, const float* __restrict__ weight,
@@ -48,6 +82,8 @@ __global__ __launch_bounds__(256) void k_tsdf_grid(const float* __restrict__ dis
             tile[(tid >> 3) * 512 + (tid & 7) + (yy << 3) + (zz << 6)] = v;
         }
     }
+    __syncthreads();
+    mark_run(tile, tb, bx0, by, bz, m);
     __syncthreads();
     const size_t base = ((size_t)bx0 + (size_t)m.nbx * ((size_t)by + (size_t)m.nby * (size_t)bz)) * 512u;
     uint4* dst = (uint4*)(bricks + base);
@@ -86,6 +122,8 @@ __global__ __launch_bounds__(256) void k_tsdf_grid4(const float* __restrict__ di
             *(uint32_t*)&tile[(quad >> 1) * 512 + (quad & 1) * 4 + (yy << 3) + (zz << 6)] = v;
         }
     }
+    __syncthreads();
+    mark_run(tile, tb, bx0, by, bz, m);
     __syncthreads();
     const size_t base = ((size_t)bx0 + (size_t)m.nbx * ((size_t)by + (size_t)m.nby * (size_t)bz)) * 512u;
     uint4* dst = (uint4*)(bricks + base);

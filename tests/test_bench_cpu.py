@@ -20,6 +20,13 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
 
 
+def test_large_work_counts_give_the_documented_algorithmic_bytes():
+    wc = bench.work_counts("large", 8 * 3000 * 720 * 120)
+    assert wc["counted"] == "all trees, exact" and wc["nodes"] == 24000 and wc["rays"] == 2073600000
+    per_step = wc["visits"] + 4 * wc["anc_tests"] + 4 * wc["rays"] + 2 * 72 * 4 * wc["nodes"]
+    assert per_step == pytest.approx(757.57e9, rel=1e-4)
+
+
 def test_step_work_counts_give_the_documented_algorithmic_bytes():
     wc = bench.work_counts("step")
     assert wc["nodes"] == 500 and wc["rays"] == 500 * 360 * 60
@@ -45,7 +52,7 @@ def test_traffic_summary_applies_only_to_its_sources(tmp_path):
 def test_roofline_uses_the_union_of_launch_intervals():
     wc = {"visits": 1000, "anc_tests": 100, "rays": 10, "counted": "all trees, exact"}
     trace = {"launches": 6, "busy_ms": 2.0, "total_ms": 3.0}
-    r = bench.roofline_of(wc, trace, steps=2, n_total=2, yaw_bins=4, ms_per_step=5.0, sources_ok=None)
+    r = bench.roofline_of(wc, trace, steps=2, n_total=2, yaw_bins=4, ms_per_step=5.0, traffic=None)
     alg = 1000 + 4 * 100 + 4 * 10 + 2 * 2 * 4 * 4
     assert r["algorithmic_bytes_per_step"] == alg
     assert r["busy_ms_per_step"] == 1.0 and r["summed_launch_ms_per_step"] == 1.5
