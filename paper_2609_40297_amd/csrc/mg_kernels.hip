@@ -412,28 +412,20 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build(MapDev M, SensorDe
 
 // ---------------------------------------------------------------- ray traversal
 
-// Boundaries still ahead inside the voxel's brick along an axis, before the
-// brick's own exit boundary (0 for an axis the ray does not move along).
-__device__ __forceinline__ int32_t inner_left(int32_t i, int32_t s) {
-    return s > 0 ? 7 - (i & 7) : (s < 0 ? (i & 7) : 0);
-}
-
-// How many of one axis's boundaries b0, b0 + db, b0 + 2 db, ... (at most `lim`,
-// lim <= 7) the DDA crosses before the crossing at parameter T: a boundary with
-// parameter t = (b - q) * f comes first when t < T, or when t == T and the axis
-// precedes the other one in the tie order (`first`). Parameters grow along the
-// axis, so these boundaries are a prefix and three probes find its length.
-__device__ __forceinline__ int32_t crossings_before(float b0, float db, float q, float f, int32_t lim, float T,
-                                                    bool first) {
-    int32_t k = 0;
-#pragma unroll
-    for (int32_t step = 4; step >= 1; step >>= 1) {
-        const int32_t m = k + step - 1;
-        const float tb = ((b0 + (float)m * db) - q) * f;
-        const bool before = (tb < T) | ((tb == T) & first);
-        k += ((m < lim) & before) ? step : 0;
-    }
-    return k;
+// How many of one axis's boundaries b0, b0 + db, b0 + 2 db, ... the DDA
+// crosses before the crossing at parameter Tc: those with parameter
+// t = (b - q) * f below Tc (a caller that wants ties counted passes the next
+// float above the crossing). Parameters grow by at least 1 from one boundary
+// to the next, so these boundaries are a prefix; the caller's crossing leaves
+// the brick, so the prefix ends at the axis's own brick exit, at most 7
+// boundaries on, and three probes (at 3, then 3 +- 2, then +- 1) find its
+// length. Boundaries are evaluated exactly as the single step evaluates them
+// (the fused multiply-add of integers is exact). Returned as a float count.
+__device__ __forceinline__ float crossings_before(float b0, float db, float q, float f, float Tc) {
+    float m = 3.f;
+    m += ((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 2.f : -2.f;
+    m += ((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 1.f : -1.f;
+    return m + (((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 1.f : 0.f);
 }
 
 // One workgroup = kTh / 64 pixel blocks (tile `tile`) of one node, one block of
@@ -495,9 +487,15 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     float bz = sz ? (float)(iz + (sz > 0 ? 1 : 0)) : inf;
     const float fx = sx ? iv.x : 1.f, fy = sy ? iv.y : 1.f, fz = sz ? iv.z : 1.f;
     const float dbx = (float)sx, dby = (float)sy, dbz = (float)sz;
-    float tx = (bx - p.x) * fx;
-    float ty = (by - p.y) * fy;
-    float tz = (bz - p.z) * fz;
+    // the node's coordinates, -inf on an axis the ray does not move along: every
+    // boundary parameter of that axis, (b - q) * 1 with b = +inf or a brick
+    // exit, is then +inf
+    const float qx = sx ? p.x : -inf, qy = sy ? p.y : -inf, qz = sz ? p.z : -inf;
+    // a brick's exit boundary along an axis: its low face, plus 8 when moving up
+    const int32_t eox = sx > 0 ? 8 : 0, eoy = sy > 0 ? 8 : 0, eoz = sz > 0 ? 8 : 0;
+    float tx = (bx - qx) * fx;
+    float ty = (by - qy) * fy;
+    float tz = (bz - qz) * fz;
     float t = 0.f, h = S.rv;
     uint32_t n_abs = 0, n_new = 0;
     const gbytes_t grid = as_global(M.bricks);
@@ -545,27 +543,28 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 cand = code != kMaskMixed;
             }
             if (cand) {
-                const float ex = sx > 0 ? (float)((ix | 7) + 1) : (float)(ix & ~7);
-                const float ey = sy > 0 ? (float)((iy | 7) + 1) : (float)(iy & ~7);
-                const float ez = sz > 0 ? (float)((iz | 7) + 1) : (float)(iz & ~7);
-                const float Tx = sx ? (ex - p.x) * fx : inf;
-                const float Ty = sy ? (ey - p.y) * fy : inf;
-                const float Tz = sz ? (ez - p.z) * fz : inf;
+                const float Tx = ((float)((ix & ~7) + eox) - qx) * fx;
+                const float Ty = ((float)((iy & ~7) + eoy) - qy) * fy;
+                const float Tz = ((float)((iz & ~7) + eoz) - qz) * fz;
                 const bool fx_ = (Tx <= Ty) & (Tx <= Tz);
                 const bool fy_ = !fx_ & (Ty <= Tz);
                 const bool fz_ = !fx_ & !fy_;
                 const float T = fx_ ? Tx : (fy_ ? Ty : Tz);
                 whole = (st == kFreeBrick) | (T < S.rv);
                 if (whole) {
-                    const int32_t kx = crossings_before(bx, dbx, p.x, fx, inner_left(ix, sx), T, !fx_) + (int32_t)fx_;
-                    const int32_t ky = crossings_before(by, dby, p.y, fy, inner_left(iy, sy), T, fz_) + (int32_t)fy_;
-                    const int32_t kz = crossings_before(bz, dbz, p.z, fz, inner_left(iz, sz), T, false) + (int32_t)fz_;
-                    ix += __mul24(kx, sx);
-                    iy += __mul24(ky, sy);
-                    iz += __mul24(kz, sz);
-                    bx += (float)kx * dbx;
-                    by += (float)ky * dby;
-                    bz += (float)kz * dbz;
+                    // An axis that precedes the exit axis in the tie order also
+                    // counts a boundary whose parameter equals T: it compares with
+                    // the next float above T (T >= 0; +0 for -0 first).
+                    const float Tn = __uint_as_float(__float_as_uint(T + 0.f) + 1u);
+                    const float kx = crossings_before(bx, dbx, qx, fx, fx_ ? T : Tn) + (fx_ ? 1.f : 0.f);
+                    const float ky = crossings_before(by, dby, qy, fy, fz_ ? Tn : T) + (fy_ ? 1.f : 0.f);
+                    const float kz = crossings_before(bz, dbz, qz, fz, T) + (fz_ ? 1.f : 0.f);
+                    ix += __mul24((int32_t)kx, sx);
+                    iy += __mul24((int32_t)ky, sy);
+                    iz += __mul24((int32_t)kz, sz);
+                    bx = __builtin_fmaf(kx, dbx, bx);
+                    by = __builtin_fmaf(ky, dby, by);
+                    bz = __builtin_fmaf(kz, dbz, bz);
                     tn = T;
                     if (st == kUnknownBrick) {
                         const uint32_t v = (uint32_t)(kx + ky + kz);
@@ -603,9 +602,9 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             alive = ballot(next_ok);
             addr = next_ok ? voxel_addr(ix, iy, iz, M) : M.outside;
             st = grid[addr];
-            tx = (bx - p.x) * fx;
-            ty = (by - p.y) * fy;
-            tz = (bz - p.z) * fz;
+            tx = (bx - qx) * fx;
+            ty = (by - qy) * fy;
+            tz = (bz - qz) * fz;
             t = tn;
         } while (alive);
     }
