@@ -25,8 +25,16 @@ enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3, kUnknownB
 __host__ __device__ inline bool is_unknown(uint32_t s) { return (s & 3u) == 0u; }
 
 // Per brick of a path mask (one byte): its 512 bits are mixed, all clear (no
-// voxel of the brick observed) or all set.
+// voxel of the brick observed) or all set. Only unknown voxels' bits are ever
+// read, so a mask keeps its code current for every brick that holds an
+// unknown voxel, and its 16 words for such a brick whenever they can be read:
+// the code is mixed, or the brick also holds known voxels (unknown voxels of
+// such a brick are looked up by word, without the code). Words of bricks
+// without unknown voxels, and of wholly unknown bricks with a uniform code,
+// are never written.
 enum : uint8_t { kMaskMixed = 0, kMaskNone = 1, kMaskAll = 2 };
+// brick_unk values: no unknown voxel, some, all 512 (the kUnknownBrick marks)
+enum : uint8_t { kBrickKnown = 0, kBrickSomeUnknown = 1, kBrickAllUnknown = 2 };
 
 // Occupancy grid in 8x8x8-voxel bricks (512 B each, x fastest inside a
 // brick, bricks x fastest): a ray stays inside one brick for several steps,
@@ -45,8 +53,9 @@ struct MapDev {
     // the grid, ceil(n / 8), and 32-bit words per mask (16 per brick).
     uint32_t mbx, mby, mbz;
     uint32_t mask_words;
-    // [mbx * mby * mbz] per mask brick: 1 when it holds an unknown voxel (kept
-    // current, with the kFreeBrick marks, by every write of the map's states)
+    // [mbx * mby * mbz] per mask brick: kBrickKnown, kBrickSomeUnknown or
+    // kBrickAllUnknown (kept current, with the whole-brick marks, by every
+    // write of the map's states)
     uint8_t* brick_unk;
 };
 

@@ -56,8 +56,8 @@ __global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__
     }
 }
 
-// Per-brick summaries, after any write of the states: brick_unk[b] = 1 when
-// brick b holds an unknown voxel, and a brick whose 512 voxels are all unknown
+// Per-brick summaries, after any write of the states: brick_unk[b] says whether
+// brick b holds no, some or only unknown voxels, and a brick whose 512 voxels are all unknown
 // (all free) has them marked kUnknownBrick (kFreeBrick); unknown and free
 // voxels of any other brick are plain kUnknown and kFree. One wave per brick,
 // each lane reading 8 of its 512 bytes and writing them back only if a mark
@@ -83,7 +83,9 @@ __global__ void k_brick_flags(MapDev m) {
         const bool any_unk = ballot(unk) != 0;
         const bool all_unk = ballot(not_unk) == 0;
         const bool all_free = ballot(not_free) == 0;
-        if (lane == 0) m.brick_unk[b] = any_unk ? 1 : 0;
+        if (lane == 0)
+            m.brick_unk[b] = any_unk ? (all_unk ? (uint8_t)kBrickAllUnknown : (uint8_t)kBrickSomeUnknown)
+                                     : (uint8_t)kBrickKnown;
         uint64_t w = v;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -221,8 +223,9 @@ __device__ bool may_see_brick(const SensorDev& S, const float* __restrict__ tm, 
 // the parent's bits (and code) without testing when it lies beyond the range,
 // wholly outside the node's azimuth wedge (margins cover the brick's voxel
 // centres, within 3.5 sqrt(3) of its centre and 3.5 sqrt(2) across in x and
-// y, and rounding), holds no unknown voxel, or fails the depth cull
-// (may_see_brick). The window's tables are loaded into LDS only when some
+// y, and rounding), holds no unknown voxel, has every bit set already, or
+// fails the depth cull (may_see_brick); of such a brick only what can be read
+// is written (the code, and the words when they can be read). The window's tables are loaded into LDS only when some
 // brick of the chunk is tested. One wave tests one brick: each lane one (x, y)
 // column of 8 voxels. Whole workgroup; chunks past the map's last brick do
 // nothing (a batch launch covers its largest map).
@@ -254,6 +257,8 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     const int32_t cnt = (int32_t)min((uint32_t)bricks, nb - lo);
     if (tid == 0) *s_any = 0;
     __syncthreads();
+    // per brick of the chunk (s_live): bit 4 live, bits 2-3 its brick_unk value,
+    // bits 0-1 the parent's code (kMaskNone at the root)
     if (tid < cnt) {
         const uint32_t b = lo + (uint32_t)tid;
         const uint32_t bx = b % M.mbx, by = (b / M.mbx) % M.mby, bz = b / (M.mbx * M.mby);
@@ -263,18 +268,31 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         const bool near = rx * rx + ry * ry + rz * rz <= reach * reach;
         const float w0 = A.b0x * ry - A.b0y * rx, w1 = A.b1x * ry - A.b1y * rx;
         const bool wedge = (w0 >= -5.5f) & (w1 < 5.5f);      // 3.5 sqrt(2) = 4.95, plus rounding
-        // (a brick without unknown voxels needs no bits: only unknown voxels' bits are read)
-        const bool live = near && wedge && M.brick_unk[b] != 0 &&
+        const uint32_t bu = M.brick_unk[b];
+        const uint32_t pc = par ? (uint32_t)pcode[b] : (uint32_t)kMaskNone;
+        // (a brick without unknown voxels needs no bits: only unknown voxels' bits
+        // are read; nor does one whose voxels an ancestor all observes)
+        const bool live = near && wedge && bu != kBrickKnown && pc != kMaskAll &&
                           may_see_brick(S, Tr.tmax + (size_t)slot * S.n_tiles, q, c0, bx, by, bz);
-        s_live[tid] = (uint8_t)live;
+        s_live[tid] = (uint8_t)(((uint32_t)live << 4) | (bu << 2) | pc);
         if (live) *s_any = 1;
     }
     __syncthreads();
-    // bricks that cannot hold an observed voxel keep the parent's bits (and code)
-    for (int32_t w = tid; w < cnt * 16; w += blockDim.x)
-        if (!s_live[w >> 4]) out[lo * 16u + (uint32_t)w] = par ? par[lo * 16u + (uint32_t)w] : 0u;
+    // Bricks that cannot hold a newly observed voxel keep the parent's code and
+    // the bits that can be read: its words when they are mixed, constant words
+    // for a brick that also holds known voxels, none for a wholly unknown brick
+    // with a uniform code; bricks without unknown voxels are left alone.
+    for (int32_t w = tid; w < cnt * 16; w += blockDim.x) {
+        const uint32_t f = s_live[w >> 4];
+        const uint32_t pc = f & 3u, bu = (f >> 2) & 3u;
+        if ((f & 16u) || bu == kBrickKnown || (bu == kBrickAllUnknown && pc != kMaskMixed)) continue;
+        out[lo * 16u + (uint32_t)w] = pc == kMaskMixed ? par[lo * 16u + (uint32_t)w] : (pc == kMaskAll ? ~0u : 0u);
+    }
     uint8_t* code = Tr.mcode + (size_t)slot * nb;
-    if (tid < cnt && !s_live[tid]) code[lo + (uint32_t)tid] = par ? pcode[lo + (uint32_t)tid] : (uint8_t)kMaskNone;
+    if (tid < cnt) {
+        const uint32_t f = s_live[tid];
+        if (!(f & 16u) && ((f >> 2) & 3u) != kBrickKnown) code[lo + (uint32_t)tid] = (uint8_t)(f & 3u);
+    }
     if (!*s_any) return;
     const TableLDS L = carve_tables(smem, S);
     load_tables(L, S, c0);
@@ -285,14 +303,15 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     // (the wave's brick is wave-uniform: its index arithmetic stays scalar)
     const int32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int32_t i = wave; i < cnt; i += (int32_t)(blockDim.x >> 6)) {
-        if (!s_live[i]) continue;
+        const uint32_t f = s_live[i];
+        if (!(f & 16u)) continue;
         const uint32_t b = lo + (uint32_t)i;
         const int32_t bx = (int32_t)(b % M.mbx), by = (int32_t)((b / M.mbx) % M.mby), bz = (int32_t)(b / (M.mbx * M.mby));
         const int32_t x = bx * 8 + (lane & 7), y = by * 8 + (lane >> 3);
         const float cx = (float)x + 0.5f, cy = (float)y + 0.5f;
         const uint32_t wbase = b << 4;
-        uint32_t pw = 0u;
-        if (par && lane < 16) pw = par[wbase + (uint32_t)lane];
+        uint32_t pw = 0u;                 // the parent's bits (a live brick's parent code is not all set)
+        if ((f & 3u) == kMaskMixed && lane < 16) pw = par[wbase + (uint32_t)lane];
         // The lane's column of the brick: the azimuth column of its pixels (the
         // same for the 8 voxels, which share x and y), the row of each voxel,
         // then the 8 depths, loaded together. The voxels' states are not read: only unknown voxels' bits are ever looked
@@ -534,13 +553,17 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             bool whole = false;
             bool cand = st == kFreeBrick;
             uint32_t code = kMaskNone;          // (the absolute pass, and the root, see nothing observed)
+            // (a wholly unknown brick with a uniform code is answered by the code
+            // also when it is walked voxel by voxel: its words need not exist)
+            bool by_code = false;
             if (st == kUnknownBrick) {
                 if (kMarginal && pc != nullptr) {
                     const uint32_t b = mask_brick(ix, iy, iz, M);
                     code = b == mixed_b ? (uint32_t)kMaskMixed : (uint32_t)pc[b];
                     mixed_b = code == kMaskMixed ? b : mixed_b;
                 }
-                cand = code != kMaskMixed;
+                by_code = code != kMaskMixed;
+                cand = by_code;
             }
             if (cand) {
                 const float Tx = ((float)((ix & ~7) + eox) - qx) * fx;
@@ -579,10 +602,12 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 if (kMarginal && pm != nullptr) {
                     // every lane loads (a lane off unknown voxels reads word 0), so the
                     // word lands in the register the next step reads
-                    const uint32_t off = (unk ? mask_word(ix, iy, iz, M) : 0u) << 2;   // < 2^29 bytes
+                    const bool by_word = unk & !by_code;
+                    const uint32_t off = (by_word ? mask_word(ix, iy, iz, M) : 0u) << 2;   // < 2^29 bytes
                     mw = *(gwords_t)((gbytes_t)pm + off);
                     mb = mask_bit(ix, iy);
-                    pend = unk;
+                    pend = by_word;
+                    n_new += (by_code & (code == kMaskNone)) ? 1u : 0u;
                 }
                 const bool mx = (tx <= ty) & (tx <= tz);
                 const bool my = !mx & (ty <= tz);

@@ -23,8 +23,8 @@ __device__ __forceinline__ uint8_t tsdf_state(float d, float w, float surface, f
 // k_brick_flags, done here so that a whole-grid conversion needs no second
 // pass): one wave per brick, each lane 8 of its 512 bytes; the unknown and free
 // voxels of a brick that holds only that state get its mark, and brick_unk
-// records whether it holds an unknown voxel (bricks wholly in the padding have
-// no entry). Whole workgroup of 256.
+// records whether it holds no, some or only unknown voxels (bricks wholly in
+// the padding have no entry). Whole workgroup of 256.
 __device__ __forceinline__ void mark_run(uint8_t* tile, int32_t tb, int32_t bx0, int32_t by, int32_t bz,
                                          const MapDev& m) {
     const int32_t lane = (int32_t)threadIdx.x & 63, wave = (int32_t)threadIdx.x >> 6;
@@ -48,7 +48,8 @@ __device__ __forceinline__ void mark_run(uint8_t* tile, int32_t tb, int32_t bx0,
         }
         const int32_t bx = bx0 + k;
         if (lane == 0 && (uint32_t)bx < m.mbx && (uint32_t)by < m.mby && (uint32_t)bz < m.mbz)
-            m.brick_unk[(uint32_t)bx + m.mbx * ((uint32_t)by + m.mby * (uint32_t)bz)] = any_unk ? 1 : 0;
+            m.brick_unk[(uint32_t)bx + m.mbx * ((uint32_t)by + m.mby * (uint32_t)bz)] =
+                any_unk ? (all_unk ? (uint8_t)kBrickAllUnknown : (uint8_t)kBrickSomeUnknown) : (uint8_t)kBrickKnown;
     }
 }
 
