@@ -131,6 +131,36 @@ def test_free_bricks_crossed_at_once(mg, orc, dims):
         assert int(ref["g_abs"].sum()) > 0
 
 
+def test_evaluations_of_one_tree_do_not_see_each_others_masks(mg, orc):
+    """A path mask keeps only what can be read (the words of a wholly unknown brick only when its
+    code is mixed), so its memory holds what an earlier evaluation of the same tree left there.
+    Marginal, single-parent and marginal again on one tree object, each against the oracle, with
+    ranges that end inside wholly unknown bricks (rays that walk such a brick voxel by voxel
+    read its code, not its words)."""
+    import torch
+    m = _free_brick_map(955, (40, 32, 24))
+    pos = np.array([[8.0, 8.0, 8.0], [16.0, 16.0, 8.0], [8.0, 12.5, 12.0], [24.0, 8.0, 16.0], [12.5, 12.5, 12.5],
+                    [16.0, 8.0, 4.5], [9.5, 17.0, 8.0], [31.0, 23.0, 15.0], [4.25, 20.75, 19.5], [20.0, 20.0, 10.0]],
+                   np.float32)
+    tree = W.Tree(pos_m=pos, parent=np.array([-1, 0, 0, 1, 1, 2, 3, 4, 6, 8], np.int32))
+    for rng in (11.3, 17.7):
+        sen = W.Sensor(n_az=72, n_el=13, fov_h_deg=90, fov_v_deg=80, range_m=rng, yaw_bins=24)
+        log(f"[parity] alternating evaluations, range {rng}")
+        ref = orc.eval_tree(m, tree, sen, n_threads=threads())
+        ref1 = orc.eval_tree(m, tree, sen, max_anc=1, n_threads=threads())
+        M = mg.Map(m.states, m.voxel_m, m.origin_m)
+        T = mg.Tree(M, tree.pos_m, tree.parent, sen)
+        try:
+            for mode in ("marginal", "single", "marginal", "single"):
+                g, y, _ = T.eval_marginal() if mode == "marginal" else T.eval_single_parent()
+                torch.cuda.synchronize()
+                r = ref if mode == "marginal" else ref1
+                assert_same({"g_db": mg.as_u32(g), "k_db": y.cpu().numpy()}, r, keys=("g_db", "k_db"))
+        finally:
+            T.close()
+            M.close()
+
+
 def test_occupied_everywhere_and_unknown_everywhere(mg, orc):
     sen = W.Sensor(n_az=64, n_el=12, fov_h_deg=90, fov_v_deg=60, range_m=6.0, yaw_bins=16)
     pos = np.array([[4.3, 4.6, 3.2], [5.1, 4.2, 3.7], [3.2, 5.5, 2.9]], np.float32)
