@@ -550,6 +550,8 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             // observes any of them. An unknown brick is crossed this way only if
             // it is left before the range ends.
             float tn;                           // entry parameter of the next voxel
+            float kx, ky, kz;                   // boundaries this step crosses along each axis (set by
+                                                // the crossing when it is taken, else by the voxel step)
             bool whole = false;
             bool cand = st == kFreeBrick;
             uint32_t code = kMaskNone;          // (the absolute pass, and the root, see nothing observed)
@@ -579,15 +581,9 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                     // counts a boundary whose parameter equals T: it compares with
                     // the next float above T (T >= 0; +0 for -0 first).
                     const float Tn = __uint_as_float(__float_as_uint(T + 0.f) + 1u);
-                    const float kx = crossings_before(bx, dbx, qx, fx, fx_ ? T : Tn) + (fx_ ? 1.f : 0.f);
-                    const float ky = crossings_before(by, dby, qy, fy, fz_ ? Tn : T) + (fy_ ? 1.f : 0.f);
-                    const float kz = crossings_before(bz, dbz, qz, fz, T) + (fz_ ? 1.f : 0.f);
-                    ix += __mul24((int32_t)kx, sx);
-                    iy += __mul24((int32_t)ky, sy);
-                    iz += __mul24((int32_t)kz, sz);
-                    bx = __builtin_fmaf(kx, dbx, bx);
-                    by = __builtin_fmaf(ky, dby, by);
-                    bz = __builtin_fmaf(kz, dbz, bz);
+                    kx = crossings_before(bx, dbx, qx, fx, fx_ ? T : Tn) + (fx_ ? 1.f : 0.f);
+                    ky = crossings_before(by, dby, qy, fy, fz_ ? Tn : T) + (fy_ ? 1.f : 0.f);
+                    kz = crossings_before(bz, dbz, qz, fz, T) + (fz_ ? 1.f : 0.f);
                     tn = T;
                     if (st == kUnknownBrick) {
                         const uint32_t v = (uint32_t)(kx + ky + kz);
@@ -613,13 +609,17 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 const bool my = !mx & (ty <= tz);
                 const bool mz = !mx & !my;
                 tn = mx ? tx : (my ? ty : tz);
-                ix += mx ? sx : 0;
-                iy += my ? sy : 0;
-                iz += mz ? sz : 0;
-                bx += mx ? dbx : 0.f;
-                by += my ? dby : 0.f;
-                bz += mz ? dbz : 0.f;
+                kx = mx ? 1.f : 0.f;
+                ky = my ? 1.f : 0.f;
+                kz = mz ? 1.f : 0.f;
             }
+            // one update for both kinds of step (counts are small integers: exact)
+            ix += __mul24((int32_t)kx, sx);
+            iy += __mul24((int32_t)ky, sy);
+            iz += __mul24((int32_t)kz, sz);
+            bx = __builtin_fmaf(kx, dbx, bx);
+            by = __builtin_fmaf(ky, dby, by);
+            bz = __builtin_fmaf(kz, dbz, bz);
             // a lane that stops here (occupied, finished or outside) compares +inf
             // with the range: one comparison gives the mask the ballot takes
             const float tn_go = (st & 2u) == 0u ? tn : inf;
