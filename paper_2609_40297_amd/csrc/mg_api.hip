@@ -665,7 +665,7 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
     H->o_mn = take(sizeof(int32_t) * std::max<size_t>(H->mask_nodes.size(), 1));
     H->o_masks = take(sizeof(uint32_t) * (size_t)map->dev.mask_words * (size_t)H->n_masks);
     const size_t n_tiles = (size_t)((wb + kTileCols - 1) / kTileCols) * (size_t)((sensor->n_el + kTileRows - 1) / kTileRows);
-    H->o_tm = take(sizeof(float) * n_tiles * (size_t)std::max(H->n_masks, 1));
+    H->o_tm = take(sizeof(float) * 2 * n_tiles * (size_t)std::max(H->n_masks, 1));
     H->o_mc = take((size_t)(map->dev.mask_words >> 4) * (size_t)std::max(H->n_masks, 1));
     H->total = off;
     return MG_OK;

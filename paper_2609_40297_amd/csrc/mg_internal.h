@@ -136,7 +136,7 @@ struct TreeDev {
     uint32_t* masks;           // [nodes with children][mask_words]
     const int32_t* mask_slot;  // [n] index into masks, -1 for a leaf
     const int32_t* mask_nodes; // nodes with children, by depth level
-    float* tmax;               // [nodes with children][n_tiles]: largest first hit of each tile of the window
+    float* tmax;               // [nodes with children][2][n_tiles]: largest, then smallest first hit of each tile of the window
     uint8_t* mcode;            // [nodes with children][mask bricks]: kMaskMixed / kMaskNone / kMaskAll
     int32_t n;
     int32_t anc_cap;           // ancestors that condition a node: kMaxAnc (all) or 1 (the parent only)

@@ -163,21 +163,27 @@ __device__ __forceinline__ void load_tables(const TableLDS& L, const SensorDev& 
     for (int32_t i = threadIdx.x; i < S.n_lut_row; i += blockDim.x) L.lut_row[i] = S.lut_row[i];
 }
 
-// Whether the node may observe a voxel of brick (bx, by, bz), from below: the
-// pixels that the brick's voxel centres can fall in lie inside a rectangle of
-// the window (azimuth from the corners of the centres' box seen from outside,
-// elevation from its nearest and farthest horizontal distance; both widened by
-// a pixel, so float angles cannot drop a pixel), and no voxel centre is nearer
-// than the box; if the largest first hit over the tiles that cover the
-// rectangle is below that distance, no voxel of the brick is observed. Returns
-// true (no cull) when the node is within a voxel of the box horizontally or the
-// rectangle covers more than 64 tiles.
-__device__ bool may_see_brick(const SensorDev& S, const float* __restrict__ tm, float4 q, int32_t c0, uint32_t bx,
-                              uint32_t by, uint32_t bz) {
+// What the node can observe of brick (bx, by, bz), from below: the pixels that
+// the brick's voxel centres can fall in lie inside a rectangle of the window
+// (azimuth from the corners of the centres' box seen from outside, elevation
+// from its nearest and farthest horizontal distance; both widened by a pixel,
+// so float angles cannot drop a pixel), and every centre lies between the
+// box's nearest and farthest distances. Returns kViewNone when the largest
+// first hit over the tiles that cover the rectangle is below the nearest
+// distance (no voxel is observed); kViewAll when the rectangle lies inside the
+// window and its row band with a pixel to spare and the farthest distance is
+// within the range and below the smallest first hit over those tiles (every
+// voxel centre passes the per-voxel test, with margins for rounding); else
+// kViewSome (the node is within a voxel of the box horizontally, the rectangle
+// covers more than 64 tiles, or the voxels must be tested one by one).
+// tm: the node's tile maxima, then its tile minima.
+enum : int { kViewNone = 0, kViewSome = 1, kViewAll = 2 };
+__device__ int brick_view(const SensorDev& S, const float* __restrict__ tm, float4 q, int32_t c0, uint32_t bx,
+                          uint32_t by, uint32_t bz) {
     const float x0 = (float)(bx * 8u) + 0.5f - q.x, x1 = x0 + 7.f;
     const float y0 = (float)(by * 8u) + 0.5f - q.y, y1 = y0 + 7.f;
     const float z0 = (float)(bz * 8u) + 0.5f - q.z, z1 = z0 + 7.f;
-    if (x0 <= 1.f && x1 >= -1.f && y0 <= 1.f && y1 >= -1.f) return true;
+    if (x0 <= 1.f && x1 >= -1.f && y0 <= 1.f && y1 >= -1.f) return kViewSome;
     // window columns of the four corners, unwrapped around the window
     const float W = (float)S.W, sh = 0.5f * (float)(S.W - S.WB);
     float lo = 1e30f, hi = -1e30f;
@@ -189,10 +195,11 @@ __device__ bool may_see_brick(const SensorDev& S, const float* __restrict__ tm, 
         lo = fminf(lo, v);
         hi = fmaxf(hi, v);
     }
-    if (hi - lo > 0.5f * W) return true;
-    if (hi + 1.f < 0.f || lo - 1.f >= (float)S.WB) return false;
-    const int32_t c_lo = (int32_t)fmaxf(floorf(lo) - 1.f, 0.f);
-    const int32_t c_hi = (int32_t)fminf(floorf(hi) + 1.f, (float)(S.WB - 1));
+    if (hi - lo > 0.5f * W) return kViewSome;
+    if (hi + 1.f < 0.f || lo - 1.f >= (float)S.WB) return kViewNone;
+    const float fc_lo = floorf(lo) - 1.f, fc_hi = floorf(hi) + 1.f;
+    const int32_t c_lo = (int32_t)fmaxf(fc_lo, 0.f);
+    const int32_t c_hi = (int32_t)fminf(fc_hi, (float)(S.WB - 1));
     const float dx = x0 > 0.f ? x0 : (x1 < 0.f ? -x1 : 0.f);
     const float dy = y0 > 0.f ? y0 : (y1 < 0.f ? -y1 : 0.f);
     const float dz = z0 > 0.f ? z0 : (z1 < 0.f ? -z1 : 0.f);
@@ -201,15 +208,21 @@ __device__ bool may_see_brick(const SensorDev& S, const float* __restrict__ tm, 
     const float e_hi = atan2f(z1, z1 >= 0.f ? rmin : rmax);
     const float e_lo = atan2f(z0, z0 >= 0.f ? rmax : rmin);
     const float r_lo = floorf((e_lo - S.el0) * S.del_inv) - 1.f, r_hi = floorf((e_hi - S.el0) * S.del_inv) + 1.f;
-    if (r_hi < 0.f || r_lo > (float)(S.H - 1)) return false;
+    if (r_hi < 0.f || r_lo > (float)(S.H - 1)) return kViewNone;
     const int32_t j_lo = (int32_t)fmaxf(r_lo, 0.f), j_hi = (int32_t)fminf(r_hi, (float)(S.H - 1));
     const int32_t tc0 = c_lo / kTileCols, tc1 = c_hi / kTileCols, tr0 = j_lo / kTileRows, tr1 = j_hi / kTileRows;
-    if ((tc1 - tc0 + 1) * (tr1 - tr0 + 1) > 64) return true;
-    float m = 0.f;
+    if ((tc1 - tc0 + 1) * (tr1 - tr0 + 1) > 64) return kViewSome;
+    float m = 0.f, mn = __builtin_inff();
     for (int32_t tc = tc0; tc <= tc1; ++tc)
-        for (int32_t tr = tr0; tr <= tr1; ++tr) m = fmaxf(m, tm[tc * S.trows + tr]);
+        for (int32_t tr = tr0; tr <= tr1; ++tr) {
+            m = fmaxf(m, tm[tc * S.trows + tr]);
+            mn = fminf(mn, tm[S.n_tiles + tc * S.trows + tr]);
+        }
     const float dmin2 = dx * dx + dy * dy + dz * dz;
-    return m * m * 1.0001f + 0.01f >= dmin2;
+    if (!(m * m * 1.0001f + 0.01f >= dmin2)) return kViewNone;
+    const bool inside = (fc_lo >= 0.f) & (fc_hi <= (float)(S.WB - 1)) & (r_lo >= 0.f) & (r_hi <= (float)(S.H - 1));
+    const float dmax2 = fmaxf(x0 * x0, x1 * x1) + fmaxf(y0 * y0, y1 * y1) + fmaxf(z0 * z0, z1 * z1);
+    return (inside && dmax2 * 1.0001f + 0.01f <= fminf(S.rv2, mn * mn)) ? kViewAll : kViewSome;
 }
 
 // Path mask of node `node` over bricks [chunk * bricks, ...) of the mask grid:
@@ -224,8 +237,10 @@ __device__ bool may_see_brick(const SensorDev& S, const float* __restrict__ tm, 
 // wholly outside the node's azimuth wedge (margins cover the brick's voxel
 // centres, within 3.5 sqrt(3) of its centre and 3.5 sqrt(2) across in x and
 // y, and rounding), holds no unknown voxel, has every bit set already, or
-// fails the depth cull (may_see_brick); of such a brick only what can be read
-// is written (the code, and the words when they can be read). The window's tables are loaded into LDS only when some
+// fails the depth cull (brick_view); a brick whose voxels the node observes
+// all (brick_view again) gets every bit set without testing. Of these bricks
+// only what can be read is written (the code, and the words when they can be
+// read). The window's tables are loaded into LDS only when some
 // brick of the chunk is tested. One wave tests one brick: each lane one (x, y)
 // column of 8 voxels. Whole workgroup; chunks past the map's last brick do
 // nothing (a batch launch covers its largest map).
@@ -272,9 +287,13 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         const uint32_t pc = par ? (uint32_t)pcode[b] : (uint32_t)kMaskNone;
         // (a brick without unknown voxels needs no bits: only unknown voxels' bits
         // are read; nor does one whose voxels an ancestor all observes)
-        const bool live = near && wedge && bu != kBrickKnown && pc != kMaskAll &&
-                          may_see_brick(S, Tr.tmax + (size_t)slot * S.n_tiles, q, c0, bx, by, bz);
-        s_live[tid] = (uint8_t)(((uint32_t)live << 4) | (bu << 2) | pc);
+        const int view = (near && wedge && bu != kBrickKnown && pc != kMaskAll)
+                             ? brick_view(S, Tr.tmax + (size_t)slot * 2 * S.n_tiles, q, c0, bx, by, bz)
+                             : kViewNone;
+        // (a brick whose voxels the node observes all gets every bit set, as the
+        // per-voxel test would give it)
+        const bool live = view == kViewSome;
+        s_live[tid] = (uint8_t)(((uint32_t)live << 4) | (bu << 2) | (view == kViewAll ? (uint32_t)kMaskAll : pc));
         if (live) *s_any = 1;
     }
     __syncthreads();
@@ -665,25 +684,30 @@ __global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeD
 // with the smallest k. Whole workgroup; returns (sum << 32) | (B - 1 - k) to
 // every thread. Bins are read with atomic loads (they were accumulated with
 // device-scope atomics, possibly by other workgroups).
-// The largest first hit of each tile of a node's window (kTileCols x kTileRows
-// pixels, partial at the window's edges), for the mask builder's depth cull of
-// the node's bricks; only nodes with children have a path mask to build.
+// The largest and the smallest first hit of each tile of a node's window
+// (kTileCols x kTileRows pixels, partial at the window's edges), for the mask
+// builder's whole-brick tests of the node's bricks; only nodes with children
+// have a path mask to build.
 // Consecutive threads take consecutive tiles of a tile column, so their reads
 // of the column-major panorama are contiguous.
 __device__ __forceinline__ void tile_max(const SensorDev& S, const TreeDev& Tr, int32_t node, int32_t c0) {
     const int32_t slot = Tr.mask_slot[node];
     if (slot < 0) return;
     const float* src = Tr.dpan + (size_t)node * S.R;
-    float* dst = Tr.tmax + (size_t)slot * S.n_tiles;
+    float* dst = Tr.tmax + (size_t)slot * 2 * S.n_tiles;
     for (int32_t t = threadIdx.x; t < S.n_tiles; t += blockDim.x) {
         const int32_t tc = t / S.trows, tr = t - tc * S.trows;
         const int32_t j0 = tr * kTileRows, j1 = min(j0 + kTileRows, S.H);
-        float m = 0.f;
+        float m = 0.f, mn = __builtin_inff();
         for (int32_t i = tc * kTileCols; i < min((tc + 1) * kTileCols, S.WB); ++i) {
             const float* col = src + (size_t)wrap(c0 + i, S.W) * S.H;
-            for (int32_t j = j0; j < j1; ++j) m = fmaxf(m, col[j]);
+            for (int32_t j = j0; j < j1; ++j) {
+                m = fmaxf(m, col[j]);
+                mn = fminf(mn, col[j]);
+            }
         }
         dst[t] = m;
+        dst[S.n_tiles + t] = mn;
     }
 }
 
