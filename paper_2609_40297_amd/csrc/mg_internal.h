@@ -17,12 +17,56 @@ constexpr int kTileCols = 4;       // depth-cull tiles of a node's window: 4 col
 constexpr int kTileRows = 4;       // by 4 rows
 
 // kOutside marks the padding around the grid: a traversal that reaches it
-// has left the grid. kUnknownBrick and kFreeBrick are an unknown and a free
-// voxel whose whole 8x8x8 brick holds that state (the traversal may cross
-// such a brick in one step): the low two bits of a byte are the state, and
-// bit 1 set (kOccupied, kOutside) ends a traversal.
+// has left the grid. The low two bits of a byte are the state, and bit 1 set
+// (kOccupied, kOutside) ends a traversal. Bits 2-3 of an unknown or a free
+// voxel name the largest aligned block around it that holds that state only
+// (the traversal may cross such a block in one step): 1 its whole 8x8x8 brick
+// (kUnknownBrick, kFreeBrick), 2 its 4x4x4 quarter brick, 3 (free voxels
+// only) its 2x2x2 block, 0 none; the block's edge is 16 >> level voxels.
+// Unknown voxels get levels 1 and 2, free voxels 1 to 3.
 enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3, kUnknownBrick = 4, kFreeBrick = 5 };
 __host__ __device__ inline bool is_unknown(uint32_t s) { return (s & 3u) == 0u; }
+
+// The block levels of one brick's voxels, by one wave: each lane holds the 8
+// voxels (x = 0..7, bytes 0..7 of v) of row (y, z) = (lane & 7, lane >> 3) of
+// the brick, as states or as marked bytes; returns them marked. any_unk and
+// all_unk: whether the brick holds an unknown voxel, only unknown voxels.
+__device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bool* any_unk, bool* all_unk) {
+    uint32_t fb = 0u, ub = 0u;          // per byte: free, unknown
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t s = (uint32_t)(v >> (8 * k)) & 3u;
+        fb |= (s == kFree ? 1u : 0u) << k;
+        ub |= (s == kUnknown ? 1u : 0u) << k;
+    }
+    const bool all_free = __builtin_amdgcn_ballot_w64(fb != 0xffu) == 0ull;
+    *all_unk = __builtin_amdgcn_ballot_w64(ub != 0xffu) == 0ull;
+    *any_unk = __builtin_amdgcn_ballot_w64(ub != 0u) != 0ull;
+    // quarter bricks: x halves of the row, over the 4x4 rows (y, z) of the lane's quarter
+    const uint32_t y = lane & 7u, z = lane >> 3;
+    const uint64_t quarter = (0x0f0f0f0full << (y & 4u)) << (8u * (z & 4u));
+    const uint64_t nf_lo = __builtin_amdgcn_ballot_w64((fb & 0x0fu) != 0x0fu), nf_hi = __builtin_amdgcn_ballot_w64((fb & 0xf0u) != 0xf0u);
+    const uint64_t nu_lo = __builtin_amdgcn_ballot_w64((ub & 0x0fu) != 0x0fu), nu_hi = __builtin_amdgcn_ballot_w64((ub & 0xf0u) != 0xf0u);
+    // 2x2x2 blocks: x pairs of the row, over the 2x2 rows of the lane's pair of rows
+    const uint64_t pairs = 0x303ull << ((y & 6u) + 8u * (z & 6u));
+    uint32_t f2 = 0u;                   // bit p: x pair p of this row lies in a wholly free block
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+        f2 |= ((__builtin_amdgcn_ballot_w64(((fb >> (2 * p)) & 3u) != 3u) & pairs) == 0ull ? 1u : 0u) << p;
+    const bool f4lo = (nf_lo & quarter) == 0ull, f4hi = (nf_hi & quarter) == 0ull;
+    const bool u4lo = (nu_lo & quarter) == 0ull, u4hi = (nu_hi & quarter) == 0ull;
+    uint64_t out = 0ull;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t s = (uint32_t)(v >> (8 * k)) & 3u;
+        const bool f4 = k < 4 ? f4lo : f4hi, u4 = k < 4 ? u4lo : u4hi;
+        uint32_t lv = 0u;
+        if (s == kFree) lv = all_free ? 1u : (f4 ? 2u : (((f2 >> (k >> 1)) & 1u) ? 3u : 0u));
+        if (s == kUnknown) lv = *all_unk ? 1u : (u4 ? 2u : 0u);
+        out |= (uint64_t)(s | (lv << 2)) << (8 * k);
+    }
+    return out;
+}
 
 // Per brick of a path mask (one byte): its 512 bits are mixed, all clear (no
 // voxel of the brick observed) or all set. Only unknown voxels' bits are ever

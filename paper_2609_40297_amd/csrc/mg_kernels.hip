@@ -57,12 +57,11 @@ __global__ void k_brick(const uint8_t* __restrict__ dense, uint8_t* __restrict__
 }
 
 // Per-brick summaries, after any write of the states: brick_unk[b] says whether
-// brick b holds no, some or only unknown voxels, and a brick whose 512 voxels are all unknown
-// (all free) has them marked kUnknownBrick (kFreeBrick); unknown and free
-// voxels of any other brick are plain kUnknown and kFree. One wave per brick,
-// each lane reading 8 of its 512 bytes and writing them back only if a mark
-// changes (padding voxels past the grid hold kOutside, so a brick that reaches
-// past the grid is never marked).
+// brick b holds no, some or only unknown voxels, and every unknown and free
+// voxel gets the level of the largest block around it that holds its state
+// only (mark_brick_row). One wave per brick, each lane reading 8 of its 512
+// bytes and writing them back only if a mark changes (padding voxels past the
+// grid hold kOutside, so a block that reaches past the grid is never marked).
 __global__ void k_brick_flags(MapDev m) {
     const uint32_t nb = m.mask_words >> 4;
     const uint32_t lane = threadIdx.x & 63u;
@@ -72,29 +71,11 @@ __global__ void k_brick_flags(MapDev m) {
         const uint32_t base = voxel_addr((int32_t)(bx * 8u), (int32_t)(by * 8u), (int32_t)(bz * 8u), m);
         uint64_t* p = reinterpret_cast<uint64_t*>(grid + base + lane * 8u);
         const uint64_t v = *p;
-        bool unk = false, not_unk = false, not_free = false;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t x = (uint32_t)(v >> (8 * k)) & 0xffu;
-            unk |= x == kUnknown || x == kUnknownBrick;
-            not_unk |= x != kUnknown && x != kUnknownBrick;
-            not_free |= x != kFree && x != kFreeBrick;
-        }
-        const bool any_unk = ballot(unk) != 0;
-        const bool all_unk = ballot(not_unk) == 0;
-        const bool all_free = ballot(not_free) == 0;
+        bool any_unk, all_unk;
+        const uint64_t w = mark_brick_row(v, lane, &any_unk, &all_unk);
         if (lane == 0)
             m.brick_unk[b] = any_unk ? (all_unk ? (uint8_t)kBrickAllUnknown : (uint8_t)kBrickSomeUnknown)
                                      : (uint8_t)kBrickKnown;
-        uint64_t w = v;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t x = (uint32_t)(v >> (8 * k)) & 0xffu;
-            uint32_t y = x;
-            if (x == kFree || x == kFreeBrick) y = all_free ? kFreeBrick : kFree;
-            if (x == kUnknown || x == kUnknownBrick) y = all_unk ? kUnknownBrick : kUnknown;
-            w = (w & ~(0xffull << (8 * k))) | ((uint64_t)y << (8 * k));
-        }
         if (w != v) *p = w;
     }
 }
@@ -455,9 +436,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build(MapDev M, SensorDe
 // t = (b - q) * f below Tc (a caller that wants ties counted passes the next
 // float above the crossing). Parameters grow by at least 1 from one boundary
 // to the next, so these boundaries are a prefix; the caller's crossing leaves
-// the brick, so the prefix ends at the axis's own brick exit, at most 7
-// boundaries on, and three probes (at 3, then 3 +- 2, then +- 1) find its
-// length. Boundaries are evaluated exactly as the single step evaluates them
+// a block of at most 8 voxels a side, so the prefix ends at the axis's own
+// exit from that block, at most 7 boundaries on, and three probes (at 3, then
+// 3 +- 2, then +- 1) find its length. Boundaries are evaluated exactly as the single step evaluates them
 // (the fused multiply-add of integers is exact). Returned as a float count.
 __device__ __forceinline__ float crossings_before(float b0, float db, float q, float f, float Tc) {
     float m = 3.f;
@@ -529,8 +510,8 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     // boundary parameter of that axis, (b - q) * 1 with b = +inf or a brick
     // exit, is then +inf
     const float qx = sx ? p.x : -inf, qy = sy ? p.y : -inf, qz = sz ? p.z : -inf;
-    // a brick's exit boundary along an axis: its low face, plus 8 when moving up
-    const int32_t eox = sx > 0 ? 8 : 0, eoy = sy > 0 ? 8 : 0, eoz = sz > 0 ? 8 : 0;
+    // a block's exit boundary along an axis: its low face, plus its edge when moving up
+    const int32_t upx = sx > 0 ? -1 : 0, upy = sy > 0 ? -1 : 0, upz = sz > 0 ? -1 : 0;
     float tx = (bx - qx) * fx;
     float ty = (by - qy) * fy;
     float tz = (bz - qz) * fz;
@@ -559,25 +540,29 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 pend = false;
             }
             h = st == kOccupied ? t : h;
-            // A brick whose voxels are all free, or all unknown with the parent's
-            // mask uniform over it (every bit clear or every bit set), is crossed
-            // in one step: it is left through the face whose boundary parameter
-            // comes first (ties x, y, z) and every other axis has crossed the
-            // boundaries that come before that crossing in the same order. The
-            // voxels crossed are one per crossing; crossing an unknown brick
-            // counts them all as absolute, and as marginal when no ancestor
-            // observes any of them. An unknown brick is crossed this way only if
-            // it is left before the range ends.
+            // An aligned block (a brick, a quarter brick or, for free voxels, a
+            // 2x2x2 block) whose voxels are all free, or all unknown with the
+            // parent's mask uniform over their brick (every bit clear or every
+            // bit set), is crossed in one step: it is left through the face whose
+            // boundary parameter comes first (ties x, y, z) and every other axis
+            // has crossed the boundaries that come before that crossing in the
+            // same order. The voxels crossed are one per crossing; crossing an
+            // unknown block counts them all as absolute, and as marginal when no
+            // ancestor observes any of them. An unknown block is crossed this way
+            // only if it is left before the range ends.
             float tn;                           // entry parameter of the next voxel
             float kx, ky, kz;                   // boundaries this step crosses along each axis (set by
                                                 // the crossing when it is taken, else by the voxel step)
             bool whole = false;
-            bool cand = st == kFreeBrick;
+            const uint32_t level = st >> 2;     // the voxel's block: edge 16 >> level, or none (0)
+            const bool free_blk = (level != 0u) & ((st & 3u) == kFree);
+            bool cand = free_blk;
             uint32_t code = kMaskNone;          // (the absolute pass, and the root, see nothing observed)
-            // (a wholly unknown brick with a uniform code is answered by the code
-            // also when it is walked voxel by voxel: its words need not exist)
+            // (a wholly unknown block with a uniform code is answered by the code
+            // also when it is walked voxel by voxel: the words of its brick need
+            // not exist)
             bool by_code = false;
-            if (st == kUnknownBrick) {
+            if ((level != 0u) & ((st & 3u) == kUnknown)) {
                 if (kMarginal && pc != nullptr) {
                     const uint32_t b = mask_brick(ix, iy, iz, M);
                     code = b == mixed_b ? (uint32_t)kMaskMixed : (uint32_t)pc[b];
@@ -587,14 +572,15 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 cand = by_code;
             }
             if (cand) {
-                const float Tx = ((float)((ix & ~7) + eox) - qx) * fx;
-                const float Ty = ((float)((iy & ~7) + eoy) - qy) * fy;
-                const float Tz = ((float)((iz & ~7) + eoz) - qz) * fz;
+                const int32_t edge = 16 >> level;
+                const float Tx = ((float)((ix & -edge) + (edge & upx)) - qx) * fx;
+                const float Ty = ((float)((iy & -edge) + (edge & upy)) - qy) * fy;
+                const float Tz = ((float)((iz & -edge) + (edge & upz)) - qz) * fz;
                 const bool fx_ = (Tx <= Ty) & (Tx <= Tz);
                 const bool fy_ = !fx_ & (Ty <= Tz);
                 const bool fz_ = !fx_ & !fy_;
                 const float T = fx_ ? Tx : (fy_ ? Ty : Tz);
-                whole = (st == kFreeBrick) | (T < S.rv);
+                whole = free_blk | (T < S.rv);
                 if (whole) {
                     // An axis that precedes the exit axis in the tie order also
                     // counts a boundary whose parameter equals T: it compares with
@@ -604,7 +590,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                     ky = crossings_before(by, dby, qy, fy, fz_ ? Tn : T) + (fy_ ? 1.f : 0.f);
                     kz = crossings_before(bz, dbz, qz, fz, T) + (fz_ ? 1.f : 0.f);
                     tn = T;
-                    if (st == kUnknownBrick) {
+                    if (!free_blk) {
                         const uint32_t v = (uint32_t)(kx + ky + kz);
                         n_abs += v;
                         if (kMarginal) n_new += code == kMaskNone ? v : 0u;

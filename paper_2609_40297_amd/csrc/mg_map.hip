@@ -22,30 +22,16 @@ __device__ __forceinline__ uint8_t tsdf_state(float d, float w, float surface, f
 // The summaries of the run's bricks assembled in LDS (the work of
 // k_brick_flags, done here so that a whole-grid conversion needs no second
 // pass): one wave per brick, each lane 8 of its 512 bytes; the unknown and free
-// voxels of a brick that holds only that state get its mark, and brick_unk
-// records whether it holds no, some or only unknown voxels (bricks wholly in
-// the padding have no entry). Whole workgroup of 256.
+// voxels get their block levels (mark_brick_row), and brick_unk records
+// whether the brick holds no, some or only unknown voxels (bricks wholly in the
+// padding have no entry). Whole workgroup of 256.
 __device__ __forceinline__ void mark_run(uint8_t* tile, int32_t tb, int32_t bx0, int32_t by, int32_t bz,
                                          const MapDev& m) {
     const int32_t lane = (int32_t)threadIdx.x & 63, wave = (int32_t)threadIdx.x >> 6;
     for (int32_t k = wave; k < tb; k += 4) {
         uint64_t* p = reinterpret_cast<uint64_t*>(tile + k * 512) + lane;
-        const uint64_t v = *p;
-        bool unk = false, not_unk = false, not_free = false;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t x = (uint32_t)(v >> (8 * q)) & 0xffu;
-            unk |= x == kUnknown;
-            not_unk |= x != kUnknown;
-            not_free |= x != kFree;
-        }
-        const bool any_unk = __builtin_amdgcn_ballot_w64(unk) != 0;
-        const bool all_unk = __builtin_amdgcn_ballot_w64(not_unk) == 0;
-        const bool all_free = __builtin_amdgcn_ballot_w64(not_free) == 0;
-        if (all_unk | all_free) {
-            const uint64_t add = (all_unk ? (uint64_t)kUnknownBrick : (uint64_t)(kFreeBrick - kFree)) * 0x0101010101010101ull;
-            *p = v + add;
-        }
+        bool any_unk, all_unk;
+        *p = mark_brick_row(*p, (uint32_t)lane, &any_unk, &all_unk);
         const int32_t bx = bx0 + k;
         if (lane == 0 && (uint32_t)bx < m.mbx && (uint32_t)by < m.mby && (uint32_t)bz < m.mbz)
             m.brick_unk[(uint32_t)bx + m.mbx * ((uint32_t)by + m.mby * (uint32_t)bz)] =
