@@ -18,20 +18,24 @@ constexpr int kTileRows = 4;       // by 4 rows
 
 // kOutside marks the padding around the grid: a traversal that reaches it
 // has left the grid. The low two bits of a byte are the state, and bit 1 set
-// (kOccupied, kOutside) ends a traversal. Bits 2-3 of an unknown or a free
+// (kOccupied, kOutside) ends a traversal. Bits 2-4 of an unknown or a free
 // voxel name the largest aligned block around it that holds that state only
-// (the traversal may cross such a block in one step): 1 its whole 8x8x8 brick
-// (kUnknownBrick, kFreeBrick), 2 its 4x4x4 quarter brick, 3 (free voxels
-// only) its 2x2x2 block, 0 none; the block's edge is 16 >> level voxels.
-// Unknown voxels get levels 1 and 2, free voxels 1 to 3.
-enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3, kUnknownBrick = 4, kFreeBrick = 5 };
+// (the traversal may cross such a block in one step): 1 (free voxels only)
+// its 16x16x16 block of 8 bricks, 2 its 8x8x8 brick (kUnknownBrick,
+// kFreeBrick), 3 its 4x4x4 quarter brick, 4 (free voxels only) its 2x2x2
+// block, 0 none; the block's edge is 32 >> level voxels.
+enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3, kUnknownBrick = 8, kFreeBrick = 9 };
+constexpr uint32_t kLevelShift = 2, kLevelMask = 7;
 __host__ __device__ inline bool is_unknown(uint32_t s) { return (s & 3u) == 0u; }
 
-// The block levels of one brick's voxels, by one wave: each lane holds the 8
-// voxels (x = 0..7, bytes 0..7 of v) of row (y, z) = (lane & 7, lane >> 3) of
-// the brick, as states or as marked bytes; returns them marked. any_unk and
-// all_unk: whether the brick holds an unknown voxel, only unknown voxels.
-__device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bool* any_unk, bool* all_unk) {
+// The block levels of one brick's voxels up to the brick (levels 2 to 4; the
+// 16x16x16 blocks are marked afterwards, from the bricks' summaries), by one
+// wave: each lane holds the 8 voxels (x = 0..7, bytes 0..7 of v) of row
+// (y, z) = (lane & 7, lane >> 3) of the brick, as states or as marked bytes;
+// returns them marked. any_unk, all_unk, all_free: whether the brick holds an
+// unknown voxel, only unknown voxels, only free voxels.
+__device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bool* any_unk, bool* all_unk,
+                                                   bool* all_free_out) {
     uint32_t fb = 0u, ub = 0u;          // per byte: free, unknown
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -40,6 +44,7 @@ __device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bo
         ub |= (s == kUnknown ? 1u : 0u) << k;
     }
     const bool all_free = __builtin_amdgcn_ballot_w64(fb != 0xffu) == 0ull;
+    *all_free_out = all_free;
     *all_unk = __builtin_amdgcn_ballot_w64(ub != 0xffu) == 0ull;
     *any_unk = __builtin_amdgcn_ballot_w64(ub != 0u) != 0ull;
     // quarter bricks: x halves of the row, over the 4x4 rows (y, z) of the lane's quarter
@@ -61,9 +66,9 @@ __device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bo
         const uint32_t s = (uint32_t)(v >> (8 * k)) & 3u;
         const bool f4 = k < 4 ? f4lo : f4hi, u4 = k < 4 ? u4lo : u4hi;
         uint32_t lv = 0u;
-        if (s == kFree) lv = all_free ? 1u : (f4 ? 2u : (((f2 >> (k >> 1)) & 1u) ? 3u : 0u));
-        if (s == kUnknown) lv = *all_unk ? 1u : (u4 ? 2u : 0u);
-        out |= (uint64_t)(s | (lv << 2)) << (8 * k);
+        if (s == kFree) lv = all_free ? 2u : (f4 ? 3u : (((f2 >> (k >> 1)) & 1u) ? 4u : 0u));
+        if (s == kUnknown) lv = *all_unk ? 2u : (u4 ? 3u : 0u);
+        out |= (uint64_t)(s | (lv << kLevelShift)) << (8 * k);
     }
     return out;
 }
@@ -77,8 +82,13 @@ __device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bo
 // without unknown voxels, and of wholly unknown bricks with a uniform code,
 // are never written.
 enum : uint8_t { kMaskMixed = 0, kMaskNone = 1, kMaskAll = 2 };
-// brick_unk values: no unknown voxel, some, all 512 (the kUnknownBrick marks)
-enum : uint8_t { kBrickKnown = 0, kBrickSomeUnknown = 1, kBrickAllUnknown = 2 };
+// brick_unk values (bits 0-1): no unknown voxel, some, all 512 (the
+// kUnknownBrick marks); bit 2 (kBrickAllFree) set when all 512 are free
+enum : uint8_t { kBrickKnown = 0, kBrickSomeUnknown = 1, kBrickAllUnknown = 2, kBrickAllFree = 4 };
+__device__ __forceinline__ uint8_t brick_summary(bool any_unk, bool all_unk, bool all_free) {
+    return (uint8_t)((any_unk ? (all_unk ? kBrickAllUnknown : kBrickSomeUnknown) : kBrickKnown) |
+                     (all_free ? kBrickAllFree : 0));
+}
 
 // Occupancy grid in 8x8x8-voxel bricks (512 B each, x fastest inside a
 // brick, bricks x fastest): a ray stays inside one brick for several steps,
@@ -98,8 +108,8 @@ struct MapDev {
     uint32_t mbx, mby, mbz;
     uint32_t mask_words;
     // [mbx * mby * mbz] per mask brick: kBrickKnown, kBrickSomeUnknown or
-    // kBrickAllUnknown (kept current, with the whole-brick marks, by every
-    // write of the map's states)
+    // kBrickAllUnknown, with kBrickAllFree (kept current, with the block
+    // marks, by every write of the map's states)
     uint8_t* brick_unk;
 };
 
@@ -215,8 +225,11 @@ hipError_t launch_map_scatter(const uint32_t* ids, const uint8_t* states, uint32
                               uint32_t* rejected, hipStream_t s);
 hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s);
 hipError_t launch_fill_outside(const MapDev& m, hipStream_t s);
-// Recomputes brick_unk from the states (after any write of the states).
+// Recomputes brick_unk and the block marks from the states (after any write
+// of the states): the bricks' summaries, then the 16x16x16 free blocks.
 hipError_t launch_brick_flags(const MapDev& m, hipStream_t s);
+// The 16x16x16 free blocks alone (after a conversion that took the bricks' summaries itself).
+hipError_t launch_free_blocks16(const MapDev& m, hipStream_t s);
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
                         int32_t n_nodes, bool marginal, hipStream_t s);
 // Path masks of the listed nodes (all with children), after their windows are chosen.

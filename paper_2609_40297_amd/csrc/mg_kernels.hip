@@ -71,12 +71,34 @@ __global__ void k_brick_flags(MapDev m) {
         const uint32_t base = voxel_addr((int32_t)(bx * 8u), (int32_t)(by * 8u), (int32_t)(bz * 8u), m);
         uint64_t* p = reinterpret_cast<uint64_t*>(grid + base + lane * 8u);
         const uint64_t v = *p;
-        bool any_unk, all_unk;
-        const uint64_t w = mark_brick_row(v, lane, &any_unk, &all_unk);
-        if (lane == 0)
-            m.brick_unk[b] = any_unk ? (all_unk ? (uint8_t)kBrickAllUnknown : (uint8_t)kBrickSomeUnknown)
-                                     : (uint8_t)kBrickKnown;
+        bool any_unk, all_unk, all_free;
+        const uint64_t w = mark_brick_row(v, lane, &any_unk, &all_unk, &all_free);
+        if (lane == 0) m.brick_unk[b] = brick_summary(any_unk, all_unk, all_free);
         if (w != v) *p = w;
+    }
+}
+
+// 16x16x16 free blocks, after the bricks' summaries: a brick whose aligned
+// block of 2x2x2 bricks lies in the grid's bricks and holds only wholly free
+// bricks has its voxels marked at level 1. One wave per brick, each lane
+// writing 8 of its 512 bytes.
+__global__ void k_free_blocks16(MapDev m) {
+    const uint32_t nb = m.mask_words >> 4;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint8_t* grid = const_cast<uint8_t*>(m.bricks);
+    for (uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < nb; b += (gridDim.x * blockDim.x) >> 6) {
+        const uint32_t bx = b % m.mbx, by = (b / m.mbx) % m.mby, bz = b / (m.mbx * m.mby);
+        const uint32_t x0 = bx & ~1u, y0 = by & ~1u, z0 = bz & ~1u;
+        if (x0 + 1u >= m.mbx || y0 + 1u >= m.mby || z0 + 1u >= m.mbz) continue;
+        bool all = true;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            const uint32_t n = (x0 + (k & 1u)) + m.mbx * ((y0 + ((k >> 1) & 1u)) + m.mby * (z0 + (k >> 2)));
+            all = all && (m.brick_unk[n] & kBrickAllFree) != 0;
+        }
+        if (!all) continue;
+        const uint32_t base = voxel_addr((int32_t)(bx * 8u), (int32_t)(by * 8u), (int32_t)(bz * 8u), m);
+        *reinterpret_cast<uint64_t*>(grid + base + lane * 8u) = (uint64_t)(kFree | (1u << kLevelShift)) * 0x0101010101010101ull;
     }
 }
 
@@ -264,7 +286,7 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         const bool near = rx * rx + ry * ry + rz * rz <= reach * reach;
         const float w0 = A.b0x * ry - A.b0y * rx, w1 = A.b1x * ry - A.b1y * rx;
         const bool wedge = (w0 >= -5.5f) & (w1 < 5.5f);      // 3.5 sqrt(2) = 4.95, plus rounding
-        const uint32_t bu = M.brick_unk[b];
+        const uint32_t bu = M.brick_unk[b] & 3u;            // (without the all-free bit)
         const uint32_t pc = par ? (uint32_t)pcode[b] : (uint32_t)kMaskNone;
         // (a brick without unknown voxels needs no bits: only unknown voxels' bits
         // are read; nor does one whose voxels an ancestor all observes)
@@ -436,12 +458,16 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build(MapDev M, SensorDe
 // t = (b - q) * f below Tc (a caller that wants ties counted passes the next
 // float above the crossing). Parameters grow by at least 1 from one boundary
 // to the next, so these boundaries are a prefix; the caller's crossing leaves
-// a block of at most 8 voxels a side, so the prefix ends at the axis's own
-// exit from that block, at most 7 boundaries on, and three probes (at 3, then
-// 3 +- 2, then +- 1) find its length. Boundaries are evaluated exactly as the single step evaluates them
-// (the fused multiply-add of integers is exact). Returned as a float count.
-__device__ __forceinline__ float crossings_before(float b0, float db, float q, float f, float Tc) {
+// a block of at most 16 voxels a side, so the prefix ends at the axis's own
+// exit from that block, at most 15 boundaries on. Three probes (at 3, then
+// 3 +- 2, then +- 1) find its length when the block's edge is at most 8; a
+// first probe at 7 (then 11 or 3) extends the search to 15 (`wide`, uniform
+// over the wave). Boundaries are evaluated exactly as the single step
+// evaluates them (the fused multiply-add of integers is exact). Returned as a
+// float count.
+__device__ __forceinline__ float crossings_before(float b0, float db, float q, float f, float Tc, bool wide) {
     float m = 3.f;
+    if (wide) m = ((__builtin_fmaf(7.f, db, b0) - q) * f < Tc) ? 11.f : 3.f;
     m += ((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 2.f : -2.f;
     m += ((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 1.f : -1.f;
     return m + (((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 1.f : 0.f);
@@ -540,8 +566,9 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 pend = false;
             }
             h = st == kOccupied ? t : h;
-            // An aligned block (a brick, a quarter brick or, for free voxels, a
-            // 2x2x2 block) whose voxels are all free, or all unknown with the
+            // An aligned block (for free voxels a block of 2x2x2 bricks, a brick,
+            // a quarter brick or a 2x2x2 block; for unknown voxels a brick or a
+            // quarter brick) whose voxels are all free, or all unknown with the
             // parent's mask uniform over their brick (every bit clear or every
             // bit set), is crossed in one step: it is left through the face whose
             // boundary parameter comes first (ties x, y, z) and every other axis
@@ -554,7 +581,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             float kx, ky, kz;                   // boundaries this step crosses along each axis (set by
                                                 // the crossing when it is taken, else by the voxel step)
             bool whole = false;
-            const uint32_t level = st >> 2;     // the voxel's block: edge 16 >> level, or none (0)
+            const uint32_t level = (st >> kLevelShift) & kLevelMask;   // the voxel's block: edge 32 >> level, or none (0)
             const bool free_blk = (level != 0u) & ((st & 3u) == kFree);
             bool cand = free_blk;
             uint32_t code = kMaskNone;          // (the absolute pass, and the root, see nothing observed)
@@ -572,7 +599,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 cand = by_code;
             }
             if (cand) {
-                const int32_t edge = 16 >> level;
+                const int32_t edge = 32 >> level;
                 const float Tx = ((float)((ix & -edge) + (edge & upx)) - qx) * fx;
                 const float Ty = ((float)((iy & -edge) + (edge & upy)) - qy) * fy;
                 const float Tz = ((float)((iz & -edge) + (edge & upz)) - qz) * fz;
@@ -586,9 +613,10 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                     // counts a boundary whose parameter equals T: it compares with
                     // the next float above T (T >= 0; +0 for -0 first).
                     const float Tn = __uint_as_float(__float_as_uint(T + 0.f) + 1u);
-                    kx = crossings_before(bx, dbx, qx, fx, fx_ ? T : Tn) + (fx_ ? 1.f : 0.f);
-                    ky = crossings_before(by, dby, qy, fy, fz_ ? Tn : T) + (fy_ ? 1.f : 0.f);
-                    kz = crossings_before(bz, dbz, qz, fz, T) + (fz_ ? 1.f : 0.f);
+                    const bool wide = ballot(level == 1u) != 0ull;     // some lane crosses a 16-voxel block
+                    kx = crossings_before(bx, dbx, qx, fx, fx_ ? T : Tn, wide) + (fx_ ? 1.f : 0.f);
+                    ky = crossings_before(by, dby, qy, fy, fz_ ? Tn : T, wide) + (fy_ ? 1.f : 0.f);
+                    kz = crossings_before(bz, dbz, qz, fz, T, wide) + (fz_ ? 1.f : 0.f);
                     tn = T;
                     if (!free_blk) {
                         const uint32_t v = (uint32_t)(kx + ky + kz);
@@ -971,6 +999,13 @@ hipError_t launch_brick(const uint8_t* dense, uint8_t* bricks, const MapDev& m, 
 hipError_t launch_brick_flags(const MapDev& m, hipStream_t s) {
     const size_t threads = (size_t)(m.mask_words >> 4) * 64u;
     hipLaunchKernelGGL(k_brick_flags, dim3(grid_for(threads, 256)), dim3(256), 0, s, m);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_free_blocks16(m, s) : e;
+}
+
+hipError_t launch_free_blocks16(const MapDev& m, hipStream_t s) {
+    const size_t threads = (size_t)(m.mask_words >> 4) * 64u;
+    hipLaunchKernelGGL(k_free_blocks16, dim3(grid_for(threads, 256)), dim3(256), 0, s, m);
     return hipGetLastError();
 }
 

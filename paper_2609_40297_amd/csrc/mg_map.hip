@@ -30,12 +30,12 @@ __device__ __forceinline__ void mark_run(uint8_t* tile, int32_t tb, int32_t bx0,
     const int32_t lane = (int32_t)threadIdx.x & 63, wave = (int32_t)threadIdx.x >> 6;
     for (int32_t k = wave; k < tb; k += 4) {
         uint64_t* p = reinterpret_cast<uint64_t*>(tile + k * 512) + lane;
-        bool any_unk, all_unk;
-        *p = mark_brick_row(*p, (uint32_t)lane, &any_unk, &all_unk);
+        bool any_unk, all_unk, all_free;
+        *p = mark_brick_row(*p, (uint32_t)lane, &any_unk, &all_unk, &all_free);
         const int32_t bx = bx0 + k;
         if (lane == 0 && (uint32_t)bx < m.mbx && (uint32_t)by < m.mby && (uint32_t)bz < m.mbz)
             m.brick_unk[(uint32_t)bx + m.mbx * ((uint32_t)by + m.mby * (uint32_t)bz)] =
-                any_unk ? (all_unk ? (uint8_t)kBrickAllUnknown : (uint8_t)kBrickSomeUnknown) : (uint8_t)kBrickKnown;
+                brick_summary(any_unk, all_unk, all_free);
     }
 }
 
@@ -192,7 +192,8 @@ hipError_t launch_tsdf_grid(const float* dist, const float* weight, const MapDev
     else
         hipLaunchKernelGGL(k_tsdf_grid, grid, dim3(256), 0, s, dist, weight, (uint8_t*)m.bricks, m, surface,
                            min_weight);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_free_blocks16(m, s) : e;       // (the bricks' summaries are taken above)
 }
 
 hipError_t launch_tsdf_box(const float* dist, const float* weight, const MapDev& m, const int32_t lo[3],

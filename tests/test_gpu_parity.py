@@ -131,6 +131,59 @@ def test_free_bricks_crossed_at_once(mg, orc, dims):
         assert int(ref["g_abs"].sum()) > 0
 
 
+def _nested_block_map(seed, dims):
+    """A map of nested aligned blocks: each 16x16x16 block wholly free or split into 8x8x8 bricks,
+    each brick wholly free, wholly unknown or split into 4x4x4 quarters, each quarter wholly free,
+    wholly unknown or split into 2x2x2 blocks, each of those wholly free, wholly unknown or of
+    mixed voxels (a few occupied), so that rays cross blocks of every size the traversal crosses
+    in one step."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = dims
+    st = np.full((nz, ny, nx), W.FREE, np.uint8)
+
+    def fill(z, y, x, e):
+        sl = st[z:z + e, y:y + e, x:x + e]
+        u = rng.uniform()
+        if u < 0.3:
+            return
+        if e == 16:
+            u = 0.6                                  # (no wholly unknown 16-voxel blocks: split)
+        if u < 0.55:
+            sl[...] = W.UNK
+            return
+        if e == 2:
+            sl[rng.uniform(size=sl.shape) < 0.5] = W.UNK
+            sl[rng.uniform(size=sl.shape) < 0.04] = W.OCC
+            return
+        h = e // 2
+        for dz in (0, h):
+            for dy in (0, h):
+                for dx in (0, h):
+                    fill(z + dz, y + dy, x + dx, h)
+    for z in range(0, nz, 16):
+        for y in range(0, ny, 16):
+            for x in range(0, nx, 16):
+                fill(z, y, x, 16)
+    return W.Map(states=st, voxel_m=1.0, origin_m=np.zeros(3, dtype=np.float32))
+
+
+@pytest.mark.parametrize("dims", [(40, 32, 24), (37, 29, 21), (48, 48, 34)])
+def test_nested_blocks_crossed_at_once(mg, orc, dims):
+    """Rays through wholly free blocks of 2x2x2 bricks, bricks, quarter bricks and 2x2x2 blocks and
+    wholly unknown bricks and quarter bricks (each crossed in one step on the device) against the oracle's
+    voxel-by-voxel DDA: nodes on block corners, edges and faces, 45-degree rays whose boundary
+    parameters tie, ranges that end inside blocks; grids whose last blocks reach past the grid."""
+    m = _nested_block_map(1200 + dims[0], dims)
+    pos = np.array([[8.0, 8.0, 8.0], [16.0, 16.0, 8.0], [12.0, 12.0, 4.0], [24.0, 8.0, 16.0], [10.0, 14.0, 6.0],
+                    [16.0, 8.0, 4.5], [9.5, 17.0, 8.0], [30.0, 22.0, 14.0], [4.25, 20.75, 19.5], [20.0, 20.0, 10.0],
+                    [6.0, 26.0, 2.0], [18.5, 2.0, 12.0]], np.float32)
+    tree = W.Tree(pos_m=pos, parent=np.array([-1, 0, 0, 1, 1, 2, 3, 4, 6, 8, 9, 10], np.int32))
+    for sen in (W.Sensor(n_az=8, n_el=3, fov_h_deg=90, fov_v_deg=90, range_m=30.0, yaw_bins=8, az_offset_deg=-22.5),
+                W.Sensor(n_az=100, n_el=17, fov_h_deg=90, fov_v_deg=80, range_m=13.7, yaw_bins=20)):
+        got, ref = _full_parity(mg, orc, m, tree, sen, f"nested blocks {dims} {sen.n_az}x{sen.n_el}")
+        assert int(ref["g_abs"].sum()) > 0
+
+
 def test_evaluations_of_one_tree_do_not_see_each_others_masks(mg, orc):
     """A path mask keeps only what can be read (the words of a wholly unknown brick only when its
     code is mixed), so its memory holds what an earlier evaluation of the same tree left there.
