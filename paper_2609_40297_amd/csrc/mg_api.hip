@@ -666,7 +666,7 @@ int prepare_tree(mg_map map, const float* pos_m, const int32_t* parent, int32_t 
     H->o_masks = take(sizeof(uint32_t) * (size_t)map->dev.mask_words * (size_t)H->n_masks);
     const size_t n_tiles = (size_t)((wb + kTileCols - 1) / kTileCols) * (size_t)((sensor->n_el + kTileRows - 1) / kTileRows);
     H->o_tm = take(sizeof(float) * 2 * n_tiles * (size_t)std::max(H->n_masks, 1));
-    H->o_mc = take((size_t)(map->dev.mask_words >> 4) * (size_t)std::max(H->n_masks, 1));
+    H->o_mc = take(sizeof(uint32_t) * (size_t)(map->dev.mask_words >> 4) * (size_t)std::max(H->n_masks, 1));
     H->total = off;
     return MG_OK;
 }
@@ -715,16 +715,16 @@ int finish_upload(mg_map map, const mgb::HostTree& H, const mg_sensor* sensor, h
     t->dev.mask_nodes = (const int32_t*)(base + H.o_mn);
     t->dev.masks = (uint32_t*)(base + H.o_masks);
     t->dev.tmax = (float*)(base + H.o_tm);
-    t->dev.mcode = (uint8_t*)(base + H.o_mc);
+    t->dev.mcode = (uint32_t*)(base + H.o_mc);
     t->dev.n = n;
     t->dev.anc_cap = kMaxAnc;
     t->scratch_gain = (uint32_t*)(base + H.o_g);
     t->scratch_yaw = (int32_t*)(base + H.o_y);
     t->sd = sensor_dev(t->sensor, sensor->range_m / map->voxel_m);
-    if (build_lds_bytes(t->sd) + 256 > lds_limit()) {
+    if (build_lds_total(t->sd) > lds_limit()) {
         release_sensor(t->sensor);
         return fail(MG_E_UNSUPPORTED, "sensor tables need %zu bytes of LDS per workgroup, the device has %zu",
-                    build_lds_bytes(t->sd), lds_limit());
+                    build_lds_total(t->sd), lds_limit());
     }
     t->map = map;
     t->params = *sensor;

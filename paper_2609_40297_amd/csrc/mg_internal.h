@@ -82,6 +82,10 @@ __device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bo
 // without unknown voxels, and of wholly unknown bricks with a uniform code,
 // are never written.
 enum : uint8_t { kMaskMixed = 0, kMaskNone = 1, kMaskAll = 2 };
+// A brick's code word: bits 0-1 the code of its 512 bits, bits 2 + 2q and
+// 3 + 2q the code of its quarter q (the 4x4x4 voxels with (x & 4, y & 4, z & 4)
+// = 4 * (q & 1, (q >> 1) & 1, q >> 2)).
+__host__ __device__ inline uint32_t uniform_code_word(uint32_t c) { return c * 0x15555u; }
 // brick_unk values (bits 0-1): no unknown voxel, some, all 512 (the
 // kUnknownBrick marks); bit 2 (kBrickAllFree) set when all 512 are free
 enum : uint8_t { kBrickKnown = 0, kBrickSomeUnknown = 1, kBrickAllUnknown = 2, kBrickAllFree = 4 };
@@ -191,7 +195,7 @@ struct TreeDev {
     const int32_t* mask_slot;  // [n] index into masks, -1 for a leaf
     const int32_t* mask_nodes; // nodes with children, by depth level
     float* tmax;               // [nodes with children][2][n_tiles]: largest, then smallest first hit of each tile of the window
-    uint8_t* mcode;            // [nodes with children][mask bricks]: kMaskMixed / kMaskNone / kMaskAll
+    uint32_t* mcode;           // [nodes with children][mask bricks]: code words
     int32_t n;
     int32_t anc_cap;           // ancestors that condition a node: kMaxAnc (all) or 1 (the parent only)
 };
@@ -245,6 +249,7 @@ void shape_of(int shape, int* threads, int* bricks);
 int32_t tiles_per_node(const SensorDev& sd, int shape);
 size_t lds_limit();                        // LDS bytes one workgroup may use on the current device
 size_t build_lds_bytes(const SensorDev& sd);   // LDS of the mask builder (sensor tables)
+size_t build_lds_total(const SensorDev& sd);   // and with its fixed arrays
 // Path score of every node of the trees (eq. 3, eq. 4) and each tree's best node.
 hipError_t launch_score(const BatchTree* trees, int32_t n_trees, uint32_t max_nodes, const uint32_t* gain,
                         double lambda, double* cost, double* obj, int32_t* best, int32_t* branch, hipStream_t s);

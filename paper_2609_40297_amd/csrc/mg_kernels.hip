@@ -133,6 +133,8 @@ struct Shape {
 constexpr Shape kShapes[] = {{256, 64}, {128, 64}, {512, 64}, {256, 128}, {256, 32}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMaxBuildBricks = 128;
+// the builder's fixed LDS beside its tables: a flag byte and a code word per brick, and a word
+constexpr size_t kBuildFixedLds = (size_t)kMaxBuildBricks * 5u + 16u;
 constexpr int kBuildThreads = 256;
 
 struct TableLDS {
@@ -249,7 +251,7 @@ __device__ int brick_view(const SensorDev& S, const float* __restrict__ tm, floa
 // nothing (a batch launch covers its largest map).
 __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
                                             int32_t chunk, int32_t bricks, char* smem, uint8_t* s_live,
-                                            int32_t* s_any) {
+                                            uint32_t* s_cw, int32_t* s_any) {
     const int32_t tid = threadIdx.x;
     const int32_t slot = Tr.mask_slot[node];
     const uint32_t nb = M.mask_words >> 4;
@@ -258,7 +260,7 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     uint32_t* out = Tr.masks + (size_t)slot * M.mask_words;
     const int32_t a0 = Tr.anc_ptr[node];
     const uint32_t* par = nullptr;
-    const uint8_t* pcode = nullptr;
+    const uint32_t* pcode = nullptr;
     if (Tr.anc_cap > 1 && Tr.anc_ptr[node + 1] > a0) {
         const int32_t ps = Tr.mask_slot[Tr.anc_ids[a0]];
         par = Tr.masks + (size_t)ps * M.mask_words;
@@ -287,7 +289,8 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         const float w0 = A.b0x * ry - A.b0y * rx, w1 = A.b1x * ry - A.b1y * rx;
         const bool wedge = (w0 >= -5.5f) & (w1 < 5.5f);      // 3.5 sqrt(2) = 4.95, plus rounding
         const uint32_t bu = M.brick_unk[b] & 3u;            // (without the all-free bit)
-        const uint32_t pc = par ? (uint32_t)pcode[b] : (uint32_t)kMaskNone;
+        const uint32_t pcw = par ? pcode[b] : uniform_code_word(kMaskNone);   // the parent's code word
+        const uint32_t pc = pcw & 3u;
         // (a brick without unknown voxels needs no bits: only unknown voxels' bits
         // are read; nor does one whose voxels an ancestor all observes)
         const int view = (near && wedge && bu != kBrickKnown && pc != kMaskAll)
@@ -297,6 +300,7 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         // per-voxel test would give it)
         const bool live = view == kViewSome;
         s_live[tid] = (uint8_t)(((uint32_t)live << 4) | (bu << 2) | (view == kViewAll ? (uint32_t)kMaskAll : pc));
+        s_cw[tid] = view == kViewAll ? uniform_code_word(kMaskAll) : pcw;
         if (live) *s_any = 1;
     }
     __syncthreads();
@@ -310,10 +314,10 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         if ((f & 16u) || bu == kBrickKnown || (bu == kBrickAllUnknown && pc != kMaskMixed)) continue;
         out[lo * 16u + (uint32_t)w] = pc == kMaskMixed ? par[lo * 16u + (uint32_t)w] : (pc == kMaskAll ? ~0u : 0u);
     }
-    uint8_t* code = Tr.mcode + (size_t)slot * nb;
+    uint32_t* code = Tr.mcode + (size_t)slot * nb;
     if (tid < cnt) {
         const uint32_t f = s_live[tid];
-        if (!(f & 16u) && ((f >> 2) & 3u) != kBrickKnown) code[lo + (uint32_t)tid] = (uint8_t)(f & 3u);
+        if (!(f & 16u) && ((f >> 2) & 3u) != kBrickKnown) code[lo + (uint32_t)tid] = s_cw[tid];
     }
     if (!*s_any) return;
     const TableLDS L = carve_tables(smem, S);
@@ -435,10 +439,21 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         }
         word |= pw;
         if (lane < 16) out[wbase + (uint32_t)lane] = word;
-        // the brick's code: all 512 bits clear, all set, or mixed
-        const bool none = ballot((lane < 16) & (word != 0u)) == 0;
-        const bool all = ballot((lane < 16) & (word != ~0u)) == 0;
-        if (lane == 0) code[b] = none ? (uint8_t)kMaskNone : (all ? (uint8_t)kMaskAll : (uint8_t)kMaskMixed);
+        // the brick's code word: its 512 bits and each quarter's 64 all clear, all
+        // set, or mixed (word l holds slice l / 2, rows 4 (l & 1) .. + 3, x in its
+        // bytes' low and high nibbles)
+        const bool w_ok = lane < 16;
+        const uint64_t nz_lo = ballot(w_ok & ((word & 0x0f0f0f0fu) != 0u)), nz_hi = ballot(w_ok & ((word & 0xf0f0f0f0u) != 0u));
+        const uint64_t nf_lo = ballot(w_ok & ((word | 0xf0f0f0f0u) != ~0u)), nf_hi = ballot(w_ok & ((word | 0x0f0f0f0fu) != ~0u));
+        uint32_t cw = (nz_lo | nz_hi) == 0ull ? (uint32_t)kMaskNone : ((nf_lo | nf_hi) == 0ull ? (uint32_t)kMaskAll : (uint32_t)kMaskMixed);
+#pragma unroll
+        for (uint32_t qd = 0; qd < 8; ++qd) {
+            const uint64_t lq = 0x55ull << (8u * (qd >> 2) + ((qd >> 1) & 1u));   // words of the quarter's slices and rows
+            const uint64_t nz = (qd & 1u) ? nz_hi : nz_lo, nf = (qd & 1u) ? nf_hi : nf_lo;
+            const uint32_t qc = (nz & lq) == 0ull ? (uint32_t)kMaskNone : ((nf & lq) == 0ull ? (uint32_t)kMaskAll : (uint32_t)kMaskMixed);
+            cw |= qc << (2u + 2u * qd);
+        }
+        if (lane == 0) code[b] = cw;
     }
 }
 
@@ -447,8 +462,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build(MapDev M, SensorDe
                                                               int32_t bricks) {
     extern __shared__ char smem[];
     __shared__ uint8_t s_live[kMaxBuildBricks];
+    __shared__ uint32_t s_cw[kMaxBuildBricks];
     __shared__ int32_t s_any;
-    build_chunk(M, S, Tr, nodes[blockIdx.x / chunks], (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, &s_any);
+    build_chunk(M, S, Tr, nodes[blockIdx.x / chunks], (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, s_cw, &s_any);
 }
 
 // ---------------------------------------------------------------- ray traversal
@@ -492,7 +508,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                                            int32_t tile, uint32_t* __restrict__ s_bins) {
     const int32_t tid = threadIdx.x;
     const uint32_t* pmask = nullptr;     // the parent's path mask
-    const uint8_t* pcode = nullptr;      // and its brick codes
+    const uint32_t* pcode = nullptr;     // and its bricks' code words
     if (kMarginal) {
         const int32_t a0 = Tr.anc_ptr[node];
         if (Tr.anc_cap > 0 && Tr.anc_ptr[node + 1] > a0) {
@@ -502,7 +518,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
         }
     }
     const gwords_t pm = as_global(uniform_ptr(pmask));
-    const gbytes_t pc = as_global(uniform_ptr(pcode));
+    const gwords_t pc = as_global(uniform_ptr(pcode));
     for (int32_t i = tid; i < 2 * S.B; i += kTh) s_bins[i] = 0u;
     __syncthreads();
 
@@ -553,7 +569,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     uint32_t st = M.bricks[addr];
     uint32_t mw = 0u, mb = 0u;          // mask word of the last unknown voxel, and its bit
     bool pend = false;                  // (a word requested in the previous step)
-    uint32_t mixed_b = ~0u;             // last unknown brick found mixed in the parent's mask
+    uint32_t cb_idx = ~0u, cw = 0u;     // the last unknown block's brick and its code word
     if (ballot(has_ray)) {
         uint64_t alive;
         do {
@@ -569,8 +585,10 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             // An aligned block (for free voxels a block of 2x2x2 bricks, a brick,
             // a quarter brick or a 2x2x2 block; for unknown voxels a brick or a
             // quarter brick) whose voxels are all free, or all unknown with the
-            // parent's mask uniform over their brick (every bit clear or every
-            // bit set), is crossed in one step: it is left through the face whose
+            // parent's mask uniform over it (every bit clear or every bit set; a
+            // wholly unknown brick over which the mask is mixed is crossed a
+            // quarter at a time where it is uniform over the quarter), is crossed
+            // in one step: it is left through the face whose
             // boundary parameter comes first (ties x, y, z) and every other axis
             // has crossed the boundaries that come before that crossing in the
             // same order. The voxels crossed are one per crossing; crossing an
@@ -581,7 +599,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             float kx, ky, kz;                   // boundaries this step crosses along each axis (set by
                                                 // the crossing when it is taken, else by the voxel step)
             bool whole = false;
-            const uint32_t level = (st >> kLevelShift) & kLevelMask;   // the voxel's block: edge 32 >> level, or none (0)
+            uint32_t level = (st >> kLevelShift) & kLevelMask;   // the voxel's block: edge 32 >> level, or none (0)
             const bool free_blk = (level != 0u) & ((st & 3u) == kFree);
             bool cand = free_blk;
             uint32_t code = kMaskNone;          // (the absolute pass, and the root, see nothing observed)
@@ -592,8 +610,15 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             if ((level != 0u) & ((st & 3u) == kUnknown)) {
                 if (kMarginal && pc != nullptr) {
                     const uint32_t b = mask_brick(ix, iy, iz, M);
-                    code = b == mixed_b ? (uint32_t)kMaskMixed : (uint32_t)pc[b];
-                    mixed_b = code == kMaskMixed ? b : mixed_b;
+                    if (b != cb_idx) {
+                        cw = pc[b];
+                        cb_idx = b;
+                    }
+                    // the brick's code, else its quarter's (a quarter block at most)
+                    const uint32_t qs = 2u + ((((uint32_t)ix >> 1) & 2u) | ((uint32_t)iy & 4u) | (((uint32_t)iz << 1) & 8u));
+                    const bool brick_uniform = (cw & 3u) != kMaskMixed;
+                    code = brick_uniform ? (cw & 3u) : ((cw >> qs) & 3u);
+                    level = brick_uniform ? level : 3u;
                 }
                 by_code = code != kMaskMixed;
                 cand = by_code;
@@ -818,6 +843,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchT
                                                                     SensorDev S, int32_t chunks, int32_t bricks) {
     extern __shared__ char smem[];
     __shared__ uint8_t s_live[kMaxBuildBricks];
+    __shared__ uint32_t s_cw[kMaxBuildBricks];
     __shared__ int32_t s_any;
     const unsigned long long it = items[blockIdx.x / chunks];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
@@ -827,7 +853,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchT
     St.rv2 = BT.rv2;
     const MapDev M = BT.map;
     const TreeDev Tr = BT.td;
-    build_chunk(M, St, Tr, (int32_t)(uint32_t)it, (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, &s_any);
+    build_chunk(M, St, Tr, (int32_t)(uint32_t)it, (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, s_cw, &s_any);
 }
 
 // Window selection of one (tree, node) item of a batch: gain, window, the
@@ -921,6 +947,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
     __shared__ uint32_t s_p[2 * kMaxBins + 1];
     __shared__ unsigned long long s_best[kThreads / 64];
     __shared__ uint8_t s_live[kMaxBuildBricks];
+    __shared__ uint32_t s_cw[kMaxBuildBricks];
     __shared__ int32_t s_any, s_ok;
     uint32_t target = 0;
     const uint32_t G = gridDim.x;
@@ -961,7 +988,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
                 St.rv2 = BT.rv2;
                 const MapDev M = BT.map;
                 const TreeDev Tr = BT.td;
-                build_chunk(M, St, Tr, (int32_t)(uint32_t)it, chunk, bricks, smem, s_live, &s_any);
+                build_chunk(M, St, Tr, (int32_t)(uint32_t)it, chunk, bricks, smem, s_live, s_cw, &s_any);
             }
             __syncthreads();
         }
@@ -1027,6 +1054,8 @@ size_t build_lds_bytes(const SensorDev& sd) {
            sizeof(uint16_t) * (sd.n_lut_col + sd.n_lut_row);
 }
 
+size_t build_lds_total(const SensorDev& sd) { return build_lds_bytes(sd) + kBuildFixedLds; }
+
 size_t lds_limit() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1059,7 +1088,7 @@ hipError_t launch_mask_build(const MapDev& m, const SensorDev& sd, const TreeDev
     if (n_nodes <= 0) return hipSuccess;
     const int32_t bricks = kShapes[0].bricks, chunks = build_chunks(m, bricks);
     const size_t lds = build_lds_bytes(sd);
-    if (lds + kMaxBuildBricks > lds_limit()) return hipErrorInvalidConfiguration;
+    if (lds + kBuildFixedLds > lds_limit()) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_mask_build, dim3((unsigned)n_nodes * (unsigned)chunks), dim3(kBuildThreads), lds, s, m, sd,
                        td, nodes, chunks, bricks);
     return hipGetLastError();
@@ -1248,7 +1277,7 @@ hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* 
     if (n_items <= 0) return hipSuccess;
     if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
     const size_t lds = build_lds_bytes(sd);
-    if (lds + kMaxBuildBricks > lds_limit()) return hipErrorInvalidConfiguration;
+    if (lds + kBuildFixedLds > lds_limit()) return hipErrorInvalidConfiguration;
     launch_multi_shape<0>(shape, trees, items, n_items, sd, s, t0, t1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1287,7 +1316,7 @@ hipError_t launch_batch_persistent(const BatchTree* trees, const unsigned long l
                                    hipStream_t s) {
     if (levels <= 0) return hipSuccess;
     const size_t lds = build_lds_bytes(sd);
-    if (lds + kMaxBuildBricks > lds_limit()) return hipErrorInvalidConfiguration;
+    if (lds + kBuildFixedLds > lds_limit()) return hipErrorInvalidConfiguration;
     int32_t grid = 0;
     hipError_t e = persistent_grid(sd, &grid);
     if (e != hipSuccess) return e;
