@@ -36,17 +36,22 @@ __host__ __device__ inline bool is_unknown(uint32_t s) { return (s & 3u) == 0u; 
 // unknown voxel, only unknown voxels, only free voxels.
 __device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bool* any_unk, bool* all_unk,
                                                    bool* all_free_out) {
+    const uint64_t ones = 0x0101010101010101ull;
+    const uint64_t s8 = v & (3ull * ones);                       // the states, a byte each
+    // (a byte is unknown when it is zero: states are below 0x80, so the borrow test is exact)
+    const bool row_unk = ((s8 - ones) & ~s8 & (0x80ull * ones)) != 0ull;
+    const bool all_free = __builtin_amdgcn_ballot_w64(s8 != ones) == 0ull;
+    *all_free_out = all_free;
+    *all_unk = __builtin_amdgcn_ballot_w64(s8 != 0ull) == 0ull;
+    *any_unk = __builtin_amdgcn_ballot_w64(row_unk) != 0ull;
+    if (all_free | *all_unk) return s8 | ((uint64_t)(2u << kLevelShift) * ones);   // (the whole brick: level 2)
     uint32_t fb = 0u, ub = 0u;          // per byte: free, unknown
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t s = (uint32_t)(v >> (8 * k)) & 3u;
+        const uint32_t s = (uint32_t)(s8 >> (8 * k));
         fb |= (s == kFree ? 1u : 0u) << k;
         ub |= (s == kUnknown ? 1u : 0u) << k;
     }
-    const bool all_free = __builtin_amdgcn_ballot_w64(fb != 0xffu) == 0ull;
-    *all_free_out = all_free;
-    *all_unk = __builtin_amdgcn_ballot_w64(ub != 0xffu) == 0ull;
-    *any_unk = __builtin_amdgcn_ballot_w64(ub != 0u) != 0ull;
     // quarter bricks: x halves of the row, over the 4x4 rows (y, z) of the lane's quarter
     const uint32_t y = lane & 7u, z = lane >> 3;
     const uint64_t quarter = (0x0f0f0f0full << (y & 4u)) << (8u * (z & 4u));
@@ -66,8 +71,8 @@ __device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bo
         const uint32_t s = (uint32_t)(v >> (8 * k)) & 3u;
         const bool f4 = k < 4 ? f4lo : f4hi, u4 = k < 4 ? u4lo : u4hi;
         uint32_t lv = 0u;
-        if (s == kFree) lv = all_free ? 2u : (f4 ? 3u : (((f2 >> (k >> 1)) & 1u) ? 4u : 0u));
-        if (s == kUnknown) lv = *all_unk ? 2u : (u4 ? 3u : 0u);
+        if (s == kFree) lv = f4 ? 3u : (((f2 >> (k >> 1)) & 1u) ? 4u : 0u);
+        if (s == kUnknown) lv = u4 ? 3u : 0u;
         out |= (uint64_t)(s | (lv << kLevelShift)) << (8 * k);
     }
     return out;

@@ -80,13 +80,13 @@ __global__ void k_brick_flags(MapDev m) {
 
 // 16x16x16 free blocks, after the bricks' summaries: a brick whose aligned
 // block of 2x2x2 bricks lies in the grid's bricks and holds only wholly free
-// bricks has its voxels marked at level 1. One wave per brick, each lane
-// writing 8 of its 512 bytes.
+// bricks has its voxels marked at level 1. One thread per brick; the few
+// bricks of such blocks are written by their thread, 16 bytes at a time.
 __global__ void k_free_blocks16(MapDev m) {
     const uint32_t nb = m.mask_words >> 4;
-    const uint32_t lane = threadIdx.x & 63u;
     uint8_t* grid = const_cast<uint8_t*>(m.bricks);
-    for (uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < nb; b += (gridDim.x * blockDim.x) >> 6) {
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+        if (!(m.brick_unk[b] & kBrickAllFree)) continue;
         const uint32_t bx = b % m.mbx, by = (b / m.mbx) % m.mby, bz = b / (m.mbx * m.mby);
         const uint32_t x0 = bx & ~1u, y0 = by & ~1u, z0 = bz & ~1u;
         if (x0 + 1u >= m.mbx || y0 + 1u >= m.mby || z0 + 1u >= m.mbz) continue;
@@ -98,7 +98,9 @@ __global__ void k_free_blocks16(MapDev m) {
         }
         if (!all) continue;
         const uint32_t base = voxel_addr((int32_t)(bx * 8u), (int32_t)(by * 8u), (int32_t)(bz * 8u), m);
-        *reinterpret_cast<uint64_t*>(grid + base + lane * 8u) = (uint64_t)(kFree | (1u << kLevelShift)) * 0x0101010101010101ull;
+        const uint32_t w = (kFree | (1u << kLevelShift)) * 0x01010101u;
+        uint4* p = reinterpret_cast<uint4*>(grid + base);        // (a brick is 512 contiguous, aligned bytes)
+        for (int k = 0; k < 32; ++k) p[k] = make_uint4(w, w, w, w);
     }
 }
 
@@ -1031,7 +1033,7 @@ hipError_t launch_brick_flags(const MapDev& m, hipStream_t s) {
 }
 
 hipError_t launch_free_blocks16(const MapDev& m, hipStream_t s) {
-    const size_t threads = (size_t)(m.mask_words >> 4) * 64u;
+    const size_t threads = (size_t)(m.mask_words >> 4);
     hipLaunchKernelGGL(k_free_blocks16, dim3(grid_for(threads, 256)), dim3(256), 0, s, m);
     return hipGetLastError();
 }
