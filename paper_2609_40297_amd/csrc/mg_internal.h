@@ -48,7 +48,7 @@ __device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bo
     uint32_t fb = 0u, ub = 0u;          // per byte: free, unknown
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t s = (uint32_t)(s8 >> (8 * k));
+        const uint32_t s = (uint32_t)(s8 >> (8 * k)) & 0xffu;
         fb |= (s == kFree ? 1u : 0u) << k;
         ub |= (s == kUnknown ? 1u : 0u) << k;
     }
