@@ -122,6 +122,15 @@ int mg_map_update(mg_map map, void* hip_stream, const uint32_t* voxel_ids, const
  * enqueued on hip_stream. */
 int mg_map_read(mg_map map, void* hip_stream, uint8_t* states);
 
+/* Diagnostic: the map's bytes as the traversal reads them, in the layout of
+ * mg_map_read: bits 0-1 the state, bits 2-4 of an unknown or free voxel the
+ * level of the largest aligned block around it that holds its state only and
+ * lies inside the grid (1: 16x16x16, free voxels only; 2: its 8x8x8 brick;
+ * 3: its 4x4x4 quarter brick; 4: its 2x2x2 block, free voxels only; 0: none).
+ * The marks let the traversal cross such a block in one step; they are kept
+ * current by every write of the states. */
+int mg_map_read_marked(mg_map map, void* hip_stream, uint8_t* bytes);
+
 /* Candidate tree (Sec. III-A: nodes with positions; Sec. IV-D: the whole tree
  * is built first, then evaluated).
  *   pos_m: HOST array [n][3] in metres; parent: HOST array [n] with

@@ -514,6 +514,15 @@ extern "C" int mg_map_read(mg_map map, void* hip_stream, uint8_t* states) {
     return MG_OK;
 }
 
+extern "C" int mg_map_read_marked(mg_map map, void* hip_stream, uint8_t* bytes) {
+    if (!map || !bytes) return fail(MG_E_INVALID, "map/bytes is NULL");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != map->device) return fail(MG_E_INVALID, "the map lives on another device");
+    HIP_TRY(launch_unbrick(map->dev, bytes, (hipStream_t)hip_stream, true));
+    return MG_OK;
+}
+
 extern "C" int mg_map_destroy(mg_map map) {
     if (!map) return fail(MG_E_INVALID, "map is NULL");
     if (map->trees.load() != 0)

@@ -232,7 +232,7 @@ hipError_t launch_tsdf_box(const float* dist, const float* weight, const MapDev&
                            const int32_t size[3], float surface, float min_weight, hipStream_t s);
 hipError_t launch_map_scatter(const uint32_t* ids, const uint8_t* states, uint32_t count, const MapDev& m,
                               uint32_t* rejected, hipStream_t s);
-hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s);
+hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s, bool marks = false);
 hipError_t launch_fill_outside(const MapDev& m, hipStream_t s);
 // Recomputes brick_unk and the block marks from the states (after any write
 // of the states): the bricks' summaries, then the 16x16x16 free blocks.

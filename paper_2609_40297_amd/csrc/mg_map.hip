@@ -150,13 +150,13 @@ __global__ void k_map_scatter(const uint32_t* __restrict__ ids, const uint8_t* _
 }
 
 // Dense x-fastest copy of the grid's states.
-__global__ void k_unbrick(const uint8_t* __restrict__ bricks, MapDev m, uint8_t* __restrict__ dense) {
+__global__ void k_unbrick(const uint8_t* __restrict__ bricks, MapDev m, uint8_t* __restrict__ dense, uint32_t keep) {
     const size_t nxy = (size_t)m.nx * (size_t)m.ny;
     const size_t nvox = nxy * (size_t)m.nz;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nvox; i += (size_t)gridDim.x * blockDim.x) {
         const int32_t x = (int32_t)(i % (size_t)m.nx), y = (int32_t)((i / (size_t)m.nx) % (size_t)m.ny);
         const int32_t z = (int32_t)(i / nxy);
-        dense[i] = bricks[voxel_addr(x, y, z, m)] & 3u;     // (without the whole-brick marks)
+        dense[i] = bricks[voxel_addr(x, y, z, m)] & keep;   // (the state, or the state with its block mark)
     }
 }
 
@@ -213,9 +213,9 @@ hipError_t launch_map_scatter(const uint32_t* ids, const uint8_t* states, uint32
     return hipGetLastError();
 }
 
-hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s) {
+hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s, bool marks) {
     const size_t nvox = (size_t)m.nx * m.ny * m.nz;
-    hipLaunchKernelGGL(k_unbrick, dim3(blocks_for(nvox)), dim3(256), 0, s, m.bricks, m, dense);
+    hipLaunchKernelGGL(k_unbrick, dim3(blocks_for(nvox)), dim3(256), 0, s, m.bricks, m, dense, marks ? 0xffu : 3u);
     return hipGetLastError();
 }
 

@@ -33,7 +33,8 @@ EXPORTS = ("mg_map_create", "mg_map_destroy", "mg_tree_upload", "mg_tree_destroy
            "mg_batch_plan_info", "mg_score_branches", "mg_eval_interval", "mg_interval_tables",
            "mg_interval_config", "mg_map_create_tsdf", "mg_map_update_tsdf", "mg_map_update", "mg_map_read",
            "mg_eval_exact", "mg_server_map_update", "mg_eval_exact_marginal", "mg_eval_marginal_batch_noalloc",
-           "mg_server_cancel", "mg_server_fail_request", "mg_server_pause", "mg_batch_barrier_polls")
+           "mg_server_cancel", "mg_server_fail_request", "mg_server_pause", "mg_batch_barrier_polls",
+           "mg_map_read_marked")
 
 
 class MGError(RuntimeError):
@@ -78,6 +79,7 @@ def lib() -> C.CDLL:
         L.mg_map_update_tsdf.argtypes = [P, P, P, P, P, P, C.c_float, C.c_float]
         L.mg_map_update.argtypes = [P, P, P, P, I32, P]
         L.mg_map_read.argtypes = [P, P, P]
+        L.mg_map_read_marked.argtypes = [P, P, P]
         L.mg_eval_exact.argtypes = [P, P, P, P, P, P]
         L.mg_eval_exact_marginal.argtypes = [P, P, P, P]
         L.mg_interval_config.argtypes = [I32]
@@ -350,6 +352,10 @@ def mg_map_read(m: int, states, stream=None):
     _check(lib().mg_map_read(C.c_void_p(m), _stream(stream), _dev_ptr(states)))
 
 
+def mg_map_read_marked(m: int, out, stream=None):
+    _check(lib().mg_map_read_marked(C.c_void_p(m), _stream(stream), _dev_ptr(out)))
+
+
 class Map:
     """Device-resident occupancy grid (wraps mg_map_create / mg_map_destroy)."""
 
@@ -370,6 +376,13 @@ class Map:
         import torch
         out = torch.empty(self.shape, dtype=torch.uint8, device="cuda")
         mg_map_read(self.handle, out, stream)
+        return out
+
+    def read_marked(self, stream=None):
+        """Device uint8 tensor [nz, ny, nx]: each voxel's byte with its block mark (mg_map_read_marked)."""
+        import torch
+        out = torch.empty(self.shape, dtype=torch.uint8, device="cuda")
+        mg_map_read_marked(self.handle, out, stream)
         return out
 
     def close(self):

@@ -121,3 +121,97 @@ def test_evaluation_on_converted_and_updated_maps(mg):
     assert a2[0].astype(np.int64).sum() < a[0].astype(np.int64).sum()      # less left unknown
     for M in (Mt, Mu, M2):
         M.close()
+
+
+# ----------------------------------------------------------------- block marks
+
+def _expected_marks(st):
+    """The bytes mg_map_read_marked should return for states st [nz, ny, nx]: every unknown or
+    free voxel carries the level of the largest aligned block around it that lies inside the grid
+    and holds its state only (1: 16 voxels a side, free only; 2: 8; 3: 4; 4: 2, free only)."""
+    nz, ny, nx = st.shape
+    level = np.zeros(st.shape, np.uint8)
+    for edge, lv, states in ((2, 4, (W.FREE,)), (4, 3, (W.UNK, W.FREE)), (8, 2, (W.UNK, W.FREE)), (16, 1, (W.FREE,))):
+        bz, by, bx = nz // edge, ny // edge, nx // edge
+        if min(bz, by, bx) == 0:
+            continue
+        blocks = st[:bz * edge, :by * edge, :bx * edge].reshape(bz, edge, by, edge, bx, edge)
+        blocks = blocks.transpose(0, 2, 4, 1, 3, 5).reshape(bz, by, bx, -1)
+        first = blocks[..., 0]
+        uniform = (blocks == first[..., None]).all(-1) & np.isin(first, states)
+        full = np.repeat(np.repeat(np.repeat(uniform, edge, 0), edge, 1), edge, 2)
+        level[:bz * edge, :by * edge, :bx * edge][full] = lv
+    return (st | (level << 2)).astype(np.uint8)
+
+
+def _nested_states(seed, dims):
+    from tests.test_gpu_parity import _nested_block_map
+    return _nested_block_map(seed, dims).states
+
+
+@pytest.mark.parametrize("case", ["nested48", "nested37", "step", "micro"])
+def test_block_marks_are_the_largest_uniform_blocks(mg, case):
+    """Every unknown and free voxel's mark names the largest aligned uniform block around it (the
+    traversal crosses marked blocks in one step, so a missing mark costs time and a wrong one a
+    wrong gain): after the map's upload, after listed updates that break and make blocks, after a
+    whole-grid TSDF conversion."""
+    import torch
+    if case == "nested48":
+        st = _nested_states(1248, (48, 48, 34))
+    elif case == "nested37":
+        st = _nested_states(1237, (37, 29, 21))
+    elif case == "step":
+        st = W.make("step").map.states
+    else:
+        st = W.random_micro(77, dims=(21, 18, 13), n_nodes=1, range_vox=6.0)[0].states
+    st = np.ascontiguousarray(st, dtype=np.uint8)
+    log(f"[marks] {case}: {st.shape}")
+    M = mg.Map(st, 1.0, (0.0, 0.0, 0.0))
+    try:
+        got = M.read_marked().cpu().numpy()
+        exp = _expected_marks(st)
+        assert np.array_equal(got, exp), (case, int((got != exp).sum()))
+        # updates: occupied voxels into free and unknown blocks, and a freed region
+        rng = np.random.Generator(np.random.PCG64(5))
+        nz, ny, nx = st.shape
+        ids = rng.choice(st.size, size=min(200, st.size // 20), replace=False).astype(np.uint32)
+        new = rng.choice(np.array([W.UNK, W.FREE, W.OCC], np.uint8), size=ids.size)
+        z0, y0, x0 = 0, 0, 0
+        box = np.arange(st.size, dtype=np.uint32).reshape(st.shape)[z0:z0 + 16, y0:y0 + 16, x0:x0 + 16].ravel()
+        ids = np.concatenate([box, ids[~np.isin(ids, box)]])
+        new = np.concatenate([np.full(box.size, W.FREE, np.uint8), new[:ids.size - box.size]])
+        mg.mg_map_update(M.handle, torch.from_numpy(ids).cuda(), torch.from_numpy(new).cuda())
+        st2 = st.copy().reshape(-1)
+        st2[ids] = new
+        st2 = st2.reshape(st.shape)
+        got = M.read_marked().cpu().numpy()
+        assert np.array_equal(got, _expected_marks(st2)), (case, "after updates", int((got != _expected_marks(st2)).sum()))
+    finally:
+        M.close()
+
+
+def test_block_marks_after_tsdf_conversion(mg):
+    """The whole-grid conversion takes the marks in its own pass (and the 16-voxel free blocks in a
+    second): on a field of free space with box obstacles and unobserved slabs, the marks equal the
+    largest uniform blocks of the converted states."""
+    import torch
+    nx, ny, nz = 72, 64, 40
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d = np.full((nz, ny, nx), 1.0, np.float32)
+    for cx, cy, cz, r in ((20, 20, 10, 5), (50, 40, 25, 7), (10, 50, 30, 3)):
+        inside = (np.abs(x - cx) <= r) & (np.abs(y - cy) <= r) & (np.abs(z - cz) <= r)
+        d[inside] = -0.5
+    w = np.full((nz, ny, nx), 2.0, np.float32)
+    w[:, :, 56:] = 0.0                      # an unobserved slab
+    w[30:, :20, :] = 0.0
+    M = mg.Map.from_tsdf(torch.from_numpy(d).cuda(), torch.from_numpy(w).cuda(), 1.0, (0.0, 0.0, 0.0),
+                         surface_m=0.0, min_weight=1.0)
+    try:
+        st = M.read().cpu().numpy()
+        got = M.read_marked().cpu().numpy()
+        exp = _expected_marks(st)
+        assert (got & 3).tolist() == st.tolist()
+        assert np.array_equal(got, exp), int((got != exp).sum())
+        assert (exp >> 2 == 1).any() and (exp >> 2 == 2).any() and (exp >> 2 == 3).any()
+    finally:
+        M.close()
