@@ -20,6 +20,8 @@ Modes
   batched  the whole request in one call (mg_eval_marginal_batch), one copy
            of the results at the end; per depth level a trace, a window and a
            mask-builder launch on two stream groups.
+  graph    the same call with the plan's launches recorded once into a HIP
+           graph and replayed (mg_batch_config(-1, 1)).
   persistent  the same call configured as one cooperative launch per step
            (co-resident workgroups, grid barriers between the phases).
 `value` is the batched mode's rays/s; the other modes are reported beside it.
@@ -144,8 +146,9 @@ def parse():
                          "the large headline, none otherwise; 'none' skips them)")
     ap.add_argument("--requests", type=int, default=64, help="serve16: number of replanning requests")
     ap.add_argument("--trees", type=int, default=None, help="keep only the first trees of a multi-tree workload")
-    ap.add_argument("--modes", default="plain,batched,persistent",
-                    help="plain, batched (per-level launches), persistent (one cooperative launch per step)")
+    ap.add_argument("--modes", default="plain,batched,graph,persistent",
+                    help="plain, batched (per-level launches), graph (those launches replayed from a HIP graph), "
+                         "persistent (one cooperative launch per step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sp-steps", type=int, default=5, help="timed single-parent (g_sp) passes; 0 skips")
     ap.add_argument("--ivl-steps", type=int, default=3, help="timed interval-mode passes; 0 skips")
@@ -614,11 +617,12 @@ def measure(mg, W, name, steps, warmup, modes, n_trees=None):
     trace = None
     saved = None
     for mode in modes:
-        fn = {"plain": step_plain, "batched": step_batched, "persistent": step_batched}[mode]
-        if mode == "persistent":            # the same call, its plan one cooperative launch
+        fn = {"plain": step_plain, "batched": step_batched, "graph": step_batched, "persistent": step_batched}[mode]
+        if mode in ("graph", "persistent"):
+            # the same call, its plan's launches replayed from a HIP graph, or one cooperative launch
             if "batched" in results:
                 saved = (host_g.numpy().copy(), host_y.numpy().copy())
-            mg.mg_batch_config(-1, 2)
+            mg.mg_batch_config(-1, 1 if mode == "graph" else 2)
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -643,10 +647,10 @@ def measure(mg, W, name, steps, warmup, modes, n_trees=None):
                              p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                              kernel_ms=float(np.mean(kernel_ms)) if kernel_ms else None)
         log(f"[bench] {name} {mode}: {results[mode]}")
-        if mode == "persistent":
+        if mode in ("graph", "persistent"):
             if saved is not None:
-                assert np.array_equal(saved[0], host_g.numpy()), "batched and persistent differ"
-                assert np.array_equal(saved[1], host_y.numpy()), "batched and persistent differ"
+                assert np.array_equal(saved[0], host_g.numpy()), f"batched and {mode} differ"
+                assert np.array_equal(saved[1], host_y.numpy()), f"batched and {mode} differ"
             mg.mg_batch_config(-1, 0)
             if "batched" in results:
                 step_batched()              # the default plan again (its shape is cached)

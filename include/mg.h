@@ -125,7 +125,7 @@ int mg_map_read(mg_map map, void* hip_stream, uint8_t* states);
 /* Diagnostic: the map's bytes as the traversal reads them, in the layout of
  * mg_map_read: bits 0-1 the state, bits 2-4 of an unknown or free voxel the
  * level of the largest aligned block around it that holds its state only and
- * lies inside the grid (1: 16x16x16, free voxels only; 2: its 8x8x8 brick;
+ * lies inside the grid (1: 16x16x16; 2: its 8x8x8 brick;
  * 3: its 4x4x4 quarter brick; 4: its 2x2x2 block, free voxels only; 0: none).
  * The marks let the traversal cross such a block in one step; they are kept
  * current by every write of the states. */

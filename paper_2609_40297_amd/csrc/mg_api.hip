@@ -399,6 +399,7 @@ int map_alloc(int32_t nx, int32_t ny, int32_t nz, float voxel_m, const float ori
     m->dev.mby = (uint32_t)(ny + 7) / 8u;
     m->dev.mbz = (uint32_t)(nz + 7) / 8u;
     m->dev.mask_words = 16u * m->dev.mbx * m->dev.mby * m->dev.mbz;    // < 2^32 / 32 (voxels < 2^32)
+    m->dev.build_slots = 8u * ((m->dev.mbx + 1u) / 2u) * ((m->dev.mby + 1u) / 2u) * ((m->dev.mbz + 1u) / 2u);
     m->dev.brick_unk = m->bricks + padded;
     m->voxel_m = voxel_m;
     for (int a = 0; a < 3; ++a) m->origin[a] = origin_m[a];

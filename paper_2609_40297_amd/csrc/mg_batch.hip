@@ -38,7 +38,7 @@ struct Plan {
     const BatchTree* dtrees = nullptr;
     const unsigned long long* ditems = nullptr;
     const unsigned long long* dmitems = nullptr;
-    uint32_t mask_bricks = 0;              // bricks of the largest path mask among the trees
+    uint32_t mask_bricks = 0;              // build slots of the largest map among the trees
     // Launch records in host order: stream 0 is the caller's (the shared
     // prefix of levels), stream g + 1 runs group g. [mbegin, mbegin + mcount)
     // are the launch's nodes with children (their path masks are built).
@@ -134,7 +134,7 @@ int build_plan(const std::vector<mg_tree>& trees, uint32_t* gain, int32_t* yaw, 
             return mgb::set_error(MG_E_UNSUPPORTED, "batch has 2^31 nodes or more");
         P->total += (uint32_t)v.n;
         P->max_nodes = std::max(P->max_nodes, (uint32_t)v.n);
-        P->mask_bricks = std::max(P->mask_bricks, v.map->mask_words >> 4);
+        P->mask_bricks = std::max(P->mask_bricks, v.map->build_slots);
         levels = std::max(levels, v.levels);
     }
     P->sd = *v0.sd;

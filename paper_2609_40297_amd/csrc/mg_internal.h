@@ -20,10 +20,10 @@ constexpr int kTileRows = 4;       // by 4 rows
 // has left the grid. The low two bits of a byte are the state, and bit 1 set
 // (kOccupied, kOutside) ends a traversal. Bits 2-4 of an unknown or a free
 // voxel name the largest aligned block around it that holds that state only
-// (the traversal may cross such a block in one step): 1 (free voxels only)
-// its 16x16x16 block of 8 bricks, 2 its 8x8x8 brick (kUnknownBrick,
-// kFreeBrick), 3 its 4x4x4 quarter brick, 4 (free voxels only) its 2x2x2
-// block, 0 none; the block's edge is 32 >> level voxels.
+// (the traversal may cross such a block in one step): 1 its 16x16x16 block
+// of 8 bricks, 2 its 8x8x8 brick (kUnknownBrick, kFreeBrick), 3 its 4x4x4
+// quarter brick, 4 (free voxels only) its 2x2x2 block, 0 none; the block's
+// edge is 32 >> level voxels.
 enum : uint8_t { kUnknown = 0, kFree = 1, kOccupied = 2, kOutside = 3, kUnknownBrick = 8, kFreeBrick = 9 };
 constexpr uint32_t kLevelShift = 2, kLevelMask = 7;
 __host__ __device__ inline bool is_unknown(uint32_t s) { return (s & 3u) == 0u; }
@@ -89,7 +89,8 @@ __device__ __forceinline__ uint64_t mark_brick_row(uint64_t v, uint32_t lane, bo
 enum : uint8_t { kMaskMixed = 0, kMaskNone = 1, kMaskAll = 2 };
 // A brick's code word: bits 0-1 the code of its 512 bits, bits 2 + 2q and
 // 3 + 2q the code of its quarter q (the 4x4x4 voxels with (x & 4, y & 4, z & 4)
-// = 4 * (q & 1, (q >> 1) & 1, q >> 2)).
+// = 4 * (q & 1, (q >> 1) & 1, q >> 2)), bits 18-19 the code of its block of
+// 2x2x2 bricks when those are all wholly unknown (else mixed).
 __host__ __device__ inline uint32_t uniform_code_word(uint32_t c) { return c * 0x15555u; }
 // brick_unk values (bits 0-1): no unknown voxel, some, all 512 (the
 // kUnknownBrick marks); bit 2 (kBrickAllFree) set when all 512 are free
@@ -116,6 +117,9 @@ struct MapDev {
     // the grid, ceil(n / 8), and 32-bit words per mask (16 per brick).
     uint32_t mbx, mby, mbz;
     uint32_t mask_words;
+    // The mask builder visits bricks by blocks of 2x2x2 (ceil(mb / 2) blocks per
+    // axis, x fastest; in a block x, then y, then z): slots = 8 * blocks.
+    uint32_t build_slots;
     // [mbx * mby * mbz] per mask brick: kBrickKnown, kBrickSomeUnknown or
     // kBrickAllUnknown, with kBrickAllFree (kept current, with the block
     // marks, by every write of the map's states)
@@ -235,10 +239,10 @@ hipError_t launch_map_scatter(const uint32_t* ids, const uint8_t* states, uint32
 hipError_t launch_unbrick(const MapDev& m, uint8_t* dense, hipStream_t s, bool marks = false);
 hipError_t launch_fill_outside(const MapDev& m, hipStream_t s);
 // Recomputes brick_unk and the block marks from the states (after any write
-// of the states): the bricks' summaries, then the 16x16x16 free blocks.
+// of the states): the bricks' summaries, then the 16x16x16 blocks.
 hipError_t launch_brick_flags(const MapDev& m, hipStream_t s);
-// The 16x16x16 free blocks alone (after a conversion that took the bricks' summaries itself).
-hipError_t launch_free_blocks16(const MapDev& m, hipStream_t s);
+// The 16x16x16 blocks alone (after a conversion that took the bricks' summaries itself).
+hipError_t launch_blocks16(const MapDev& m, hipStream_t s);
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
                         int32_t n_nodes, bool marginal, hipStream_t s);
 // Path masks of the listed nodes (all with children), after their windows are chosen.
@@ -264,7 +268,7 @@ hipError_t launch_batch_zero(const BatchTree* trees, int32_t n_trees, uint32_t m
 // selection, then the path masks of the level's nodes with children
 // (`mitems`, a subset of `items`). t0/t1 and b0/b1 (may be null): events the
 // trace and the builder dispatches themselves record at their start and end.
-// mask_bricks: bricks of the largest path mask among the launch's trees.
+// mask_bricks: build slots (MapDev::build_slots) of the largest map among the launch's trees.
 hipError_t launch_batch_level(const BatchTree* trees, const unsigned long long* items, int32_t n_items,
                               const unsigned long long* mitems, int32_t n_mitems, uint32_t mask_bricks,
                               const SensorDev& sd, hipStream_t s, int shape = 0, hipEvent_t t0 = nullptr,

@@ -78,15 +78,18 @@ __global__ void k_brick_flags(MapDev m) {
     }
 }
 
-// 16x16x16 free blocks, after the bricks' summaries: a brick whose aligned
-// block of 2x2x2 bricks lies in the grid's bricks and holds only wholly free
-// bricks has its voxels marked at level 1. One thread per brick; the few
-// bricks of such blocks are written by their thread, 16 bytes at a time.
-__global__ void k_free_blocks16(MapDev m) {
+// 16x16x16 blocks, after the bricks' summaries: a brick whose aligned block
+// of 2x2x2 bricks lies in the grid's bricks and holds only wholly free (or
+// only wholly unknown) bricks has its voxels marked at level 1. One thread per
+// brick; the few bricks of such blocks are written by their thread, 16 bytes
+// at a time.
+__global__ void k_blocks16(MapDev m) {
     const uint32_t nb = m.mask_words >> 4;
     uint8_t* grid = const_cast<uint8_t*>(m.bricks);
     for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
-        if (!(m.brick_unk[b] & kBrickAllFree)) continue;
+        const uint32_t own = m.brick_unk[b];
+        const bool free_b = (own & kBrickAllFree) != 0, unk_b = (own & 3u) == kBrickAllUnknown;
+        if (!free_b && !unk_b) continue;
         const uint32_t bx = b % m.mbx, by = (b / m.mbx) % m.mby, bz = b / (m.mbx * m.mby);
         const uint32_t x0 = bx & ~1u, y0 = by & ~1u, z0 = bz & ~1u;
         if (x0 + 1u >= m.mbx || y0 + 1u >= m.mby || z0 + 1u >= m.mbz) continue;
@@ -94,11 +97,12 @@ __global__ void k_free_blocks16(MapDev m) {
 #pragma unroll
         for (uint32_t k = 0; k < 8; ++k) {
             const uint32_t n = (x0 + (k & 1u)) + m.mbx * ((y0 + ((k >> 1) & 1u)) + m.mby * (z0 + (k >> 2)));
-            all = all && (m.brick_unk[n] & kBrickAllFree) != 0;
+            const uint32_t s = m.brick_unk[n];
+            all = all && (free_b ? (s & kBrickAllFree) != 0 : (s & 3u) == kBrickAllUnknown);
         }
         if (!all) continue;
         const uint32_t base = voxel_addr((int32_t)(bx * 8u), (int32_t)(by * 8u), (int32_t)(bz * 8u), m);
-        const uint32_t w = (kFree | (1u << kLevelShift)) * 0x01010101u;
+        const uint32_t w = ((free_b ? kFree : kUnknown) | (1u << kLevelShift)) * 0x01010101u;
         uint4* p = reinterpret_cast<uint4*>(grid + base);        // (a brick is 512 contiguous, aligned bytes)
         for (int k = 0; k < 32; ++k) p[k] = make_uint4(w, w, w, w);
     }
@@ -135,8 +139,8 @@ struct Shape {
 constexpr Shape kShapes[] = {{256, 64}, {128, 64}, {512, 64}, {256, 128}, {256, 32}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMaxBuildBricks = 128;
-// the builder's fixed LDS beside its tables: a flag byte and a code word per brick, and a word
-constexpr size_t kBuildFixedLds = (size_t)kMaxBuildBricks * 5u + 16u;
+// the builder's fixed LDS beside its tables: a flag byte, a code word and a brick index per slot, and a word
+constexpr size_t kBuildFixedLds = (size_t)kMaxBuildBricks * 9u + 16u;
 constexpr int kBuildThreads = 256;
 
 struct TableLDS {
@@ -251,14 +255,19 @@ __device__ int brick_view(const SensorDev& S, const float* __restrict__ tm, floa
 // brick of the chunk is tested. One wave tests one brick: each lane one (x, y)
 // column of 8 voxels. Whole workgroup; chunks past the map's last brick do
 // nothing (a batch launch covers its largest map).
+__device__ __forceinline__ void build_live(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
+                                           const WindowGeom& A, float4 q, const uint32_t* par, uint32_t* out,
+                                           char* smem, const uint8_t* s_live, uint32_t* s_cw, const uint32_t* s_b,
+                                           int32_t cnt);
+
 __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
                                             int32_t chunk, int32_t bricks, char* smem, uint8_t* s_live,
-                                            uint32_t* s_cw, int32_t* s_any) {
+                                            uint32_t* s_cw, uint32_t* s_b, int32_t* s_any) {
     const int32_t tid = threadIdx.x;
     const int32_t slot = Tr.mask_slot[node];
     const uint32_t nb = M.mask_words >> 4;
-    const uint32_t lo = (uint32_t)chunk * (uint32_t)bricks;
-    if (slot < 0 || lo >= nb) return;                        // a leaf (nothing reads its mask), or past the map
+    const uint32_t lo = (uint32_t)chunk * (uint32_t)bricks;  // first build slot (bricks is a multiple of 8)
+    if (slot < 0 || lo >= M.build_slots) return;             // a leaf (nothing reads its mask), or past the map
     uint32_t* out = Tr.masks + (size_t)slot * M.mask_words;
     const int32_t a0 = Tr.anc_ptr[node];
     const uint32_t* par = nullptr;
@@ -276,13 +285,24 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     A.qx = q.x; A.qy = q.y; A.qz = q.z; A.c0 = c0;
     const float2 b0 = S.bv[c0], b1 = S.bv[c1];
     A.b0x = b0.x; A.b0y = b0.y; A.b1x = b1.x; A.b1y = b1.y;
-    const int32_t cnt = (int32_t)min((uint32_t)bricks, nb - lo);
+    const int32_t cnt = bricks;
     if (tid == 0) *s_any = 0;
+    // The chunk's slots, a block of 2x2x2 bricks per 8 slots: s_b holds each slot's
+    // brick (~0 for a slot past the grid's bricks).
+    const uint32_t mbx2 = (M.mbx + 1u) >> 1, mby2 = (M.mby + 1u) >> 1;
+    if (tid < cnt) {
+        const uint32_t sl = lo + (uint32_t)tid, blk = sl >> 3, j = sl & 7u;
+        const uint32_t bx = 2u * (blk % mbx2) + (j & 1u), by = 2u * ((blk / mbx2) % mby2) + ((j >> 1) & 1u),
+                       bz = 2u * (blk / (mbx2 * mby2)) + (j >> 2);
+        s_b[tid] = (bx < M.mbx && by < M.mby && bz < M.mbz) ? bx + M.mbx * (by + M.mby * bz) : ~0u;
+    }
     __syncthreads();
     // per brick of the chunk (s_live): bit 4 live, bits 2-3 its brick_unk value,
-    // bits 0-1 the parent's code (kMaskNone at the root)
-    if (tid < cnt) {
-        const uint32_t b = lo + (uint32_t)tid;
+    // bits 0-1 the parent's code (kMaskNone at the root); a slot past the grid's
+    // bricks holds no unknown voxel
+    if (tid < cnt && s_b[tid] == ~0u) s_live[tid] = (uint8_t)(kBrickKnown << 2);
+    if (tid < cnt && s_b[tid] != ~0u) {
+        const uint32_t b = s_b[tid];
         const uint32_t bx = b % M.mbx, by = (b / M.mbx) % M.mby, bz = b / (M.mbx * M.mby);
         const float rx = (float)(bx * 8u) + 4.0f - q.x, ry = (float)(by * 8u) + 4.0f - q.y,
                     rz = (float)(bz * 8u) + 4.0f - q.z;
@@ -314,14 +334,41 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         const uint32_t f = s_live[w >> 4];
         const uint32_t pc = f & 3u, bu = (f >> 2) & 3u;
         if ((f & 16u) || bu == kBrickKnown || (bu == kBrickAllUnknown && pc != kMaskMixed)) continue;
-        out[lo * 16u + (uint32_t)w] = pc == kMaskMixed ? par[lo * 16u + (uint32_t)w] : (pc == kMaskAll ? ~0u : 0u);
+        const uint32_t wi = s_b[w >> 4] * 16u + (uint32_t)(w & 15);
+        out[wi] = pc == kMaskMixed ? par[wi] : (pc == kMaskAll ? ~0u : 0u);
     }
     uint32_t* code = Tr.mcode + (size_t)slot * nb;
+    if (*s_any) build_live(M, S, Tr, node, A, q, par, out, smem, s_live, s_cw, s_b, cnt);
+    __syncthreads();
+    // Code words of the chunk's bricks that hold an unknown voxel, with the code
+    // of their block of 2x2x2 bricks (bits 18-19): uniform when the block's 8
+    // bricks are all wholly unknown and their codes all clear or all set.
     if (tid < cnt) {
         const uint32_t f = s_live[tid];
-        if (!(f & 16u) && ((f >> 2) & 3u) != kBrickKnown) code[lo + (uint32_t)tid] = s_cw[tid];
+        if (((f >> 2) & 3u) != kBrickKnown) {
+            const int32_t g = tid & ~7;
+            uint32_t all_none = 1u, all_set = 1u;
+#pragma unroll
+            for (int32_t k = 0; k < 8; ++k) {
+                const uint32_t fk = s_live[g + k], ck = s_cw[g + k] & 3u;
+                const bool unk = ((fk >> 2) & 3u) == kBrickAllUnknown;
+                all_none &= (unk && ck == kMaskNone) ? 1u : 0u;
+                all_set &= (unk && ck == kMaskAll) ? 1u : 0u;
+            }
+            const uint32_t bc = all_none ? (uint32_t)kMaskNone : (all_set ? (uint32_t)kMaskAll : (uint32_t)kMaskMixed);
+            code[s_b[tid]] = (s_cw[tid] & 0x3ffffu) | (bc << 18);
+        }
     }
-    if (!*s_any) return;
+}
+
+// The live bricks of a chunk (build_chunk): one wave tests one brick, each lane
+// one (x, y) column of 8 voxels; the brick's code word goes to s_cw.
+__device__ __forceinline__ void build_live(const MapDev& M, const SensorDev& S, const TreeDev& Tr, int32_t node,
+                                           const WindowGeom& A, float4 q, const uint32_t* par, uint32_t* out,
+                                           char* smem, const uint8_t* s_live, uint32_t* s_cw, const uint32_t* s_b,
+                                           int32_t cnt) {
+    const int32_t tid = threadIdx.x;
+    const int32_t c0 = A.c0;
     const TableLDS L = carve_tables(smem, S);
     load_tables(L, S, c0);
     __syncthreads();
@@ -333,7 +380,7 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     for (int32_t i = wave; i < cnt; i += (int32_t)(blockDim.x >> 6)) {
         const uint32_t f = s_live[i];
         if (!(f & 16u)) continue;
-        const uint32_t b = lo + (uint32_t)i;
+        const uint32_t b = s_b[i];
         const int32_t bx = (int32_t)(b % M.mbx), by = (int32_t)((b / M.mbx) % M.mby), bz = (int32_t)(b / (M.mbx * M.mby));
         const int32_t x = bx * 8 + (lane & 7), y = by * 8 + (lane >> 3);
         const float cx = (float)x + 0.5f, cy = (float)y + 0.5f;
@@ -455,7 +502,7 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
             const uint32_t qc = (nz & lq) == 0ull ? (uint32_t)kMaskNone : ((nf & lq) == 0ull ? (uint32_t)kMaskAll : (uint32_t)kMaskMixed);
             cw |= qc << (2u + 2u * qd);
         }
-        if (lane == 0) code[b] = cw;
+        if (lane == 0) s_cw[i] = cw;
     }
 }
 
@@ -465,8 +512,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build(MapDev M, SensorDe
     extern __shared__ char smem[];
     __shared__ uint8_t s_live[kMaxBuildBricks];
     __shared__ uint32_t s_cw[kMaxBuildBricks];
+    __shared__ uint32_t s_b[kMaxBuildBricks];
     __shared__ int32_t s_any;
-    build_chunk(M, S, Tr, nodes[blockIdx.x / chunks], (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, s_cw, &s_any);
+    build_chunk(M, S, Tr, nodes[blockIdx.x / chunks], (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, s_cw, s_b, &s_any);
 }
 
 // ---------------------------------------------------------------- ray traversal
@@ -584,13 +632,12 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 pend = false;
             }
             h = st == kOccupied ? t : h;
-            // An aligned block (for free voxels a block of 2x2x2 bricks, a brick,
-            // a quarter brick or a 2x2x2 block; for unknown voxels a brick or a
-            // quarter brick) whose voxels are all free, or all unknown with the
-            // parent's mask uniform over it (every bit clear or every bit set; a
-            // wholly unknown brick over which the mask is mixed is crossed a
-            // quarter at a time where it is uniform over the quarter), is crossed
-            // in one step: it is left through the face whose
+            // An aligned block (a block of 2x2x2 bricks, a brick, a quarter brick
+            // or, for free voxels, a 2x2x2 block) whose voxels are all free, or
+            // all unknown with the parent's mask uniform over it (every bit clear
+            // or every bit set; a wholly unknown block over which the mask is
+            // mixed is crossed a brick or a quarter at a time where it is uniform
+            // over that), is crossed in one step: it is left through the face whose
             // boundary parameter comes first (ties x, y, z) and every other axis
             // has crossed the boundaries that come before that crossing in the
             // same order. The voxels crossed are one per crossing; crossing an
@@ -616,11 +663,14 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                         cw = pc[b];
                         cb_idx = b;
                     }
-                    // the brick's code, else its quarter's (a quarter block at most)
+                    // the code of its block of 2x2x2 bricks (a 16-voxel block), else the
+                    // brick's (a brick at most), else its quarter's (a quarter at most)
                     const uint32_t qs = 2u + ((((uint32_t)ix >> 1) & 2u) | ((uint32_t)iy & 4u) | (((uint32_t)iz << 1) & 8u));
+                    const uint32_t bc = (cw >> 18) & 3u;
+                    const bool block_uniform = (level == 1u) & (bc != kMaskMixed);
                     const bool brick_uniform = (cw & 3u) != kMaskMixed;
-                    code = brick_uniform ? (cw & 3u) : ((cw >> qs) & 3u);
-                    level = brick_uniform ? level : 3u;
+                    code = block_uniform ? bc : (brick_uniform ? (cw & 3u) : ((cw >> qs) & 3u));
+                    level = block_uniform ? 1u : (brick_uniform ? (level > 2u ? level : 2u) : 3u);
                 }
                 by_code = code != kMaskMixed;
                 cand = by_code;
@@ -846,6 +896,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchT
     extern __shared__ char smem[];
     __shared__ uint8_t s_live[kMaxBuildBricks];
     __shared__ uint32_t s_cw[kMaxBuildBricks];
+    __shared__ uint32_t s_b[kMaxBuildBricks];
     __shared__ int32_t s_any;
     const unsigned long long it = items[blockIdx.x / chunks];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
@@ -855,7 +906,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchT
     St.rv2 = BT.rv2;
     const MapDev M = BT.map;
     const TreeDev Tr = BT.td;
-    build_chunk(M, St, Tr, (int32_t)(uint32_t)it, (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, s_cw, &s_any);
+    build_chunk(M, St, Tr, (int32_t)(uint32_t)it, (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, s_cw, s_b, &s_any);
 }
 
 // Window selection of one (tree, node) item of a batch: gain, window, the
@@ -950,6 +1001,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
     __shared__ unsigned long long s_best[kThreads / 64];
     __shared__ uint8_t s_live[kMaxBuildBricks];
     __shared__ uint32_t s_cw[kMaxBuildBricks];
+    __shared__ uint32_t s_b[kMaxBuildBricks];
     __shared__ int32_t s_any, s_ok;
     uint32_t target = 0;
     const uint32_t G = gridDim.x;
@@ -990,7 +1042,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
                 St.rv2 = BT.rv2;
                 const MapDev M = BT.map;
                 const TreeDev Tr = BT.td;
-                build_chunk(M, St, Tr, (int32_t)(uint32_t)it, chunk, bricks, smem, s_live, s_cw, &s_any);
+                build_chunk(M, St, Tr, (int32_t)(uint32_t)it, chunk, bricks, smem, s_live, s_cw, s_b, &s_any);
             }
             __syncthreads();
         }
@@ -1029,12 +1081,12 @@ hipError_t launch_brick_flags(const MapDev& m, hipStream_t s) {
     const size_t threads = (size_t)(m.mask_words >> 4) * 64u;
     hipLaunchKernelGGL(k_brick_flags, dim3(grid_for(threads, 256)), dim3(256), 0, s, m);
     const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? launch_free_blocks16(m, s) : e;
+    return e == hipSuccess ? launch_blocks16(m, s) : e;
 }
 
-hipError_t launch_free_blocks16(const MapDev& m, hipStream_t s) {
+hipError_t launch_blocks16(const MapDev& m, hipStream_t s) {
     const size_t threads = (size_t)(m.mask_words >> 4);
-    hipLaunchKernelGGL(k_free_blocks16, dim3(grid_for(threads, 256)), dim3(256), 0, s, m);
+    hipLaunchKernelGGL(k_blocks16, dim3(grid_for(threads, 256)), dim3(256), 0, s, m);
     return hipGetLastError();
 }
 
@@ -1082,7 +1134,7 @@ hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td,
 }
 
 static int32_t build_chunks(const MapDev& m, int32_t bricks) {
-    return (int32_t)(((m.mask_words >> 4) + (uint32_t)bricks - 1) / (uint32_t)bricks);
+    return (int32_t)((m.build_slots + (uint32_t)bricks - 1) / (uint32_t)bricks);
 }
 
 hipError_t launch_mask_build(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,

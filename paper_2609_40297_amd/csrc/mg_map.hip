@@ -193,7 +193,7 @@ hipError_t launch_tsdf_grid(const float* dist, const float* weight, const MapDev
         hipLaunchKernelGGL(k_tsdf_grid, grid, dim3(256), 0, s, dist, weight, (uint8_t*)m.bricks, m, surface,
                            min_weight);
     const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? launch_free_blocks16(m, s) : e;       // (the bricks' summaries are taken above)
+    return e == hipSuccess ? launch_blocks16(m, s) : e;            // (the bricks' summaries are taken above)
 }
 
 hipError_t launch_tsdf_box(const float* dist, const float* weight, const MapDev& m, const int32_t lo[3],

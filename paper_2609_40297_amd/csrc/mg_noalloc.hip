@@ -105,7 +105,7 @@ extern "C" int mg_eval_marginal_batch_noalloc(const mg_tree* trees, int32_t n_tr
         total += (uint64_t)v.n;
         total_m += (uint64_t)v.mask_nodes->size();
         max_nodes = std::max(max_nodes, (uint32_t)v.n);
-        mask_bricks = std::max(mask_bricks, v.map->mask_words >> 4);
+        mask_bricks = std::max(mask_bricks, v.map->build_slots);
     }
     if (total >= (1ull << 31)) return mgb::set_error(MG_E_UNSUPPORTED, "batch has 2^31 nodes or more");
     const size_t o_items = align256(sizeof(BatchTree) * (size_t)n_trees);

@@ -359,7 +359,7 @@ int mg_server_s::step() {
     for (Request* r : active) {
         n_items += (size_t)((*r->level_ptr)[r->level + 1] - (*r->level_ptr)[r->level]);
         n_mitems += (size_t)((*r->mask_level_ptr)[r->level + 1] - (*r->mask_level_ptr)[r->level]);
-        mask_bricks = std::max(mask_bricks, mgb::map_dev(r->map)->mask_words >> 4);
+        mask_bricks = std::max(mask_bricks, mgb::map_dev(r->map)->build_slots);
         if (r->level + 1 == r->levels) stage += 2 * (size_t)r->n;
     }
     int rc = grow(active.size(), n_items + n_mitems, stage);

@@ -128,10 +128,10 @@ def test_evaluation_on_converted_and_updated_maps(mg):
 def _expected_marks(st):
     """The bytes mg_map_read_marked should return for states st [nz, ny, nx]: every unknown or
     free voxel carries the level of the largest aligned block around it that lies inside the grid
-    and holds its state only (1: 16 voxels a side, free only; 2: 8; 3: 4; 4: 2, free only)."""
+    and holds its state only (1: 16 voxels a side; 2: 8; 3: 4; 4: 2, free only)."""
     nz, ny, nx = st.shape
     level = np.zeros(st.shape, np.uint8)
-    for edge, lv, states in ((2, 4, (W.FREE,)), (4, 3, (W.UNK, W.FREE)), (8, 2, (W.UNK, W.FREE)), (16, 1, (W.FREE,))):
+    for edge, lv, states in ((2, 4, (W.FREE,)), (4, 3, (W.UNK, W.FREE)), (8, 2, (W.UNK, W.FREE)), (16, 1, (W.UNK, W.FREE))):
         bz, by, bx = nz // edge, ny // edge, nx // edge
         if min(bz, by, bx) == 0:
             continue

@@ -146,8 +146,8 @@ def _nested_block_map(seed, dims):
         u = rng.uniform()
         if u < 0.3:
             return
-        if e == 16:
-            u = 0.6                                  # (no wholly unknown 16-voxel blocks: split)
+        if e == 16 and u >= 0.45:
+            u = 0.6                                  # (16-voxel blocks: wholly free, wholly unknown or split)
         if u < 0.55:
             sl[...] = W.UNK
             return
