@@ -136,9 +136,9 @@ __device__ __forceinline__ bool left_of(float2 b, float rx, float ry) { return b
 struct Shape {
     int threads, bricks;
 };
-constexpr Shape kShapes[] = {{256, 64}, {128, 64}, {512, 64}, {256, 128}, {256, 32}, {256, 256}, {128, 128}, {128, 256}, {512, 128}};
+constexpr Shape kShapes[] = {{256, 64}, {128, 64}, {512, 64}, {256, 128}, {256, 32}, {256, 256}, {128, 128}, {128, 256}, {512, 128}, {128, 512}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-constexpr int kMaxBuildBricks = 256;
+constexpr int kMaxBuildBricks = 512;
 // the builder's fixed LDS beside its tables: a flag byte, a code word and a brick index per slot, and a word
 constexpr size_t kBuildFixedLds = (size_t)kMaxBuildBricks * 9u + 16u;
 constexpr int kBuildThreads = 256;
@@ -290,19 +290,22 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     // The chunk's slots, a block of 2x2x2 bricks per 8 slots: s_b holds each slot's
     // brick (~0 for a slot past the grid's bricks).
     const uint32_t mbx2 = (M.mbx + 1u) >> 1, mby2 = (M.mby + 1u) >> 1;
-    if (tid < cnt) {
-        const uint32_t sl = lo + (uint32_t)tid, blk = sl >> 3, j = sl & 7u;
+    for (int32_t i = tid; i < cnt; i += (int32_t)blockDim.x) {
+        const uint32_t sl = lo + (uint32_t)i, blk = sl >> 3, j = sl & 7u;
         const uint32_t bx = 2u * (blk % mbx2) + (j & 1u), by = 2u * ((blk / mbx2) % mby2) + ((j >> 1) & 1u),
                        bz = 2u * (blk / (mbx2 * mby2)) + (j >> 2);
-        s_b[tid] = (bx < M.mbx && by < M.mby && bz < M.mbz) ? bx + M.mbx * (by + M.mby * bz) : ~0u;
+        s_b[i] = (bx < M.mbx && by < M.mby && bz < M.mbz) ? bx + M.mbx * (by + M.mby * bz) : ~0u;
     }
     __syncthreads();
     // per brick of the chunk (s_live): bit 4 live, bits 2-3 its brick_unk value,
     // bits 0-1 the parent's code (kMaskNone at the root); a slot past the grid's
     // bricks holds no unknown voxel
-    if (tid < cnt && s_b[tid] == ~0u) s_live[tid] = (uint8_t)(kBrickKnown << 2);
-    if (tid < cnt && s_b[tid] != ~0u) {
-        const uint32_t b = s_b[tid];
+    for (int32_t i = tid; i < cnt; i += (int32_t)blockDim.x) {
+        const uint32_t b = s_b[i];
+        if (b == ~0u) {
+            s_live[i] = (uint8_t)(kBrickKnown << 2);
+            continue;
+        }
         const uint32_t bx = b % M.mbx, by = (b / M.mbx) % M.mby, bz = b / (M.mbx * M.mby);
         const float rx = (float)(bx * 8u) + 4.0f - q.x, ry = (float)(by * 8u) + 4.0f - q.y,
                     rz = (float)(bz * 8u) + 4.0f - q.z;
@@ -321,8 +324,8 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
         // (a brick whose voxels the node observes all gets every bit set, as the
         // per-voxel test would give it)
         const bool live = view == kViewSome;
-        s_live[tid] = (uint8_t)(((uint32_t)live << 4) | (bu << 2) | (view == kViewAll ? (uint32_t)kMaskAll : pc));
-        s_cw[tid] = view == kViewAll ? uniform_code_word(kMaskAll) : pcw;
+        s_live[i] = (uint8_t)(((uint32_t)live << 4) | (bu << 2) | (view == kViewAll ? (uint32_t)kMaskAll : pc));
+        s_cw[i] = view == kViewAll ? uniform_code_word(kMaskAll) : pcw;
         if (live) *s_any = 1;
     }
     __syncthreads();
@@ -343,10 +346,10 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
     // Code words of the chunk's bricks that hold an unknown voxel, with the code
     // of their block of 2x2x2 bricks (bits 18-19): uniform when the block's 8
     // bricks are all wholly unknown and their codes all clear or all set.
-    if (tid < cnt) {
-        const uint32_t f = s_live[tid];
+    for (int32_t i = tid; i < cnt; i += (int32_t)blockDim.x) {
+        const uint32_t f = s_live[i];
         if (((f >> 2) & 3u) != kBrickKnown) {
-            const int32_t g = tid & ~7;
+            const int32_t g = i & ~7;
             uint32_t all_none = 1u, all_set = 1u;
 #pragma unroll
             for (int32_t k = 0; k < 8; ++k) {
@@ -356,7 +359,7 @@ __device__ __forceinline__ void build_chunk(const MapDev& M, const SensorDev& S,
                 all_set &= (unk && ck == kMaskAll) ? 1u : 0u;
             }
             const uint32_t bc = all_none ? (uint32_t)kMaskNone : (all_set ? (uint32_t)kMaskAll : (uint32_t)kMaskMixed);
-            code[s_b[tid]] = (s_cw[tid] & 0x3ffffu) | (bc << 18);
+            code[s_b[i]] = (s_cw[i] & 0x3ffffu) | (bc << 18);
         }
     }
 }
