@@ -120,8 +120,8 @@ def test_launch_shape_table_and_config_validation():
     shapes = mg.mg_trace_shapes()
     assert len(shapes) >= 2
     for th, bricks in shapes:      # rays per trace workgroup, bricks per mask-builder workgroup
-        # (a builder chunk holds whole blocks of 2x2x2 bricks, at most 512 bricks)
-        assert th % 64 == 0 and 64 <= th <= 1024 and 16 <= bricks <= 512 and bricks % 8 == 0
+        # (a builder chunk holds whole blocks of 2x2x2 bricks, at most 1024 bricks)
+        assert th % 64 == 0 and 64 <= th <= 1024 and 16 <= bricks <= 1024 and bricks % 8 == 0
     for bad in [(-2, 0), (len(shapes), 0), (0, 3), (0, -1)]:
         with pytest.raises(mg.MGError) as e:
             mg._check(mg.lib().mg_batch_config(*bad))
