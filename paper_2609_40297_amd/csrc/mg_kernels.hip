@@ -136,7 +136,7 @@ __device__ __forceinline__ bool left_of(float2 b, float rx, float ry) { return b
 struct Shape {
     int threads, bricks;
 };
-constexpr Shape kShapes[] = {{256, 64}, {128, 64}, {512, 64}, {256, 128}, {256, 32}, {256, 256}, {128, 128}, {128, 256}, {512, 128}, {128, 512}, {128, 1024}};
+constexpr Shape kShapes[] = {{256, 64}, {128, 64}, {512, 64}, {256, 128}, {256, 32}, {256, 256}, {128, 128}, {128, 256}, {512, 128}, {128, 512}, {128, 1024}, {64, 1024}, {64, 256}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMaxBuildBricks = 1024;
 // the builder's fixed LDS beside its tables: a flag byte, a code word and a brick index per slot, and a word
