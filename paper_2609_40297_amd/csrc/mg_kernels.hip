@@ -871,6 +871,17 @@ __global__ void k_batch_zero(const BatchTree* __restrict__ trees, int32_t B2) {
         T.td.bins[i] = 0u;
 }
 
+// Workgroups are dealt to the chip's 8 XCDs (each with its own L2) in turn:
+// this permutation of the grid gives each XCD runs of kXcdRun consecutive work
+// units (neighbouring pixel blocks, or bricks, of one node) while the runs
+// still alternate over the whole grid; the grid's last partial round keeps
+// the identity.
+constexpr uint32_t kXcdRun = 16;
+__device__ __forceinline__ uint32_t xcd_grouped(uint32_t g, uint32_t n) {
+    const uint32_t full = (n / (8u * kXcdRun)) * (8u * kXcdRun);
+    return g < full ? ((g >> 3) / kXcdRun) * (8u * kXcdRun) + (g & 7u) * kXcdRun + (g >> 3) % kXcdRun : g;
+}
+
 // One depth level of all trees at once: work item = (tree, node) from
 // `items` (tree << 32 | node), T workgroups per item.
 template <int kTh>
@@ -878,8 +889,9 @@ __global__ __launch_bounds__(kTh) void k_trace_multi(const BatchTree* __restrict
                                                      const unsigned long long* __restrict__ items, SensorDev S) {
     __shared__ uint32_t s_bins[2 * kMaxBins];
     // (workgroup-uniform values kept in scalar registers)
-    const int32_t item = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)S.T));
-    const int32_t tile = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x - item * S.T);
+    const uint32_t g = xcd_grouped(blockIdx.x, gridDim.x);
+    const int32_t item = __builtin_amdgcn_readfirstlane((int32_t)(g / (uint32_t)S.T));
+    const int32_t tile = __builtin_amdgcn_readfirstlane((int32_t)g - item * S.T);
     const unsigned long long it = items[item];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
     if (BT.status != nullptr && *BT.status != 0) return;      // (the request has failed)
@@ -901,7 +913,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchT
     __shared__ uint32_t s_cw[kMaxBuildBricks];
     __shared__ uint32_t s_b[kMaxBuildBricks];
     __shared__ int32_t s_any;
-    const unsigned long long it = items[blockIdx.x / chunks];
+    const uint32_t g = xcd_grouped(blockIdx.x, gridDim.x);
+    const unsigned long long it = items[g / (uint32_t)chunks];
     const BatchTree& BT = trees[(uint32_t)(it >> 32)];
     if (BT.status != nullptr && *BT.status != 0) return;      // (the request has failed)
     SensorDev St = S;
@@ -909,7 +922,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_mask_build_multi(const BatchT
     St.rv2 = BT.rv2;
     const MapDev M = BT.map;
     const TreeDev Tr = BT.td;
-    build_chunk(M, St, Tr, (int32_t)(uint32_t)it, (int32_t)(blockIdx.x % chunks), bricks, smem, s_live, s_cw, s_b, &s_any);
+    build_chunk(M, St, Tr, (int32_t)(uint32_t)it, (int32_t)(g % (uint32_t)chunks), bricks, smem, s_live, s_cw, s_b, &s_any);
 }
 
 // Window selection of one (tree, node) item of a batch: gain, window, the
