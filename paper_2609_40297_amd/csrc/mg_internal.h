@@ -255,6 +255,7 @@ hipError_t launch_depth_out(const SensorDev& sd, const TreeDev& td, float* depth
 // and bricks per workgroup of the mask builder.
 int shape_count();
 void shape_of(int shape, int* threads, int* bricks);
+int serve_shape();                         // the launch shape the server's level launches use
 int32_t tiles_per_node(const SensorDev& sd, int shape);
 size_t lds_limit();                        // LDS bytes one workgroup may use on the current device
 size_t build_lds_bytes(const SensorDev& sd);   // LDS of the mask builder (sensor tables)

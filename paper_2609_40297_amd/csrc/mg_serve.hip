@@ -391,7 +391,7 @@ int mg_server_s::step() {
                            compute);
     if (e == hipSuccess)
         e = launch_batch_level(d_trees, d_items, (int32_t)n_items, d_items + n_items, (int32_t)n_mitems, mask_bricks, sd,
-                               compute, 0);
+                               compute, serve_shape());
     size_t so = 0;
     std::vector<std::pair<Request*, size_t>> finishing;
     for (Request* r : active) {
