@@ -761,14 +761,17 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
     }
 }
 
+// Per-tree levels: one-wave workgroups (as the batch autotuner picks for the
+// large workloads).
+constexpr int kTreeTraceThreads = 64;
 template <bool kMarginal>
-__global__ __launch_bounds__(kThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
-                                                    const int32_t* __restrict__ nodes) {
+__global__ __launch_bounds__(kTreeTraceThreads) void k_trace(MapDev M, SensorDev S, TreeDev Tr,
+                                                             const int32_t* __restrict__ nodes) {
     __shared__ uint32_t s_bins[2 * kMaxBins];
     // (workgroup-uniform values kept in scalar registers)
     const int32_t item = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)S.T));
     const int32_t tile = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x - item * S.T);
-    trace_tile<kMarginal, kThreads>(M, S, Tr, nodes[item], tile, s_bins);
+    trace_tile<kMarginal, kTreeTraceThreads>(M, S, Tr, nodes[item], tile, s_bins);
 }
 
 // ---------------------------------------------------------------- window selection
@@ -1156,11 +1159,13 @@ int32_t tiles_per_node(const SensorDev& sd, int shape) {
 hipError_t launch_trace(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
                         int32_t n_nodes, bool marginal, hipStream_t s) {
     if (n_nodes <= 0) return hipSuccess;
-    dim3 grid((unsigned)n_nodes * (unsigned)sd.T);
+    SensorDev st = sd;
+    st.T = (sd.n_blocks * 64 + kTreeTraceThreads - 1) / kTreeTraceThreads;   // tiles per node at this size
+    dim3 grid((unsigned)n_nodes * (unsigned)st.T);
     if (marginal)
-        hipLaunchKernelGGL((k_trace<true>), grid, dim3(kThreads), 0, s, m, sd, td, nodes);
+        hipLaunchKernelGGL((k_trace<true>), grid, dim3(kTreeTraceThreads), 0, s, m, st, td, nodes);
     else
-        hipLaunchKernelGGL((k_trace<false>), grid, dim3(kThreads), 0, s, m, sd, td, nodes);
+        hipLaunchKernelGGL((k_trace<false>), grid, dim3(kTreeTraceThreads), 0, s, m, st, td, nodes);
     return hipGetLastError();
 }
 
@@ -1168,10 +1173,17 @@ static int32_t build_chunks(const MapDev& m, int32_t bricks) {
     return (int32_t)((m.build_slots + (uint32_t)bricks - 1) / (uint32_t)bricks);
 }
 
+// Builder chunk of a per-tree level: 256 bricks once the level still gives
+// every CU about eight workgroups with them, else 64 (small levels need the
+// finer split to fill the chip).
+static int32_t tree_build_bricks(const MapDev& m, int32_t n_nodes) {
+    return (int64_t)n_nodes * build_chunks(m, 256) >= 2048 ? 256 : 64;
+}
+
 hipError_t launch_mask_build(const MapDev& m, const SensorDev& sd, const TreeDev& td, const int32_t* nodes,
                              int32_t n_nodes, hipStream_t s) {
     if (n_nodes <= 0) return hipSuccess;
-    const int32_t bricks = kShapes[0].bricks, chunks = build_chunks(m, bricks);
+    const int32_t bricks = tree_build_bricks(m, n_nodes), chunks = build_chunks(m, bricks);
     const size_t lds = build_lds_bytes(sd);
     if (lds + kBuildFixedLds > lds_limit()) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_mask_build, dim3((unsigned)n_nodes * (unsigned)chunks), dim3(kBuildThreads), lds, s, m, sd,
