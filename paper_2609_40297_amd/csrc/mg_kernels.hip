@@ -645,20 +645,18 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
             // has crossed the boundaries that come before that crossing in the
             // same order. The voxels crossed are one per crossing; crossing an
             // unknown block counts them all as absolute, and as marginal when no
-            // ancestor observes any of them. An unknown block is crossed this way
-            // only if it is left before the range ends.
+            // ancestor observes any of them. An unknown block that the range ends
+            // in is finished in one step too: its voxels visited before the range
+            // ends are counted and the ray ends.
             float tn;                           // entry parameter of the next voxel
             float kx, ky, kz;                   // boundaries this step crosses along each axis (set by
                                                 // the crossing when it is taken, else by the voxel step)
-            bool whole = false;
             uint32_t level = (st >> kLevelShift) & kLevelMask;   // the voxel's block: edge 32 >> level, or none (0)
             const bool free_blk = (level != 0u) & ((st & 3u) == kFree);
             bool cand = free_blk;
             uint32_t code = kMaskNone;          // (the absolute pass, and the root, see nothing observed)
-            // (a wholly unknown block with a uniform code is answered by the code
-            // also when it is walked voxel by voxel: the words of its brick need
-            // not exist)
-            bool by_code = false;
+            // (a wholly unknown block with a uniform code is always crossed by its
+            // code: the words of its brick need not exist)
             if ((level != 0u) & ((st & 3u) == kUnknown)) {
                 if (kMarginal && pc != nullptr) {
                     const uint32_t b = mask_brick(ix, iy, iz, M);
@@ -675,8 +673,7 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                     code = block_uniform ? bc : (brick_uniform ? (cw & 3u) : ((cw >> qs) & 3u));
                     level = block_uniform ? 1u : (brick_uniform ? (level > 2u ? level : 2u) : 3u);
                 }
-                by_code = code != kMaskMixed;
-                cand = by_code;
+                cand = code != kMaskMixed;
             }
             if (cand) {
                 const int32_t edge = 32 >> level;
@@ -687,36 +684,36 @@ __device__ __forceinline__ void trace_tile(const MapDev& M, const SensorDev& S, 
                 const bool fy_ = !fx_ & (Ty <= Tz);
                 const bool fz_ = !fx_ & !fy_;
                 const float T = fx_ ? Tx : (fy_ ? Ty : Tz);
-                whole = free_blk | (T < S.rv);
-                if (whole) {
-                    // An axis that precedes the exit axis in the tie order also
-                    // counts a boundary whose parameter equals T: it compares with
-                    // the next float above T (T >= 0; +0 for -0 first).
-                    const float Tn = __uint_as_float(__float_as_uint(T + 0.f) + 1u);
-                    const bool wide = ballot(level == 1u) != 0ull;     // some lane crosses a 16-voxel block
-                    kx = crossings_before(bx, dbx, qx, fx, fx_ ? T : Tn, wide) + (fx_ ? 1.f : 0.f);
-                    ky = crossings_before(by, dby, qy, fy, fz_ ? Tn : T, wide) + (fy_ ? 1.f : 0.f);
-                    kz = crossings_before(bz, dbz, qz, fz, T, wide) + (fz_ ? 1.f : 0.f);
-                    tn = T;
-                    if (!free_blk) {
-                        const uint32_t v = (uint32_t)(kx + ky + kz);
-                        n_abs += v;
-                        if (kMarginal) n_new += code == kMaskNone ? v : 0u;
-                    }
+                // An axis that precedes the exit axis in the tie order also
+                // counts a boundary whose parameter equals T: it compares with
+                // the next float above T (T >= 0; +0 for -0 first). When the
+                // range ends inside an unknown block (cut), the ray's remaining
+                // voxels are the current one and one per boundary whose
+                // parameter is below the range, all inside the block: every
+                // axis counts against the range, and the ray ends (T >= range).
+                const bool cut = !free_blk & !(T < S.rv);
+                const float Tn = __uint_as_float(__float_as_uint(T + 0.f) + 1u);
+                const bool wide = ballot(level == 1u) != 0ull;     // some lane crosses a 16-voxel block
+                kx = crossings_before(bx, dbx, qx, fx, cut ? S.rv : (fx_ ? T : Tn), wide) + (fx_ ? 1.f : 0.f);
+                ky = crossings_before(by, dby, qy, fy, cut ? S.rv : (fz_ ? Tn : T), wide) + (fy_ ? 1.f : 0.f);
+                kz = crossings_before(bz, dbz, qz, fz, cut ? S.rv : T, wide) + (fz_ ? 1.f : 0.f);
+                tn = T;
+                if (!free_blk) {
+                    const uint32_t v = (uint32_t)(kx + ky + kz);
+                    n_abs += v;
+                    if (kMarginal) n_new += code == kMaskNone ? v : 0u;
                 }
             }
-            if (!whole) {
+            if (!cand) {
                 const bool unk = is_unknown(st);
                 n_abs += unk ? 1u : 0u;
                 if (kMarginal && pm != nullptr) {
                     // every lane loads (a lane off unknown voxels reads word 0), so the
                     // word lands in the register the next step reads
-                    const bool by_word = unk & !by_code;
-                    const uint32_t off = (by_word ? mask_word(ix, iy, iz, M) : 0u) << 2;   // < 2^29 bytes
+                    const uint32_t off = (unk ? mask_word(ix, iy, iz, M) : 0u) << 2;   // < 2^29 bytes
                     mw = *(gwords_t)((gbytes_t)pm + off);
                     mb = mask_bit(ix, iy);
-                    pend = by_word;
-                    n_new += (by_code & (code == kMaskNone)) ? 1u : 0u;
+                    pend = unk;
                 }
                 const bool mx = (tx <= ty) & (tx <= tz);
                 const bool my = !mx & (ty <= tz);
