@@ -188,8 +188,8 @@ def test_evaluations_of_one_tree_do_not_see_each_others_masks(mg, orc):
     """A path mask keeps only what can be read (the words of a wholly unknown brick only when its
     code is mixed), so its memory holds what an earlier evaluation of the same tree left there.
     Marginal, single-parent and marginal again on one tree object, each against the oracle, with
-    ranges that end inside wholly unknown bricks (rays that walk such a brick voxel by voxel
-    read its code, not its words)."""
+    ranges that end inside wholly unknown bricks (a ray whose range ends in such a brick counts
+    its last voxels there from the brick's code, not its words, and ends in one step)."""
     import torch
     m = _free_brick_map(955, (40, 32, 24))
     pos = np.array([[8.0, 8.0, 8.0], [16.0, 16.0, 8.0], [8.0, 12.5, 12.0], [24.0, 8.0, 16.0], [12.5, 12.5, 12.5],
