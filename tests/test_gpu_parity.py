@@ -214,6 +214,26 @@ def test_evaluations_of_one_tree_do_not_see_each_others_masks(mg, orc):
             M.close()
 
 
+def test_ranges_that_end_inside_unknown_blocks(mg, orc):
+    """A wholly unknown map of 16-voxel blocks (its last blocks reach past the grid): every ray
+    ends at the range inside a wholly unknown block, which the device finishes in one step where
+    the parent's mask is uniform over the block (or brick, or quarter) and walks voxel by voxel
+    where it is mixed. Nodes on block corners, faces and inside; integer ranges that tie the
+    boundary parameters of axis-aligned rays (a boundary at exactly the range is not crossed);
+    45-degree rays; a finer panorama with a fractional range."""
+    m = W.micro_map((48, 40, 36), fill=W.UNK)
+    pos = np.array([[16.0, 16.0, 16.0], [24.0, 16.0, 16.0], [16.0, 24.0, 20.0], [32.0, 20.0, 16.0],
+                    [8.5, 8.5, 8.5], [20.0, 28.0, 12.0], [30.25, 12.75, 18.5], [40.0, 32.0, 24.0],
+                    [16.0, 8.0, 28.0], [24.5, 24.5, 4.5]], np.float32)
+    tree = W.Tree(pos_m=pos, parent=np.array([-1, 0, 0, 1, 1, 2, 3, 6, 5, 2], np.int32))
+    for sen in (W.Sensor(n_az=8, n_el=3, fov_h_deg=90, fov_v_deg=90, range_m=12.0, yaw_bins=8, az_offset_deg=-22.5),
+                W.Sensor(n_az=8, n_el=3, fov_h_deg=90, fov_v_deg=90, range_m=16.0, yaw_bins=8, az_offset_deg=-22.5),
+                W.Sensor(n_az=96, n_el=15, fov_h_deg=90, fov_v_deg=80, range_m=10.5, yaw_bins=24)):
+        got, ref = _full_parity(mg, orc, m, tree, sen, f"unknown blocks, range {sen.range_m}")
+        assert np.all(ref["g_abs"] > 0)
+        assert np.any(ref["g_db"][1:] < ref["g_abs"][1:])   # the parents' masks decide some counts
+
+
 def test_occupied_everywhere_and_unknown_everywhere(mg, orc):
     sen = W.Sensor(n_az=64, n_el=12, fov_h_deg=90, fov_v_deg=60, range_m=6.0, yaw_bins=16)
     pos = np.array([[4.3, 4.6, 3.2], [5.1, 4.2, 3.7], [3.2, 5.5, 2.9]], np.float32)
