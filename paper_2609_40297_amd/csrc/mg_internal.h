@@ -149,6 +149,25 @@ __device__ __forceinline__ uint32_t mask_brick(int32_t x, int32_t y, int32_t z, 
     return (uint32_t)(x >> 3) + __umul24(M.mbx, (uint32_t)(y >> 3) + __umul24(M.mby, (uint32_t)(z >> 3)));
 }
 
+// How many of one axis's boundaries b0, b0 + db, b0 + 2 db, ... the DDA
+// crosses before the crossing at parameter Tc: those with parameter
+// t = (b - q) * f below Tc (a caller that wants ties counted passes the next
+// float above the crossing). Parameters grow by at least 1 from one boundary
+// to the next, so these boundaries are a prefix; the caller's crossing leaves
+// a block of at most 16 voxels a side, so the prefix ends at the axis's own
+// exit from that block, at most 15 boundaries on. Three probes (at 3, then
+// 3 +- 2, then +- 1) find its length when the block's edge is at most 8; a
+// first probe at 7 (then 11 or 3) extends the search to 15 (`wide`). Boundaries are evaluated exactly as the single step
+// evaluates them (the fused multiply-add of integers is exact). Returned as a
+// float count.
+__device__ __forceinline__ float crossings_before(float b0, float db, float q, float f, float Tc, bool wide) {
+    float m = 3.f;
+    if (wide) m = ((__builtin_fmaf(7.f, db, b0) - q) * f < Tc) ? 11.f : 3.f;
+    m += ((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 2.f : -2.f;
+    m += ((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 1.f : -1.f;
+    return m + (((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 1.f : 0.f);
+}
+
 // Panorama ray tables and yaw-window geometry (built on the host, see mg_api).
 struct SensorDev {
     const float4* d4;          // [R] unit direction (w unused)

@@ -245,6 +245,45 @@ struct Window {
     }
 };
 
+// One step over the marked block (wholly free or wholly unknown, `edge` voxels
+// a side) that voxel (ix, iy, iz) lies in, taken as the per-voxel mode's trace
+// takes it: the block is left through the face whose boundary parameter comes
+// first (ties x, then y, then z), and every axis has crossed the boundaries
+// whose parameters come before that crossing in the same order, which is where
+// the voxel-by-voxel DDA stands once it has left the block. Updates the voxel,
+// the next boundaries (integers) and their parameters, and returns the entry
+// parameter of the voxel it enters.
+__device__ __forceinline__ float cross_block(int32_t edge, float4 p, float4 inv, int32_t sx, int32_t sy, int32_t sz,
+                                             int32_t& ix, int32_t& iy, int32_t& iz, int32_t& bx, int32_t& by,
+                                             int32_t& bz, float& tx, float& ty, float& tz) {
+    const float inf = __builtin_inff();
+    // (an axis the ray does not move along: boundary +inf, node -inf, factor 1,
+    // so each of its parameters is +inf)
+    const float qx = sx ? p.x : -inf, qy = sy ? p.y : -inf, qz = sz ? p.z : -inf;
+    const float fx = sx ? inv.x : 1.f, fy = sy ? inv.y : 1.f, fz = sz ? inv.z : 1.f;
+    const float Tx = ((float)((ix & -edge) + (sx > 0 ? edge : 0)) - qx) * fx;
+    const float Ty = ((float)((iy & -edge) + (sy > 0 ? edge : 0)) - qy) * fy;
+    const float Tz = ((float)((iz & -edge) + (sz > 0 ? edge : 0)) - qz) * fz;
+    const bool ex = (Tx <= Ty) & (Tx <= Tz);
+    const bool ey = !ex & (Ty <= Tz);
+    const bool ez = !ex & !ey;
+    const float T = ex ? Tx : (ey ? Ty : Tz);
+    // an axis before the exit axis in the tie order also crosses a boundary at
+    // exactly T: it compares with the next float above T (T >= 0; +0 for -0)
+    const float Tn = __uint_as_float(__float_as_uint(T + 0.f) + 1u);
+    const bool wide = edge > 8;
+    const int32_t kx = (int32_t)crossings_before(sx ? (float)bx : inf, (float)sx, qx, fx, ex ? T : Tn, wide) + (ex ? 1 : 0);
+    const int32_t ky = (int32_t)crossings_before(sy ? (float)by : inf, (float)sy, qy, fy, ez ? Tn : T, wide) + (ey ? 1 : 0);
+    const int32_t kz = (int32_t)crossings_before(sz ? (float)bz : inf, (float)sz, qz, fz, T, wide) + (ez ? 1 : 0);
+    ix += kx * sx; bx += kx * sx;
+    iy += ky * sy; by += ky * sy;
+    iz += kz * sz; bz += kz * sz;
+    tx = sx ? ((float)bx - p.x) * inv.x : inf;
+    ty = sy ? ((float)by - p.y) * inv.y : inf;
+    tz = sz ? ((float)bz - p.z) * inv.z : inf;
+    return T;
+}
+
 // One level of one tree: workgroup = kIvlThreads panorama rays of one node.
 __global__ __launch_bounds__(kIvlThreads) void k_ivl_trace(MapDev M, SensorDev S, TreeDev Tr, Cam C,
                                                            const int32_t* __restrict__ nodes,
@@ -294,9 +333,15 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_trace(MapDev M, SensorDev S
             for (;;) {
                 if (ix < 0 || ix >= M.nx || iy < 0 || iy >= M.ny || iz < 0 || iz >= M.nz) break;
                 if (!(t < S.rv)) break;
-                if (M.bricks[voxel_addr(ix, iy, iz, M)] == kOccupied) {
+                const uint32_t st = M.bricks[voxel_addr(ix, iy, iz, M)];
+                if (st == kOccupied) {
                     h = t;
                     break;
+                }
+                const uint32_t level = (st >> kLevelShift) & kLevelMask;
+                if (level != 0u) {          // a marked block holds no occupied voxel
+                    t = cross_block(32 >> level, p, inv, sx, sy, sz, ix, iy, iz, bx, by, bz, tx, ty, tz);
+                    continue;
                 }
                 const int ax = (tx <= ty && tx <= tz) ? 0 : (ty <= tz ? 1 : 2);
                 if (ax == 0) {
@@ -321,6 +366,11 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_trace(MapDev M, SensorDev S
             if (!(t < S.rv)) break;
             const uint8_t st = M.bricks[voxel_addr(ix, iy, iz, M)];
             if (st == kOccupied) break;
+            const uint32_t level = (st >> kLevelShift) & kLevelMask;
+            if ((level != 0u) & ((st & 3u) == kFree)) {    // a free block counts nothing
+                t = cross_block(32 >> level, p, inv, sx, sy, sz, ix, iy, iz, bx, by, bz, tx, ty, tz);
+                continue;
+            }
             const int ax = (tx <= ty && tx <= tz) ? 0 : (ty <= tz ? 1 : 2);
             const float tn = ax == 0 ? tx : (ax == 1 ? ty : tz);
             if (is_unknown(st)) {
@@ -398,9 +448,16 @@ __global__ __launch_bounds__(kIvlThreads) void k_ivl_render(MapDev M, Cam C, Tre
     for (;;) {
         if (i[0] < 0 || i[0] >= n[0] || i[1] < 0 || i[1] >= n[1] || i[2] < 0 || i[2] >= n[2]) break;
         if (!(t < C.rv)) break;
-        if (M.bricks[voxel_addr(i[0], i[1], i[2], M)] == kOccupied) {
+        const uint32_t sv = M.bricks[voxel_addr(i[0], i[1], i[2], M)];
+        if (sv == kOccupied) {
             h = t;
             break;
+        }
+        const uint32_t level = (sv >> kLevelShift) & kLevelMask;
+        if (level != 0u) {              // a marked block holds no occupied voxel
+            t = cross_block(32 >> level, make_float4(qv[0], qv[1], qv[2], 0.f), make_float4(iv[0], iv[1], iv[2], 0.f),
+                            st[0], st[1], st[2], i[0], i[1], i[2], nb[0], nb[1], nb[2], tn[0], tn[1], tn[2]);
+            continue;
         }
         const int ax = (tn[0] <= tn[1] && tn[0] <= tn[2]) ? 0 : (tn[1] <= tn[2] ? 1 : 2);
         t = tn[ax];

@@ -102,6 +102,27 @@ def test_interval_degenerate_trees(mg, ivl):
             _same(got, ref)
 
 
+@pytest.mark.parametrize("dims", [(40, 32, 24), (37, 29, 21)])
+def test_interval_nested_blocks(mg, ivl, dims):
+    """Maps of nested aligned blocks (16-voxel blocks, bricks, quarters and 2x2x2 blocks, wholly
+    free or wholly unknown, some reaching past the grid): the device crosses a marked block in one
+    step in the walk to the first hit and a free one in the counting walk; the oracle walks voxel
+    by voxel. Nodes on block corners, edges and faces, 45-degree rays whose boundary parameters
+    tie, an integer range; every capacity of the merged-interval list."""
+    from tests.test_gpu_parity import _nested_block_map
+    m = _nested_block_map(1300 + dims[0], dims)
+    pos = np.array([[8.0, 8.0, 8.0], [16.0, 16.0, 8.0], [12.0, 12.0, 4.0], [24.0, 8.0, 16.0], [10.0, 14.0, 6.0],
+                    [16.0, 8.0, 4.5], [9.5, 17.0, 8.0], [30.0, 22.0, 14.0], [4.25, 20.75, 19.5], [20.0, 20.0, 10.0]],
+                   np.float32)
+    tree = W.Tree(pos_m=pos, parent=np.array([-1, 0, 0, 1, 1, 2, 3, 4, 6, 8], np.int32))
+    for sen in (W.Sensor(n_az=8, n_el=3, fov_h_deg=90, fov_v_deg=90, range_m=30.0, yaw_bins=8, az_offset_deg=-22.5),
+                W.Sensor(n_az=100, n_el=17, fov_h_deg=90, fov_v_deg=80, range_m=13.7, yaw_bins=20)):
+        log(f"[interval] nested blocks {dims} {sen.n_az}x{sen.n_el}")
+        ref = ivl.eval_tree(m, tree, sen, n_threads=threads())
+        for got in _gpu_interval(mg, m, tree, sen, caps=(-1, 1, 3)):
+            _same(got, ref)
+
+
 def test_interval_step_sampled(mg, ivl):
     """500-node planner step (160 x 93 buffers by the resolution rule): the ancestor chains of three
     deepest leaves against the oracle; the whole tree evaluated on the GPU."""
