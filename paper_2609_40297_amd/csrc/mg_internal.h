@@ -168,6 +168,45 @@ __device__ __forceinline__ float crossings_before(float b0, float db, float q, f
     return m + (((__builtin_fmaf(m, db, b0) - q) * f < Tc) ? 1.f : 0.f);
 }
 
+// One step over the marked block (wholly free or wholly unknown, `edge` voxels
+// a side) that voxel (ix, iy, iz) lies in, taken as the per-voxel trace
+// takes it: the block is left through the face whose boundary parameter comes
+// first (ties x, then y, then z), and every axis has crossed the boundaries
+// whose parameters come before that crossing in the same order, which is where
+// the voxel-by-voxel DDA stands once it has left the block. Updates the voxel,
+// the next boundaries (integers) and their parameters, and returns the entry
+// parameter of the voxel it enters.
+__device__ __forceinline__ float cross_block(int32_t edge, float4 p, float4 inv, int32_t sx, int32_t sy, int32_t sz,
+                                             int32_t& ix, int32_t& iy, int32_t& iz, int32_t& bx, int32_t& by,
+                                             int32_t& bz, float& tx, float& ty, float& tz) {
+    const float inf = __builtin_inff();
+    // (an axis the ray does not move along: boundary +inf, node -inf, factor 1,
+    // so each of its parameters is +inf)
+    const float qx = sx ? p.x : -inf, qy = sy ? p.y : -inf, qz = sz ? p.z : -inf;
+    const float fx = sx ? inv.x : 1.f, fy = sy ? inv.y : 1.f, fz = sz ? inv.z : 1.f;
+    const float Tx = ((float)((ix & -edge) + (sx > 0 ? edge : 0)) - qx) * fx;
+    const float Ty = ((float)((iy & -edge) + (sy > 0 ? edge : 0)) - qy) * fy;
+    const float Tz = ((float)((iz & -edge) + (sz > 0 ? edge : 0)) - qz) * fz;
+    const bool ex = (Tx <= Ty) & (Tx <= Tz);
+    const bool ey = !ex & (Ty <= Tz);
+    const bool ez = !ex & !ey;
+    const float T = ex ? Tx : (ey ? Ty : Tz);
+    // an axis before the exit axis in the tie order also crosses a boundary at
+    // exactly T: it compares with the next float above T (T >= 0; +0 for -0)
+    const float Tn = __uint_as_float(__float_as_uint(T + 0.f) + 1u);
+    const bool wide = edge > 8;
+    const int32_t kx = (int32_t)crossings_before(sx ? (float)bx : inf, (float)sx, qx, fx, ex ? T : Tn, wide) + (ex ? 1 : 0);
+    const int32_t ky = (int32_t)crossings_before(sy ? (float)by : inf, (float)sy, qy, fy, ez ? Tn : T, wide) + (ey ? 1 : 0);
+    const int32_t kz = (int32_t)crossings_before(sz ? (float)bz : inf, (float)sz, qz, fz, T, wide) + (ez ? 1 : 0);
+    ix += kx * sx; bx += kx * sx;
+    iy += ky * sy; by += ky * sy;
+    iz += kz * sz; bz += kz * sz;
+    tx = sx ? ((float)bx - p.x) * inv.x : inf;
+    ty = sy ? ((float)by - p.y) * inv.y : inf;
+    tz = sz ? ((float)bz - p.z) * inv.z : inf;
+    return T;
+}
+
 // Panorama ray tables and yaw-window geometry (built on the host, see mg_api).
 struct SensorDev {
     const float4* d4;          // [R] unit direction (w unused)

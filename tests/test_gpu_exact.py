@@ -62,6 +62,24 @@ def test_exact_random_micro(mg, orc, seed):
     _check(mg, orc, m, tree, sen, f"micro{seed}")
 
 
+@pytest.mark.parametrize("dims", [(40, 32, 24), (37, 29, 21)])
+def test_exact_nested_blocks(mg, orc, dims):
+    """Maps of nested aligned blocks (free blocks of every size crossed in one step by the device's
+    walk, wholly unknown ones walked voxel by voxel; some blocks reach past the grid) against the
+    oracle's voxel-by-voxel sets: nodes on block corners, edges and faces, 45-degree rays whose
+    boundary parameters tie, an integer range."""
+    from tests.test_gpu_parity import _nested_block_map
+    m = _nested_block_map(1400 + dims[0], dims)
+    pos = np.array([[8.0, 8.0, 8.0], [16.0, 16.0, 8.0], [12.0, 12.0, 4.0], [24.0, 8.0, 16.0], [10.0, 14.0, 6.0],
+                    [16.0, 8.0, 4.5], [9.5, 17.0, 8.0], [30.0, 22.0, 14.0], [4.25, 20.75, 19.5], [20.0, 20.0, 10.0]],
+                   np.float32)
+    tree = W.Tree(pos_m=pos, parent=np.array([-1, 0, 0, 1, 1, 2, 3, 4, 6, 8], np.int32))
+    for sen in (W.Sensor(n_az=8, n_el=3, fov_h_deg=90, fov_v_deg=90, range_m=30.0, yaw_bins=8, az_offset_deg=-22.5),
+                W.Sensor(n_az=100, n_el=17, fov_h_deg=90, fov_v_deg=80, range_m=13.7, yaw_bins=20)):
+        ref = _check(mg, orc, m, tree, sen, f"nested blocks {dims} {sen.n_az}x{sen.n_el}")
+        assert int(ref["X_ray"].sum()) > 0
+
+
 def test_exact_step_sampled(mg, orc):
     w = W.make("step")
     t = w.trees[0]
