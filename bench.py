@@ -19,7 +19,7 @@ Modes
            every level.
   batched  the whole request in one call (mg_eval_marginal_batch), one copy
            of the results at the end; per depth level a trace, a window and a
-           mask-builder launch on two stream groups.
+           mask-builder launch on three stream groups.
   graph    the same call with the plan's launches recorded once into a HIP
            graph and replayed (mg_batch_config(-1, 1)).
   persistent  the same call configured as one cooperative launch per step
@@ -559,7 +559,7 @@ def roofline_of(wc, trace, steps, n_total, yaw_bins, ms_per_step, traffic):
     # 2 x B x 4 B of bin counts per node
     alg_step = wc["visits"] * 1 + wc["anc_tests"] * 4 + wc["rays"] * 4 + n_total * 2 * yaw_bins * 4
     busy = trace["busy_ms"] / steps                 # union of the trace and builder launch intervals
-    summed = trace["total_ms"] / steps              # their summed durations (groups overlap on two streams)
+    summed = trace["total_ms"] / steps              # their summed durations (groups overlap on their streams)
     achieved = alg_step / (busy * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -228,7 +228,7 @@ int mg_score_branches(const mg_tree* trees, int32_t n_trees, void* hip_stream, c
  *          shape, and blocks until done; 0 .. count-1 = that shape
  *          (mg_trace_shapes).
  *   launch: 0 (default) = per depth level a trace, a window and a mask-builder
- *          launch, on two stream groups; 1 = those launches recorded once
+ *          launch, on three stream groups; 1 = those launches recorded once
  *          into a HIP graph that each call replays (on a library stream joined
  *          to hip_stream by events before and after); 2 = one persistent
  *          cooperative launch per call (Sec. IV-C's level order over all trees:

@@ -91,7 +91,7 @@ std::map<int, Replay> g_replay;
 std::mutex g_mu;
 std::map<std::vector<mg_tree>, std::unique_ptr<Plan>> g_plans;
 constexpr size_t kMaxPlans = 64;
-constexpr int32_t kGroups = 2;             // independent groups of a plan, one stream each (2 measured best of 1/2/4/8)
+constexpr int32_t kGroups = 3;             // independent groups of a plan, one stream each (3 measured best of 1/2/3/4/8)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
