@@ -370,9 +370,11 @@ int mg_server_submit(mg_server server, mg_map map, const float* pos_m, const int
 
 /* Queues a map update between replans: voxel_ids HOST uint32 [count] (linear
  * ids x + nx (y + ny z), distinct), states HOST uint8 [count] in {0, 1, 2};
- * both copied. The update is applied once it reaches the head of the queue
- * and no in-flight request uses the map, so requests submitted before it see
- * the old map and requests submitted after it the new one. *ticket works with
+ * both copied. The update is applied once every request on `map` submitted
+ * before it has finished (none is queued ahead of it or in flight), so those
+ * requests see the old map; requests on `map` submitted after it wait for it
+ * and see the new one, while requests on other maps are not held back by it.
+ * *ticket works with
  * mg_server_poll / mg_server_wait like a request's. MG_E_INVALID for an id
  * outside the grid or a larger state. Thread-safe. */
 int mg_server_map_update(mg_server server, mg_map map, const uint32_t* voxel_ids, const uint8_t* states,

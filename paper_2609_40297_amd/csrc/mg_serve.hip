@@ -10,9 +10,10 @@
 // arena block is released. Nothing on the request path allocates device memory.
 //
 // Map updates between replans are queued with the requests. An update is
-// applied when it reaches the head of the queue and no in-flight request
-// uses its map: requests submitted before it see the old map, requests
-// submitted after it the new one.
+// applied once every request on its map submitted before it has finished and
+// no in-flight request uses the map: requests submitted before it see the old
+// map, requests on that map submitted after it wait for it and see the new
+// one, and requests on other maps are not held back by it.
 //
 // Failure isolation: every in-flight request has a device status word that its
 // kernels check first; a nonzero word (set by mg_server_fail_request, as a
@@ -269,19 +270,42 @@ int mg_server_s::grow(size_t trees, size_t items, size_t stage_words) {
 
 // One step: admit, launch one level of every in-flight request, retire finished ones.
 int mg_server_s::step() {
-    // admission (FIFO; the head waits until a slot and enough arena are free)
+    // Admission, in queue order. A map update is applied once no in-flight
+    // request uses its map (and not while paused); until then every later
+    // entry on that map stays queued behind it, while entries on other maps go
+    // ahead. Requests are admitted first come first served: the first that
+    // finds no free slot or arena block ends the admission (and so holds back
+    // what is queued behind it).
     for (;;) {
         Request* r = nullptr;
         {
             std::lock_guard<std::mutex> lk(mu);
-            if (queue.empty()) break;
-            r = queue.front();
-            if (r->kind == 1) {
-                // a map update waits for the in-flight requests on its map (and for a resume)
-                if (paused) break;
-                if (std::any_of(inflight.begin(), inflight.end(), [&](Request* q) { return q->map == r->map; })) break;
-                queue.pop_front();
+            std::vector<mg_map> held;              // maps with an update still queued
+            for (auto it = queue.begin(); it != queue.end(); ++it) {
+                Request* q = *it;
+                const bool behind = std::find(held.begin(), held.end(), q->map) != held.end();
+                if (q->kind == 1) {
+                    if (!behind && !paused &&
+                        std::none_of(inflight.begin(), inflight.end(), [&](Request* f) { return f->map == q->map; })) {
+                        r = q;
+                        queue.erase(it);
+                        break;
+                    }
+                    if (!behind) held.push_back(q->map);
+                    continue;
+                }
+                if (behind) continue;                  // it must see the update queued before it
+                if ((int32_t)inflight.size() >= cfg.max_inflight) break;
+                size_t off = 0;
+                if (!arena.alloc(q->bytes, &off)) break;
+                q->arena_off = off;
+                q->slot = free_slots.back();
+                free_slots.pop_back();
+                r = q;
+                queue.erase(it);
+                break;
             }
+            if (r == nullptr) break;
         }
         if (r->kind == 1) {
             const int urc = apply_update(r);
@@ -292,16 +316,6 @@ int mg_server_s::step() {
             cv_done.notify_all();
             if (urc != MG_OK) return urc;
             continue;
-        }
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            if ((int32_t)inflight.size() >= cfg.max_inflight) break;
-            size_t off = 0;
-            if (!arena.alloc(r->bytes, &off)) break;
-            r->arena_off = off;
-            r->slot = free_slots.back();
-            free_slots.pop_back();
-            queue.pop_front();
         }
         int rc = mgb::upload_into(r->map, *r->host, &cfg.sensor, upload, (char*)arena_mem + r->arena_off, &r->tree);
         std::lock_guard<std::mutex> lk(mu);

@@ -174,6 +174,62 @@ def test_map_updates_are_ordered_with_requests(mg):
     Ms.close()
 
 
+def test_update_holds_back_only_requests_on_its_map(mg):
+    """With the server paused, a request on map A is admitted; an update of A queued next cannot be
+    applied while that request is in flight. A request on map B queued behind the update is admitted
+    at once (the update does not hold back other maps), a later request on A stays queued behind the
+    update. After resuming, the first request on A sees the old map, the later one the updated map,
+    and the request on B its own map."""
+    import time
+    import torch
+    from oracle import maps
+    w = W.make("tiny")
+    sen = w.sensor
+    st0 = w.map.states
+    rng = np.random.Generator(np.random.PCG64(91))
+    unk = np.flatnonzero(st0.reshape(-1) == W.UNK)
+    ids = rng.choice(unk, unk.size // 3, replace=False).astype(np.uint32)
+    new = rng.choice(np.array([W.FREE, W.OCC], np.uint8), ids.size, p=[0.85, 0.15])
+    st1, _ = maps.apply_updates(st0, ids, new)
+    stb = st0.copy()
+    stb.reshape(-1)[rng.choice(unk, unk.size // 5, replace=False)] = W.FREE
+    t0 = w.trees[0]
+
+    def plain(states):
+        M = mg.Map(states, w.map.voxel_m, w.map.origin_m)
+        T = mg.Tree(M, t0.pos_m, t0.parent, sen)
+        g, y, _ = T.eval_marginal()
+        torch.cuda.synchronize()
+        out = (mg.as_u32(g), y.cpu().numpy())
+        T.close()
+        M.close()
+        return out
+
+    e0, e1, eb = plain(st0), plain(st1), plain(stb)
+    MA = mg.Map(st0, w.map.voxel_m, w.map.origin_m)
+    MB = mg.Map(stb, w.map.voxel_m, w.map.origin_m)
+    S = mg.Server(sen, max_inflight=4, arena_bytes=1 << 30)
+    S.pause(True)
+    ra1 = S.submit(MA, t0.pos_m, t0.parent)
+    upd = S.map_update(MA, ids, new)
+    rb = S.submit(MB, t0.pos_m, t0.parent)
+    ra2 = S.submit(MA, t0.pos_m, t0.parent)
+    for _ in range(2000):                       # admission runs while paused
+        st = S.stats()
+        if st["in_flight"] == 2:
+            break
+        time.sleep(0.005)
+    assert st["in_flight"] == 2 and st["queued"] == 2 and st["steps"] == 0, st
+    S.pause(False)
+    for t, e in ((ra1, e0), (rb, eb), (ra2, e1)):
+        g, y, _ = S.wait(t)
+        assert np.array_equal(g, e[0]) and np.array_equal(y, e[1])
+    S.wait(upd)
+    S.close()
+    MB.close()
+    MA.close()
+
+
 def test_served_robot_maps_against_oracle(mg):
     """The serving workload's own requests (robot maps at 0.05, 0.1 and 0.2 m, trees of 167-1751
     nodes, depth 3-10) submitted together to a 16-slot server; in each request the ancestor chains of
